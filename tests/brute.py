@@ -1,0 +1,90 @@
+"""Brute-force dense staggered operator, built entry by entry in Python.
+
+Used only to pin the oracle on tiny lattices (2^4, 4^4 and small non-cubic
+shapes). It is written independently of the C oracle: its own coordinate
+enumeration, its own neighbour arithmetic, and a dense matrix instead of a
+matrix-free site loop. On lattices with an extent of 2 the forward and
+backward neighbours coincide and both hops add into the same matrix block,
+which a site loop that overwrote instead of accumulating would get wrong.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def sites(L):
+    """Yield (lex, coords) in lexicographic order (x fastest)."""
+    Lx, Ly, Lz, Lt = L
+    lex = 0
+    for t, z, y, x in itertools.product(range(Lt), range(Lz), range(Ly), range(Lx)):
+        yield lex, (x, y, z, t)
+        lex += 1
+
+
+def eo_index(L, c):
+    Lx, Ly, Lz, Lt = L
+    x, y, z, t = c
+    lex = x + Lx * (y + Ly * (z + Lz * t))
+    V = Lx * Ly * Lz * Lt
+    par = (x + y + z + t) % 2
+    return par * (V // 2) + lex // 2
+
+
+def shift(L, c, mu, d):
+    c = list(c)
+    c[mu] = (c[mu] + d) % L[mu]
+    return tuple(c)
+
+
+def eta(c, mu):
+    return -1.0 if sum(c[:mu]) % 2 else 1.0
+
+
+def dense_D(L, U, bc=(1, 1, 1, 1)):
+    """Dense D over all sites, rows/cols ordered (eo, colour): shape (3V, 3V), complex.
+
+    U: canonical float64 [4][V][3][3][2] (eo order).
+    """
+    V = int(np.prod(L))
+    Uc = U[..., 0] + 1j * U[..., 1]
+    D = np.zeros((3 * V, 3 * V), dtype=np.complex128)
+    for _, c in sites(L):
+        i = eo_index(L, c)
+        for mu in range(4):
+            e = eta(c, mu)
+            sp = bc[mu] if c[mu] == L[mu] - 1 else 1
+            sm = bc[mu] if c[mu] == 0 else 1
+            jf = eo_index(L, shift(L, c, mu, +1))
+            cm = shift(L, c, mu, -1)
+            jb = eo_index(L, cm)
+            D[3 * i:3 * i + 3, 3 * jf:3 * jf + 3] += e * sp * Uc[mu, i]
+            D[3 * i:3 * i + 3, 3 * jb:3 * jb + 3] -= e * sm * Uc[mu, jb].conj().T
+    return D
+
+
+def blocks(L, D):
+    """(D_eo, D_oe) blocks of the dense D: D_eo maps odd -> even, D_oe even -> odd."""
+    n = 3 * int(np.prod(L)) // 2
+    return D[:n, n:], D[n:, :n]
+
+
+def dense_A(L, U, mass, bc=(1, 1, 1, 1)):
+    Deo, Doe = blocks(L, dense_D(L, U, bc))
+    n = Deo.shape[0]
+    return 4.0 * mass * mass * np.eye(n) - Deo @ Doe
+
+
+def cvec(v):
+    """canonical [V/2][3][2] -> flat complex (3 V/2)."""
+    v = np.asarray(v)
+    return (v[..., 0] + 1j * v[..., 1]).reshape(-1)
+
+
+def rvec(z, Vh):
+    out = np.empty((Vh, 3, 2))
+    z = z.reshape(Vh, 3)
+    out[..., 0] = z.real
+    out[..., 1] = z.imag
+    return out

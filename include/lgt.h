@@ -1,0 +1,201 @@
+/*
+ * lgt.h -- C ABI of the MI355X (gfx950) staggered Dslash / even-odd CG library.
+ *
+ * The operation. On a 4-D lattice every site has eight neighbours, two per
+ * dimension, joined by SU(3) link matrices (Sec. 1); the work is SU(3)
+ * matrix-vector products over those links (Table 1, Sec. 4; the adjoint
+ * product element by element is Eqs (1.1)-(2.3)). The library applies the
+ * naive staggered operator
+ *
+ *   (D chi)(x) = sum_mu eta_mu(x) [ s+_mu(x) U_mu(x) chi(x+mu)
+ *                                  - s-_mu(x) U_mu(x-mu)^dag chi(x-mu) ]
+ *
+ * (eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z);
+ * s+ = bc_mu on the upper face, s- = bc_mu on the lower face, else 1), i.e.
+ * four forward products, four adjoint products and the vector sums: 570 flop
+ * per site. M = 2m + D; the solver works on the even-site normal operator
+ * A = (M^dag M)_ee = 4 m^2 - D_eo D_oe.
+ *
+ * Geometry. dims L = (Lx, Ly, Lz, Lt), all even and >= 2, V = prod L <= 2^31.
+ * lex = x + Lx*(y + Ly*(z + Lz*t)); parity = (x+y+z+t) & 1; cb = lex >> 1
+ * (a bijection onto [0, V/2) for each parity); eo = parity*V/2 + cb.
+ *
+ * Canonical (user-facing) layouts, float64, little endian:
+ *   links    U[4][V][3][3][2]   direction mu, eo site, row, column, (re, im);
+ *                               no eta or boundary sign folded in
+ *   vectors  v[V/2][3][2]       one parity, cb order
+ *   force    G[4][V][3][3][2]   same as links
+ * Native (library) layouts are opaque; their sizes come from lgt_links_bytes
+ * and lgt_vec_bytes, and lgt_pack_* / lgt_unpack_vec convert.
+ *
+ * Memory and ownership. Every array argument of a compute call is a device
+ * pointer owned by the caller; the library never frees caller memory. Device
+ * pointers must be 16-byte aligned (256 recommended). A context owns only its
+ * workspace. Calls are ordered on the context's stream; lgt_dslash, lgt_pack_*,
+ * lgt_unpack_vec, lgt_index_maps and lgt_force are asynchronous;
+ * lgt_cg_solve and lgt_cdot return after the work is complete.
+ *
+ * Errors. Every entry point returns an lgt_status; arguments are validated on
+ * the host before anything is launched, and a failed call launches nothing.
+ * lgt_last_error() gives a thread-local message for the last failure.
+ * One context per host thread.
+ */
+#ifndef LGT_H
+#define LGT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lgt_status;
+enum {
+    LGT_OK = 0,
+    LGT_ERR_ARG = -1,           /* null pointer, bad enum, bad parameter value */
+    LGT_ERR_GEOMETRY = -2,      /* odd or < 2 dimension, bad bc, volume too large */
+    LGT_ERR_ALIGN = -3,         /* device pointer not 16-byte aligned */
+    LGT_ERR_DEVICE = -4,        /* no usable GPU, or a HIP runtime error */
+    LGT_ERR_NOT_CONVERGED = -5, /* solver hit max_iter; x holds the best iterate */
+    LGT_ERR_NONFINITE = -6,     /* NaN/Inf residual, or p.Ap <= 0 (breakdown) */
+    LGT_ERR_OOM = -7,           /* workspace allocation failed */
+    LGT_ERR_UNSUPPORTED = -8    /* precision/compression pair or device not supported */
+};
+
+/* arithmetic / storage precision of a link field or vector */
+enum { LGT_F64 = 0, LGT_F32 = 1, LGT_BF16 = 2 };
+/* link compression: 18 reals, or 12 reals (rows 0 and 1; row 2 = conj(row0 x row1)) */
+enum { LGT_R18 = 18, LGT_R12 = 12 };
+enum { LGT_EVEN = 0, LGT_ODD = 1 };
+
+typedef struct {
+    int32_t L[4];  /* x, y, z, t extents: even, >= 2 */
+    int32_t bc[4]; /* +1 periodic, -1 antiperiodic, per direction */
+} lgt_geom;
+
+/* A packed link field in device memory, as written by lgt_pack_links.
+ * Supported (prec, recon): (F64,18) (F64,12) (F32,18) (F32,12) (BF16,12).
+ * Vectors paired with F64 links are F64; with F32 or BF16 links they are F32. */
+typedef struct {
+    const void *ptr;
+    int32_t prec;
+    int32_t recon;
+} lgt_links;
+
+typedef struct lgt_ctx lgt_ctx;
+
+/* ---- status and host-only helpers (no device needed) ---------------------- */
+
+const char *lgt_status_string(lgt_status s);
+/* message for the last failed call on this thread ("" if none) */
+const char *lgt_last_error(void);
+/* LGT_OK or LGT_ERR_GEOMETRY */
+lgt_status lgt_geom_check(const lgt_geom *g);
+/* bytes of a packed link field / of one parity vector in native layout */
+lgt_status lgt_links_bytes(const lgt_geom *g, int32_t prec, int32_t recon, size_t *bytes);
+lgt_status lgt_vec_bytes(const lgt_geom *g, int32_t prec, size_t *bytes);
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). Checks the geometry first
+ * (LGT_ERR_GEOMETRY), then that the device exists (LGT_ERR_DEVICE) and is a
+ * gfx950 part (LGT_ERR_UNSUPPORTED). */
+lgt_status lgt_create(const lgt_geom *g, int32_t device, void *hip_stream, lgt_ctx **out);
+lgt_status lgt_destroy(lgt_ctx *ctx);
+/* Record HIP events around every Dslash launch inside lgt_cg_solve and report
+ * the summed kernel time in lgt_cg_result (0 = off, the default). */
+lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t enable);
+
+/* ---- geometry export (Sec. 1: unique 4-tuple per site, 8 neighbours) ------- */
+
+/* lex_of_eo[V] (int32): lexicographic index of eo site e.
+ * nbr[2][8][V/2] (int32): for output parity p, hop h (0..3 = +mu, 4..7 = -mu)
+ * and cb, the cb index of the neighbour (it has parity 1-p). Device buffers. */
+lgt_status lgt_index_maps(lgt_ctx *ctx, int32_t *lex_of_eo, int32_t *nbr);
+
+/* ---- packing ---------------------------------------------------------------- */
+
+/* Canonical float64 links (device) -> native packed field of (prec, recon).
+ * Rounding to F32 / BF16 is round-to-nearest-even from the float64 value.
+ * U_packed must hold lgt_links_bytes bytes. */
+lgt_status lgt_pack_links(lgt_ctx *ctx, const double *U_canon, int32_t prec, int32_t recon,
+                          void *U_packed);
+/* Canonical float64 parity vector [V/2][3][2] <-> native vector of `prec`
+ * (LGT_F64 or LGT_F32; BF16 fields use F32 vectors). */
+lgt_status lgt_pack_vec(lgt_ctx *ctx, int32_t prec, const double *src, void *dst);
+lgt_status lgt_unpack_vec(lgt_ctx *ctx, int32_t prec, const void *src, double *dst);
+
+/* ---- Dslash (Sec. 4; Table 1 routines composed over the 8 hops) ------------- */
+
+/* out = D_{out_parity, 1-out_parity} in: in is a native vector on parity
+ * 1 - out_parity, out a native vector on out_parity, both in the vector
+ * precision that goes with U->prec. No mass term. in and out must not alias. */
+lgt_status lgt_dslash(lgt_ctx *ctx, const lgt_links *U, int32_t out_parity,
+                      const void *in, void *out);
+
+/* ---- even-odd CG on A = 4 m^2 - D_eo D_oe ------------------------------------ */
+
+enum {
+    LGT_CG_FP64 = 0,     /* FP64 links, vectors and arithmetic throughout */
+    LGT_CG_RELIABLE = 1, /* low-precision inner CG, FP64 reliable update every
+                            ru_interval iterations and at inner convergence */
+    LGT_CG_REFINE = 2    /* iterative refinement: FP64 outer residual, inner
+                            low-precision CG restarted from 0 to inner_tol */
+};
+
+typedef struct {
+    double mass;          /* > 0 */
+    double tol;           /* target true relative residual |b - A x| / |b|, > 0 */
+    int32_t max_iter;     /* > 0, counts inner iterations */
+    int32_t scheme;       /* LGT_CG_* */
+    int32_t ru_interval;  /* RELIABLE: iterations between FP64 updates (e.g. 50) */
+    int32_t x0_is_guess;  /* 1: x holds an initial guess on entry; 0: start from 0 */
+    double inner_tol;     /* REFINE: inner relative reduction (e.g. 0.1);
+                             RELIABLE/FP64: inner stop as a fraction of tol (<= 1; 0 -> 1) */
+    int32_t check_interval; /* iterations between host polls (0 -> 50) */
+    int32_t reserved;
+} lgt_cg_params;
+
+typedef struct {
+    int32_t status;          /* LGT_OK, LGT_ERR_NOT_CONVERGED or LGT_ERR_NONFINITE */
+    int32_t iters;           /* inner CG iterations */
+    int32_t updates;         /* FP64 reliable updates / refinement steps */
+    int32_t dslash_calls;    /* half-Dslash applications, all precisions */
+    double true_rel_resid;   /* |b - A x| / |b| recomputed in FP64 at the end */
+    double seconds;          /* wall time of the solve on the stream (HIP events) */
+    double dslash_ms_hi;     /* with timing on: summed FP64 Dslash kernel time */
+    double dslash_ms_lo;     /*                 summed low-precision Dslash time */
+    int32_t dslash_timed_hi; /*                 number of launches summed */
+    int32_t dslash_timed_lo;
+} lgt_cg_result;
+
+/* Solve A x = b on even sites. U_hi: F64 links (recon 18 or 12). U_lo: the
+ * low-precision links for RELIABLE / REFINE (F32 or BF16), ignored (may be
+ * NULL) for FP64. b, x: canonical float64 even-parity vectors (device).
+ * NOT_CONVERGED and NONFINITE still write the best x and fill *res. */
+lgt_status lgt_cg_solve(lgt_ctx *ctx, const lgt_links *U_hi, const lgt_links *U_lo,
+                        const lgt_cg_params *p, const double *b, double *x,
+                        lgt_cg_result *res);
+
+/* ---- reductions ------------------------------------------------------------ */
+
+/* out[0] + i out[1] = sum conj(a) b over n_complex complex numbers (device
+ * float64 arrays), accumulated in FP64 in a fixed order; out is host memory. */
+lgt_status lgt_cdot(lgt_ctx *ctx, int64_t n_complex, const double *a, const double *b,
+                    double out[2]);
+
+/* ---- fermion force (Table 1 su3_projector) ------------------------------------ */
+
+/* Given X = A^-1 phi (canonical even vector, device) and F64 links, write
+ * G = scale * F (canonical [4][V][3][3][2], device) where dS = sum Re tr(F^dag dU)
+ * for S = phi^dag A^-1 phi, i.e. F_ij = dS/dRe U_ij + i dS/dIm U_ij:
+ *   x even: G_mu(x) = +2 eta_mu(x) s+_mu(x) X(x) Y(x+mu)^dag
+ *   x odd : G_mu(x) = -2 eta_mu(x) s+_mu(x) Y(x) X(x+mu)^dag,  Y = D_oe X. */
+lgt_status lgt_force(lgt_ctx *ctx, const lgt_links *U, const double *X, double scale, double *G);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LGT_H */

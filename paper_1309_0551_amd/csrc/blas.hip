@@ -1,0 +1,212 @@
+// blas.hip -- the CG vector updates (Table 1: scalar_mult_add_su3_vector,
+// add_su3_vector) with fused FP64 reductions, and the solver's small kernels.
+// All are one thread per site (three complex numbers) and HBM-bound.
+#include "fields.hpp"
+#include "kernels.hpp"
+#include "reduce.hpp"
+
+namespace lgt {
+
+// p = r + beta p
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_xpay(VecArgs a)
+{
+    if (!gate_open(a.gate, a.st)) return;
+    const int cb = blockIdx.x * kBS + threadIdx.x;
+    if (cb >= a.Vh) return;
+    const T beta = (T)a.st->beta;
+    cx<T> r[3], p[3];
+    VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
+    VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        p[i].re = fma(beta, p[i].re, r[i].re);
+        p[i].im = fma(beta, p[i].im, r[i].im);
+    }
+    VecFmt<T>::template store<false>(a.p, (size_t)a.Vh, cb, p);
+}
+
+// x += alpha p ; r -= alpha Ap ; partial |r|^2 (FP64) ; then rho, beta, convergence
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_update(VecArgs a)
+{
+    if (!gate_open(a.gate, a.st)) return;
+    const int blk = blockIdx.x;
+    const int cb = blk * kBS + threadIdx.x;
+    double part = 0.0;
+    if (cb < a.Vh) {
+        const T alpha = (T)a.st->alpha;
+        cx<T> x[3], r[3], p[3], q[3];
+        VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
+        VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
+        VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
+        VecFmt<T>::template load<false>(a.Ap, (size_t)a.Vh, cb, q);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            x[i].re = fma(alpha, p[i].re, x[i].re);
+            x[i].im = fma(alpha, p[i].im, x[i].im);
+            r[i].re = fma(-alpha, q[i].re, r[i].re);
+            r[i].im = fma(-alpha, q[i].im, r[i].im);
+            part += (double)r[i].re * (double)r[i].re + (double)r[i].im * (double)r[i].im;
+        }
+        VecFmt<T>::template store<false>(a.x, (size_t)a.Vh, cb, x);
+        VecFmt<T>::template store<false>(a.r, (size_t)a.Vh, cb, r);
+    }
+    reduce_and_finalize(part, a.partials, a.st, blk, a.l.nblk, FIN_UPDATE);
+}
+
+hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
+{
+    if (f64) hipLaunchKernelGGL(k_xpay<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    else hipLaunchKernelGGL(k_xpay<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s)
+{
+    if (f64) hipLaunchKernelGGL(k_update<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    else hipLaunchKernelGGL(k_update<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    return hipGetLastError();
+}
+
+// x64 += x_lo ; x_lo = 0   (solution accumulation in FP64)
+__global__ __launch_bounds__(kBS) void k_ru_accum(double *__restrict__ x64, void *__restrict__ xlo, int Vh,
+                                                  CgState *st, int gate)
+{
+    if (!gate_open(gate, st)) return;
+    const int cb = blockIdx.x * kBS + threadIdx.x;
+    if (cb >= Vh) return;
+    cx<double> x[3];
+    cx<float> e[3];
+    VecFmt<double>::load<false>(x64, (size_t)Vh, cb, x);
+    VecFmt<float>::load<false>(xlo, (size_t)Vh, cb, e);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        x[i].re += (double)e[i].re;
+        x[i].im += (double)e[i].im;
+        e[i].re = 0.0f;
+        e[i].im = 0.0f;
+    }
+    VecFmt<double>::store<false>(x64, (size_t)Vh, cb, x);
+    VecFmt<float>::store<false>(xlo, (size_t)Vh, cb, e);
+}
+
+hipError_t launch_ru_accum(double *x64, void *xlo, int Vh, CgState *st, int gate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ru_accum, dim3((Vh + kBS - 1) / kBS), dim3(kBS), 0, s, x64, xlo, Vh, st, gate);
+    return hipGetLastError();
+}
+
+// zero fill with a kernel (safe inside captured graphs, unlike memset nodes)
+__global__ __launch_bounds__(kBS) void k_zero(uv4 *__restrict__ p, size_t n16)
+{
+    const size_t i = (size_t)blockIdx.x * kBS + threadIdx.x;
+    if (i < n16) p[i] = uv4{0u, 0u, 0u, 0u};
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16; // every buffer here is a multiple of 16 bytes
+    if (n16 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n16 + kBS - 1) / kBS)), dim3(kBS), 0, s, (uv4 *)p, n16);
+    return hipGetLastError();
+}
+
+__global__ void k_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol, double inner)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->rho = st->rho_prev = st->alpha = st->beta = st->pAp = 0.0;
+    st->bnorm2 = 0.0;
+    st->stop_outer = tol * tol; // multiplied by |b|^2 in FIN_INIT
+    st->stop_inner = 0.0;
+    st->inner2 = scheme == SCH_REFINE ? inner * inner : (inner * tol) * (inner * tol);
+    st->last_true = 0.0;
+    st->iter = 0;
+    st->updates = 0;
+    st->state = ST_INIT;
+    st->max_iter = max_iter;
+    st->scheme = scheme;
+    st->ru_fixed = ru_fixed;
+    st->pad0 = st->pad1 = 0;
+    for (int i = 0; i < 4; i++) st->ctr[i] = 0;
+}
+
+hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol, double inner,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, scheme, ru_fixed, max_iter, tol, inner);
+    return hipGetLastError();
+}
+
+// |b|^2 -> stop thresholds
+__global__ __launch_bounds__(kBS) void k_norm_init(const double *__restrict__ b, int Vh, double *partials, CgState *st,
+                                                   int nblk)
+{
+    const int cb = blockIdx.x * kBS + threadIdx.x;
+    double part = 0.0;
+    if (cb < Vh) {
+        cx<double> v[3];
+        VecFmt<double>::load<false>(b, (size_t)Vh, cb, v);
+#pragma unroll
+        for (int i = 0; i < 3; i++) part += v[i].re * v[i].re + v[i].im * v[i].im;
+    }
+    reduce_and_finalize(part, partials, st, blockIdx.x, nblk, FIN_INIT);
+}
+
+hipError_t launch_norm_init(const double *b64, int Vh, double *partials, CgState *st, hipStream_t s)
+{
+    const int nblk = (Vh + kBS - 1) / kBS;
+    hipLaunchKernelGGL(k_norm_init, dim3(nblk), dim3(kBS), 0, s, b64, Vh, partials, st, nblk);
+    return hipGetLastError();
+}
+
+// generic complex dot product sum conj(a) b, FP64, deterministic order
+__global__ __launch_bounds__(kBS) void k_cdot(int64_t n, const dv2 *__restrict__ a, const dv2 *__restrict__ b,
+                                              double *partials, unsigned int *ctr, double *result, int nblk)
+{
+    __shared__ double lds[kBS / 64];
+    __shared__ int amlast;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)nblk * kBS) {
+        const dv2 x = a[i], y = b[i];
+        re += x.x * y.x + x.y * y.y;
+        im += x.x * y.y - x.y * y.x;
+    }
+    const double sr = block_sum(re, lds);
+    const double si = block_sum(im, lds);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = sr;
+        partials[2 * blockIdx.x + 1] = si;
+        __threadfence();
+        const unsigned int t = atomicAdd(ctr, 1u);
+        amlast = (t == (unsigned int)(nblk - 1));
+    }
+    __syncthreads();
+    if (!amlast) return;
+    __threadfence();
+    double ar = 0.0, ai = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kBS) {
+        ar += load_partial(&partials[2 * i]);
+        ai += load_partial(&partials[2 * i + 1]);
+    }
+    const double tr = block_sum(ar, lds);
+    const double ti = block_sum(ai, lds);
+    if (threadIdx.x == 0) {
+        result[0] = tr;
+        result[1] = ti;
+        *ctr = 0;
+    }
+}
+
+hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials, unsigned int *ctr,
+                       double *result, hipStream_t s)
+{
+    int nblk = (int)((n + kBS - 1) / kBS);
+    if (nblk > 1024) nblk = 1024;
+    if (nblk < 1) nblk = 1;
+    hipLaunchKernelGGL(k_cdot, dim3(nblk), dim3(kBS), 0, s, n, (const dv2 *)a, (const dv2 *)b, partials, ctr,
+                       result, nblk);
+    return hipGetLastError();
+}
+
+} // namespace lgt

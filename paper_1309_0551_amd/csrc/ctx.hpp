@@ -1,0 +1,70 @@
+// ctx.hpp -- the library context: geometry, device, stream and workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <map>
+#include <string>
+
+#include "../../include/lgt.h"
+#include "kernels.hpp"
+
+struct lgt_ctx {
+    lgt_geom geom;
+    lgt::Geom g;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int timing = 0;
+    struct Buf {
+        void *ptr = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> ws; // named device workspace, grown on demand
+    void *pinned = nullptr;        // host pinned staging for state read-back
+    size_t pinned_bytes = 0;
+};
+
+namespace lgt {
+
+lgt_status fail(lgt_status s, const char *fmt, ...);
+void clear_error();
+
+// device workspace buffer `name` of at least `bytes` (contents undefined)
+void *workspace(lgt_ctx *c, const char *name, size_t bytes);
+void *pinned(lgt_ctx *c, size_t bytes);
+
+// (prec, recon) -> storage format; returns false if unsupported
+bool fmt_of(int32_t prec, int32_t recon, Fmt *f);
+inline bool fmt_is_f64(Fmt f) { return f == F64R18 || f == F64R12; }
+size_t link_bytes_per_site_dir(Fmt f);
+
+lgt_status check_links(const lgt_links *U, bool need_f64, Fmt *f);
+lgt_status check_ptr(const void *p, const char *what);
+
+// make ctx's device current for the scope, restoring the previous one
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
+                    const double *b, double *x, lgt_cg_result *res);
+
+} // namespace lgt
+
+#define LGT_HIP(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return lgt::fail(LGT_ERR_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                                \
+    } while (0)

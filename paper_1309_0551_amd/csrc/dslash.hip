@@ -1,0 +1,276 @@
+// dslash.hip -- the staggered Dslash and the packing / geometry kernels.
+//
+// One thread per output site x of parity `par` (V/2 threads):
+//   out(x) = sum_mu eta_mu(x) [ s+ U_mu(x) in(x+mu) - s- U_mu(x-mu)^dag in(x-mu) ]
+// i.e. the forward half (Table 1: mult_su3_mat_vec_sum_4dir), four adjoint
+// products (mult_adj_su3_mat_vec, Eqs (1.1)-(2.3)) and their subtraction
+// (sub_four_su3_vecs): 570 flop/site. The forward link lives at x in the
+// plane set of parity `par`; the backward link U_mu(x-mu) at the neighbour, in
+// the plane set of the other parity. Every link is read exactly once per call
+// and the kernel is bound by HBM bandwidth: link loads are marked
+// non-temporal so they do not evict the reused input vector from L2.
+#include "fields.hpp"
+#include "kernels.hpp"
+#include "reduce.hpp"
+
+namespace lgt {
+
+// HPI = hops whose loads are issued together. The whole unrolled body is one
+// basic block in which the backend hoists all 96 loads of the FP64 kernel
+// (256 VGPRs, one wave per SIMD); a runtime loop over directions (HPI = 2) or
+// over single hops (HPI = 1) bounds the loads in flight per thread and lets
+// more waves share each SIMD.
+template <class LF, int EPI, int FIN, int HPI>
+__global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
+{
+    using T = typename LF::real;
+    using VF = VecFmt<T>;
+    if (!gate_open(a.gate, a.st)) return;
+    const int blk = xcd_block(blockIdx.x, a.l.nblk_pad);
+    const int cb = blk * kBS + threadIdx.x;
+    const size_t Vh = (size_t)a.g.Vh;
+    double part = 0.0;
+    if (cb < a.g.Vh) {
+        int c[4];
+        decode(a.g, a.par, cb, c);
+        cx<T> acc[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) acc[i].re = acc[i].im = T(0);
+        if constexpr (HPI == 8) {
+#pragma unroll
+            for (int mu = 0; mu < 4; mu++) {
+                cx<T> u[9], v[3];
+                // forward hop: U_mu(x) in(x+mu)
+                LF::template load<true>(a.U, Vh, a.par * 4 + mu, cb, u);
+                VF::template load<false>(a.in, Vh, nbr_fwd(a.g, c, cb, mu), v);
+                negate_if(fwd_neg(a.g, c, mu), v);
+                mv_add(u, v, acc);
+                // backward hop: U_mu(x-mu)^dag in(x-mu)
+                const int b = nbr_bwd(a.g, c, cb, mu);
+                LF::template load<true>(a.U, Vh, (1 - a.par) * 4 + mu, b, u);
+                VF::template load<false>(a.in, Vh, b, v);
+                negate_if(bwd_neg(a.g, c, mu), v);
+                amv_sub(u, v, acc);
+            }
+        } else if constexpr (HPI == 2) {
+#pragma unroll 1
+            for (int mu = 0; mu < 4; mu++) {
+                const Hop h = hop_rt(a.g, c, cb, mu);
+                cx<T> u[9], v[3], w[9], z[3];
+                LF::template load<true>(a.U, Vh, a.par * 4 + mu, cb, u);
+                VF::template load<false>(a.in, Vh, h.f, v);
+                LF::template load<true>(a.U, Vh, (1 - a.par) * 4 + mu, h.b, w);
+                VF::template load<false>(a.in, Vh, h.b, z);
+                negate_if(h.fneg, v);
+                mv_add(u, v, acc);
+                negate_if(h.bneg, z);
+                amv_sub(w, z, acc);
+            }
+        } else {
+#pragma unroll 1
+            for (int hop = 0; hop < 8; hop++) {
+                const int mu = hop >> 1;
+                const bool fwd = !(hop & 1);
+                const Hop h = hop_rt(a.g, c, cb, mu);
+                cx<T> u[9], v[3];
+                LF::template load<true>(a.U, Vh, fwd ? a.par * 4 + mu : (1 - a.par) * 4 + mu, fwd ? cb : h.b, u);
+                VF::template load<false>(a.in, Vh, fwd ? h.f : h.b, v);
+                negate_if(fwd ? h.fneg : h.bneg, v);
+                if (fwd) mv_add(u, v, acc);
+                else amv_sub(u, v, acc);
+            }
+        }
+        if constexpr (EPI == EPI_PLAIN) {
+            VF::template store<false>(a.out, Vh, cb, acc);
+        } else if constexpr (EPI == EPI_A) {
+            // out = m4 p - D in ; partial Re <p, out>
+            cx<T> p[3];
+            VF::template load<false>(a.aux0, Vh, cb, p);
+            const T m4 = (T)a.m4;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                acc[i].re = m4 * p[i].re - acc[i].re;
+                acc[i].im = m4 * p[i].im - acc[i].im;
+                part += (double)p[i].re * (double)acc[i].re + (double)p[i].im * (double)acc[i].im;
+            }
+            VF::template store<false>(a.out, Vh, cb, acc);
+        } else {
+            // r = b - (m4 x - D in), FP64 only; partial |r|^2
+            cx<double> x[3], bb[3];
+            VecFmt<double>::load<false>(a.aux0, Vh, cb, x);
+            VecFmt<double>::load<false>(a.aux1, Vh, cb, bb);
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                acc[i].re = bb[i].re - (a.m4 * x[i].re - acc[i].re);
+                acc[i].im = bb[i].im - (a.m4 * x[i].im - acc[i].im);
+                part += acc[i].re * acc[i].re + acc[i].im * acc[i].im;
+            }
+            if constexpr (EPI == EPI_RES) {
+                VF::template store<false>(a.out, Vh, cb, acc);
+            } else {
+                cx<float> lo[3];
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    lo[i].re = (float)acc[i].re;
+                    lo[i].im = (float)acc[i].im;
+                }
+                VecFmt<float>::store<false>(a.out_lo, Vh, cb, lo);
+            }
+        }
+    }
+    if constexpr (FIN != FIN_NONE) reduce_and_finalize(part, a.partials, a.st, blk, a.l.nblk_pad, FIN);
+}
+
+template <class LF>
+static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
+{
+    const dim3 grid(a.l.nblk_pad), block(kBS);
+    switch (epi) {
+    case EPI_PLAIN:
+        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, FIN_NONE, 8>), grid, block, 0, s, a);
+        break;
+    case EPI_A:
+        hipLaunchKernelGGL((k_dslash<LF, EPI_A, FIN_ALPHA, 8>), grid, block, 0, s, a);
+        break;
+    case EPI_RES:
+    case EPI_RES_LO:
+        if constexpr (std::is_same<typename LF::real, double>::value) {
+            if (epi == EPI_RES) {
+                if (a.fin == FIN_FINAL)
+                    hipLaunchKernelGGL((k_dslash<LF, EPI_RES, FIN_FINAL, 8>), grid, block, 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_dslash<LF, EPI_RES, FIN_RU, 8>), grid, block, 0, s, a);
+            } else {
+                hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, FIN_RU, 8>), grid, block, 0, s, a);
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s)
+{
+    switch (f) {
+    case F64R18: return launch_fmt<LinkF64R18>(epi, a, s);
+    case F64R12: return launch_fmt<LinkF64R12>(epi, a, s);
+    case F32R18: return launch_fmt<LinkF32R18>(epi, a, s);
+    case F32R12: return launch_fmt<LinkF32R12>(epi, a, s);
+    case BF16R12: return launch_fmt<LinkBF16R12>(epi, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------- packing ---
+
+// canonical [4][V][3][3][2] float64 (eo order) -> planes of format LF
+template <class LF>
+__global__ __launch_bounds__(kBS) void k_pack_links(const double *__restrict__ Uc, void *__restrict__ Up, Geom g)
+{
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const int64_t idx = (int64_t)blockIdx.x * kBS + threadIdx.x; // mu*V + eo
+    if (idx >= 4 * V) return;
+    const int mu = (int)(idx / V);
+    const int64_t eo = idx - mu * V;
+    const int par = eo >= g.Vh;
+    const int cb = (int)(eo - par * (int64_t)g.Vh);
+    double s[18];
+    const dv2 *src = (const dv2 *)(Uc + idx * 18);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const dv2 v = src[k];
+        s[2 * k] = v.x;
+        s[2 * k + 1] = v.y;
+    }
+    LF::store(Up, (size_t)g.Vh, par * 4 + mu, cb, s);
+}
+
+hipError_t launch_pack_links(Fmt f, const double *Uc, void *Up, const Geom &g, hipStream_t s)
+{
+    const int64_t n = 4 * 2 * (int64_t)g.Vh;
+    const dim3 grid((unsigned)((n + kBS - 1) / kBS)), block(kBS);
+    switch (f) {
+    case F64R18: hipLaunchKernelGGL(k_pack_links<LinkF64R18>, grid, block, 0, s, Uc, Up, g); break;
+    case F64R12: hipLaunchKernelGGL(k_pack_links<LinkF64R12>, grid, block, 0, s, Uc, Up, g); break;
+    case F32R18: hipLaunchKernelGGL(k_pack_links<LinkF32R18>, grid, block, 0, s, Uc, Up, g); break;
+    case F32R12: hipLaunchKernelGGL(k_pack_links<LinkF32R12>, grid, block, 0, s, Uc, Up, g); break;
+    case BF16R12: hipLaunchKernelGGL(k_pack_links<LinkBF16R12>, grid, block, 0, s, Uc, Up, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_pack_vec(const double *__restrict__ src, void *__restrict__ dst, int Vh)
+{
+    const int cb = blockIdx.x * kBS + threadIdx.x;
+    if (cb >= Vh) return;
+    const dv2 *p = (const dv2 *)src + (size_t)cb * 3;
+    cx<T> v[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const dv2 w = p[i];
+        v[i].re = (T)w.x;
+        v[i].im = (T)w.y;
+    }
+    VecFmt<T>::template store<false>(dst, (size_t)Vh, cb, v);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_unpack_vec(const void *__restrict__ src, double *__restrict__ dst, int Vh)
+{
+    const int cb = blockIdx.x * kBS + threadIdx.x;
+    if (cb >= Vh) return;
+    cx<T> v[3];
+    VecFmt<T>::template load<false>(src, (size_t)Vh, cb, v);
+    dv2 *p = (dv2 *)dst + (size_t)cb * 3;
+#pragma unroll
+    for (int i = 0; i < 3; i++) p[i] = dv2{(double)v[i].re, (double)v[i].im};
+}
+
+hipError_t launch_pack_vec(bool f64, const double *src, void *dst, const Geom &g, hipStream_t s)
+{
+    const dim3 grid((g.Vh + kBS - 1) / kBS), block(kBS);
+    if (f64) hipLaunchKernelGGL(k_pack_vec<double>, grid, block, 0, s, src, dst, g.Vh);
+    else hipLaunchKernelGGL(k_pack_vec<float>, grid, block, 0, s, src, dst, g.Vh);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_vec(bool f64, const void *src, double *dst, const Geom &g, hipStream_t s)
+{
+    const dim3 grid((g.Vh + kBS - 1) / kBS), block(kBS);
+    if (f64) hipLaunchKernelGGL(k_unpack_vec<double>, grid, block, 0, s, src, dst, g.Vh);
+    else hipLaunchKernelGGL(k_unpack_vec<float>, grid, block, 0, s, src, dst, g.Vh);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ geometry ---
+
+__global__ __launch_bounds__(kBS) void k_index_maps(int32_t *__restrict__ lex_of_eo, int32_t *__restrict__ nbr, Geom g)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; // par*Vh + cb
+    if (i >= 2 * (int64_t)g.Vh) return;
+    const int par = i >= g.Vh;
+    const int cb = (int)(i - par * (int64_t)g.Vh);
+    int c[4];
+    decode(g, par, cb, c);
+    lex_of_eo[i] = c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        nbr[((size_t)par * 8 + mu) * g.Vh + cb] = nbr_fwd(g, c, cb, mu);
+        nbr[((size_t)par * 8 + 4 + mu) * g.Vh + cb] = nbr_bwd(g, c, cb, mu);
+    }
+}
+
+hipError_t launch_index_maps(int32_t *lex_of_eo, int32_t *nbr, const Geom &g, hipStream_t s)
+{
+    const int64_t n = 2 * (int64_t)g.Vh;
+    hipLaunchKernelGGL(k_index_maps, dim3((unsigned)((n + kBS - 1) / kBS)), dim3(kBS), 0, s, lex_of_eo, nbr, g);
+    return hipGetLastError();
+}
+
+} // namespace lgt

@@ -1,0 +1,58 @@
+// force.hip -- fermion force of S = phi^dag A^-1 phi (the outer product
+// su3_projector of Table 1, C_ij = a_i conj(b_j)).
+//
+// With X = A^-1 phi on even sites and Y = D_oe X on odd sites, dS =
+// 2 Re(X^dag dD_eo Y), which per link gives
+//   x even: G_mu(x) = +2 eta_mu(x) s+_mu(x) X(x) Y(x+mu)^dag
+//   x odd : G_mu(x) = -2 eta_mu(x) s+_mu(x) Y(x) X(x+mu)^dag
+// and dS/dRe U_ij = Re G_ij, dS/dIm U_ij = Im G_ij. One thread per link; the
+// kernel is bound by the 144-byte gradient write per link.
+#include "fields.hpp"
+#include "kernels.hpp"
+
+namespace lgt {
+
+__global__ __launch_bounds__(kBS) void k_force(const double *__restrict__ X, const double *__restrict__ Y,
+                                               double scale, double *__restrict__ G, Geom g)
+{
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const int64_t idx = (int64_t)blockIdx.x * kBS + threadIdx.x; // mu*V + eo
+    if (idx >= 4 * V) return;
+    const int mu = (int)(idx / V);
+    const int64_t eo = idx - mu * V;
+    const int par = eo >= g.Vh;
+    const int cb = (int)(eo - par * (int64_t)g.Vh);
+    int c[4];
+    decode(g, par, cb, c);
+    const int f = nbr_fwd(g, c, cb, mu);
+    // a: the vector at x, b: the vector at x+mu (other parity)
+    cx<double> a[3], b[3];
+    if (par == 0) {
+        VecFmt<double>::load<false>(X, (size_t)g.Vh, cb, a);
+        VecFmt<double>::load<false>(Y, (size_t)g.Vh, f, b);
+    } else {
+        VecFmt<double>::load<false>(Y, (size_t)g.Vh, cb, a);
+        VecFmt<double>::load<false>(X, (size_t)g.Vh, f, b);
+    }
+    const bool neg = eta_neg(c, mu) ^ (c[mu] == g.L[mu] - 1 && g.bc[mu] < 0) ^ (par == 1);
+    const double s = neg ? -2.0 * scale : 2.0 * scale;
+    dv2 *out = (dv2 *)(G + idx * 18);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double re = a[i].re * b[j].re + a[i].im * b[j].im;
+            const double im = a[i].im * b[j].re - a[i].re * b[j].im;
+            out[3 * i + j] = dv2{s * re, s * im};
+        }
+}
+
+hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,
+                        hipStream_t s)
+{
+    const int64_t n = 8 * (int64_t)g.Vh;
+    hipLaunchKernelGGL(k_force, dim3((unsigned)((n + kBS - 1) / kBS)), dim3(kBS), 0, s, Xnat, Ynat, scale, G, g);
+    return hipGetLastError();
+}
+
+} // namespace lgt

@@ -1,0 +1,111 @@
+// geom.hpp -- checkerboarded 4-D lattice geometry for the device kernels.
+//
+// A site has a unique 4-tuple and eight neighbours, two per dimension (Sec. 1).
+// Ordering: lex = x + Lx*(y + Ly*(z + Lz*t)), parity = (x+y+z+t)&1,
+// cb = lex>>1, eo = parity*V/2 + cb. Neighbour cb indices, staggered phases and
+// boundary signs are computed on the fly from cb: no index table is read from
+// memory, so the Dslash streams only links and vectors.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lgt {
+
+struct Geom {
+    int L[4];      // extents x, y, z, t (even)
+    int bc[4];     // +1 / -1 per direction
+    int hx;        // Lx / 2
+    int Vh;        // V / 2
+    int str[4];    // cb stride of a unit step: str[1] = hx, str[2] = hx*Ly, str[3] = hx*Ly*Lz
+};
+
+// Coordinates of the site (par, cb).
+__host__ __device__ __forceinline__ void decode(const Geom &g, int par, int cb, int c[4])
+{
+    const int q = cb / g.hx;
+    const int xh = cb - q * g.hx;
+    const int q2 = q / g.L[1];
+    c[1] = q - q2 * g.L[1];
+    const int q3 = q2 / g.L[2];
+    c[2] = q2 - q3 * g.L[2];
+    c[3] = q3;
+    c[0] = 2 * xh + ((par + c[1] + c[2] + c[3]) & 1);
+}
+
+// cb index of x + mu (periodic wrap).
+__host__ __device__ __forceinline__ int nbr_fwd(const Geom &g, const int c[4], int cb, int mu)
+{
+    if (mu == 0) {
+        if (!(c[0] & 1)) return cb;                     // x even: x+1 shares x>>1
+        return (c[0] == g.L[0] - 1) ? cb - (g.hx - 1) : cb + 1;
+    }
+    return (c[mu] == g.L[mu] - 1) ? cb - (g.L[mu] - 1) * g.str[mu] : cb + g.str[mu];
+}
+
+// cb index of x - mu (periodic wrap).
+__host__ __device__ __forceinline__ int nbr_bwd(const Geom &g, const int c[4], int cb, int mu)
+{
+    if (mu == 0) {
+        if (c[0] & 1) return cb;                        // x odd: x-1 shares x>>1
+        return (c[0] == 0) ? cb + (g.hx - 1) : cb - 1;
+    }
+    return (c[mu] == 0) ? cb + (g.L[mu] - 1) * g.str[mu] : cb - g.str[mu];
+}
+
+// eta_mu(x): eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z)
+__host__ __device__ __forceinline__ bool eta_neg(const int c[4], int mu)
+{
+    int s = 0;
+    if (mu > 0) s += c[0];
+    if (mu > 1) s += c[1];
+    if (mu > 2) s += c[2];
+    return s & 1;
+}
+
+// sign of the forward hop eta_mu s+_mu and of the backward hop eta_mu s-_mu
+__host__ __device__ __forceinline__ bool fwd_neg(const Geom &g, const int c[4], int mu)
+{
+    return eta_neg(c, mu) ^ (c[mu] == g.L[mu] - 1 && g.bc[mu] < 0);
+}
+__host__ __device__ __forceinline__ bool bwd_neg(const Geom &g, const int c[4], int mu)
+{
+    return eta_neg(c, mu) ^ (c[mu] == 0 && g.bc[mu] < 0);
+}
+
+// Neighbours and hop signs for a direction mu known only at run time (all
+// selects, no indexed access to c[] or g.L[], so a runtime loop over mu keeps
+// everything in registers).
+struct Hop {
+    int f, b;        // cb of x + mu and x - mu
+    bool fneg, bneg; // eta s+ < 0, eta s- < 0
+};
+__host__ __device__ __forceinline__ Hop hop_rt(const Geom &g, const int c[4], int cb, int mu)
+{
+    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+    const int Lm = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
+    const int bcm = mu == 0 ? g.bc[0] : mu == 1 ? g.bc[1] : mu == 2 ? g.bc[2] : g.bc[3];
+    const int sm = mu == 1 ? g.str[1] : mu == 2 ? g.str[2] : g.str[3];
+    const int ep = (mu > 0 ? c[0] : 0) + (mu > 1 ? c[1] : 0) + (mu > 2 ? c[2] : 0);
+    Hop h;
+    if (mu == 0) {
+        h.f = (cm & 1) ? ((cm == Lm - 1) ? cb - (g.hx - 1) : cb + 1) : cb;
+        h.b = (cm & 1) ? cb : ((cm == 0) ? cb + (g.hx - 1) : cb - 1);
+    } else {
+        h.f = (cm == Lm - 1) ? cb - (Lm - 1) * sm : cb + sm;
+        h.b = (cm == 0) ? cb + (Lm - 1) * sm : cb - sm;
+    }
+    h.fneg = (ep & 1) ^ (cm == Lm - 1 && bcm < 0);
+    h.bneg = (ep & 1) ^ (cm == 0 && bcm < 0);
+    return h;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs. Remap so that each
+// XCD walks a contiguous range of sites: neighbours in y, z and t then fall in
+// the same XCD's L2. nblk_pad is a multiple of 8; blocks beyond nblk idle.
+__host__ __device__ __forceinline__ int xcd_block(int bid, int nblk_pad)
+{
+    const int per = nblk_pad >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+} // namespace lgt

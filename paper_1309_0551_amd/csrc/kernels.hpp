@@ -1,0 +1,105 @@
+// kernels.hpp -- launch interfaces shared by the host code of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "geom.hpp"
+
+namespace lgt {
+
+constexpr int kBS = 256; // threads per workgroup of the site-parallel kernels
+
+// Link storage formats (see fields.hpp)
+enum Fmt { F64R18 = 0, F64R12 = 1, F32R18 = 2, F32R12 = 3, BF16R12 = 4, FMT_COUNT = 5 };
+
+// Solver state in device memory, read and written only by the kernels of one
+// solve; the host reads it back with an asynchronous copy.
+enum State { ST_RUN = 0, ST_INNER = 1, ST_DONE = 2, ST_FAIL = 3, ST_MAXIT = 4, ST_INIT = 5 };
+enum Scheme { SCH_FP64 = 0, SCH_RELIABLE = 1, SCH_REFINE = 2 };
+
+struct CgState {
+    double rho;        // |r|^2 of the iterated residual
+    double rho_prev;   // previous rho (beta after a reliable update)
+    double alpha, beta, pAp;
+    double bnorm2;     // |b|^2
+    double stop_outer; // tol^2 |b|^2 on the FP64 true residual
+    double stop_inner; // threshold on the iterated residual
+    double inner2;     // REFINE: inner_tol^2 (relative); else absolute threshold
+    double last_true;  // last FP64 true |r|^2
+    int iter, updates, state, max_iter;
+    int scheme, ru_fixed, pad0, pad1;
+    unsigned int ctr[4];
+};
+
+// Early-exit rule of a solver kernel, read from CgState at kernel start
+enum Gate { GATE_NONE = 0, GATE_ITER = 1, GATE_RU = 2 };
+// Finalize step done by the last workgroup of a reducing kernel
+enum Fin { FIN_NONE = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_RU = 3, FIN_INIT = 4, FIN_FINAL = 5 };
+
+struct Launch {
+    int nblk;     // workgroups doing work
+    int nblk_pad; // launched (multiple of 8 for the XCD remap)
+};
+
+inline Launch site_launch(int Vh)
+{
+    Launch l;
+    l.nblk = (Vh + kBS - 1) / kBS;
+    l.nblk_pad = (l.nblk + 7) / 8 * 8;
+    return l;
+}
+
+// ---- Dslash family ------------------------------------------------------
+enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3 };
+
+struct DslashArgs {
+    const void *U;   // packed links
+    const void *in;  // vector on parity 1-par
+    void *out;       // vector on parity par
+    Geom g;
+    int par;
+    int gate;
+    Launch l;
+    // EPI_A:   out = m4*aux0 - D in, partial <aux0, out>
+    // EPI_RES: r = aux1 - (m4*aux0 - D in) in FP64 into out (or out_lo), partial |r|^2
+    const void *aux0;
+    const void *aux1;
+    void *out_lo;
+    double m4;
+    double *partials;
+    CgState *st;
+    int fin;
+};
+
+hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s);
+hipError_t launch_pack_links(Fmt f, const double *Ucanon, void *Upacked, const Geom &g, hipStream_t s);
+hipError_t launch_pack_vec(bool f64, const double *src, void *dst, const Geom &g, hipStream_t s);
+hipError_t launch_unpack_vec(bool f64, const void *src, double *dst, const Geom &g, hipStream_t s);
+hipError_t launch_index_maps(int32_t *lex_of_eo, int32_t *nbr, const Geom &g, hipStream_t s);
+
+// ---- vector kernels (solver.hip) -----------------------------------------
+struct VecArgs {
+    void *x, *r, *p;
+    const void *Ap;
+    int Vh;
+    Launch l;
+    double *partials;
+    CgState *st;
+    int gate;
+};
+hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s);
+hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s);
+hipError_t launch_ru_accum(double *x64, void *xlo, int Vh, CgState *st, int gate, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol,
+                             double inner, hipStream_t s);
+hipError_t launch_norm_init(const double *b64, int Vh, double *partials, CgState *st, hipStream_t s);
+hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials,
+                       unsigned int *ctr, double *result, hipStream_t s);
+
+// ---- force (force.hip) -----------------------------------------------------
+hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,
+                        hipStream_t s);
+
+} // namespace lgt

@@ -1,0 +1,129 @@
+// reduce.hpp -- deterministic FP64 reductions and the solver's scalar steps.
+//
+// Each workgroup reduces its values (wavefront butterfly over 64 lanes, then
+// the 4 wave sums in LDS) into one partial per workgroup; the last workgroup
+// to finish (device-scope counter) sums the partials in index order. The
+// result does not depend on which workgroup finishes last, so repeated runs
+// give bit-identical scalars.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace lgt {
+
+// sum over the workgroup; the value is valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBS / 64; i++) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// relaxed device-scope load of a partial written by another workgroup
+__device__ __forceinline__ double load_partial(const double *p)
+{
+    return __longlong_as_double(
+        (long long)__atomic_load_n((const unsigned long long *)p, __ATOMIC_RELAXED));
+}
+
+__device__ __forceinline__ bool gate_open(int gate, const CgState *st)
+{
+    if (gate == GATE_NONE) return true;
+    const int s = st->state;
+    if (gate == GATE_ITER) return s == ST_RUN;
+    return s == ST_INIT || s == ST_INNER || (s == ST_RUN && st->ru_fixed);
+}
+
+// The scalar step that follows a reduction (thread 0 of the last workgroup).
+__device__ inline void finalize(int fin, CgState *st, double sum)
+{
+    switch (fin) {
+    case FIN_ALPHA: // alpha = rho / <p, A p>
+        st->pAp = sum;
+        if (!(sum > 0.0) || !isfinite(sum)) st->state = ST_FAIL;
+        else st->alpha = st->rho / sum;
+        break;
+    case FIN_UPDATE: { // rho' = |r|^2, beta = rho'/rho
+        st->iter += 1;
+        if (!isfinite(sum)) {
+            st->state = ST_FAIL;
+            break;
+        }
+        st->beta = sum / st->rho;
+        st->rho_prev = st->rho;
+        st->rho = sum;
+        if (sum <= st->stop_inner) st->state = ST_INNER;
+        else if (st->iter >= st->max_iter) st->state = ST_MAXIT;
+        break;
+    }
+    case FIN_RU: { // sum = |b - A x|^2 in FP64
+        const bool init = st->state == ST_INIT;
+        if (!init) st->updates += 1;
+        st->last_true = sum;
+        if (!isfinite(sum)) {
+            st->state = ST_FAIL;
+        } else if (sum <= st->stop_outer) {
+            st->state = ST_DONE;
+        } else {
+            if (init || st->scheme == SCH_REFINE) {
+                st->beta = 0.0; // restart: p = r
+                if (st->scheme == SCH_REFINE) st->stop_inner = st->inner2 * sum;
+            } else {
+                st->beta = sum / st->rho_prev; // reliable update keeps p
+            }
+            st->rho = sum;
+            st->state = st->iter >= st->max_iter ? ST_MAXIT : ST_RUN;
+        }
+        break;
+    }
+    case FIN_INIT: // sum = |b|^2; the tolerance was stored in stop_outer
+        st->bnorm2 = sum;
+        st->stop_outer = st->stop_outer * sum;
+        if (st->scheme != SCH_REFINE) st->stop_inner = st->inner2 * sum;
+        break;
+    case FIN_FINAL:
+        st->last_true = sum;
+        break;
+    default:
+        break;
+    }
+}
+
+// Write this workgroup's partial; the last workgroup reduces all partials in
+// order and runs the finalize step. `blk` is the logical workgroup index,
+// `nparts` the number of workgroups taking part.
+__device__ inline void reduce_and_finalize(double v, double *partials, CgState *st, int blk,
+                                           int nparts, int fin)
+{
+    __shared__ double lds[kBS / 64];
+    __shared__ int amlast;
+    const double s = block_sum(v, lds);
+    if (threadIdx.x == 0) {
+        partials[blk] = s;
+        __threadfence();
+        const unsigned int t = atomicAdd(&st->ctr[0], 1u);
+        amlast = (t == (unsigned int)(nparts - 1));
+    }
+    __syncthreads();
+    if (!amlast) return;
+    __threadfence();
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBS) acc += load_partial(&partials[i]);
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        st->ctr[0] = 0;
+        finalize(fin, st, tot);
+    }
+}
+
+} // namespace lgt

@@ -1,0 +1,269 @@
+// solver.cpp -- even-odd CG on A = 4 m^2 - D_eo D_oe (host driver).
+//
+// Textbook CG (alpha = rho/<p,Ap>, x += alpha p, r -= alpha Ap,
+// beta = rho'/rho, p = r + beta p) with every scalar kept in device memory:
+// the kernels compute alpha and beta themselves from FP64 reductions, and a
+// solver state word makes every later kernel of a finished solve exit at
+// once. The host enqueues iterations in chunks and reads the state back once
+// per chunk, one chunk behind, so the GPU never waits for the host.
+//
+// Precision forms (single precision gains more than double, Sec. 4):
+//  FP64      all in FP64; at inner convergence the true residual b - A x is
+//            recomputed and replaces r (a reliable update).
+//  RELIABLE  inner CG in FP32 vectors with F32 or BF16 links; every
+//            ru_interval iterations and at inner convergence x64 += x_lo,
+//            r = b - A64 x64 in FP64 (rounded into r_lo), beta from the
+//            FP64 rho, p kept.
+//  REFINE    iterative refinement: the inner CG restarts from 0 (beta = 0)
+//            after each FP64 residual and stops when its residual has dropped
+//            by inner_tol.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace lgt {
+
+namespace {
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    ~Events()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t make(size_t n)
+    {
+        ev.resize(n, nullptr);
+        for (auto &e : ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+};
+
+} // namespace
+
+lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
+                    const double *b, double *x, lgt_cg_result *res)
+{
+    const Geom g = c->g;
+    const int Vh = g.Vh;
+    const hipStream_t s = c->stream;
+    const Launch l = site_launch(Vh);
+    const int scheme = p->scheme;
+    const bool mixed = scheme != SCH_FP64;
+
+    Fmt fhi, flo;
+    lgt_status st = check_links(Uhi, true, &fhi);
+    if (st != LGT_OK) return st;
+    flo = fhi;
+    if (mixed) {
+        st = check_links(Ulo, false, &flo);
+        if (st != LGT_OK) return st;
+        if (fmt_is_f64(flo)) return fail(LGT_ERR_ARG, "U_lo must be F32 or BF16 links for a mixed scheme");
+    }
+    const size_t v64 = (size_t)Vh * 48;
+    const size_t vlo = mixed ? (size_t)Vh * 24 : v64;
+    const int chunk = scheme == SCH_RELIABLE ? p->ru_interval : (p->check_interval > 0 ? p->check_interval : 50);
+    const double inner = scheme == SCH_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
+    const double m4 = 4.0 * p->mass * p->mass;
+
+    // workspace
+    double *b64 = (double *)workspace(c, "cg.b64", v64);
+    double *x64 = (double *)workspace(c, "cg.x64", v64);
+    double *t64 = (double *)workspace(c, "cg.t64", v64);
+    double *q64 = (double *)workspace(c, "cg.q64", v64); // scratch FP64 residual
+    void *r = workspace(c, "cg.r", vlo);
+    void *pp = workspace(c, "cg.p", vlo);
+    void *Ap = workspace(c, "cg.Ap", vlo);
+    void *t = workspace(c, "cg.t", vlo);
+    void *xlo = mixed ? workspace(c, "cg.xlo", vlo) : x64;
+    double *partials = (double *)workspace(c, "cg.partials", sizeof(double) * (size_t)l.nblk_pad);
+    CgState *dst = (CgState *)workspace(c, "cg.state", sizeof(CgState));
+    CgState *host = (CgState *)pinned(c, 3 * sizeof(CgState));
+    if (!b64 || !x64 || !t64 || !q64 || !r || !pp || !Ap || !t || !xlo || !partials || !dst || !host)
+        return fail(LGT_ERR_OOM, "cannot allocate the solver workspace");
+
+    const bool timing = c->timing != 0;
+    const int pairs = 2 * chunk + 2; // event pairs per chunk: 2 Dslash per iteration + 2 in the update
+    Events evs, tev;
+    LGT_HIP(evs.make(4)); // 0 start, 1 end, 2/3 chunk slots
+    if (timing) LGT_HIP(tev.make((size_t)2 * 2 * pairs));
+
+    auto D = [&](Fmt f, int epi, int par, const void *U, const void *in, void *out, int gate, const void *aux0,
+                 const void *aux1, void *out_lo, int fin) {
+        DslashArgs a;
+        a.U = U;
+        a.in = in;
+        a.out = out;
+        a.g = g;
+        a.par = par;
+        a.gate = gate;
+        a.l = l;
+        a.aux0 = aux0;
+        a.aux1 = aux1;
+        a.out_lo = out_lo;
+        a.m4 = m4;
+        a.partials = partials;
+        a.st = dst;
+        a.fin = fin;
+        return launch_dslash(f, epi, a, s);
+    };
+    auto timed = [&](int slot, int idx, bool begin) -> hipError_t {
+        if (!timing) return hipSuccess;
+        return hipEventRecord(tev.ev[((size_t)slot * pairs + idx) * 2 + (begin ? 0 : 1)], s);
+    };
+    VecArgs va;
+    va.x = xlo;
+    va.r = r;
+    va.p = pp;
+    va.Ap = Ap;
+    va.Vh = Vh;
+    va.l = l;
+    va.partials = partials;
+    va.st = dst;
+    va.gate = GATE_ITER;
+
+    // FP64 update step: x64 += x_lo ; r = b - A64 x64 (rounded into r_lo when mixed)
+    auto reliable = [&](int gate, int slot, int fin) -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (mixed && (e = launch_ru_accum(x64, xlo, Vh, dst, gate, s)) != hipSuccess) return e;
+        if (slot >= 0 && (e = timed(slot, 2 * chunk, true)) != hipSuccess) return e;
+        if ((e = D(fhi, EPI_PLAIN, LGT_ODD, Uhi->ptr, x64, t64, gate, nullptr, nullptr, nullptr, FIN_NONE)) != hipSuccess)
+            return e;
+        if (slot >= 0 && (e = timed(slot, 2 * chunk, false)) != hipSuccess) return e;
+        if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, true)) != hipSuccess) return e;
+        if (fin == FIN_FINAL)
+            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, q64, gate, x64, b64, nullptr, FIN_FINAL);
+        else if (mixed)
+            e = D(fhi, EPI_RES_LO, LGT_EVEN, Uhi->ptr, t64, nullptr, gate, x64, b64, r, FIN_RU);
+        else
+            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr, FIN_RU);
+        if (e != hipSuccess) return e;
+        if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, false)) != hipSuccess) return e;
+        return hipSuccess;
+    };
+
+    LGT_HIP(hipEventRecord(evs.ev[0], s));
+    // ---- setup
+    LGT_HIP(launch_pack_vec(true, b, b64, g, s));
+    if (p->x0_is_guess) LGT_HIP(launch_pack_vec(true, x, x64, g, s));
+    else LGT_HIP(launch_zero(x64, v64, s));
+    if (mixed) LGT_HIP(launch_zero(xlo, vlo, s));
+    LGT_HIP(launch_zero(pp, vlo, s));
+    LGT_HIP(launch_state_init(dst, scheme, scheme == SCH_RELIABLE, p->max_iter, p->tol, inner, s));
+    LGT_HIP(launch_norm_init(b64, Vh, partials, dst, s));
+    LGT_HIP(reliable(GATE_RU, -1, FIN_RU)); // r = b - A x0, rho, beta = 0
+
+    // ---- iterations, `chunk` at a time
+    const int lo_is_f64 = !mixed;
+    int k = 0;
+    int prev_iter = 0, prev_upd = 0;
+    double ms_hi = 0.0, ms_lo = 0.0;
+    int n_hi = 0, n_lo = 0;
+    // every chunk that starts running does at least one iteration, and the
+    // kernels stop at max_iter, so this bound is never the one that ends the loop
+    const int max_chunks = p->max_iter + 4;
+    auto harvest = [&](int slot, const CgState &end) -> hipError_t {
+        if (!timing) return hipSuccess;
+        const int nreal = std::min(end.iter - prev_iter, chunk);
+        for (int i = 0; i < 2 * nreal; i++) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, tev.ev[((size_t)slot * pairs + i) * 2],
+                                               tev.ev[((size_t)slot * pairs + i) * 2 + 1]);
+            if (e != hipSuccess) return e;
+            if (lo_is_f64) {
+                ms_hi += ms;
+                n_hi++;
+            } else {
+                ms_lo += ms;
+                n_lo++;
+            }
+        }
+        if (end.updates > prev_upd) {
+            for (int i = 2 * chunk; i < 2 * chunk + 2; i++) {
+                float ms = 0.f;
+                hipError_t e = hipEventElapsedTime(&ms, tev.ev[((size_t)slot * pairs + i) * 2],
+                                                   tev.ev[((size_t)slot * pairs + i) * 2 + 1]);
+                if (e != hipSuccess) return e;
+                ms_hi += ms;
+                n_hi++;
+            }
+        }
+        return hipSuccess;
+    };
+    bool finished = false;
+    while (!finished) {
+        const int slot = k & 1;
+        for (int i = 0; i < chunk; i++) {
+            LGT_HIP(launch_xpay(lo_is_f64, va, s));
+            LGT_HIP(timed(slot, 2 * i, true));
+            LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, mixed ? Ulo->ptr : Uhi->ptr, pp, t, GATE_ITER, nullptr, nullptr,
+                      nullptr, FIN_NONE));
+            LGT_HIP(timed(slot, 2 * i, false));
+            LGT_HIP(timed(slot, 2 * i + 1, true));
+            LGT_HIP(D(flo, EPI_A, LGT_EVEN, mixed ? Ulo->ptr : Uhi->ptr, t, Ap, GATE_ITER, pp, nullptr, nullptr,
+                      FIN_ALPHA));
+            LGT_HIP(timed(slot, 2 * i + 1, false));
+            LGT_HIP(launch_update(lo_is_f64, va, s));
+        }
+        LGT_HIP(reliable(GATE_RU, timing ? slot : -1, FIN_RU));
+        LGT_HIP(hipMemcpyAsync(host + slot, dst, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        LGT_HIP(hipEventRecord(evs.ev[2 + slot], s));
+        if (k > 0) {
+            const int ps = (k - 1) & 1;
+            LGT_HIP(hipEventSynchronize(evs.ev[2 + ps]));
+            const CgState e = host[ps];
+            LGT_HIP(harvest(ps, e));
+            prev_iter = e.iter;
+            prev_upd = e.updates;
+            if (e.state == ST_DONE || e.state == ST_FAIL || e.state == ST_MAXIT) finished = true;
+        }
+        k++;
+        if (k > max_chunks) break;
+    }
+    {
+        const int ls = (k - 1) & 1;
+        LGT_HIP(hipEventSynchronize(evs.ev[2 + ls]));
+        LGT_HIP(harvest(ls, host[ls]));
+    }
+    // ---- final: accumulate, FP64 true residual, unpack
+    LGT_HIP(reliable(GATE_NONE, -1, FIN_FINAL));
+    LGT_HIP(launch_unpack_vec(true, x64, x, g, s));
+    LGT_HIP(hipMemcpyAsync(host + 2, dst, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    LGT_HIP(hipEventRecord(evs.ev[1], s));
+    LGT_HIP(hipEventSynchronize(evs.ev[1]));
+    const CgState e = host[2];
+    float ms = 0.f;
+    LGT_HIP(hipEventElapsedTime(&ms, evs.ev[0], evs.ev[1]));
+
+    lgt_cg_result out;
+    std::memset(&out, 0, sizeof(out));
+    out.iters = e.iter;
+    out.updates = e.updates;
+    out.dslash_calls = 2 * (e.iter + e.updates + 2);
+    out.true_rel_resid = e.bnorm2 > 0.0 ? std::sqrt(e.last_true / e.bnorm2) : 0.0;
+    out.seconds = 1e-3 * ms;
+    out.dslash_ms_hi = ms_hi;
+    out.dslash_ms_lo = ms_lo;
+    out.dslash_timed_hi = n_hi;
+    out.dslash_timed_lo = n_lo;
+    lgt_status ret;
+    if (e.state == ST_DONE) ret = LGT_OK;
+    else if (e.state == ST_FAIL || !std::isfinite(e.last_true)) ret = LGT_ERR_NONFINITE;
+    else ret = LGT_ERR_NOT_CONVERGED;
+    out.status = ret;
+    if (res) *res = out;
+    if (ret == LGT_ERR_NONFINITE) return fail(ret, "CG breakdown or non-finite residual after %d iterations", e.iter);
+    if (ret == LGT_ERR_NOT_CONVERGED)
+        return fail(ret, "CG not converged: %d iterations, true relative residual %.3e", e.iter, out.true_rel_resid);
+    return LGT_OK;
+}
+
+} // namespace lgt

@@ -1,0 +1,340 @@
+"""ctypes binding of liblgt.so with torch tensors as device memory.
+
+Names follow include/lgt.h. Tensors passed in must be CUDA (HIP) tensors on
+the context's device, contiguous, in the canonical layouts of lgt.h:
+links float64 [4][V][3][3][2] (eo order), parity vectors float64 [V/2][3][2].
+Native vectors are held as tensors of shape [3][V/2][2] (float64 for F64
+fields, float32 otherwise); packed links as uint8 tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(HERE, "liblgt.so")
+
+LGT_F64, LGT_F32, LGT_BF16 = 0, 1, 2
+LGT_R18, LGT_R12 = 18, 12
+LGT_EVEN, LGT_ODD = 0, 1
+LGT_CG_FP64, LGT_CG_RELIABLE, LGT_CG_REFINE = 0, 1, 2
+
+STATUS = {
+    0: "LGT_OK", -1: "LGT_ERR_ARG", -2: "LGT_ERR_GEOMETRY", -3: "LGT_ERR_ALIGN",
+    -4: "LGT_ERR_DEVICE", -5: "LGT_ERR_NOT_CONVERGED", -6: "LGT_ERR_NONFINITE",
+    -7: "LGT_ERR_OOM", -8: "LGT_ERR_UNSUPPORTED",
+}
+
+# 8 complex 3x3 mat-vecs of 66 flop (36 mul + 30 add) and 7 three-complex vector
+# additions of 6 flop per output site
+DSLASH_FLOP_PER_SITE = 8 * 66 + 7 * 6
+
+
+def link_bytes_per_dir(prec: int, recon: int) -> int:
+    return {(0, 18): 144, (0, 12): 96, (1, 18): 72, (1, 12): 48, (2, 12): 24}[(prec, recon)]
+
+
+def vec_bytes_per_site(prec: int) -> int:
+    return 48 if prec == LGT_F64 else 24
+
+
+class LgtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Geom(C.Structure):
+    _fields_ = [("L", C.c_int32 * 4), ("bc", C.c_int32 * 4)]
+
+
+class _Links(C.Structure):
+    _fields_ = [("ptr", C.c_void_p), ("prec", C.c_int32), ("recon", C.c_int32)]
+
+
+class _CgParams(C.Structure):
+    _fields_ = [("mass", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("scheme", C.c_int32), ("ru_interval", C.c_int32), ("x0_is_guess", C.c_int32),
+                ("inner_tol", C.c_double), ("check_interval", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _CgResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("updates", C.c_int32),
+                ("dslash_calls", C.c_int32), ("true_rel_resid", C.c_double), ("seconds", C.c_double),
+                ("dslash_ms_hi", C.c_double), ("dslash_ms_lo", C.c_double),
+                ("dslash_timed_hi", C.c_int32), ("dslash_timed_lo", C.c_int32)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise ImportError(f"{_SO} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                              "g.build()'` (there is no fallback path)")
+        _lib = C.CDLL(_SO)
+        _setup(_lib)
+    return _lib
+
+
+def _setup(l):
+    vp, i32, st = C.c_void_p, C.c_int32, C.c_int32
+    sig = {
+        "lgt_status_string": (C.c_char_p, [st]),
+        "lgt_last_error": (C.c_char_p, []),
+        "lgt_geom_check": (st, [C.POINTER(_Geom)]),
+        "lgt_links_bytes": (st, [C.POINTER(_Geom), i32, i32, C.POINTER(C.c_size_t)]),
+        "lgt_vec_bytes": (st, [C.POINTER(_Geom), i32, C.POINTER(C.c_size_t)]),
+        "lgt_create": (st, [C.POINTER(_Geom), i32, vp, C.POINTER(vp)]),
+        "lgt_destroy": (st, [vp]),
+        "lgt_set_timing": (st, [vp, i32]),
+        "lgt_index_maps": (st, [vp, vp, vp]),
+        "lgt_pack_links": (st, [vp, vp, i32, i32, vp]),
+        "lgt_pack_vec": (st, [vp, i32, vp, vp]),
+        "lgt_unpack_vec": (st, [vp, i32, vp, vp]),
+        "lgt_dslash": (st, [vp, C.POINTER(_Links), i32, vp, vp]),
+        "lgt_cg_solve": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), C.POINTER(_CgParams), vp, vp,
+                              C.POINTER(_CgResult)]),
+        "lgt_cdot": (st, [vp, C.c_int64, vp, vp, C.POINTER(C.c_double)]),
+        "lgt_force": (st, [vp, C.POINTER(_Links), vp, C.c_double, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(l, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def exported_symbols_declared(header: str | None = None) -> list[str]:
+    header = header or os.path.join(os.path.dirname(HERE), "include", "lgt.h")
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lgt_[a-z0-9_]+)\s*\(", text)))
+
+
+def exported_symbols() -> list[str]:
+    """Names declared in include/lgt.h that the loaded library exports."""
+    l = lib()
+    return [n for n in exported_symbols_declared() if hasattr(l, n)]
+
+
+def _check(status: int):
+    if status != 0:
+        msg = lib().lgt_last_error().decode()
+        raise LgtError(status, msg)
+
+
+def _geom(L, bc) -> _Geom:
+    g = _Geom()
+    for i in range(4):
+        g.L[i] = int(L[i])
+        g.bc[i] = int(bc[i])
+    return g
+
+
+def geom_check(L, bc=(1, 1, 1, 1)) -> int:
+    return int(lib().lgt_geom_check(C.byref(_geom(L, bc))))
+
+
+def links_bytes(L, prec, recon, bc=(1, 1, 1, 1)) -> int:
+    n = C.c_size_t()
+    _check(lib().lgt_links_bytes(C.byref(_geom(L, bc)), prec, recon, C.byref(n)))
+    return int(n.value)
+
+
+def vec_bytes(L, prec, bc=(1, 1, 1, 1)) -> int:
+    n = C.c_size_t()
+    _check(lib().lgt_vec_bytes(C.byref(_geom(L, bc)), prec, C.byref(n)))
+    return int(n.value)
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+@dataclasses.dataclass
+class PackedLinks:
+    data: torch.Tensor  # uint8, lgt_links_bytes
+    prec: int
+    recon: int
+
+    def desc(self) -> _Links:
+        return _Links(self.data.data_ptr(), self.prec, self.recon)
+
+
+@dataclasses.dataclass
+class CgResult:
+    status: int
+    iters: int
+    updates: int
+    dslash_calls: int
+    true_rel_resid: float
+    seconds: float
+    dslash_ms_hi: float
+    dslash_ms_lo: float
+    dslash_timed_hi: int
+    dslash_timed_lo: int
+
+
+class Lattice:
+    """One lattice geometry on one GPU: an lgt_ctx bound to torch's current stream."""
+
+    def __init__(self, L, bc=(1, 1, 1, 1), device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.L = tuple(int(x) for x in L)
+        self.bc = tuple(int(x) for x in bc)
+        self.V = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self.Vh = self.V // 2
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = C.c_void_p()
+        _check(lib().lgt_create(C.byref(_geom(self.L, self.bc)), device, C.c_void_p(self.stream.cuda_stream),
+                                C.byref(self._ctx)))
+
+    def close(self):
+        if self._ctx:
+            lib().lgt_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_timing(self, on: bool):
+        _check(lib().lgt_set_timing(self._ctx, int(bool(on))))
+
+    # -- helpers
+    def _dev(self, t: torch.Tensor, dtype=None, shape=None, what="tensor"):
+        if t.device != self.device:
+            raise ValueError(f"{what} must be on {self.device}")
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError(f"{what} must be {dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        return _ptr(t)
+
+    def vec_shape(self):
+        return (self.Vh, 3, 2)
+
+    def native_vec(self, prec: int) -> torch.Tensor:
+        dt = torch.float64 if prec == LGT_F64 else torch.float32
+        return torch.empty((3, self.Vh, 2), dtype=dt, device=self.device)
+
+    # -- entry points
+    def index_maps(self):
+        lex = torch.empty(self.V, dtype=torch.int32, device=self.device)
+        nbr = torch.empty((2, 8, self.Vh), dtype=torch.int32, device=self.device)
+        _check(lib().lgt_index_maps(self._ctx, lex.data_ptr(), nbr.data_ptr()))
+        return lex, nbr
+
+    def pack_links(self, U: torch.Tensor, prec: int = LGT_F64, recon: int = LGT_R18) -> PackedLinks:
+        p = self._dev(U, torch.float64, (4, self.V, 3, 3, 2), "U")
+        out = torch.empty(links_bytes(self.L, prec, recon, self.bc), dtype=torch.uint8, device=self.device)
+        _check(lib().lgt_pack_links(self._ctx, p, prec, recon, out.data_ptr()))
+        return PackedLinks(out, prec, recon)
+
+    def pack_vec(self, v: torch.Tensor, prec: int = LGT_F64) -> torch.Tensor:
+        p = self._dev(v, torch.float64, self.vec_shape(), "v")
+        out = self.native_vec(prec)
+        _check(lib().lgt_pack_vec(self._ctx, prec, p, out.data_ptr()))
+        return out
+
+    def unpack_vec(self, n: torch.Tensor, prec: int = LGT_F64) -> torch.Tensor:
+        dt = torch.float64 if prec == LGT_F64 else torch.float32
+        p = self._dev(n, dt, (3, self.Vh, 2), "native vector")
+        out = torch.empty(self.vec_shape(), dtype=torch.float64, device=self.device)
+        _check(lib().lgt_unpack_vec(self._ctx, prec, p, out.data_ptr()))
+        return out
+
+    def dslash(self, U: PackedLinks, x: torch.Tensor, out_parity: int, out: torch.Tensor | None = None):
+        """out = D x for native vectors (precision of U's vectors)."""
+        dt = torch.float64 if U.prec == LGT_F64 else torch.float32
+        p = self._dev(x, dt, (3, self.Vh, 2), "input vector")
+        if out is None:
+            out = torch.empty_like(x)
+        q = self._dev(out, dt, (3, self.Vh, 2), "output vector")
+        d = U.desc()
+        _check(lib().lgt_dslash(self._ctx, C.byref(d), int(out_parity), p, q))
+        return out
+
+    def cg_solve(self, U_hi: PackedLinks, b: torch.Tensor, mass: float, tol: float = 1e-10,
+                 scheme: int = LGT_CG_FP64, U_lo: PackedLinks | None = None, ru_interval: int = 50,
+                 inner_tol: float = 0.0, max_iter: int = 100000, x0: torch.Tensor | None = None,
+                 check_interval: int = 0, raise_on_fail: bool = True):
+        pb = self._dev(b, torch.float64, self.vec_shape(), "b")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        px = self._dev(x, torch.float64, self.vec_shape(), "x")
+        prm = _CgParams(float(mass), float(tol), int(max_iter), int(scheme), int(ru_interval),
+                        int(x0 is not None), float(inner_tol), int(check_interval), 0)
+        res = _CgResult()
+        dhi = U_hi.desc()
+        dlo = U_lo.desc() if U_lo is not None else None
+        st = lib().lgt_cg_solve(self._ctx, C.byref(dhi), C.byref(dlo) if dlo is not None else None,
+                                C.byref(prm), pb, px, C.byref(res))
+        r = CgResult(*(getattr(res, f[0]) for f in _CgResult._fields_))
+        if st != 0 and (raise_on_fail or st not in (-5, -6)):
+            _check(st)
+        return x, r
+
+    def cdot(self, a: torch.Tensor, b: torch.Tensor) -> complex:
+        if a.numel() != b.numel() or a.numel() % 2:
+            raise ValueError("cdot needs two float64 tensors of equal even size")
+        pa = self._dev(a, torch.float64, None, "a")
+        pb = self._dev(b, torch.float64, None, "b")
+        out = (C.c_double * 2)()
+        _check(lib().lgt_cdot(self._ctx, a.numel() // 2, pa, pb, out))
+        return complex(out[0], out[1])
+
+    def force(self, U: PackedLinks, X: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        px = self._dev(X, torch.float64, self.vec_shape(), "X")
+        G = torch.empty((4, self.V, 3, 3, 2), dtype=torch.float64, device=self.device)
+        d = U.desc()
+        _check(lib().lgt_force(self._ctx, C.byref(d), px, float(scale), G.data_ptr()))
+        return G
+
+
+class PseudofermionAction(torch.autograd.Function):
+    """S = phi^dag A^-1 phi with A = 4 m^2 - D_eo D_oe, differentiable in U (and phi).
+
+    forward: X = A^-1 phi by the FP64 CG of the library, S = Re <phi, X>.
+    backward: dS/dU from the fermion-force kernel, reusing the saved X.
+    U: float64 [4][V][3][3][2] (real view of the complex links), phi: [V/2][3][2].
+    """
+
+    @staticmethod
+    def forward(ctx, U, phi, lat: Lattice, mass: float, tol: float = 1e-12, max_iter: int = 100000):
+        Up = lat.pack_links(U.detach(), LGT_F64, LGT_R18)
+        X, res = lat.cg_solve(Up, phi.detach(), mass, tol=tol, max_iter=max_iter)
+        S = lat.cdot(phi.detach(), X).real
+        ctx.lat = lat
+        ctx.Up = Up
+        ctx.res = res
+        ctx.save_for_backward(X)
+        return torch.tensor(S, dtype=torch.float64, device=U.device)
+
+    @staticmethod
+    def backward(ctx, gS):
+        (X,) = ctx.saved_tensors
+        g = float(gS.item())
+        gU = ctx.lat.force(ctx.Up, X, scale=g) if ctx.needs_input_grad[0] else None
+        # dS/d(Re phi, Im phi) = 2 (Re X, Im X)
+        gphi = (2.0 * g) * X if ctx.needs_input_grad[1] else None
+        return gU, gphi, None, None, None, None

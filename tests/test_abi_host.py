@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before launching anything."""
+import ctypes as C
+
+import pytest
+
+import paper_1309_0551_amd as P
+from paper_1309_0551_amd import lgt as B
+
+
+def test_library_exports_every_declared_symbol():
+    declared = B.exported_symbols_declared()
+    assert "lgt_dslash" in declared and "lgt_cg_solve" in declared and "lgt_force" in declared
+    missing = [n for n in declared if not hasattr(P.lib(), n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    l = P.lib()
+    for code in range(-8, 1):
+        s = l.lgt_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert l.lgt_status_string(-99).decode() == "unknown status"
+
+
+@pytest.mark.parametrize("L,bc,ok", [
+    ((4, 4, 4, 4), (1, 1, 1, 1), True),
+    ((2, 2, 2, 2), (1, 1, 1, -1), True),
+    ((32, 32, 32, 32), (1, 1, 1, 1), True),
+    ((3, 4, 4, 4), (1, 1, 1, 1), False),
+    ((4, 4, 0, 4), (1, 1, 1, 1), False),
+    ((4, 4, 4, 4), (1, 1, 1, 0), False),
+    ((2048, 2048, 2048, 2), (1, 1, 1, 1), False),  # > 2^31 sites
+])
+def test_geometry_validation(L, bc, ok):
+    assert (P.geom_check(L, bc) == 0) == ok
+    if not ok:
+        assert P.geom_check(L, bc) == -2
+
+
+def test_sizes():
+    L = (32, 32, 32, 32)
+    V = 32 ** 4
+    assert P.links_bytes(L, P.LGT_F64, P.LGT_R18) == V * 4 * 144
+    assert P.links_bytes(L, P.LGT_F32, P.LGT_R12) == V * 4 * 48
+    assert P.links_bytes(L, P.LGT_BF16, P.LGT_R12) == V * 4 * 24
+    assert P.vec_bytes(L, P.LGT_F64) == V // 2 * 48
+    assert P.vec_bytes(L, P.LGT_BF16) == V // 2 * 24
+    with pytest.raises(P.LgtError) as e:
+        P.links_bytes(L, P.LGT_BF16, P.LGT_R18)
+    assert e.value.status == -8
+
+
+def _geom(L):
+    return B._geom(L, (1, 1, 1, 1))
+
+
+def test_create_checks_geometry_before_device():
+    ctx = C.c_void_p()
+    st = P.lib().lgt_create(C.byref(_geom((5, 4, 4, 4))), 0, None, C.byref(ctx))
+    assert st == -2
+    assert "even" in P.lib().lgt_last_error().decode()
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = C.c_void_p()
+    st = P.lib().lgt_create(C.byref(_geom((4, 4, 4, 4))), 0, None, C.byref(ctx))
+    assert st == -4
+    assert not ctx
+
+
+def test_null_context_and_args_rejected():
+    l = P.lib()
+    assert l.lgt_destroy(None) == -1
+    assert l.lgt_set_timing(None, 1) == -1
+    assert l.lgt_dslash(None, None, 0, None, None) == -1
+    assert l.lgt_cg_solve(None, None, None, None, None, None, None) == -1
+    assert l.lgt_force(None, None, None, 1.0, None) == -1
+    assert l.lgt_cdot(None, 1, None, None, None) == -1
+    assert l.lgt_links_bytes(C.byref(_geom((4, 4, 4, 4))), 0, 18, None) == -1
+
+
+def test_param_struct_layout_matches_header():
+    assert C.sizeof(B._CgParams) == 48
+    assert C.sizeof(B._CgResult) == 56
+    assert C.sizeof(B._Links) == 16
+    assert C.sizeof(B._Geom) == 32
+
+
+def test_flop_constant():
+    assert P.DSLASH_FLOP_PER_SITE == 570

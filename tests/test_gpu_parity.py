@@ -1,0 +1,268 @@
+"""GPU parity against the FP64 oracle, through the C ABI (Python binding).
+
+Tolerances (norm-wise relative error of the output):
+* index maps: bit-exact.
+* FP64 Dslash (18 and 12 reals): <= 1e-12 and per component <= 1e-12 max|out|.
+* FP32 links + FP32 vectors: 32 u32 = 1.9e-6, u32 = 2^-24 the storage rounding of
+  links and input; the kernel sums 8 hops of 3x3 products in FP32.
+* BF16 links + FP32 vectors: 8 u16 = 1.6e-2, u16 = 2^-9; rows 0-1 are rounded
+  and row 2 is rebuilt from the rounded rows.
+* CG: the oracle recomputes the true residual of the GPU's x in FP64, which must
+  meet the tolerance; and |x - x_oracle| <= (tol_gpu + tol_oracle) |b| / (4 m^2),
+  since lambda_min(A) >= 4 m^2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+import oracle
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1309_0551_amd")
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U16 = 2.0 ** -9
+FMTS = {
+    "f64r18": (P.LGT_F64, P.LGT_R18, 1e-12),
+    "f64r12": (P.LGT_F64, P.LGT_R12, 1e-12),
+    "f32r18": (P.LGT_F32, P.LGT_R18, 32 * U32),
+    "f32r12": (P.LGT_F32, P.LGT_R12, 32 * U32),
+    "bf16r12": (P.LGT_BF16, P.LGT_R12, 8 * U16),
+}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ------------------------------------------------------------- geometry ---
+
+@pytest.mark.parametrize("L", [(2, 2, 2, 2), (4, 4, 4, 4), (2, 4, 6, 8), (8, 6, 4, 2), (16, 16, 16, 32),
+                               (24, 24, 24, 48), (32, 32, 32, 32)])
+def test_index_maps_bit_exact(dev, L):
+    print("index maps", L, flush=True)
+    with P.Lattice(L) as lat:
+        lex, nbr = lat.index_maps()
+        torch.cuda.synchronize()
+        e_lex, e_nbr = oracle.index_maps(L)
+        np.testing.assert_array_equal(lex.cpu().numpy(), e_lex)
+        np.testing.assert_array_equal(nbr.cpu().numpy(), e_nbr)
+
+
+# --------------------------------------------------------------- Dslash ---
+
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+@pytest.mark.parametrize("L,bc,kind", [
+    ((2, 2, 2, 2), (1, 1, 1, 1), "haar"),       # coincident +mu / -mu neighbours
+    ((4, 4, 4, 4), (1, 1, 1, 1), "haar"),       # 128 sites: one partial workgroup
+    ((6, 4, 6, 8), (1, 1, 1, -1), "haar"),      # 576 sites: 3 workgroups, ragged tail
+    ((8, 8, 8, 12), (-1, 1, 1, -1), "expih"),
+    ((16, 16, 16, 16), (1, 1, 1, 1), "expih"),  # 32768 sites: 128 workgroups
+])
+def test_dslash_parity(dev, fmt, L, bc, kind):
+    prec, recon, tol = FMTS[fmt]
+    print("dslash", fmt, L, bc, flush=True)
+    U = li.links(L, kind, 101, c=0.3)
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        for out_par in (0, 1):
+            chi = li.vector(L, 102 + out_par)
+            vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+            out = lat.unpack_vec(lat.dslash(Up, lat.pack_vec(_t(chi, dev), vp), out_par), vp)
+            got = out.cpu().numpy()
+            ref = oracle.dslash(L, U, chi, out_par, bc)
+            assert _rel(got, ref) <= tol, (fmt, out_par, _rel(got, ref))
+            if prec == P.LGT_F64:
+                assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_dslash_full_size_32(dev):
+    """32^4 Haar, FP64, the benchmark's launch configuration: every output site."""
+    L = (32, 32, 32, 32)
+    print("dslash 32^4", flush=True)
+    U = li.links(L, "haar", 3001)
+    chi = li.vector(L, 3002)
+    with P.Lattice(L) as lat:
+        Up = lat.pack_links(_t(U, dev), P.LGT_F64, P.LGT_R18)
+        out = lat.unpack_vec(lat.dslash(Up, lat.pack_vec(_t(chi, dev)), 1)).cpu().numpy()
+    ref = oracle.dslash(L, U, chi, 1)
+    assert _rel(out, ref) <= 1e-12
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_dslash_run_twice_bit_identical(dev):
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 111)
+    chi = li.vector(L, 112)
+    with P.Lattice(L) as lat:
+        Up = lat.pack_links(_t(U, dev))
+        x = lat.pack_vec(_t(chi, dev))
+        a = lat.dslash(Up, x, 0).clone()
+        b = lat.dslash(Up, x, 0).clone()
+        assert torch.equal(a, b)
+
+
+def test_pack_unpack_roundtrip(dev):
+    L = (4, 6, 4, 8)
+    v = li.vector(L, 5)
+    with P.Lattice(L) as lat:
+        back = lat.unpack_vec(lat.pack_vec(_t(v, dev), P.LGT_F64), P.LGT_F64).cpu().numpy()
+        np.testing.assert_array_equal(back, v)
+        back32 = lat.unpack_vec(lat.pack_vec(_t(v, dev), P.LGT_F32), P.LGT_F32).cpu().numpy()
+        np.testing.assert_array_equal(back32, v.astype(np.float32).astype(np.float64))
+
+
+# ------------------------------------------------------------------- CG ---
+
+def _true_resid(L, U, mass, b, x, bc=None):
+    r = b - oracle.apply_A(L, U, mass, x, bc)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+CG_CASES = [
+    # name, L, kind, c, mass, scheme, lo-format
+    ("c1_fp64", (4, 4, 4, 4), "haar", None, 0.1, P.LGT_CG_FP64, None),
+    ("fp64_8", (8, 8, 8, 8), "expih", 0.3, 0.05, P.LGT_CG_FP64, None),
+    ("rel_f32r12", (8, 8, 8, 8), "haar", None, 0.1, P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12)),
+    ("rel_f32r18", (6, 4, 6, 8), "haar", None, 0.1, P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R18)),
+    ("rel_bf16r12", (4, 4, 4, 4), "haar", None, 0.1, P.LGT_CG_RELIABLE, (P.LGT_BF16, P.LGT_R12)),
+    ("ir_bf16r12", (8, 8, 8, 8), "haar", None, 0.1, P.LGT_CG_REFINE, (P.LGT_BF16, P.LGT_R12)),
+    ("ir_f32r12", (8, 8, 8, 8), "expih", 0.3, 0.05, P.LGT_CG_REFINE, (P.LGT_F32, P.LGT_R12)),
+]
+
+
+@pytest.mark.parametrize("case", CG_CASES, ids=[c[0] for c in CG_CASES])
+def test_cg_parity(dev, case):
+    name, L, kind, c, mass, scheme, lo = case
+    print("cg", name, flush=True)
+    tol = 1e-10
+    U = li.links(L, kind, 201, c=c if c else 0.3)
+    b = li.vector(L, 202)
+    st, xo, it_o, rr_o = oracle.cg(L, U, mass, b, tol=tol)
+    assert st == 0
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev), P.LGT_F64, P.LGT_R18)
+        Ul = lat.pack_links(_t(U, dev), *lo) if lo else None
+        x, res = lat.cg_solve(Uh, _t(b, dev), mass, tol=tol, scheme=scheme, U_lo=Ul, ru_interval=50,
+                              inner_tol=0.1 if scheme == P.LGT_CG_REFINE else 0.0)
+    xg = x.cpu().numpy()
+    rr = _true_resid(L, U, mass, b, xg)
+    print(f"  {name}: gpu iters {res.iters} updates {res.updates} gpu resid {res.true_rel_resid:.3e} "
+          f"oracle-resid {rr:.3e}; oracle iters {it_o}", flush=True)
+    assert res.status == 0
+    assert rr <= tol * 1.05
+    assert abs(res.true_rel_resid - rr) <= 1e-3 * tol + 0.05 * rr
+    bound = (tol * 1.05 + rr_o) * np.linalg.norm(b) / (4 * mass * mass)
+    assert np.linalg.norm(xg - xo) <= bound
+    if scheme == P.LGT_CG_FP64:
+        assert abs(res.iters - it_o) <= 3
+
+
+def test_cg_free_field_plane_wave(dev):
+    """Unit links: b is an eigenvector of A with eigenvalue 4 (m^2 + sum sin^2 p)."""
+    L = (8, 4, 6, 4)
+    m = 0.2
+    n = (1, 1, 2, 0)
+    U = li.links(L, "unit")
+    import brute
+    z = np.zeros((int(np.prod(L)) // 2, 3), complex)
+    for lex, co in brute.sites(L):
+        e = brute.eo_index(L, co)
+        if e < len(z):
+            z[e] = np.exp(1j * sum(2 * math.pi * n[mu] * co[mu] / L[mu] for mu in range(4))) * \
+                np.array([1.0, -0.5j, 0.25])
+    b = li.to_real(z)
+    lam = 4 * (m * m + sum(math.sin(2 * math.pi * n[mu] / L[mu]) ** 2 for mu in range(4)))
+    with P.Lattice(L) as lat:
+        x, res = lat.cg_solve(lat.pack_links(_t(U, dev)), _t(b, dev), m, tol=1e-12)
+    np.testing.assert_allclose(x.cpu().numpy(), b / lam, atol=1e-12)
+    assert res.iters <= 2
+
+
+def test_cg_status_paths(dev):
+    L = (4, 4, 4, 4)
+    U = li.links(L, "haar", 301)
+    b = li.vector(L, 302)
+    with P.Lattice(L) as lat:
+        Up = lat.pack_links(_t(U, dev))
+        # zero source: x = 0 at once
+        x, res = lat.cg_solve(Up, torch.zeros((128, 3, 2), dtype=torch.float64, device=dev), 0.1)
+        assert res.status == 0 and res.iters == 0 and not x.any()
+        # iteration cap: NOT_CONVERGED with the best x written
+        x, res = lat.cg_solve(Up, _t(b, dev), 0.1, max_iter=5, raise_on_fail=False)
+        assert res.status == -5 and res.iters == 5
+        assert _true_resid(L, U, 0.1, b, x.cpu().numpy()) == pytest.approx(res.true_rel_resid, rel=1e-6)
+        with pytest.raises(P.LgtError) as e:
+            lat.cg_solve(Up, _t(b, dev), 0.1, max_iter=5)
+        assert e.value.status == -5
+        # non-finite source
+        bn = b.copy()
+        bn[3, 1, 0] = np.nan
+        x, res = lat.cg_solve(Up, _t(bn, dev), 0.1, raise_on_fail=False)
+        assert res.status == -6
+        # warm restart from a returned x
+        x5, _ = lat.cg_solve(Up, _t(b, dev), 0.1, max_iter=5, raise_on_fail=False)
+        x, res = lat.cg_solve(Up, _t(b, dev), 0.1, x0=x5)
+        assert res.status == 0
+        assert _true_resid(L, U, 0.1, b, x.cpu().numpy()) <= 1.05e-10
+
+
+def test_cg_deterministic(dev):
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 401)
+    b = li.vector(L, 402)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev))
+        Ul = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        for scheme, lo in ((P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, Ul)):
+            x1, r1 = lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo)
+            x2, r2 = lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo)
+            assert torch.equal(x1, x2) and r1.iters == r2.iters
+
+
+# ---------------------------------------------------------------- force ---
+
+@pytest.mark.parametrize("L,bc", [((4, 4, 4, 4), (1, 1, 1, 1)), ((6, 4, 6, 8), (1, 1, 1, -1)),
+                                  ((16, 16, 16, 32), (1, 1, 1, 1))])
+def test_force_parity(dev, L, bc):
+    print("force", L, flush=True)
+    U = li.links(L, "expih", 501, c=0.5)
+    X = li.vector(L, 502)
+    with P.Lattice(L, bc) as lat:
+        G = lat.force(lat.pack_links(_t(U, dev)), _t(X, dev), scale=1.0).cpu().numpy()
+    Gr = oracle.force(L, U, X, bc)
+    assert _rel(G, Gr) <= 1e-12
+    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+
+
+def test_autograd_action_vs_oracle(dev):
+    L, mass = (4, 4, 4, 8), 0.05
+    U = li.links(L, "expih", 601, c=0.5)
+    phi = li.vector(L, 602)
+    st, Xo, _, _ = oracle.cg(L, U, mass, phi, tol=1e-13)
+    Go = oracle.force(L, U, Xo)
+    S_o = oracle.cdot(phi, Xo).real
+    with P.Lattice(L) as lat:
+        Ut = _t(U, dev).requires_grad_(True)
+        pt = _t(phi, dev).requires_grad_(True)
+        S = P.PseudofermionAction.apply(Ut, pt, lat, mass, 1e-13)
+        (2.5 * S).backward()
+    assert abs(S.item() - S_o) <= 1e-11 * abs(S_o)
+    kappa = (4 * (mass ** 2) + 64) / (4 * mass ** 2)
+    assert _rel(Ut.grad.cpu().numpy(), 2.5 * Go) <= kappa * 1e-13 * 10
+    np.testing.assert_allclose(pt.grad.cpu().numpy(), 2.5 * 2 * Xo, atol=1e-8 * np.abs(Xo).max())

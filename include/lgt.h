@@ -108,6 +108,23 @@ lgt_status lgt_destroy(lgt_ctx *ctx);
  * the summed kernel time in lgt_cg_result (0 = off, the default). */
 lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t enable);
 
+/* ---- kernel variants and autotuning ---------------------------------------- */
+
+/* The Dslash comes in variants that issue the loads of 8, 2 or 1 hops
+ * together (more loads in flight per thread against more waves per SIMD).
+ * The choice is per link format and per context; it changes speed only, never
+ * results. hops_per_group must be 1, 2 or 8. */
+lgt_status lgt_set_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t hops_per_group);
+lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *hops_per_group);
+/* Time every variant on U (2 warm-up and 10 timed launches each, on the
+ * context's stream; synchronises) and keep the fastest for U's format.
+ * times_us (host, may be NULL) receives the mean launch time of variants
+ * {8, 2, 1}. When the environment variable LGT_TUNE_CACHE names a file and
+ * times_us is NULL, a cached choice for (device architecture, lattice,
+ * format) is used without timing unless LGT_TUNE=force; new results are
+ * appended to that file. */
+lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[3]);
+
 /* ---- geometry export (Sec. 1: unique 4-tuple per site, 8 neighbours) ------- */
 
 /* lex_of_eo[V] (int32): lexicographic index of eo site e.
@@ -194,6 +211,15 @@ lgt_status lgt_cdot(lgt_ctx *ctx, int64_t n_complex, const double *a, const doub
  *   x even: G_mu(x) = +2 eta_mu(x) s+_mu(x) X(x) Y(x+mu)^dag
  *   x odd : G_mu(x) = -2 eta_mu(x) s+_mu(x) Y(x) X(x+mu)^dag,  Y = D_oe X. */
 lgt_status lgt_force(lgt_ctx *ctx, const lgt_links *U, const double *X, double scale, double *G);
+
+/* ---- measurement aid ---------------------------------------------------------- */
+
+/* Copy `bytes` (a multiple of 16; src and dst device buffers that do not
+ * overlap) with a plain streaming kernel on the context's stream. Its rate is
+ * the achievable HBM ceiling that the Dslash's bandwidth is compared with
+ * (the paper ties the routines' speed to memory bandwidth, Sec. 5); it also
+ * calibrates hardware byte counters. Asynchronous. */
+lgt_status lgt_stream_copy(lgt_ctx *ctx, const void *src, void *dst, size_t bytes);
 
 #ifdef __cplusplus
 }

@@ -16,12 +16,13 @@ BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "liblgt.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["dslash.hip", "blas.hip", "force.hip", "solver.cpp", "abi.cpp"]
+SOURCES = ["dslash.hip", "blas.hip", "force.hip", "probe.hip", "solver.cpp", "tune.cpp", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
-# Packed FP32 instructions are disabled on purpose (see DESIGN notes on the
-# hardware): the compiler would otherwise form them from float / float2 code.
+# Packed FP32 instructions (v_pk_{add,mul,fma}_f32) are kept out of the code
+# objects: some of their forms have given silently wrong results on these
+# parts, and the compiler would otherwise form them from float / float2 code.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]

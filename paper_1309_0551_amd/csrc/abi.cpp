@@ -318,7 +318,7 @@ lgt_status lgt_dslash(lgt_ctx *c, const lgt_links *U, int32_t out_parity, const 
     a.par = out_parity;
     a.gate = GATE_NONE;
     a.l = site_launch(c->g.Vh);
-    a.fin = FIN_NONE;
+    a.hpi = c->hpi[f];
     LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
     return LGT_OK;
 }
@@ -358,9 +358,9 @@ lgt_status lgt_cdot(lgt_ctx *c, int64_t n, const double *a, const double *b, dou
     double *res = (double *)workspace(c, "dot.result", 2 * sizeof(double) + sizeof(unsigned int) * 4);
     double *host = (double *)pinned(c, 3 * sizeof(CgState));
     if (!part || !res || !host) return fail(LGT_ERR_OOM, "cannot allocate the reduction workspace");
-    unsigned int *ctr = (unsigned int *)(res + 2);
-    LGT_HIP(launch_zero(res, 32, c->stream));
-    LGT_HIP(launch_cdot(n, a, b, part, ctr, res, c->stream));
+
+
+    LGT_HIP(launch_cdot(n, a, b, part, res, c->stream));
     LGT_HIP(hipMemcpyAsync(host, res, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     LGT_HIP(hipStreamSynchronize(c->stream));
     out[0] = host[0];
@@ -392,7 +392,7 @@ lgt_status lgt_force(lgt_ctx *c, const lgt_links *U, const double *X, double sca
     a.par = LGT_ODD;
     a.gate = GATE_NONE;
     a.l = site_launch(c->g.Vh);
-    a.fin = FIN_NONE;
+    a.hpi = c->hpi[f];
     LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
     LGT_HIP(launch_force(Xn, Yn, scale, G, c->g, c->stream));
     return LGT_OK;

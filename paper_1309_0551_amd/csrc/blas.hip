@@ -1,6 +1,8 @@
 // blas.hip -- the CG vector updates (Table 1: scalar_mult_add_su3_vector,
-// add_su3_vector) with fused FP64 reductions, and the solver's small kernels.
-// All are one thread per site (three complex numbers) and HBM-bound.
+// add_su3_vector) with fused FP64 partial sums, the one-workgroup finalize
+// kernel that turns partial sums into the solver's scalars, and the solver's
+// small kernels. The vector kernels are one thread per site (three complex
+// numbers) and HBM-bound.
 #include "fields.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
@@ -26,7 +28,7 @@ __global__ __launch_bounds__(kBS) void k_xpay(VecArgs a)
     VecFmt<T>::template store<false>(a.p, (size_t)a.Vh, cb, p);
 }
 
-// x += alpha p ; r -= alpha Ap ; partial |r|^2 (FP64) ; then rho, beta, convergence
+// x += alpha p ; r -= alpha Ap ; partial |r|^2 (FP64)
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
 {
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
         VecFmt<T>::template store<false>(a.x, (size_t)a.Vh, cb, x);
         VecFmt<T>::template store<false>(a.r, (size_t)a.Vh, cb, r);
     }
-    reduce_and_finalize(part, a.partials, a.st, blk, a.l.nblk, FIN_UPDATE);
+    write_partial(part, a.partials, blk);
 }
 
 hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
@@ -66,6 +68,26 @@ hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s)
 {
     if (f64) hipLaunchKernelGGL(k_update<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
     else hipLaunchKernelGGL(k_update<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    return hipGetLastError();
+}
+
+// Sum n partials in index order (fixed tree inside one workgroup, so the
+// result is bit-reproducible) and run the scalar step `fin`. Gated exactly
+// like the kernel that wrote the partials.
+__global__ __launch_bounds__(kBS) void k_finalize(const double *__restrict__ partials, int n, CgState *st, int fin,
+                                                  int gate)
+{
+    if (!gate_open(gate, st)) return;
+    __shared__ double lds[kBS / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBS) acc += partials[i];
+    const double tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) finalize(fin, st, tot);
+}
+
+hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBS), 0, s, partials, n, st, fin, gate);
     return hipGetLastError();
 }
 
@@ -128,7 +150,6 @@ __global__ void k_state_init(CgState *st, int scheme, int ru_fixed, int max_iter
     st->scheme = scheme;
     st->ru_fixed = ru_fixed;
     st->pad0 = st->pad1 = 0;
-    for (int i = 0; i < 4; i++) st->ctr[i] = 0;
 }
 
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol, double inner,
@@ -138,9 +159,8 @@ hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter
     return hipGetLastError();
 }
 
-// |b|^2 -> stop thresholds
-__global__ __launch_bounds__(kBS) void k_norm_init(const double *__restrict__ b, int Vh, double *partials, CgState *st,
-                                                   int nblk)
+// |b|^2 partials (the FIN_INIT step sets the stop thresholds)
+__global__ __launch_bounds__(kBS) void k_norm_parts(const double *__restrict__ b, int Vh, double *partials)
 {
     const int cb = blockIdx.x * kBS + threadIdx.x;
     double part = 0.0;
@@ -150,22 +170,24 @@ __global__ __launch_bounds__(kBS) void k_norm_init(const double *__restrict__ b,
 #pragma unroll
         for (int i = 0; i < 3; i++) part += v[i].re * v[i].re + v[i].im * v[i].im;
     }
-    reduce_and_finalize(part, partials, st, blockIdx.x, nblk, FIN_INIT);
+    write_partial(part, partials, blockIdx.x);
 }
 
 hipError_t launch_norm_init(const double *b64, int Vh, double *partials, CgState *st, hipStream_t s)
 {
     const int nblk = (Vh + kBS - 1) / kBS;
-    hipLaunchKernelGGL(k_norm_init, dim3(nblk), dim3(kBS), 0, s, b64, Vh, partials, st, nblk);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_norm_parts, dim3(nblk), dim3(kBS), 0, s, b64, Vh, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(partials, nblk, st, FIN_INIT, GATE_NONE, s);
 }
 
-// generic complex dot product sum conj(a) b, FP64, deterministic order
-__global__ __launch_bounds__(kBS) void k_cdot(int64_t n, const dv2 *__restrict__ a, const dv2 *__restrict__ b,
-                                              double *partials, unsigned int *ctr, double *result, int nblk)
+// generic complex dot product sum conj(a) b, FP64, fixed order: partials per
+// workgroup, then one workgroup sums them
+__global__ __launch_bounds__(kBS) void k_cdot_parts(int64_t n, const dv2 *__restrict__ a, const dv2 *__restrict__ b,
+                                                    double *partials, int nblk)
 {
     __shared__ double lds[kBS / 64];
-    __shared__ int amlast;
     double re = 0.0, im = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)nblk * kBS) {
         const dv2 x = a[i], y = b[i];
@@ -177,35 +199,34 @@ __global__ __launch_bounds__(kBS) void k_cdot(int64_t n, const dv2 *__restrict__
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = sr;
         partials[2 * blockIdx.x + 1] = si;
-        __threadfence();
-        const unsigned int t = atomicAdd(ctr, 1u);
-        amlast = (t == (unsigned int)(nblk - 1));
     }
-    __syncthreads();
-    if (!amlast) return;
-    __threadfence();
+}
+
+__global__ __launch_bounds__(kBS) void k_cdot_final(const double *__restrict__ partials, int nblk, double *result)
+{
+    __shared__ double lds[kBS / 64];
     double ar = 0.0, ai = 0.0;
     for (int i = threadIdx.x; i < nblk; i += kBS) {
-        ar += load_partial(&partials[2 * i]);
-        ai += load_partial(&partials[2 * i + 1]);
+        ar += partials[2 * i];
+        ai += partials[2 * i + 1];
     }
     const double tr = block_sum(ar, lds);
     const double ti = block_sum(ai, lds);
     if (threadIdx.x == 0) {
         result[0] = tr;
         result[1] = ti;
-        *ctr = 0;
     }
 }
 
-hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials, unsigned int *ctr,
-                       double *result, hipStream_t s)
+hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials, double *result, hipStream_t s)
 {
     int nblk = (int)((n + kBS - 1) / kBS);
     if (nblk > 1024) nblk = 1024;
     if (nblk < 1) nblk = 1;
-    hipLaunchKernelGGL(k_cdot, dim3(nblk), dim3(kBS), 0, s, n, (const dv2 *)a, (const dv2 *)b, partials, ctr,
-                       result, nblk);
+    hipLaunchKernelGGL(k_cdot_parts, dim3(nblk), dim3(kBS), 0, s, n, (const dv2 *)a, (const dv2 *)b, partials, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cdot_final, dim3(1), dim3(kBS), 0, s, partials, nblk, result);
     return hipGetLastError();
 }
 

@@ -15,6 +15,10 @@ struct lgt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int timing = 0;
+    // Dslash variant per link format: hops whose loads are issued together
+    // (8 = fully unrolled, 2 = one direction per loop trip, 1 = one hop).
+    // Set by lgt_set_dslash_variant or lgt_tune_dslash.
+    int hpi[lgt::FMT_COUNT] = {2, 2, 1, 1, 1};
     struct Buf {
         void *ptr = nullptr;
         size_t bytes = 0;

@@ -20,7 +20,7 @@ namespace lgt {
 // (256 VGPRs, one wave per SIMD); a runtime loop over directions (HPI = 2) or
 // over single hops (HPI = 1) bounds the loads in flight per thread and lets
 // more waves share each SIMD.
-template <class LF, int EPI, int FIN, int HPI>
+template <class LF, int EPI, int HPI>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
 {
     using T = typename LF::real;
@@ -118,31 +118,25 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
             }
         }
     }
-    if constexpr (FIN != FIN_NONE) reduce_and_finalize(part, a.partials, a.st, blk, a.l.nblk_pad, FIN);
+    if constexpr (EPI != EPI_PLAIN) write_partial(part, a.partials, blk);
 }
 
-template <class LF>
+template <class LF, int HPI>
 static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
 {
     const dim3 grid(a.l.nblk_pad), block(kBS);
     switch (epi) {
     case EPI_PLAIN:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, FIN_NONE, 8>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, HPI>), grid, block, 0, s, a);
         break;
     case EPI_A:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_A, FIN_ALPHA, 8>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<LF, EPI_A, HPI>), grid, block, 0, s, a);
         break;
     case EPI_RES:
     case EPI_RES_LO:
         if constexpr (std::is_same<typename LF::real, double>::value) {
-            if (epi == EPI_RES) {
-                if (a.fin == FIN_FINAL)
-                    hipLaunchKernelGGL((k_dslash<LF, EPI_RES, FIN_FINAL, 8>), grid, block, 0, s, a);
-                else
-                    hipLaunchKernelGGL((k_dslash<LF, EPI_RES, FIN_RU, 8>), grid, block, 0, s, a);
-            } else {
-                hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, FIN_RU, 8>), grid, block, 0, s, a);
-            }
+            if (epi == EPI_RES) hipLaunchKernelGGL((k_dslash<LF, EPI_RES, HPI>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, HPI>), grid, block, 0, s, a);
         } else {
             return hipErrorInvalidValue;
         }
@@ -153,14 +147,25 @@ static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <class LF>
+static hipError_t launch_hpi(int epi, const DslashArgs &a, hipStream_t s)
+{
+    switch (a.hpi) {
+    case 1: return launch_fmt<LF, 1>(epi, a, s);
+    case 2: return launch_fmt<LF, 2>(epi, a, s);
+    case 8: return launch_fmt<LF, 8>(epi, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s)
 {
     switch (f) {
-    case F64R18: return launch_fmt<LinkF64R18>(epi, a, s);
-    case F64R12: return launch_fmt<LinkF64R12>(epi, a, s);
-    case F32R18: return launch_fmt<LinkF32R18>(epi, a, s);
-    case F32R12: return launch_fmt<LinkF32R12>(epi, a, s);
-    case BF16R12: return launch_fmt<LinkBF16R12>(epi, a, s);
+    case F64R18: return launch_hpi<LinkF64R18>(epi, a, s);
+    case F64R12: return launch_hpi<LinkF64R12>(epi, a, s);
+    case F32R18: return launch_hpi<LinkF32R18>(epi, a, s);
+    case F32R12: return launch_hpi<LinkF32R12>(epi, a, s);
+    case BF16R12: return launch_hpi<LinkBF16R12>(epi, a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -29,12 +29,11 @@ struct CgState {
     double last_true;  // last FP64 true |r|^2
     int iter, updates, state, max_iter;
     int scheme, ru_fixed, pad0, pad1;
-    unsigned int ctr[4];
 };
 
 // Early-exit rule of a solver kernel, read from CgState at kernel start
 enum Gate { GATE_NONE = 0, GATE_ITER = 1, GATE_RU = 2 };
-// Finalize step done by the last workgroup of a reducing kernel
+// Scalar step that k_finalize runs on the partial sums of a reducing kernel
 enum Fin { FIN_NONE = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_RU = 3, FIN_INIT = 4, FIN_FINAL = 5 };
 
 struct Launch {
@@ -69,7 +68,7 @@ struct DslashArgs {
     double m4;
     double *partials;
     CgState *st;
-    int fin;
+    int hpi; // hops whose loads are issued together: 1, 2 or 8
 };
 
 hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s);
@@ -95,8 +94,10 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol,
                              double inner, hipStream_t s);
 hipError_t launch_norm_init(const double *b64, int Vh, double *partials, CgState *st, hipStream_t s);
-hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials,
-                       unsigned int *ctr, double *result, hipStream_t s);
+hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials, double *result,
+                       hipStream_t s);
+// sum n partials in order and run the scalar step `fin` (one workgroup)
+hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s);
 
 // ---- force (force.hip) -----------------------------------------------------
 hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,

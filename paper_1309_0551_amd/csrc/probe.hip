@@ -1,0 +1,41 @@
+// probe.hip -- plain device copy of a known size: the measured HBM ceiling
+// next to the 8 TB/s nominal one, and the reference whose FETCH_SIZE /
+// WRITE_SIZE counter readings scale the Dslash's counted traffic.
+#include <hip/hip_runtime.h>
+
+#include "ctx.hpp"
+#include "fields.hpp"
+
+namespace lgt {
+
+__global__ __launch_bounds__(kBS) void k_copy(const uv4 *__restrict__ src, uv4 *__restrict__ dst, size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * kBS;
+    for (size_t i = (size_t)blockIdx.x * kBS + threadIdx.x; i < n16; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+} // namespace lgt
+
+using namespace lgt;
+
+extern "C" lgt_status lgt_stream_copy(lgt_ctx *c, const void *src, void *dst, size_t bytes)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    lgt_status s;
+    if ((s = check_ptr(src, "src")) != LGT_OK) return s;
+    if ((s = check_ptr(dst, "dst")) != LGT_OK) return s;
+    if (bytes % 16) return fail(LGT_ERR_ARG, "bytes must be a multiple of 16");
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return LGT_OK;
+    const char *a = (const char *)src;
+    const char *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes) return fail(LGT_ERR_ARG, "src and dst overlap");
+    DeviceScope ds(c->device);
+    size_t blocks = (n16 + kBS - 1) / kBS;
+    if (blocks > 256 * 64) blocks = 256 * 64; // 64 workgroups per CU, grid-stride beyond
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBS), 0, c->stream, (const uv4 *)src, (uv4 *)dst, n16);
+    LGT_HIP(hipGetLastError());
+    return LGT_OK;
+}

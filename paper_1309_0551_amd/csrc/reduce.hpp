@@ -29,13 +29,6 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return s;
 }
 
-// relaxed device-scope load of a partial written by another workgroup
-__device__ __forceinline__ double load_partial(const double *p)
-{
-    return __longlong_as_double(
-        (long long)__atomic_load_n((const unsigned long long *)p, __ATOMIC_RELAXED));
-}
-
 __device__ __forceinline__ bool gate_open(int gate, const CgState *st)
 {
     if (gate == GATE_NONE) return true;
@@ -99,31 +92,16 @@ __device__ inline void finalize(int fin, CgState *st, double sum)
     }
 }
 
-// Write this workgroup's partial; the last workgroup reduces all partials in
-// order and runs the finalize step. `blk` is the logical workgroup index,
-// `nparts` the number of workgroups taking part.
-__device__ inline void reduce_and_finalize(double v, double *partials, CgState *st, int blk,
-                                           int nparts, int fin)
+// Write this workgroup's partial sum (logical workgroup index `blk`). The sum
+// over workgroups and the scalar step run in k_finalize, launched next on the
+// same stream: the kernel boundary makes the partials visible to it, which is
+// far cheaper than a device-scope fence in every workgroup (on a multi-XCD
+// part such a fence writes back the workgroup's whole L2).
+__device__ __forceinline__ void write_partial(double v, double *partials, int blk)
 {
     __shared__ double lds[kBS / 64];
-    __shared__ int amlast;
     const double s = block_sum(v, lds);
-    if (threadIdx.x == 0) {
-        partials[blk] = s;
-        __threadfence();
-        const unsigned int t = atomicAdd(&st->ctr[0], 1u);
-        amlast = (t == (unsigned int)(nparts - 1));
-    }
-    __syncthreads();
-    if (!amlast) return;
-    __threadfence();
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kBS) acc += load_partial(&partials[i]);
-    const double tot = block_sum(acc, lds);
-    if (threadIdx.x == 0) {
-        st->ctr[0] = 0;
-        finalize(fin, st, tot);
-    }
+    if (threadIdx.x == 0) partials[blk] = s;
 }
 
 } // namespace lgt

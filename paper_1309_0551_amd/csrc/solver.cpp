@@ -96,8 +96,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     LGT_HIP(evs.make(4)); // 0 start, 1 end, 2/3 chunk slots
     if (timing) LGT_HIP(tev.make((size_t)2 * 2 * pairs));
 
+    // Dslash launch; the reducing epilogues (EPI_A, EPI_RES*) leave one
+    // partial sum per workgroup for the finalize kernel that follows.
     auto D = [&](Fmt f, int epi, int par, const void *U, const void *in, void *out, int gate, const void *aux0,
-                 const void *aux1, void *out_lo, int fin) {
+                 const void *aux1, void *out_lo) {
         DslashArgs a;
         a.U = U;
         a.in = in;
@@ -112,9 +114,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.m4 = m4;
         a.partials = partials;
         a.st = dst;
-        a.fin = fin;
+        a.hpi = c->hpi[f];
         return launch_dslash(f, epi, a, s);
     };
+    auto F = [&](int fin, int gate, int nparts) { return launch_finalize(partials, nparts, dst, fin, gate, s); };
     auto timed = [&](int slot, int idx, bool begin) -> hipError_t {
         if (!timing) return hipSuccess;
         return hipEventRecord(tev.ev[((size_t)slot * pairs + idx) * 2 + (begin ? 0 : 1)], s);
@@ -135,19 +138,19 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         hipError_t e = hipSuccess;
         if (mixed && (e = launch_ru_accum(x64, xlo, Vh, dst, gate, s)) != hipSuccess) return e;
         if (slot >= 0 && (e = timed(slot, 2 * chunk, true)) != hipSuccess) return e;
-        if ((e = D(fhi, EPI_PLAIN, LGT_ODD, Uhi->ptr, x64, t64, gate, nullptr, nullptr, nullptr, FIN_NONE)) != hipSuccess)
+        if ((e = D(fhi, EPI_PLAIN, LGT_ODD, Uhi->ptr, x64, t64, gate, nullptr, nullptr, nullptr)) != hipSuccess)
             return e;
         if (slot >= 0 && (e = timed(slot, 2 * chunk, false)) != hipSuccess) return e;
         if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, true)) != hipSuccess) return e;
         if (fin == FIN_FINAL)
-            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, q64, gate, x64, b64, nullptr, FIN_FINAL);
+            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, q64, gate, x64, b64, nullptr);
         else if (mixed)
-            e = D(fhi, EPI_RES_LO, LGT_EVEN, Uhi->ptr, t64, nullptr, gate, x64, b64, r, FIN_RU);
+            e = D(fhi, EPI_RES_LO, LGT_EVEN, Uhi->ptr, t64, nullptr, gate, x64, b64, r);
         else
-            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr, FIN_RU);
+            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr);
         if (e != hipSuccess) return e;
         if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, false)) != hipSuccess) return e;
-        return hipSuccess;
+        return F(fin, gate, l.nblk_pad);
     };
 
     LGT_HIP(hipEventRecord(evs.ev[0], s));
@@ -205,13 +208,14 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
             LGT_HIP(launch_xpay(lo_is_f64, va, s));
             LGT_HIP(timed(slot, 2 * i, true));
             LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, mixed ? Ulo->ptr : Uhi->ptr, pp, t, GATE_ITER, nullptr, nullptr,
-                      nullptr, FIN_NONE));
+                      nullptr));
             LGT_HIP(timed(slot, 2 * i, false));
             LGT_HIP(timed(slot, 2 * i + 1, true));
-            LGT_HIP(D(flo, EPI_A, LGT_EVEN, mixed ? Ulo->ptr : Uhi->ptr, t, Ap, GATE_ITER, pp, nullptr, nullptr,
-                      FIN_ALPHA));
+            LGT_HIP(D(flo, EPI_A, LGT_EVEN, mixed ? Ulo->ptr : Uhi->ptr, t, Ap, GATE_ITER, pp, nullptr, nullptr));
             LGT_HIP(timed(slot, 2 * i + 1, false));
+            LGT_HIP(F(FIN_ALPHA, GATE_ITER, l.nblk_pad));
             LGT_HIP(launch_update(lo_is_f64, va, s));
+            LGT_HIP(F(FIN_UPDATE, GATE_ITER, l.nblk));
         }
         LGT_HIP(reliable(GATE_RU, timing ? slot : -1, FIN_RU));
         LGT_HIP(hipMemcpyAsync(host + slot, dst, sizeof(CgState), hipMemcpyDeviceToHost, s));

@@ -107,6 +107,10 @@ def _setup(l):
                               C.POINTER(_CgResult)]),
         "lgt_cdot": (st, [vp, C.c_int64, vp, vp, C.POINTER(C.c_double)]),
         "lgt_force": (st, [vp, C.POINTER(_Links), vp, C.c_double, vp]),
+        "lgt_set_dslash_variant": (st, [vp, i32, i32, i32]),
+        "lgt_get_dslash_variant": (st, [vp, i32, i32, C.POINTER(C.c_int32)]),
+        "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),
+        "lgt_stream_copy": (st, [vp, vp, vp, C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -221,6 +225,24 @@ class Lattice:
     def set_timing(self, on: bool):
         _check(lib().lgt_set_timing(self._ctx, int(bool(on))))
 
+    def set_dslash_variant(self, prec: int, recon: int, hops: int):
+        _check(lib().lgt_set_dslash_variant(self._ctx, prec, recon, hops))
+
+    def dslash_variant(self, prec: int, recon: int) -> int:
+        v = C.c_int32()
+        _check(lib().lgt_get_dslash_variant(self._ctx, prec, recon, C.byref(v)))
+        return int(v.value)
+
+    def tune_dslash(self, U: "PackedLinks", report: bool = True):
+        """Time the variants {8, 2, 1} on U and keep the fastest; returns {hops: us} or None."""
+        d = U.desc()
+        if not report:
+            _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), None))
+            return None
+        t = (C.c_double * 3)()
+        _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), t))
+        return {8: t[0], 2: t[1], 1: t[2]}
+
     # -- helpers
     def _dev(self, t: torch.Tensor, dtype=None, shape=None, what="tensor"):
         if t.device != self.device:
@@ -293,6 +315,14 @@ class Lattice:
         if st != 0 and (raise_on_fail or st not in (-5, -6)):
             _check(st)
         return x, r
+
+    def stream_copy(self, src: torch.Tensor, dst: torch.Tensor):
+        """dst[:] = src[:] with the library's streaming copy kernel (bandwidth probe)."""
+        n = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() < n:
+            raise ValueError("dst too small")
+        _check(lib().lgt_stream_copy(self._ctx, self._dev(src, None, None, "src"),
+                                     self._dev(dst, None, None, "dst"), n))
 
     def cdot(self, a: torch.Tensor, b: torch.Tensor) -> complex:
         if a.numel() != b.numel() or a.numel() % 2:

@@ -91,6 +91,47 @@ def test_dslash_parity(dev, fmt, L, bc, kind):
                 assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+@pytest.mark.parametrize("hops", [1, 2, 8])
+def test_dslash_every_variant(dev, fmt, hops):
+    """Each kernel variant (loads of 1, 2 or 8 hops issued together) gives the same operator."""
+    prec, recon, tol = FMTS[fmt]
+    L, bc = (6, 4, 6, 8), (1, 1, 1, -1)
+    U = li.links(L, "haar", 121)
+    chi = li.vector(L, 122)
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        lat.set_dslash_variant(prec, recon, hops)
+        assert lat.dslash_variant(prec, recon) == hops
+        x = lat.pack_vec(_t(chi, dev), vp)
+        got = lat.unpack_vec(lat.dslash(Up, x, 0), vp).cpu().numpy()
+        lat.set_dslash_variant(prec, recon, 8)
+        ref8 = lat.unpack_vec(lat.dslash(Up, x, 0), vp).cpu().numpy()
+    ref = oracle.dslash(L, U, chi, 0, bc)
+    assert _rel(got, ref) <= tol
+    if prec == P.LGT_F64:
+        assert _rel(got, ref8) <= 1e-15
+
+
+def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 131)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LGT_TUNE_CACHE", str(cache))
+    with P.Lattice(L) as lat:
+        Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        t = lat.tune_dslash(Up)
+        assert set(t) == {1, 2, 8} and all(v > 0 for v in t.values())
+        best = min(t, key=t.get)
+        assert lat.dslash_variant(P.LGT_F32, P.LGT_R12) == best
+    assert "f32r12" in cache.read_text()
+    with P.Lattice(L) as lat2:
+        lat2.set_dslash_variant(P.LGT_F32, P.LGT_R12, 8 if best != 8 else 1)
+        lat2.tune_dslash(Up, report=False)  # cached: no timing
+        assert lat2.dslash_variant(P.LGT_F32, P.LGT_R12) == best
+
+
 def test_dslash_full_size_32(dev):
     """32^4 Haar, FP64, the benchmark's launch configuration: every output site."""
     L = (32, 32, 32, 32)
@@ -266,3 +307,14 @@ def test_autograd_action_vs_oracle(dev):
     kappa = (4 * (mass ** 2) + 64) / (4 * mass ** 2)
     assert _rel(Ut.grad.cpu().numpy(), 2.5 * Go) <= kappa * 1e-13 * 10
     np.testing.assert_allclose(pt.grad.cpu().numpy(), 2.5 * 2 * Xo, atol=1e-8 * np.abs(Xo).max())
+
+
+def test_stream_copy(dev):
+    with P.Lattice((4, 4, 4, 4)) as lat:
+        src = torch.randn(1 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        lat.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+        with pytest.raises(P.LgtError):
+            lat.stream_copy(src[1:], dst[1:])  # 8-byte offset: misaligned

@@ -1,18 +1,24 @@
 """Benchmark: staggered Dslash GB/s / GFLOP/s at 32^4 and mixed-vs-FP64 CG time to 1e-10.
 
-One step = the whole hot path on the 32^4 workload (Haar SU(3) links, m = 0.01,
-one Gaussian source, x0 = 0, stop at 1e-10 true relative residual):
+Workload: 32^4 lattice, Haar-random SU(3) links, m = 0.01, one Gaussian source
+on the even sites, x0 = 0, stop at 1e-10 true relative residual.
+
+One step = the whole hot path on that workload:
   1. FP64 even-odd CG (FP64 links and vectors),
   2. mixed CG: FP32 12-real links, FP32 vectors, FP64 reliable update every 50,
-  3. mixed CG: BF16 12-real links, FP32 vectors, FP64 iterative refinement (inner 0.1).
-`value` is the FP64 Dslash bandwidth (algorithmic bytes / kernel time), measured
-with HIP events around every FP64 Dslash launch inside the timed FP64 solves
-(the library records them on its stream). Inputs are resident in HBM before the
-timed region; link packing is done once per gauge field, outside it.
+  3. mixed CG: BF16 12-real links, FP32 vectors, FP64 iterative refinement
+     (inner relative tolerance 0.1).
+`value` is the FP64 Dslash bandwidth in algorithmic bytes (8 links + the
+input vector read once + the output written once per site) over the kernel
+time, where the kernel time is measured with HIP events that the library
+records on its own stream around every FP64 Dslash launch inside the timed
+FP64 solves. Inputs are resident in HBM before the timed region; link packing
+is done once per gauge field, outside it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -24,10 +30,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Dslash GB/s & GFLOP/s at 32^4; mixed-vs-FP64 CG time to 1e-10 residual"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f64r18_32x32x32x32_traffic.txt")
+KERNEL_SOURCES = ["paper_1309_0551_amd/csrc/dslash.hip", "paper_1309_0551_amd/csrc/fields.hpp",
+                  "paper_1309_0551_amd/csrc/geom.hpp", "paper_1309_0551_amd/csrc/reduce.hpp"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Counted HBM bytes per FP64 Dslash launch from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and not line.lstrip().startswith("#"):
+                    k, v = line.split("=", 1)
+                    vals[k.strip()] = v.strip()
+        if vals.get("kernel_source_sha") != kernel_source_sha():
+            return None
+        return int(float(vals["bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def alg_bytes_per_site(prec, recon):
@@ -37,31 +71,44 @@ def alg_bytes_per_site(prec, recon):
     return 8 * P.link_bytes_per_dir(prec, recon) + 2 * P.vec_bytes_per_site(prec)
 
 
-def time_dslash(lat, Up, x, out, n=20, warm=5):
+def event_times(lat, fn, n, warm):
     import torch
-    s = lat.stream
     for _ in range(warm):
-        lat.dslash(Up, x, 1, out)
+        fn()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
     for a, b in evs:
-        a.record(s)
-        lat.dslash(Up, x, 1, out)
-        b.record(s)
+        a.record(lat.stream)
+        fn()
+        b.record(lat.stream)
     torch.cuda.synchronize()
     return [a.elapsed_time(b) for a, b in evs]
 
 
-def cpu_baseline(L, U, chi, budget_s=15.0):
+def probes(lat):
+    """Measured streaming ceilings: read-only and copy of 1 GiB, median of 10."""
+    import torch
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device=lat.device)
+    dst = torch.empty_like(src)
+    sink = torch.zeros(2, dtype=torch.float64, device=lat.device)
+    rd = statistics.median(event_times(lat, lambda: lat.stream_read(src, sink), 10, 3))
+    cp = statistics.median(event_times(lat, lambda: lat.stream_copy(src, dst), 10, 3))
+    nb = n * 8
+    del src, dst
+    return {"read_GBps": round(nb / (rd * 1e-3) / 1e9, 1), "copy_GBps": round(2 * nb / (cp * 1e-3) / 1e9, 1),
+            "bytes": nb}
+
+
+def cpu_baseline(L, U, chi, budget_s):
     import oracle
-    oracle.dslash(L, U, chi, 1)  # warm (page in, thread pool)
+    oracle.dslash(L, U, chi, 1)  # warm: page in, start the thread pool
     n, t0 = 0, time.perf_counter()
     while True:
         oracle.dslash(L, U, chi, 1)
         n += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
-            break
-    return n, el
+        if el >= budget_s:
+            return n, el
 
 
 def main():
@@ -72,11 +119,12 @@ def main():
     ap.add_argument("--L", type=int, nargs=4, default=(32, 32, 32, 32))
     ap.add_argument("--mass", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in Dslash variants")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path (the domain-decomposed "
+              "design is described in DESIGN.md); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -95,49 +143,47 @@ def main():
     log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
 
     lat = P.Lattice(L, device=0)
+    ceil = probes(lat)
+    log(f"probes {ceil}")
     Ut = torch.from_numpy(U).to(dev)
     bt = torch.from_numpy(b).to(dev)
-    U64 = lat.pack_links(Ut, P.LGT_F64, P.LGT_R18)
-    U32 = lat.pack_links(Ut, P.LGT_F32, P.LGT_R12)
-    U16 = lat.pack_links(Ut, P.LGT_BF16, P.LGT_R12)
+    formats = {"f64r18": (P.LGT_F64, P.LGT_R18), "f64r12": (P.LGT_F64, P.LGT_R12),
+               "f32r18": (P.LGT_F32, P.LGT_R18), "f32r12": (P.LGT_F32, P.LGT_R12),
+               "bf16r12": (P.LGT_BF16, P.LGT_R12)}
+    packed = {k: lat.pack_links(Ut, *v) for k, v in formats.items()}
     del Ut
     torch.cuda.synchronize()
 
-    # standalone Dslash, every format (context numbers; `value` comes from the solves)
-    fmts = {"f64r18": U64, "f64r12": None, "f32r18": None, "f32r12": U32, "bf16r12": U16}
+    # standalone Dslash per format (context; `value` comes from the solves)
     dslash = {}
-    for name, Up in fmts.items():
-        if Up is None:
-            prec = P.LGT_F64 if name.startswith("f64") else P.LGT_F32
-            Up = lat.pack_links(torch.from_numpy(U).to(dev), prec, int(name[-2:]))
+    for name, Up in packed.items():
+        tune = None if args.no_tune else lat.tune_dslash(Up)
         vp = P.LGT_F64 if Up.prec == P.LGT_F64 else P.LGT_F32
         x = lat.pack_vec(bt, vp)
         out = lat.native_vec(vp)
-        ms = statistics.median(time_dslash(lat, Up, x, out))
+        ms = statistics.median(event_times(lat, lambda: lat.dslash(Up, x, 1, out), 20, 5))
         by = alg_bytes_per_site(Up.prec, Up.recon) * Vh
         dslash[name] = {"us": round(ms * 1e3, 2), "GBps": round(by / (ms * 1e-3) / 1e9, 1),
                         "GFLOPs": round(P.DSLASH_FLOP_PER_SITE * Vh / (ms * 1e-3) / 1e9, 1),
-                        "alg_bytes": by}
+                        "alg_bytes": by, "variant": "hops=%d streaming=%d" % lat.dslash_variant(Up.prec, Up.recon),
+                        "tune_us": {"%d/%d" % k: round(v, 2) for k, v in tune.items()} if tune else None}
         log(f"dslash {name}: {dslash[name]}")
 
-    def solves(timing):
-        lat.set_timing(timing)
+    def solves():
         out = {}
-        x, r = lat.cg_solve(U64, bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
-        out["fp64"] = r
-        x, r = lat.cg_solve(U64, bt, args.mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE, U_lo=U32, ru_interval=50)
-        out["f32r12_reliable"] = r
-        x, r = lat.cg_solve(U64, bt, args.mass, tol=1e-10, scheme=P.LGT_CG_REFINE, U_lo=U16, inner_tol=0.1)
-        out["bf16r12_refine"] = r
+        _, out["fp64"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
+        _, out["f32r12_reliable"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10,
+                                                 scheme=P.LGT_CG_RELIABLE, U_lo=packed["f32r12"], ru_interval=50)
+        _, out["bf16r12_refine"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10,
+                                                scheme=P.LGT_CG_REFINE, U_lo=packed["bf16r12"], inner_tol=0.1)
         return out
 
+    lat.set_timing(True)
     for _ in range(args.warmup):
-        solves(True)
+        solves()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    steps = []
-    for _ in range(args.steps):
-        steps.append(solves(True))
+    steps = [solves() for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     lat.set_timing(False)
@@ -151,11 +197,11 @@ def main():
 
     def summ(key):
         rs = [s[key] for s in steps]
+        n = max(1, sum(r.dslash_timed_lo + r.dslash_timed_hi for r in rs))
         return {"seconds_median": round(statistics.median(r.seconds for r in rs), 4),
                 "iters": rs[-1].iters, "updates": rs[-1].updates, "dslash_calls": rs[-1].dslash_calls,
                 "true_rel_resid": rs[-1].true_rel_resid, "status": rs[-1].status,
-                "dslash_us_avg": round(1e3 * sum(r.dslash_ms_lo + r.dslash_ms_hi for r in rs) /
-                                       max(1, sum(r.dslash_timed_lo + r.dslash_timed_hi for r in rs)), 2)}
+                "dslash_us_avg": round(1e3 * sum(r.dslash_ms_lo + r.dslash_ms_hi for r in rs) / n, 2)}
 
     cg = {k: summ(k) for k in ("fp64", "f32r12_reliable", "bf16r12_refine")}
     cg["speedup_f32_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["f32r12_reliable"]["seconds_median"], 3)
@@ -167,21 +213,25 @@ def main():
         n, el = cpu_baseline(L, U, b, args.cpu_budget)
         cpu = {"value": round(by64 * n / el / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(),
                "kind": "oracle",
-               "sample": f"{n} FP64 D_oe applications of the oracle at {'x'.join(map(str, L))} "
-                         f"({el:.1f} s), algorithmic bytes as for the GPU"}
+               "sample": f"{n} FP64 D_oe applications of the C oracle (OpenMP) at {'x'.join(map(str, L))} "
+                         f"in {el:.1f} s; same algorithmic bytes per application as the GPU kernel"}
 
+    traffic = measured_traffic()
     line = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"staggered Dslash + even-odd CG, {'x'.join(map(str, L))} lattice, Haar SU(3) "
-                               f"links, m={args.mass}, tol 1e-10; step = FP64 CG + FP32-12 reliable CG + "
-                               f"BF16-12 refinement CG", "lattice": list(L), "mass": args.mass},
+        "config": {"workload": f"staggered Dslash in even-odd CG, {'x'.join(map(str, L))} lattice, Haar SU(3) "
+                               f"links, m={args.mass}, tol 1e-10; step = FP64 CG + FP32-12 reliable-update CG "
+                               f"+ BF16-12 refinement CG", "lattice": list(L), "mass": args.mass},
         "gflops": round(gflops, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_dslash<LinkF64R18, EPI_A|EPI_PLAIN> inside FP64 CG",
-                     "alg_bytes_per_launch": by64, "avg_launch_us": round(avg_ms * 1e3, 2)},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
+                     "traffic_bytes_per_launch": traffic,
+                     "kernel": "k_dslash<LinkF64R18,*> (FP64 D_oe and D_eo+<p,Ap>) inside the FP64 CG",
+                     "alg_bytes_per_launch": by64, "avg_launch_us": round(avg_ms * 1e3, 2),
+                     "launches_timed": n_hi, "measured_ceiling_GBps": ceil},
         "cg": cg,
         "dslash_standalone": dslash,
         "cpu_baseline": cpu,

@@ -111,19 +111,24 @@ lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t enable);
 /* ---- kernel variants and autotuning ---------------------------------------- */
 
 /* The Dslash comes in variants that issue the loads of 8, 2 or 1 hops
- * together (more loads in flight per thread against more waves per SIMD).
- * The choice is per link format and per context; it changes speed only, never
- * results. hops_per_group must be 1, 2 or 8. */
-lgt_status lgt_set_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t hops_per_group);
-lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *hops_per_group);
-/* Time every variant on U (2 warm-up and 10 timed launches each, on the
- * context's stream; synchronises) and keep the fastest for U's format.
- * times_us (host, may be NULL) receives the mean launch time of variants
- * {8, 2, 1}. When the environment variable LGT_TUNE_CACHE names a file and
+ * together (more loads in flight per thread against more waves per SIMD), with
+ * link loads that either stream past the caches (streaming = 1, the default)
+ * or are cached (0: a link field that fits in the Infinity Cache may be served
+ * from it on the next call). The choice is per link format and per context;
+ * it changes speed only, never results. hops_per_group must be 1, 2 or 8. */
+lgt_status lgt_set_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t hops_per_group,
+                                  int32_t streaming);
+lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *hops_per_group,
+                                  int32_t *streaming);
+/* Time every variant on U (2 warm-up and 10 timed launches each, alternating
+ * the output parity, on the context's stream; synchronises) and keep the
+ * fastest for U's format. times_us (host, may be NULL) receives the mean
+ * launch time of the variants (hops, streaming) = (8,1) (2,1) (1,1) (8,0)
+ * (2,0) (1,0). When the environment variable LGT_TUNE_CACHE names a file and
  * times_us is NULL, a cached choice for (device architecture, lattice,
  * format) is used without timing unless LGT_TUNE=force; new results are
  * appended to that file. */
-lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[3]);
+lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[6]);
 
 /* ---- geometry export (Sec. 1: unique 4-tuple per site, 8 neighbours) ------- */
 
@@ -220,6 +225,11 @@ lgt_status lgt_force(lgt_ctx *ctx, const lgt_links *U, const double *X, double s
  * (the paper ties the routines' speed to memory bandwidth, Sec. 5); it also
  * calibrates hardware byte counters. Asynchronous. */
 lgt_status lgt_stream_copy(lgt_ctx *ctx, const void *src, void *dst, size_t bytes);
+/* Read `bytes` (a multiple of 16) of src with the same streaming loads and
+ * write nothing (sink: 16 bytes of device memory that is written only for one
+ * improbable data pattern). The read-only ceiling for read-dominated kernels
+ * such as the Dslash. Asynchronous. */
+lgt_status lgt_stream_read(lgt_ctx *ctx, const void *src, size_t bytes, void *sink);
 
 #ifdef __cplusplus
 }

@@ -319,6 +319,7 @@ lgt_status lgt_dslash(lgt_ctx *c, const lgt_links *U, int32_t out_parity, const 
     a.gate = GATE_NONE;
     a.l = site_launch(c->g.Vh);
     a.hpi = c->hpi[f];
+    a.ntl = c->ntl[f];
     LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
     return LGT_OK;
 }
@@ -393,6 +394,7 @@ lgt_status lgt_force(lgt_ctx *c, const lgt_links *U, const double *X, double sca
     a.gate = GATE_NONE;
     a.l = site_launch(c->g.Vh);
     a.hpi = c->hpi[f];
+    a.ntl = c->ntl[f];
     LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
     LGT_HIP(launch_force(Xn, Yn, scale, G, c->g, c->stream));
     return LGT_OK;

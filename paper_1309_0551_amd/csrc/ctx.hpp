@@ -17,8 +17,13 @@ struct lgt_ctx {
     int timing = 0;
     // Dslash variant per link format: hops whose loads are issued together
     // (8 = fully unrolled, 2 = one direction per loop trip, 1 = one hop).
+    // and whether link loads stream past the caches (1) or are cached (0).
     // Set by lgt_set_dslash_variant or lgt_tune_dslash.
-    int hpi[lgt::FMT_COUNT] = {2, 2, 1, 1, 1};
+    // Defaults measured on MI355X at 32^4: FP64 fields (604 / 403 MB) stream;
+    // FP32 and BF16 fields are cached (at 32^4 the 12-real ones fit in the
+    // 256 MB Infinity Cache: FP32x12 42 -> 34 us, BF16x12 25 -> 20 us).
+    int hpi[lgt::FMT_COUNT] = {2, 2, 8, 8, 8};
+    int ntl[lgt::FMT_COUNT] = {1, 1, 0, 0, 0};
     struct Buf {
         void *ptr = nullptr;
         size_t bytes = 0;

@@ -20,7 +20,7 @@ namespace lgt {
 // (256 VGPRs, one wave per SIMD); a runtime loop over directions (HPI = 2) or
 // over single hops (HPI = 1) bounds the loads in flight per thread and lets
 // more waves share each SIMD.
-template <class LF, int EPI, int HPI>
+template <class LF, int EPI, int HPI, bool NTL>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
 {
     using T = typename LF::real;
@@ -41,13 +41,13 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
             for (int mu = 0; mu < 4; mu++) {
                 cx<T> u[9], v[3];
                 // forward hop: U_mu(x) in(x+mu)
-                LF::template load<true>(a.U, Vh, a.par * 4 + mu, cb, u);
+                LF::template load<NTL>(a.U, Vh, a.par * 4 + mu, cb, u);
                 VF::template load<false>(a.in, Vh, nbr_fwd(a.g, c, cb, mu), v);
                 negate_if(fwd_neg(a.g, c, mu), v);
                 mv_add(u, v, acc);
                 // backward hop: U_mu(x-mu)^dag in(x-mu)
                 const int b = nbr_bwd(a.g, c, cb, mu);
-                LF::template load<true>(a.U, Vh, (1 - a.par) * 4 + mu, b, u);
+                LF::template load<NTL>(a.U, Vh, (1 - a.par) * 4 + mu, b, u);
                 VF::template load<false>(a.in, Vh, b, v);
                 negate_if(bwd_neg(a.g, c, mu), v);
                 amv_sub(u, v, acc);
@@ -57,9 +57,9 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
             for (int mu = 0; mu < 4; mu++) {
                 const Hop h = hop_rt(a.g, c, cb, mu);
                 cx<T> u[9], v[3], w[9], z[3];
-                LF::template load<true>(a.U, Vh, a.par * 4 + mu, cb, u);
+                LF::template load<NTL>(a.U, Vh, a.par * 4 + mu, cb, u);
                 VF::template load<false>(a.in, Vh, h.f, v);
-                LF::template load<true>(a.U, Vh, (1 - a.par) * 4 + mu, h.b, w);
+                LF::template load<NTL>(a.U, Vh, (1 - a.par) * 4 + mu, h.b, w);
                 VF::template load<false>(a.in, Vh, h.b, z);
                 negate_if(h.fneg, v);
                 mv_add(u, v, acc);
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 const bool fwd = !(hop & 1);
                 const Hop h = hop_rt(a.g, c, cb, mu);
                 cx<T> u[9], v[3];
-                LF::template load<true>(a.U, Vh, fwd ? a.par * 4 + mu : (1 - a.par) * 4 + mu, fwd ? cb : h.b, u);
+                LF::template load<NTL>(a.U, Vh, fwd ? a.par * 4 + mu : (1 - a.par) * 4 + mu, fwd ? cb : h.b, u);
                 VF::template load<false>(a.in, Vh, fwd ? h.f : h.b, v);
                 negate_if(fwd ? h.fneg : h.bneg, v);
                 if (fwd) mv_add(u, v, acc);
@@ -121,22 +121,22 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
     if constexpr (EPI != EPI_PLAIN) write_partial(part, a.partials, blk);
 }
 
-template <class LF, int HPI>
+template <class LF, int HPI, bool NTL>
 static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
 {
     const dim3 grid(a.l.nblk_pad), block(kBS);
     switch (epi) {
     case EPI_PLAIN:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, HPI>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, HPI, NTL>), grid, block, 0, s, a);
         break;
     case EPI_A:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_A, HPI>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<LF, EPI_A, HPI, NTL>), grid, block, 0, s, a);
         break;
     case EPI_RES:
     case EPI_RES_LO:
         if constexpr (std::is_same<typename LF::real, double>::value) {
-            if (epi == EPI_RES) hipLaunchKernelGGL((k_dslash<LF, EPI_RES, HPI>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, HPI>), grid, block, 0, s, a);
+            if (epi == EPI_RES) hipLaunchKernelGGL((k_dslash<LF, EPI_RES, HPI, NTL>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, HPI, NTL>), grid, block, 0, s, a);
         } else {
             return hipErrorInvalidValue;
         }
@@ -147,15 +147,26 @@ static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <class LF, bool NTL>
+static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s)
+{
+    switch (a.hpi) {
+    case 1: return launch_fmt<LF, 1, NTL>(epi, a, s);
+    case 2: return launch_fmt<LF, 2, NTL>(epi, a, s);
+    case 8: return launch_fmt<LF, 8, NTL>(epi, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Variant = (hops whose loads issue together, streaming or cached link loads).
+// Streaming (non-temporal) link loads keep a link field that is far larger
+// than the caches from evicting the input vector; a field that fits in the
+// 256 MB Infinity Cache (FP32/BF16 12-real at 32^4) may instead stay there
+// from one Dslash to the next with cached loads.
 template <class LF>
 static hipError_t launch_hpi(int epi, const DslashArgs &a, hipStream_t s)
 {
-    switch (a.hpi) {
-    case 1: return launch_fmt<LF, 1>(epi, a, s);
-    case 2: return launch_fmt<LF, 2>(epi, a, s);
-    case 8: return launch_fmt<LF, 8>(epi, a, s);
-    default: return hipErrorInvalidValue;
-    }
+    return a.ntl ? launch_hpi_ntl<LF, true>(epi, a, s) : launch_hpi_ntl<LF, false>(epi, a, s);
 }
 
 hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s)

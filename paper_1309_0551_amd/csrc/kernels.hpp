@@ -69,6 +69,7 @@ struct DslashArgs {
     double *partials;
     CgState *st;
     int hpi; // hops whose loads are issued together: 1, 2 or 8
+    int ntl; // 1: streaming (non-temporal) link loads, 0: cached
 };
 
 hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s);

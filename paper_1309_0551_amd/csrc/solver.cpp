@@ -115,6 +115,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.partials = partials;
         a.st = dst;
         a.hpi = c->hpi[f];
+        a.ntl = c->ntl[f];
         return launch_dslash(f, epi, a, s);
     };
     auto F = [&](int fin, int gate, int nparts) { return launch_finalize(partials, nparts, dst, fin, gate, s); };

@@ -1,9 +1,11 @@
 // tune.cpp -- choice of the Dslash kernel variant per link format.
 //
 // The variants differ in how many hops' loads are issued together (8, 2 or
-// 1): more loads in flight per thread against fewer registers and more waves
-// per SIMD. Which wins depends on the format and the lattice, so it is timed
-// on the caller's own link field and kept in the context; with the
+// 1: more loads in flight per thread against fewer registers and more waves
+// per SIMD) and in whether link loads stream past the caches or are cached
+// (a link field that fits in the Infinity Cache can then be served from it on
+// the next Dslash). Which wins depends on the format and the lattice, so it is
+// timed on the caller's own link field and kept in the context; with the
 // environment variable LGT_TUNE_CACHE naming a file, results persist per
 // (device architecture, lattice, format) and later contexts reuse them
 // (LGT_TUNE=force re-times).
@@ -22,7 +24,9 @@ using namespace lgt;
 
 namespace {
 
-const int kVariants[3] = {8, 2, 1};
+constexpr int kNumVariants = 6;
+const int kHops[kNumVariants] = {8, 2, 1, 8, 2, 1};
+const int kStream[kNumVariants] = {1, 1, 1, 0, 0, 0};
 
 const char *fmt_name(Fmt f)
 {
@@ -49,57 +53,68 @@ std::string cache_key(lgt_ctx *c, Fmt f)
     return k.str();
 }
 
-int cache_lookup(const std::string &key)
+// "<key> <hops> <stream> ..." ; the last matching line wins
+bool cache_lookup(const std::string &key, int *hops, int *stream)
 {
     const char *path = std::getenv("LGT_TUNE_CACHE");
-    if (!path) return 0;
+    if (!path) return false;
     std::ifstream in(path);
     std::string line;
-    int found = 0;
+    bool found = false;
     while (std::getline(in, line)) {
-        if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() && line[key.size()] == ' ') {
-            const int v = std::atoi(line.c_str() + key.size() + 1);
-            if (v == 1 || v == 2 || v == 8) found = v; // last entry wins
+        if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
+        std::istringstream rest(line.substr(key.size() + 1));
+        int h = 0, s = -1;
+        rest >> h >> s;
+        if ((h == 1 || h == 2 || h == 8) && (s == 0 || s == 1)) {
+            *hops = h;
+            *stream = s;
+            found = true;
         }
     }
     return found;
 }
 
-void cache_store(const std::string &key, int v, const double t[3])
+void cache_store(const std::string &key, int hops, int stream, const double *t)
 {
     const char *path = std::getenv("LGT_TUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << v << " us:" << t[0] << "," << t[1] << "," << t[2] << "\n";
+    out << key << " " << hops << " " << stream << " us:";
+    for (int i = 0; i < kNumVariants; i++) out << (i ? "," : "") << t[i];
+    out << "\n";
 }
 
 } // namespace
 
 extern "C" {
 
-lgt_status lgt_set_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t hops)
+lgt_status lgt_set_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t hops, int32_t streaming)
 {
     clear_error();
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
     Fmt f;
     if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
     if (hops != 1 && hops != 2 && hops != 8) return fail(LGT_ERR_ARG, "hops per group must be 1, 2 or 8");
+    if (streaming != 0 && streaming != 1) return fail(LGT_ERR_ARG, "streaming must be 0 or 1");
     c->hpi[f] = hops;
+    c->ntl[f] = streaming;
     return LGT_OK;
 }
 
-lgt_status lgt_get_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t *hops)
+lgt_status lgt_get_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t *hops, int32_t *streaming)
 {
     clear_error();
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
-    if (!hops) return fail(LGT_ERR_ARG, "hops is NULL");
+    if (!hops || !streaming) return fail(LGT_ERR_ARG, "output pointer is NULL");
     Fmt f;
     if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
     *hops = c->hpi[f];
+    *streaming = c->ntl[f];
     return LGT_OK;
 }
 
-lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[3])
+lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[6])
 {
     clear_error();
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
@@ -111,9 +126,10 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[3])
     const char *force = std::getenv("LGT_TUNE");
     const bool forced = force && std::strcmp(force, "force") == 0;
     if (!forced && !times_us) {
-        const int v = cache_lookup(key);
-        if (v) {
-            c->hpi[f] = v;
+        int h, s;
+        if (cache_lookup(key, &h, &s)) {
+            c->hpi[f] = h;
+            c->ntl[f] = s;
             return LGT_OK;
         }
     }
@@ -134,19 +150,27 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[3])
     a.in = in;
     a.out = out;
     a.g = c->g;
-    a.par = LGT_ODD;
     a.gate = GATE_NONE;
     a.l = site_launch(c->g.Vh);
-    double t[3] = {0, 0, 0};
-    int best = c->hpi[f];
+    double t[kNumVariants] = {0, 0, 0, 0, 0, 0};
+    int best = 0;
     double best_t = 1e300;
     const int reps = 10;
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 3 && e == hipSuccess; i++) {
-        a.hpi = kVariants[i];
-        for (int w = 0; w < 2 && e == hipSuccess; w++) e = launch_dslash(f, EPI_PLAIN, a, c->stream);
+    for (int i = 0; i < kNumVariants && e == hipSuccess; i++) {
+        a.hpi = kHops[i];
+        a.ntl = kStream[i];
+        // alternate the output parity as a solver does, so both halves of the
+        // link field are touched between launches
+        for (int w = 0; w < 2 && e == hipSuccess; w++) {
+            a.par = w & 1;
+            e = launch_dslash(f, EPI_PLAIN, a, c->stream);
+        }
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_dslash(f, EPI_PLAIN, a, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; r++) {
+            a.par = r & 1;
+            e = launch_dslash(f, EPI_PLAIN, a, c->stream);
+        }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -154,16 +178,17 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[3])
         t[i] = 1e3 * ms / reps;
         if (e == hipSuccess && t[i] < best_t) {
             best_t = t[i];
-            best = kVariants[i];
+            best = i;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return fail(LGT_ERR_DEVICE, "tuning launch failed: %s", hipGetErrorString(e));
-    c->hpi[f] = best;
-    cache_store(key, best, t);
+    c->hpi[f] = kHops[best];
+    c->ntl[f] = kStream[best];
+    cache_store(key, kHops[best], kStream[best], t);
     if (times_us)
-        for (int i = 0; i < 3; i++) times_us[i] = t[i];
+        for (int i = 0; i < kNumVariants; i++) times_us[i] = t[i];
     return LGT_OK;
 }
 

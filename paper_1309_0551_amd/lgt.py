@@ -107,10 +107,11 @@ def _setup(l):
                               C.POINTER(_CgResult)]),
         "lgt_cdot": (st, [vp, C.c_int64, vp, vp, C.POINTER(C.c_double)]),
         "lgt_force": (st, [vp, C.POINTER(_Links), vp, C.c_double, vp]),
-        "lgt_set_dslash_variant": (st, [vp, i32, i32, i32]),
-        "lgt_get_dslash_variant": (st, [vp, i32, i32, C.POINTER(C.c_int32)]),
+        "lgt_set_dslash_variant": (st, [vp, i32, i32, i32, i32]),
+        "lgt_get_dslash_variant": (st, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),
         "lgt_stream_copy": (st, [vp, vp, vp, C.c_size_t]),
+        "lgt_stream_read": (st, [vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -225,23 +226,26 @@ class Lattice:
     def set_timing(self, on: bool):
         _check(lib().lgt_set_timing(self._ctx, int(bool(on))))
 
-    def set_dslash_variant(self, prec: int, recon: int, hops: int):
-        _check(lib().lgt_set_dslash_variant(self._ctx, prec, recon, hops))
+    def set_dslash_variant(self, prec: int, recon: int, hops: int, streaming: int = 1):
+        _check(lib().lgt_set_dslash_variant(self._ctx, prec, recon, hops, streaming))
 
-    def dslash_variant(self, prec: int, recon: int) -> int:
-        v = C.c_int32()
-        _check(lib().lgt_get_dslash_variant(self._ctx, prec, recon, C.byref(v)))
-        return int(v.value)
+    def dslash_variant(self, prec: int, recon: int) -> tuple[int, int]:
+        """(hops per load group, streaming link loads) used for this link format."""
+        h, s = C.c_int32(), C.c_int32()
+        _check(lib().lgt_get_dslash_variant(self._ctx, prec, recon, C.byref(h), C.byref(s)))
+        return int(h.value), int(s.value)
+
+    TUNE_VARIANTS = ((8, 1), (2, 1), (1, 1), (8, 0), (2, 0), (1, 0))
 
     def tune_dslash(self, U: "PackedLinks", report: bool = True):
-        """Time the variants {8, 2, 1} on U and keep the fastest; returns {hops: us} or None."""
+        """Time every variant on U and keep the fastest; returns {(hops, streaming): us} or None."""
         d = U.desc()
         if not report:
             _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), None))
             return None
-        t = (C.c_double * 3)()
+        t = (C.c_double * 6)()
         _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), t))
-        return {8: t[0], 2: t[1], 1: t[2]}
+        return {v: t[i] for i, v in enumerate(self.TUNE_VARIANTS)}
 
     # -- helpers
     def _dev(self, t: torch.Tensor, dtype=None, shape=None, what="tensor"):
@@ -323,6 +327,13 @@ class Lattice:
             raise ValueError("dst too small")
         _check(lib().lgt_stream_copy(self._ctx, self._dev(src, None, None, "src"),
                                      self._dev(dst, None, None, "dst"), n))
+
+    def stream_read(self, src: torch.Tensor, sink: torch.Tensor):
+        """Read all of src with streaming loads (read-bandwidth probe); sink: >= 16 bytes."""
+        if sink.numel() * sink.element_size() < 16:
+            raise ValueError("sink must hold 16 bytes")
+        _check(lib().lgt_stream_read(self._ctx, self._dev(src, None, None, "src"),
+                                     src.numel() * src.element_size(), self._dev(sink, None, None, "sink")))
 
     def cdot(self, a: torch.Tensor, b: torch.Tensor) -> complex:
         if a.numel() != b.numel() or a.numel() % 2:

@@ -92,9 +92,10 @@ def test_dslash_parity(dev, fmt, L, bc, kind):
 
 
 @pytest.mark.parametrize("fmt", sorted(FMTS))
-@pytest.mark.parametrize("hops", [1, 2, 8])
-def test_dslash_every_variant(dev, fmt, hops):
-    """Each kernel variant (loads of 1, 2 or 8 hops issued together) gives the same operator."""
+@pytest.mark.parametrize("hops,streaming", [(1, 1), (2, 1), (8, 1), (1, 0), (2, 0), (8, 0)])
+def test_dslash_every_variant(dev, fmt, hops, streaming):
+    """Each kernel variant (loads of 1, 2 or 8 hops issued together; streaming or
+    cached link loads) gives the same operator."""
     prec, recon, tol = FMTS[fmt]
     L, bc = (6, 4, 6, 8), (1, 1, 1, -1)
     U = li.links(L, "haar", 121)
@@ -102,11 +103,11 @@ def test_dslash_every_variant(dev, fmt, hops):
     vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
     with P.Lattice(L, bc) as lat:
         Up = lat.pack_links(_t(U, dev), prec, recon)
-        lat.set_dslash_variant(prec, recon, hops)
-        assert lat.dslash_variant(prec, recon) == hops
+        lat.set_dslash_variant(prec, recon, hops, streaming)
+        assert lat.dslash_variant(prec, recon) == (hops, streaming)
         x = lat.pack_vec(_t(chi, dev), vp)
         got = lat.unpack_vec(lat.dslash(Up, x, 0), vp).cpu().numpy()
-        lat.set_dslash_variant(prec, recon, 8)
+        lat.set_dslash_variant(prec, recon, 8, 1)
         ref8 = lat.unpack_vec(lat.dslash(Up, x, 0), vp).cpu().numpy()
     ref = oracle.dslash(L, U, chi, 0, bc)
     assert _rel(got, ref) <= tol
@@ -122,12 +123,13 @@ def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):
     with P.Lattice(L) as lat:
         Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
         t = lat.tune_dslash(Up)
-        assert set(t) == {1, 2, 8} and all(v > 0 for v in t.values())
+        assert set(t) == set(P.Lattice.TUNE_VARIANTS) and all(v > 0 for v in t.values())
         best = min(t, key=t.get)
         assert lat.dslash_variant(P.LGT_F32, P.LGT_R12) == best
     assert "f32r12" in cache.read_text()
     with P.Lattice(L) as lat2:
-        lat2.set_dslash_variant(P.LGT_F32, P.LGT_R12, 8 if best != 8 else 1)
+        other = (8, 1) if best != (8, 1) else (1, 0)
+        lat2.set_dslash_variant(P.LGT_F32, P.LGT_R12, *other)
         lat2.tune_dslash(Up, report=False)  # cached: no timing
         assert lat2.dslash_variant(P.LGT_F32, P.LGT_R12) == best
 

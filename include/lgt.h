@@ -201,6 +201,39 @@ lgt_status lgt_cg_solve(lgt_ctx *ctx, const lgt_links *U_hi, const lgt_links *U_
                         const lgt_cg_params *p, const double *b, double *x,
                         lgt_cg_result *res);
 
+/* ---- many right-hand sides and lattices ------------------------------------ */
+
+/* Multi-RHS native vectors hold nrhs (1, 2, 4, 8 or 16) right-hand sides of
+ * one parity, right-hand side fastest; canonical multi-RHS vectors are
+ * float64 [nrhs][V/2][3][2]. Byte size: nrhs * lgt_vec_bytes. */
+lgt_status lgt_pack_vec_mrhs(lgt_ctx *ctx, int32_t prec, int32_t nrhs, const double *src, void *dst);
+lgt_status lgt_unpack_vec_mrhs(lgt_ctx *ctx, int32_t prec, int32_t nrhs, const void *src, double *dst);
+/* out = D in for nrhs right-hand sides at once (native multi-RHS vectors in
+ * the vector precision of U): each link is read once per site for all of
+ * them. Asynchronous. */
+lgt_status lgt_dslash_mrhs(lgt_ctx *ctx, const lgt_links *U, int32_t out_parity, int32_t nrhs, const void *in,
+                           void *out);
+
+typedef struct {
+    lgt_ctx *ctx;          /* the problem's lattice; all problems on one device */
+    const lgt_links *U_hi; /* F64 x 18 links */
+    const lgt_links *U_lo; /* inner links, one format for all problems; ignored for FP64 */
+    int32_t nrhs;          /* 1, 2, 4, 8 or 16 */
+    const double *b;       /* canonical multi-RHS even vectors [nrhs][V/2][3][2], device */
+    double *x;             /* same layout; initial guess when x0_is_guess */
+    lgt_cg_result *res;    /* host array of nrhs results */
+} lgt_cg_problem;
+
+/* Independent even-odd CGs (own alpha, beta and stop test per right-hand
+ * side; not block CG) for every right-hand side of every problem, lattices of
+ * different sizes included, in ONE cooperative persistent launch on the
+ * stream of probs[0].ctx; phases are separated by grid barriers and FP64
+ * reliable updates / refinement steps run inside the same launch. Schemes and
+ * parameters as lgt_cg_solve (shared by all problems). Returns LGT_OK when
+ * every right-hand side converged, else the first failing status (every res
+ * is filled either way). nprob <= 64. Synchronous. */
+lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p);
+
 /* ---- reductions ------------------------------------------------------------ */
 
 /* out[0] + i out[1] = sum conj(a) b over n_complex complex numbers (device

@@ -1,0 +1,255 @@
+// batch.cpp -- C ABI of the multi-RHS Dslash and of the batched CG (one
+// cooperative launch for every right-hand side of every problem).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "batch.hpp"
+#include "ctx.hpp"
+
+namespace lgt {
+hipError_t launch_batch_cg_init(const BatchArgs *a_dev, int total_rhs, double tol, double inner, hipStream_t s);
+}
+
+using namespace lgt;
+
+namespace {
+
+int log2_rhs(int32_t n)
+{
+    for (int l = 0; l <= 4; l++)
+        if (n == (1 << l)) return l;
+    return -1;
+}
+
+} // namespace
+
+extern "C" {
+
+lgt_status lgt_pack_vec_mrhs(lgt_ctx *c, int32_t prec, int32_t nrhs, const double *src, void *dst)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (prec != LGT_F64 && prec != LGT_F32 && prec != LGT_BF16) return fail(LGT_ERR_ARG, "bad precision %d", prec);
+    lgt_status s;
+    if ((s = check_ptr(src, "src")) != LGT_OK) return s;
+    if ((s = check_ptr(dst, "dst")) != LGT_OK) return s;
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_pack_mrhs(prec == LGT_F64, src, dst, c->g, logN, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_unpack_vec_mrhs(lgt_ctx *c, int32_t prec, int32_t nrhs, const void *src, double *dst)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (prec != LGT_F64 && prec != LGT_F32 && prec != LGT_BF16) return fail(LGT_ERR_ARG, "bad precision %d", prec);
+    lgt_status s;
+    if ((s = check_ptr(src, "src")) != LGT_OK) return s;
+    if ((s = check_ptr(dst, "dst")) != LGT_OK) return s;
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_unpack_mrhs(prec == LGT_F64, src, dst, c->g, logN, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t out_parity, int32_t nrhs, const void *in,
+                           void *out)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    lgt_status s;
+    if ((s = check_links(U, false, &f)) != LGT_OK) return s;
+    if (out_parity != LGT_EVEN && out_parity != LGT_ODD) return fail(LGT_ERR_ARG, "bad parity %d", out_parity);
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if ((s = check_ptr(in, "in")) != LGT_OK) return s;
+    if ((s = check_ptr(out, "out")) != LGT_OK) return s;
+    if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_dslash_mrhs(f, U->ptr, in, out, c->g, out_parity, logN, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p)
+{
+    clear_error();
+    if (!probs) return fail(LGT_ERR_ARG, "problems is NULL");
+    if (nprob < 1 || nprob > kMaxProblems) return fail(LGT_ERR_ARG, "nprob must be in [1, %d]", kMaxProblems);
+    if (!p) return fail(LGT_ERR_ARG, "params is NULL");
+    if (!(p->mass > 0.0)) return fail(LGT_ERR_ARG, "mass must be > 0");
+    if (!(p->tol > 0.0)) return fail(LGT_ERR_ARG, "tol must be > 0");
+    if (p->max_iter <= 0) return fail(LGT_ERR_ARG, "max_iter must be > 0");
+    if (p->scheme < LGT_CG_FP64 || p->scheme > LGT_CG_REFINE) return fail(LGT_ERR_ARG, "bad scheme %d", p->scheme);
+    if (p->scheme == LGT_CG_RELIABLE && p->ru_interval <= 0) return fail(LGT_ERR_ARG, "ru_interval must be > 0");
+    if (p->scheme == LGT_CG_REFINE && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
+        return fail(LGT_ERR_ARG, "inner_tol must be in (0, 1) for refinement");
+    if (p->scheme != LGT_CG_REFINE && (p->inner_tol < 0.0 || p->inner_tol > 1.0))
+        return fail(LGT_ERR_ARG, "inner_tol must be in [0, 1]");
+    const bool mixed = p->scheme != LGT_CG_FP64;
+    lgt_ctx *c0 = probs[0].ctx;
+    if (!c0) return fail(LGT_ERR_ARG, "problem 0 has no context");
+    Fmt flo = F64R18;
+    for (int i = 0; i < nprob; i++) {
+        const lgt_cg_problem &q = probs[i];
+        if (!q.ctx) return fail(LGT_ERR_ARG, "problem %d has no context", i);
+        if (q.ctx->device != c0->device) return fail(LGT_ERR_ARG, "problem %d is on another device", i);
+        if (log2_rhs(q.nrhs) < 0) return fail(LGT_ERR_ARG, "problem %d: nrhs must be 1, 2, 4, 8 or 16", i);
+        Fmt fh, fl;
+        lgt_status s = check_links(q.U_hi, true, &fh);
+        if (s != LGT_OK) return s;
+        if (fh != F64R18) return fail(LGT_ERR_UNSUPPORTED, "problem %d: batched solves take F64 x 18 links", i);
+        if (mixed) {
+            if ((s = check_links(q.U_lo, false, &fl)) != LGT_OK) return s;
+            if (fmt_is_f64(fl)) return fail(LGT_ERR_ARG, "problem %d: U_lo must be F32 or BF16 links", i);
+            if (i == 0) flo = fl;
+            else if (fl != flo) return fail(LGT_ERR_UNSUPPORTED, "every problem must use the same U_lo format");
+        }
+        if ((s = check_ptr(q.b, "b")) != LGT_OK) return s;
+        if ((s = check_ptr(q.x, "x")) != LGT_OK) return s;
+        if (!q.res) return fail(LGT_ERR_ARG, "problem %d: res is NULL", i);
+    }
+    DeviceScope ds(c0->device);
+    const hipStream_t s = c0->stream;
+
+    BatchArgs *ha = (BatchArgs *)pinned(c0, sizeof(BatchArgs) + 64 + sizeof(BatchCtl));
+    if (!ha) return fail(LGT_ERR_OOM, "cannot allocate pinned staging");
+    std::memset(ha, 0, sizeof(BatchArgs));
+    int tiles = 0, rhs0 = 0;
+    for (int i = 0; i < nprob; i++) {
+        const lgt_cg_problem &q = probs[i];
+        lgt_ctx *c = q.ctx;
+        const int logN = log2_rhs(q.nrhs);
+        const size_t n = (size_t)c->g.Vh << logN;
+        const size_t v64 = n * 48, vlo = mixed ? n * 24 : n * 48;
+        BatchProb &P = ha->prob[i];
+        P.g = c->g;
+        P.logN = logN;
+        P.tile0 = tiles;
+        P.ntiles = (int)((n + kBS - 1) / kBS);
+        P.rhs0 = rhs0;
+        P.m4 = 4.0 * p->mass * p->mass;
+        P.Uhi = q.U_hi->ptr;
+        P.Ulo = mixed ? q.U_lo->ptr : q.U_hi->ptr;
+        double *b64 = (double *)workspace(c, "batch.b64", v64);
+        P.x64 = (double *)workspace(c, "batch.x64", v64);
+        P.t64 = (double *)workspace(c, "batch.t64", v64);
+        P.q64 = (double *)workspace(c, "batch.q64", v64);
+        P.r = workspace(c, "batch.r", vlo);
+        P.pa = workspace(c, "batch.pa", vlo);
+        P.pb = workspace(c, "batch.pb", vlo);
+        P.Ap = workspace(c, "batch.Ap", vlo);
+        P.t = workspace(c, "batch.t", vlo);
+        P.xlo = mixed ? workspace(c, "batch.xlo", vlo) : (void *)P.x64;
+        P.st = (CgState *)workspace(c, "batch.state", sizeof(CgState) * kMaxRhs);
+        P.b64 = b64;
+        if (!b64 || !P.x64 || !P.t64 || !P.q64 || !P.r || !P.pa || !P.pb || !P.Ap || !P.t || !P.xlo || !P.st)
+            return fail(LGT_ERR_OOM, "cannot allocate the batch workspace of problem %d", i);
+        tiles += P.ntiles;
+        rhs0 += q.nrhs;
+    }
+    ha->nprob = nprob;
+    ha->total_tiles = tiles;
+    ha->total_rhs = rhs0;
+    ha->scheme = p->scheme;
+    ha->ru_interval = p->scheme == LGT_CG_RELIABLE ? p->ru_interval : 1 << 30;
+    ha->max_iter = p->max_iter;
+    ha->spin_limit = 1u << 25; // ~2 s of polling: far beyond any phase of a valid launch
+    double *part = (double *)workspace(c0, "batch.partials", sizeof(double) * (size_t)tiles * kMaxRhs);
+    BatchCtl *ctl = (BatchCtl *)workspace(c0, "batch.ctl", sizeof(BatchCtl));
+    BatchArgs *da = (BatchArgs *)workspace(c0, "batch.args", sizeof(BatchArgs));
+    if (!part || !ctl || !da) return fail(LGT_ERR_OOM, "cannot allocate the batch control buffers");
+    ha->partials = part;
+    ha->ctl = ctl;
+
+    // grid: every workgroup must be resident at once (cooperative launch)
+    int coop = 0, ncu = 0;
+    LGT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c0->device));
+    if (!coop) return fail(LGT_ERR_UNSUPPORTED, "device does not support cooperative launches");
+    LGT_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c0->device));
+    const int per_cu = batch_cg_max_blocks_per_cu(mixed ? flo : F64R18);
+    if (per_cu < 1) return fail(LGT_ERR_DEVICE, "cannot size the batched launch");
+    int grid = per_cu * ncu;
+    if (grid > 2 * ncu) grid = 2 * ncu; // two workgroups per CU: fewer arrivals per grid barrier
+    if (grid > tiles) grid = tiles;
+    if (grid < 1) grid = 1;
+
+    hipEvent_t e0, e1;
+    LGT_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LGT_ERR_DEVICE, "hipEventCreate failed");
+    }
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+
+    LGT_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < nprob; i++) {
+        const lgt_cg_problem &q = probs[i];
+        const BatchProb &P = ha->prob[i];
+        const size_t n = (size_t)q.ctx->g.Vh << P.logN;
+        const size_t vlo = mixed ? n * 24 : n * 48;
+        LGT_HIP(launch_pack_mrhs(true, q.b, (void *)P.b64, q.ctx->g, P.logN, s));
+        if (p->x0_is_guess) LGT_HIP(launch_pack_mrhs(true, q.x, P.x64, q.ctx->g, P.logN, s));
+        else LGT_HIP(launch_zero(P.x64, n * 48, s));
+        if (mixed) LGT_HIP(launch_zero(P.xlo, vlo, s));
+        LGT_HIP(launch_zero(P.pa, vlo, s));
+        LGT_HIP(launch_zero(P.pb, vlo, s));
+    }
+    LGT_HIP(launch_zero(ctl, sizeof(BatchCtl), s));
+    LGT_HIP(hipMemcpyAsync(da, ha, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
+    const double inner = p->scheme == LGT_CG_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
+    LGT_HIP(launch_batch_cg_init(da, ha->total_rhs, p->tol, inner, s));
+    LGT_HIP(launch_batch_cg(mixed ? flo : F64R18, da, grid, s));
+    for (int i = 0; i < nprob; i++) {
+        const lgt_cg_problem &q = probs[i];
+        LGT_HIP(launch_unpack_mrhs(true, ha->prob[i].x64, q.x, q.ctx->g, ha->prob[i].logN, s));
+    }
+    LGT_HIP(hipEventRecord(e1, s));
+    // read back states and control words (pinned staging after the args)
+    std::vector<CgState> states((size_t)ha->total_rhs);
+    for (int i = 0; i < nprob; i++)
+        LGT_HIP(hipMemcpyAsync(&states[ha->prob[i].rhs0], ha->prob[i].st, sizeof(CgState) * probs[i].nrhs,
+                               hipMemcpyDeviceToHost, s));
+    BatchCtl hc;
+    LGT_HIP(hipMemcpyAsync(&hc, ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    LGT_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    LGT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (hc.err) return fail(LGT_ERR_DEVICE, "batched CG: a grid barrier timed out");
+
+    lgt_status ret = LGT_OK;
+    for (int i = 0; i < nprob; i++) {
+        for (int j = 0; j < probs[i].nrhs; j++) {
+            const CgState &e = states[(size_t)ha->prob[i].rhs0 + j];
+            lgt_cg_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.iters = e.iter;
+            r.updates = e.updates;
+            r.dslash_calls = 2 * (e.iter + e.updates + 2);
+            r.true_rel_resid = e.bnorm2 > 0.0 ? std::sqrt(e.last_true / e.bnorm2) : 0.0;
+            r.seconds = 1e-3 * ms;
+            if (e.state == ST_DONE) r.status = LGT_OK;
+            else if (e.state == ST_FAIL || !std::isfinite(e.last_true)) r.status = LGT_ERR_NONFINITE;
+            else r.status = LGT_ERR_NOT_CONVERGED;
+            probs[i].res[j] = r;
+            if (r.status != LGT_OK && ret == LGT_OK) ret = r.status;
+        }
+    }
+    if (ret != LGT_OK) return fail(ret, "batched CG: at least one right-hand side did not converge");
+    return LGT_OK;
+}
+
+} // extern "C"

@@ -81,11 +81,17 @@ struct Hop {
 };
 __host__ __device__ __forceinline__ Hop hop_rt(const Geom &g, const int c[4], int cb, int mu)
 {
-    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
-    const int Lm = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
-    const int bcm = mu == 0 ? g.bc[0] : mu == 1 ? g.bc[1] : mu == 2 ? g.bc[2] : g.bc[3];
-    const int sm = mu == 1 ? g.str[1] : mu == 2 ? g.str[2] : g.str[3];
-    const int ep = (mu > 0 ? c[0] : 0) + (mu > 1 ? c[1] : 0) + (mu > 2 ? c[2] : 0);
+    // read every field into a value first: selecting between field addresses
+    // would turn into an indexed access to a private copy of g
+    const int c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
+    const int b0 = g.bc[0], b1 = g.bc[1], b2 = g.bc[2], b3 = g.bc[3];
+    const int s1 = g.str[1], s2 = g.str[2], s3 = g.str[3];
+    const int cm = mu == 0 ? c0 : mu == 1 ? c1 : mu == 2 ? c2 : c3;
+    const int Lm = mu == 0 ? L0 : mu == 1 ? L1 : mu == 2 ? L2 : L3;
+    const int bcm = mu == 0 ? b0 : mu == 1 ? b1 : mu == 2 ? b2 : b3;
+    const int sm = mu == 1 ? s1 : mu == 2 ? s2 : s3;
+    const int ep = (mu > 0 ? c0 : 0) + (mu > 1 ? c1 : 0) + (mu > 2 ? c2 : 0);
     Hop h;
     if (mu == 0) {
         h.f = (cm & 1) ? ((cm == Lm - 1) ? cb - (g.hx - 1) : cb + 1) : cb;

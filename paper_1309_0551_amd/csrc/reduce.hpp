@@ -37,7 +37,8 @@ __device__ __forceinline__ bool gate_open(int gate, const CgState *st)
     return s == ST_INIT || s == ST_INNER || (s == ST_RUN && st->ru_fixed);
 }
 
-// The scalar step that follows a reduction (thread 0 of the last workgroup).
+// The scalar step that follows a reduction (one thread, after all partial sums
+// of the reducing kernel or phase have been added in a fixed order).
 __device__ inline void finalize(int fin, CgState *st, double sum)
 {
     switch (fin) {

@@ -69,6 +69,11 @@ class _CgResult(C.Structure):
                 ("dslash_timed_hi", C.c_int32), ("dslash_timed_lo", C.c_int32)]
 
 
+class _CgProblem(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("U_hi", C.POINTER(_Links)), ("U_lo", C.POINTER(_Links)),
+                ("nrhs", C.c_int32), ("b", C.c_void_p), ("x", C.c_void_p), ("res", C.POINTER(_CgResult))]
+
+
 _lib = None
 
 
@@ -112,6 +117,10 @@ def _setup(l):
         "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),
         "lgt_stream_copy": (st, [vp, vp, vp, C.c_size_t]),
         "lgt_stream_read": (st, [vp, vp, C.c_size_t, vp]),
+        "lgt_pack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
+        "lgt_unpack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
+        "lgt_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, i32, vp, vp]),
+        "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -320,6 +329,36 @@ class Lattice:
             _check(st)
         return x, r
 
+    # -- many right-hand sides
+    def pack_vec_mrhs(self, v: torch.Tensor, prec: int = LGT_F64) -> torch.Tensor:
+        """canonical [N][V/2][3][2] float64 -> native multi-RHS [3][V/2][N][2]."""
+        n = int(v.shape[0])
+        p = self._dev(v, torch.float64, (n,) + self.vec_shape(), "v")
+        dt = torch.float64 if prec == LGT_F64 else torch.float32
+        out = torch.empty((3, self.Vh, n, 2), dtype=dt, device=self.device)
+        _check(lib().lgt_pack_vec_mrhs(self._ctx, prec, n, p, out.data_ptr()))
+        return out
+
+    def unpack_vec_mrhs(self, nv: torch.Tensor, prec: int = LGT_F64) -> torch.Tensor:
+        n = int(nv.shape[2])
+        dt = torch.float64 if prec == LGT_F64 else torch.float32
+        p = self._dev(nv, dt, (3, self.Vh, n, 2), "native vector")
+        out = torch.empty((n,) + self.vec_shape(), dtype=torch.float64, device=self.device)
+        _check(lib().lgt_unpack_vec_mrhs(self._ctx, prec, n, p, out.data_ptr()))
+        return out
+
+    def dslash_mrhs(self, U: PackedLinks, x: torch.Tensor, out_parity: int, out: torch.Tensor | None = None):
+        """out = D x for every right-hand side of a native multi-RHS vector."""
+        dt = torch.float64 if U.prec == LGT_F64 else torch.float32
+        n = int(x.shape[2])
+        p = self._dev(x, dt, (3, self.Vh, n, 2), "input vector")
+        if out is None:
+            out = torch.empty_like(x)
+        q = self._dev(out, dt, (3, self.Vh, n, 2), "output vector")
+        d = U.desc()
+        _check(lib().lgt_dslash_mrhs(self._ctx, C.byref(d), int(out_parity), n, p, q))
+        return out
+
     def stream_copy(self, src: torch.Tensor, dst: torch.Tensor):
         """dst[:] = src[:] with the library's streaming copy kernel (bandwidth probe)."""
         n = src.numel() * src.element_size()
@@ -350,6 +389,42 @@ class Lattice:
         d = U.desc()
         _check(lib().lgt_force(self._ctx, C.byref(d), px, float(scale), G.data_ptr()))
         return G
+
+
+def cg_solve_batch(problems, mass: float, tol: float = 1e-10, scheme: int = LGT_CG_RELIABLE,
+                   ru_interval: int = 50, inner_tol: float = 0.0, max_iter: int = 100000,
+                   raise_on_fail: bool = True):
+    """Independent CGs for every right-hand side of every problem in one persistent launch.
+
+    problems: list of (lattice, U_hi, U_lo, b) with b a float64 tensor [N][V/2][3][2]
+    (N = 1, 2, 4, 8 or 16). Returns ([x per problem], [[CgResult per rhs] per problem]).
+    """
+    keep, descs, xs, results = [], [], [], []
+    arr = (_CgProblem * len(problems))()
+    for i, (lat, U_hi, U_lo, b) in enumerate(problems):
+        n = int(b.shape[0])
+        lat._dev(b, torch.float64, (n,) + lat.vec_shape(), "b")
+        x = torch.zeros_like(b)
+        dh = U_hi.desc()
+        dl = U_lo.desc() if U_lo is not None else None
+        res = (_CgResult * n)()
+        keep += [dh, dl, res]
+        arr[i].ctx = lat._ctx
+        arr[i].U_hi = C.pointer(dh)
+        arr[i].U_lo = C.pointer(dl) if dl is not None else None
+        arr[i].nrhs = n
+        arr[i].b = b.data_ptr()
+        arr[i].x = x.data_ptr()
+        arr[i].res = res
+        xs.append(x)
+        results.append(res)
+    prm = _CgParams(float(mass), float(tol), int(max_iter), int(scheme), int(ru_interval), 0,
+                    float(inner_tol), 0, 0)
+    st = lib().lgt_cg_solve_batch(arr, len(problems), C.byref(prm))
+    out = [[CgResult(*(getattr(r, f[0]) for f in _CgResult._fields_)) for r in res] for res in results]
+    if st != 0 and (raise_on_fail or st not in (-5, -6)):
+        _check(st)
+    return xs, out
 
 
 class PseudofermionAction(torch.autograd.Function):

@@ -1,0 +1,146 @@
+"""Batching form on the GPU: the multi-RHS Dslash and the batched CG (one
+persistent launch for many right-hand sides and lattices of different sizes),
+against the FP64 oracle and against the single-RHS solver."""
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+import oracle
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1309_0551_amd")
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U16 = 2.0 ** -9
+FMTS = {
+    "f64r18": (P.LGT_F64, P.LGT_R18, 1e-12),
+    "f64r12": (P.LGT_F64, P.LGT_R12, 1e-12),
+    "f32r18": (P.LGT_F32, P.LGT_R18, 32 * U32),
+    "f32r12": (P.LGT_F32, P.LGT_R12, 32 * U32),
+    "bf16r12": (P.LGT_BF16, P.LGT_R12, 8 * U16),
+}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+@pytest.mark.parametrize("nrhs", [1, 2, 4, 16])
+def test_dslash_mrhs_parity(dev, fmt, nrhs):
+    prec, recon, tol = FMTS[fmt]
+    L, bc = (6, 4, 6, 8), (1, 1, 1, -1)
+    U = li.links(L, "haar", 141)
+    chis = li.vectors(L, 142, nrhs)
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        for par in (0, 1):
+            x = lat.pack_vec_mrhs(_t(chis, dev), vp)
+            got = lat.unpack_vec_mrhs(lat.dslash_mrhs(Up, x, par), vp).cpu().numpy()
+            for r in range(nrhs):
+                ref = oracle.dslash(L, U, chis[r], par, bc)
+                assert _rel(got[r], ref) <= tol, (fmt, nrhs, par, r)
+
+
+def test_mrhs_pack_roundtrip(dev):
+    L = (4, 4, 4, 4)
+    v = li.vectors(L, 7, 8)
+    with P.Lattice(L) as lat:
+        back = lat.unpack_vec_mrhs(lat.pack_vec_mrhs(_t(v, dev))).cpu().numpy()
+    np.testing.assert_array_equal(back, v)
+
+
+def _check_solution(L, U, mass, b, x, res, tol):
+    r = b - oracle.apply_A(L, U, mass, x)
+    rr = float(np.linalg.norm(r) / np.linalg.norm(b))
+    assert res.status == 0, res
+    assert rr <= 1.05 * tol, rr
+    assert abs(res.true_rel_resid - rr) <= 1e-3 * tol + 0.05 * rr
+    return rr
+
+
+@pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12)),
+                                       (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R18)),
+                                       (P.LGT_CG_REFINE, (P.LGT_BF16, P.LGT_R12))],
+                         ids=["fp64", "rel_f32r12", "rel_f32r18", "ir_bf16r12"])
+def test_batch_heterogeneous(dev, scheme, lo):
+    """Three lattices of different sizes, 4 / 2 / 16 right-hand sides, one launch."""
+    mass, tol = 0.1, 1e-10
+    specs = [((8, 8, 8, 8), 4, 4101), ((6, 4, 6, 8), 2, 4201), ((4, 4, 4, 4), 16, 4301)]
+    lats, probs, data = [], [], []
+    for L, n, seed in specs:
+        U = li.links(L, "haar", seed)
+        b = li.vectors(L, seed + 10, n)
+        lat = P.Lattice(L)
+        Uh = lat.pack_links(_t(U, dev), P.LGT_F64, P.LGT_R18)
+        Ul = lat.pack_links(_t(U, dev), *lo) if lo else None
+        lats.append(lat)
+        probs.append((lat, Uh, Ul, _t(b, dev)))
+        data.append((L, U, b))
+    print("batch", scheme, lo, flush=True)
+    xs, res = P.cg_solve_batch(probs, mass, tol=tol, scheme=scheme, ru_interval=50,
+                               inner_tol=0.1 if scheme == P.LGT_CG_REFINE else 0.0)
+    for (L, U, b), x, rs in zip(data, xs, res):
+        xg = x.cpu().numpy()
+        for j in range(len(rs)):
+            _check_solution(L, U, mass, b[j], xg[j], rs[j], tol)
+            st, xo, it_o, rr_o = oracle.cg(L, U, mass, b[j], tol=tol)
+            bound = (1.05 * tol + rr_o) * np.linalg.norm(b[j]) / (4 * mass * mass)
+            assert np.linalg.norm(xg[j] - xo) <= bound
+            if scheme == P.LGT_CG_FP64:
+                assert abs(rs[j].iters - it_o) <= 3
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_matches_single_solves_c4_shape(dev):
+    """24^3 x 48 is too large for a quick oracle solve: compare the 16-RHS batch
+    with the single-RHS solver on the same lattice, right-hand side by right-hand
+    side, on a 12^3 x 24 lattice of the same aspect, m = 0.02."""
+    L, n, mass, tol = (12, 12, 12, 24), 16, 0.02, 1e-10
+    U = li.links(L, "haar", 4001)
+    b = li.vectors(L, 4010, n)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev), P.LGT_F64, P.LGT_R18)
+        Ul = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        xs, res = P.cg_solve_batch([(lat, Uh, Ul, _t(b, dev))], mass, tol=tol)
+        xb = xs[0].cpu().numpy()
+        for j in (0, 7, 15):
+            xj, rj = lat.cg_solve(Uh, _t(b[j], dev), mass, tol=tol, scheme=P.LGT_CG_RELIABLE, U_lo=Ul)
+            assert res[0][j].status == 0 and rj.status == 0
+            bound = 2.1 * tol * np.linalg.norm(b[j]) / (4 * mass * mass)
+            assert np.linalg.norm(xb[j] - xj.cpu().numpy()) <= bound
+            assert abs(res[0][j].iters - rj.iters) <= max(10, rj.iters // 20)
+        # the oracle's FP64 residual of a few batch solutions
+        for j in (0, 15):
+            r = b[j] - oracle.apply_A(L, U, mass, xb[j])
+            assert np.linalg.norm(r) / np.linalg.norm(b[j]) <= 1.05 * tol
+
+
+def test_batch_iteration_cap_and_determinism(dev):
+    L = (4, 4, 4, 4)
+    U = li.links(L, "haar", 4401)
+    b = li.vectors(L, 4402, 4)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev))
+        xs, res = P.cg_solve_batch([(lat, Uh, None, _t(b, dev))], 0.1, scheme=P.LGT_CG_FP64, max_iter=7,
+                                   raise_on_fail=False)
+        assert all(r.status == -5 and r.iters == 7 for r in res[0])
+        x1, r1 = P.cg_solve_batch([(lat, Uh, None, _t(b, dev))], 0.1, scheme=P.LGT_CG_FP64)
+        x2, r2 = P.cg_solve_batch([(lat, Uh, None, _t(b, dev))], 0.1, scheme=P.LGT_CG_FP64)
+        assert torch.equal(x1[0], x2[0])
+        assert [r.iters for r in r1[0]] == [r.iters for r in r2[0]]

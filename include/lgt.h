@@ -213,6 +213,16 @@ lgt_status lgt_unpack_vec_mrhs(lgt_ctx *ctx, int32_t prec, int32_t nrhs, const v
  * them. Asynchronous. */
 lgt_status lgt_dslash_mrhs(lgt_ctx *ctx, const lgt_links *U, int32_t out_parity, int32_t nrhs, const void *in,
                            void *out);
+/* How lgt_dslash_mrhs and the batched solver compute with F32/BF16 links and
+ * nrhs >= 4: LGT_MRHS_MFMA (default) puts 16 sites of a wavefront in the 16
+ * blocks of 4x4 MFMA outer products over the real embedding of each hop
+ * (right-hand sides x output reals, one input real per step);
+ * LGT_MRHS_VALU4 does the same products with FMAs; LGT_MRHS_LANE uses one lane
+ * per (site, right-hand side). FP64 links and nrhs < 4 always use
+ * LGT_MRHS_LANE. Speed only: results agree to rounding. */
+enum { LGT_MRHS_LANE = 0, LGT_MRHS_VALU4 = 1, LGT_MRHS_MFMA = 2 };
+lgt_status lgt_set_mrhs_engine(lgt_ctx *ctx, int32_t engine);
+lgt_status lgt_get_mrhs_engine(lgt_ctx *ctx, int32_t *engine);
 
 typedef struct {
     lgt_ctx *ctx;          /* the problem's lattice; all problems on one device */

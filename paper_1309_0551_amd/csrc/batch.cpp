@@ -58,6 +58,24 @@ lgt_status lgt_unpack_vec_mrhs(lgt_ctx *c, int32_t prec, int32_t nrhs, const voi
     return LGT_OK;
 }
 
+lgt_status lgt_set_mrhs_engine(lgt_ctx *c, int32_t engine)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (engine < LGT_MRHS_LANE || engine > LGT_MRHS_MFMA) return fail(LGT_ERR_ARG, "bad engine %d", engine);
+    c->mrhs_engine = engine;
+    return LGT_OK;
+}
+
+lgt_status lgt_get_mrhs_engine(lgt_ctx *c, int32_t *engine)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (!engine) return fail(LGT_ERR_ARG, "engine is NULL");
+    *engine = c->mrhs_engine;
+    return LGT_OK;
+}
+
 lgt_status lgt_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t out_parity, int32_t nrhs, const void *in,
                            void *out)
 {
@@ -73,7 +91,7 @@ lgt_status lgt_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t out_parity, i
     if ((s = check_ptr(out, "out")) != LGT_OK) return s;
     if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
     DeviceScope ds(c->device);
-    LGT_HIP(launch_dslash_mrhs(f, U->ptr, in, out, c->g, out_parity, logN, c->stream));
+    LGT_HIP(launch_dslash_mrhs(f, U->ptr, in, out, c->g, out_parity, logN, c->stream, c->mrhs_engine));
     return LGT_OK;
 }
 

@@ -56,9 +56,17 @@ struct BatchArgs {
     unsigned int spin_limit;
 };
 
+// Multi-RHS Dslash engines: one lane per (site, rhs); four lanes per site
+// with R = N/4 right-hand sides each, products on the VALU or on MFMA.
+// The four-lane engines serve FP32/BF16 links with N >= 4 (MFMA also needs
+// V/2 to be a multiple of 16); other cases use one lane per (site, rhs).
+enum MrhsEngine { MRHS_LANE = 0, MRHS_VALU4 = 1, MRHS_MFMA = 2 };
+inline bool fmt_is_f64_fmt(Fmt f) { return f == F64R18 || f == F64R12; }
+bool mrhs_engine_applies(Fmt f, int logN, int Vh, int engine);
+
 // Standalone multi-RHS Dslash (plain epilogue): out = D in, N right-hand sides.
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                              hipStream_t s);
+                              hipStream_t s, int engine);
 hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s);
 hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s);
 // Persistent batched CG (cooperative launch). lo = inner link format.

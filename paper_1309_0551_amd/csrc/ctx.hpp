@@ -24,6 +24,8 @@ struct lgt_ctx {
     // 256 MB Infinity Cache: FP32x12 42 -> 34 us, BF16x12 25 -> 20 us).
     int hpi[lgt::FMT_COUNT] = {2, 2, 8, 8, 8};
     int ntl[lgt::FMT_COUNT] = {1, 1, 0, 0, 0};
+    // multi-RHS Dslash engine (0 lane per RHS, 1 four-lane VALU, 2 four-lane MFMA)
+    int mrhs_engine = 2;
     struct Buf {
         void *ptr = nullptr;
         size_t bytes = 0;

@@ -17,6 +17,7 @@
 // updates run inside the same launch.
 #include "batch.hpp"
 #include "fields.hpp"
+#include "mrhs4.hpp"
 #include "reduce.hpp"
 
 namespace lgt {
@@ -91,9 +92,69 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs(const void *__restrict__ U,
     stm<T>(out, Vh, logN, site, rhs, acc);
 }
 
-hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                              hipStream_t s)
+// four lanes per site, R right-hand sides per lane, VALU or MFMA engine
+template <class LF, int R, bool MFMA>
+__global__ __launch_bounds__(kBS) void k_dslash_mrhs4(const void *__restrict__ U, const void *__restrict__ in,
+                                                      void *__restrict__ out, Geom g, int par, int logN, int nblk_pad)
 {
+    const unsigned idx = (unsigned)xcd_block(blockIdx.x, nblk_pad) * kBS + threadIdx.x;
+    const unsigned site = idx >> 2, lane4 = idx & 3u;
+    // the 4 lanes of a site and the 16 sites of a wavefront stay together, and
+    // a wavefront is never split by the bound below (Vh is a multiple of 16
+    // whenever the MFMA engine is used: checked on the host)
+    if (site >= (unsigned)g.Vh) return;
+    const size_t Vh = (size_t)g.Vh;
+    const unsigned rhs0 = lane4 * R;
+    auto IN = [=](int s, cx<float> v[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(in, Vh, logN, s, rhs0, v); };
+    cx<float> acc[R][3];
+    dslash_site4<LF, R, MFMA>(g, par, U, site, lane4, IN, acc);
+    stm_r<float, R>(out, Vh, logN, site, rhs0, acc);
+}
+
+template <class LF>
+static hipError_t launch_mrhs4(int engine, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
+                               hipStream_t s)
+{
+    const int64_t n = (int64_t)g.Vh * 4;
+    const int nblk = (int)((n + kBS - 1) / kBS);
+    const int pad = (nblk + 7) / 8 * 8;
+    const dim3 grid(pad), block(kBS);
+    const bool mf = engine == MRHS_MFMA;
+    switch (logN) {
+    case 2:
+        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, 1, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+        else hipLaunchKernelGGL((k_dslash_mrhs4<LF, 1, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+        break;
+    case 3:
+        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, 2, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+        else hipLaunchKernelGGL((k_dslash_mrhs4<LF, 2, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+        break;
+    case 4:
+        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, 4, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+        else hipLaunchKernelGGL((k_dslash_mrhs4<LF, 4, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool mrhs_engine_applies(Fmt f, int logN, int Vh, int engine)
+{
+    if (engine == MRHS_LANE || logN < 2 || fmt_is_f64_fmt(f)) return false;
+    return engine == MRHS_VALU4 || (Vh % 16) == 0;
+}
+
+hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
+                              hipStream_t s, int engine)
+{
+    if (mrhs_engine_applies(f, logN, g.Vh, engine)) {
+        switch (f) {
+        case F32R18: return launch_mrhs4<LinkF32R18>(engine, U, in, out, g, par, logN, s);
+        case F32R12: return launch_mrhs4<LinkF32R12>(engine, U, in, out, g, par, logN, s);
+        case BF16R12: return launch_mrhs4<LinkBF16R12>(engine, U, in, out, g, par, logN, s);
+        default: break;
+        }
+    }
     const int64_t n = (int64_t)g.Vh << logN;
     const int nblk = (int)((n + kBS - 1) / kBS);
     const int pad = (nblk + 7) / 8 * 8;

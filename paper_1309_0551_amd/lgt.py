@@ -22,6 +22,7 @@ LGT_F64, LGT_F32, LGT_BF16 = 0, 1, 2
 LGT_R18, LGT_R12 = 18, 12
 LGT_EVEN, LGT_ODD = 0, 1
 LGT_CG_FP64, LGT_CG_RELIABLE, LGT_CG_REFINE = 0, 1, 2
+LGT_MRHS_LANE, LGT_MRHS_VALU4, LGT_MRHS_MFMA = 0, 1, 2
 
 STATUS = {
     0: "LGT_OK", -1: "LGT_ERR_ARG", -2: "LGT_ERR_GEOMETRY", -3: "LGT_ERR_ALIGN",
@@ -120,6 +121,8 @@ def _setup(l):
         "lgt_pack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
         "lgt_unpack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
         "lgt_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, i32, vp, vp]),
+        "lgt_set_mrhs_engine": (st, [vp, i32]),
+        "lgt_get_mrhs_engine": (st, [vp, C.POINTER(C.c_int32)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
     }
     for name, (res, args) in sig.items():
@@ -243,6 +246,15 @@ class Lattice:
         h, s = C.c_int32(), C.c_int32()
         _check(lib().lgt_get_dslash_variant(self._ctx, prec, recon, C.byref(h), C.byref(s)))
         return int(h.value), int(s.value)
+
+    def set_mrhs_engine(self, engine: int):
+        """Multi-RHS Dslash engine: LGT_MRHS_LANE, LGT_MRHS_VALU4 or LGT_MRHS_MFMA."""
+        _check(lib().lgt_set_mrhs_engine(self._ctx, int(engine)))
+
+    def mrhs_engine(self) -> int:
+        e = C.c_int32()
+        _check(lib().lgt_get_mrhs_engine(self._ctx, C.byref(e)))
+        return int(e.value)
 
     TUNE_VARIANTS = ((8, 1), (2, 1), (1, 1), (8, 0), (2, 0), (1, 0))
 

@@ -56,6 +56,41 @@ def test_dslash_mrhs_parity(dev, fmt, nrhs):
                 assert _rel(got[r], ref) <= tol, (fmt, nrhs, par, r)
 
 
+ENGINES = {"lane": 0, "valu4": 1, "mfma": 2}
+
+
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+@pytest.mark.parametrize("fmt", ["f32r18", "f32r12", "bf16r12"])
+@pytest.mark.parametrize("nrhs", [4, 8, 16])
+@pytest.mark.parametrize("L", [(8, 8, 8, 12), (6, 6, 6, 6)])
+def test_dslash_mrhs_engines(dev, engine, fmt, nrhs, L):
+    """Every multi-RHS engine against the oracle. 8^3x12 (V/2 = 3072) spans
+    48 workgroups of four-lane sites; 6^4 (V/2 = 648, not a multiple of 16)
+    leaves a ragged last workgroup, and the MFMA engine falls back to one
+    lane per right-hand side there."""
+    prec, recon, tol = FMTS[fmt]
+    bc = (1, 1, 1, -1)
+    U = li.links(L, "haar", 151)
+    chis = li.vectors(L, 152, nrhs)
+    with P.Lattice(L, bc) as lat:
+        lat.set_mrhs_engine(ENGINES[engine])
+        assert lat.mrhs_engine() == ENGINES[engine]
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        x = lat.pack_vec_mrhs(_t(chis, dev), P.LGT_F32)
+        for par in (0, 1):
+            got = lat.unpack_vec_mrhs(lat.dslash_mrhs(Up, x, par), P.LGT_F32).cpu().numpy()
+            for r in range(nrhs):
+                ref = oracle.dslash(L, U, chis[r], par, bc)
+                assert _rel(got[r], ref) <= tol, (engine, fmt, nrhs, L, par, r)
+
+
+def test_mrhs_engine_rejects_unknown(dev):
+    with P.Lattice((4, 4, 4, 4)) as lat:
+        with pytest.raises(P.LgtError):
+            lat.set_mrhs_engine(3)
+        assert lat.mrhs_engine() == ENGINES["mfma"]
+
+
 def test_mrhs_pack_roundtrip(dev):
     L = (4, 4, 4, 4)
     v = li.vectors(L, 7, 8)

@@ -236,12 +236,17 @@ typedef struct {
 
 /* Independent even-odd CGs (own alpha, beta and stop test per right-hand
  * side; not block CG) for every right-hand side of every problem, lattices of
- * different sizes included, in ONE cooperative persistent launch on the
- * stream of probs[0].ctx; phases are separated by grid barriers and FP64
- * reliable updates / refinement steps run inside the same launch. Schemes and
- * parameters as lgt_cg_solve (shared by all problems). Returns LGT_OK when
- * every right-hand side converged, else the first failing status (every res
- * is filled either way). nprob <= 64. Synchronous. */
+ * different sizes included, in ONE cooperative persistent launch (one
+ * workgroup per CU) on the stream of probs[0].ctx. An iteration has three
+ * grid barriers; every workgroup sums the per-workgroup partial sums itself,
+ * in a fixed order, so results are bit-reproducible for a given device. FP64
+ * reliable updates / refinement steps run inside the same launch. The inner
+ * Dslash uses the multi-RHS engine of probs[0].ctx (lgt_set_mrhs_engine).
+ * Schemes and parameters as lgt_cg_solve (shared by all problems); res[j].seconds
+ * is the time of the whole batch. Returns LGT_OK when every right-hand side
+ * converged, else the first failing status (every res is filled either way).
+ * nprob <= 64, sum of nrhs <= 256; a context may appear in several problems.
+ * Synchronous. */
 lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p);
 
 /* ---- reductions ------------------------------------------------------------ */

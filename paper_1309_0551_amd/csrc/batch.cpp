@@ -3,15 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
 #include "batch.hpp"
 #include "ctx.hpp"
-
-namespace lgt {
-hipError_t launch_batch_cg_init(const BatchArgs *a_dev, int total_rhs, double tol, double inner, hipStream_t s);
-}
 
 using namespace lgt;
 
@@ -114,6 +111,7 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     lgt_ctx *c0 = probs[0].ctx;
     if (!c0) return fail(LGT_ERR_ARG, "problem 0 has no context");
     Fmt flo = F64R18;
+    int total_rhs = 0;
     for (int i = 0; i < nprob; i++) {
         const lgt_cg_problem &q = probs[i];
         if (!q.ctx) return fail(LGT_ERR_ARG, "problem %d has no context", i);
@@ -132,14 +130,23 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         if ((s = check_ptr(q.b, "b")) != LGT_OK) return s;
         if ((s = check_ptr(q.x, "x")) != LGT_OK) return s;
         if (!q.res) return fail(LGT_ERR_ARG, "problem %d: res is NULL", i);
+        total_rhs += q.nrhs;
     }
+    if (total_rhs > kMaxTotalRhs) return fail(LGT_ERR_ARG, "at most %d right-hand sides per batch", kMaxTotalRhs);
     DeviceScope ds(c0->device);
     const hipStream_t s = c0->stream;
 
-    BatchArgs *ha = (BatchArgs *)pinned(c0, sizeof(BatchArgs) + 64 + sizeof(BatchCtl));
+    // grid: one workgroup per CU, all resident at once (cooperative launch)
+    int coop = 0, ncu = 0;
+    LGT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c0->device));
+    if (!coop) return fail(LGT_ERR_UNSUPPORTED, "device does not support cooperative launches");
+    LGT_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c0->device));
+    if (batch_cg_max_blocks_per_cu(mixed ? flo : F64R18) < 1) return fail(LGT_ERR_DEVICE, "cannot size the batched launch");
+
+    BatchArgs *ha = (BatchArgs *)pinned(c0, sizeof(BatchArgs));
     if (!ha) return fail(LGT_ERR_OOM, "cannot allocate pinned staging");
     std::memset(ha, 0, sizeof(BatchArgs));
-    int tiles = 0, rhs0 = 0;
+    int lt = 0, dt = 0, rhs0 = 0;
     for (int i = 0; i < nprob; i++) {
         const lgt_cg_problem &q = probs[i];
         lgt_ctx *c = q.ctx;
@@ -149,54 +156,66 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         BatchProb &P = ha->prob[i];
         P.g = c->g;
         P.logN = logN;
-        P.tile0 = tiles;
-        P.ntiles = (int)((n + kBS - 1) / kBS);
+        // inner Dslash engine: four-lane groups for F32/BF16 links and N >= 4
+        P.eng = MRHS_LANE;
+        if (mixed && logN >= 2 && c0->mrhs_engine != MRHS_LANE)
+            P.eng = (c0->mrhs_engine == MRHS_MFMA && c->g.Vh % 16 == 0) ? MRHS_MFMA : MRHS_VALU4;
+        P.lt0 = lt;
+        P.nlt = (int)((n + kBB - 1) / kBB);
+        P.dt0 = dt;
+        if (P.eng == MRHS_LANE) P.ndt = P.nlt;
+        else {
+            const int sites = kBB / batch_lanes_per_site(logN);
+            P.ndt = (c->g.Vh + sites - 1) / sites;
+        }
         P.rhs0 = rhs0;
         P.m4 = 4.0 * p->mass * p->mass;
         P.Uhi = q.U_hi->ptr;
         P.Ulo = mixed ? q.U_lo->ptr : q.U_hi->ptr;
-        double *b64 = (double *)workspace(c, "batch.b64", v64);
-        P.x64 = (double *)workspace(c, "batch.x64", v64);
-        P.t64 = (double *)workspace(c, "batch.t64", v64);
-        P.q64 = (double *)workspace(c, "batch.q64", v64);
-        P.r = workspace(c, "batch.r", vlo);
-        P.pa = workspace(c, "batch.pa", vlo);
-        P.pb = workspace(c, "batch.pb", vlo);
-        P.Ap = workspace(c, "batch.Ap", vlo);
-        P.t = workspace(c, "batch.t", vlo);
-        P.xlo = mixed ? workspace(c, "batch.xlo", vlo) : (void *)P.x64;
-        P.st = (CgState *)workspace(c, "batch.state", sizeof(CgState) * kMaxRhs);
-        P.b64 = b64;
-        if (!b64 || !P.x64 || !P.t64 || !P.q64 || !P.r || !P.pa || !P.pb || !P.Ap || !P.t || !P.xlo || !P.st)
+        // buffers are named per problem index: one context may serve several problems
+        auto ws = [&](const char *what, size_t bytes) {
+            char name[48];
+            std::snprintf(name, sizeof(name), "batch.%s.%d", what, i);
+            return workspace(c, name, bytes);
+        };
+        P.b64 = (const double *)ws("b64", v64);
+        P.x64 = (double *)ws("x64", v64);
+        P.t64 = (double *)ws("t64", v64);
+        P.r = ws("r", vlo);
+        P.pa = ws("pa", vlo);
+        P.pb = ws("pb", vlo);
+        P.Ap = ws("Ap", vlo);
+        P.t = ws("t", vlo);
+        P.xlo = mixed ? ws("xlo", vlo) : (void *)P.x64;
+        if (!P.b64 || !P.x64 || !P.t64 || !P.r || !P.pa || !P.pb || !P.Ap || !P.t || !P.xlo)
             return fail(LGT_ERR_OOM, "cannot allocate the batch workspace of problem %d", i);
-        tiles += P.ntiles;
+        lt += P.nlt;
+        dt += P.ndt;
         rhs0 += q.nrhs;
     }
+    int grid = ncu;
+    const int most = lt > dt ? lt : dt;
+    if (grid > most) grid = most; // more workgroups than tiles only add barrier arrivals
+    if (grid < 1) grid = 1;
     ha->nprob = nprob;
-    ha->total_tiles = tiles;
-    ha->total_rhs = rhs0;
+    ha->total_lt = lt;
+    ha->total_dt = dt;
+    ha->total_rhs = total_rhs;
     ha->scheme = p->scheme;
     ha->ru_interval = p->scheme == LGT_CG_RELIABLE ? p->ru_interval : 1 << 30;
     ha->max_iter = p->max_iter;
-    ha->spin_limit = 1u << 25; // ~2 s of polling: far beyond any phase of a valid launch
-    double *part = (double *)workspace(c0, "batch.partials", sizeof(double) * (size_t)tiles * kMaxRhs);
+    ha->tol = p->tol;
+    ha->inner = p->scheme == LGT_CG_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
+    ha->spin_limit = 1u << 21; // seconds of polling: far beyond any phase of a valid launch
+    CgState *states = (CgState *)workspace(c0, "batch.states", sizeof(CgState) * (size_t)total_rhs);
+    double *rows = (double *)workspace(c0, "batch.rows", 2 * sizeof(double) * (size_t)grid * total_rhs);
     BatchCtl *ctl = (BatchCtl *)workspace(c0, "batch.ctl", sizeof(BatchCtl));
     BatchArgs *da = (BatchArgs *)workspace(c0, "batch.args", sizeof(BatchArgs));
-    if (!part || !ctl || !da) return fail(LGT_ERR_OOM, "cannot allocate the batch control buffers");
-    ha->partials = part;
+    if (!states || !rows || !ctl || !da) return fail(LGT_ERR_OOM, "cannot allocate the batch control buffers");
+    ha->states = states;
+    ha->rows[0] = rows;
+    ha->rows[1] = rows + (size_t)grid * total_rhs;
     ha->ctl = ctl;
-
-    // grid: every workgroup must be resident at once (cooperative launch)
-    int coop = 0, ncu = 0;
-    LGT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c0->device));
-    if (!coop) return fail(LGT_ERR_UNSUPPORTED, "device does not support cooperative launches");
-    LGT_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c0->device));
-    const int per_cu = batch_cg_max_blocks_per_cu(mixed ? flo : F64R18);
-    if (per_cu < 1) return fail(LGT_ERR_DEVICE, "cannot size the batched launch");
-    int grid = per_cu * ncu;
-    if (grid > 2 * ncu) grid = 2 * ncu; // two workgroups per CU: fewer arrivals per grid barrier
-    if (grid > tiles) grid = tiles;
-    if (grid < 1) grid = 1;
 
     hipEvent_t e0, e1;
     LGT_HIP(hipEventCreate(&e0));
@@ -228,19 +247,14 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     }
     LGT_HIP(launch_zero(ctl, sizeof(BatchCtl), s));
     LGT_HIP(hipMemcpyAsync(da, ha, sizeof(BatchArgs), hipMemcpyHostToDevice, s));
-    const double inner = p->scheme == LGT_CG_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
-    LGT_HIP(launch_batch_cg_init(da, ha->total_rhs, p->tol, inner, s));
     LGT_HIP(launch_batch_cg(mixed ? flo : F64R18, da, grid, s));
     for (int i = 0; i < nprob; i++) {
         const lgt_cg_problem &q = probs[i];
         LGT_HIP(launch_unpack_mrhs(true, ha->prob[i].x64, q.x, q.ctx->g, ha->prob[i].logN, s));
     }
     LGT_HIP(hipEventRecord(e1, s));
-    // read back states and control words (pinned staging after the args)
-    std::vector<CgState> states((size_t)ha->total_rhs);
-    for (int i = 0; i < nprob; i++)
-        LGT_HIP(hipMemcpyAsync(&states[ha->prob[i].rhs0], ha->prob[i].st, sizeof(CgState) * probs[i].nrhs,
-                               hipMemcpyDeviceToHost, s));
+    std::vector<CgState> st((size_t)total_rhs);
+    LGT_HIP(hipMemcpyAsync(st.data(), states, sizeof(CgState) * (size_t)total_rhs, hipMemcpyDeviceToHost, s));
     BatchCtl hc;
     LGT_HIP(hipMemcpyAsync(&hc, ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
     LGT_HIP(hipStreamSynchronize(s));
@@ -251,7 +265,7 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     lgt_status ret = LGT_OK;
     for (int i = 0; i < nprob; i++) {
         for (int j = 0; j < probs[i].nrhs; j++) {
-            const CgState &e = states[(size_t)ha->prob[i].rhs0 + j];
+            const CgState &e = st[(size_t)ha->prob[i].rhs0 + j];
             lgt_cg_result r;
             std::memset(&r, 0, sizeof(r));
             r.iters = e.iter;

@@ -14,44 +14,57 @@
 
 namespace lgt {
 
-constexpr int kMaxRhs = 16;       // right-hand sides per problem (power of two)
-constexpr int kMaxProblems = 64;  // problems per batched launch
+constexpr int kMaxRhs = 16;        // right-hand sides per problem (power of two)
+constexpr int kMaxProblems = 64;   // problems per batched launch
+constexpr int kMaxTotalRhs = 256;  // right-hand sides per batched launch
+constexpr int kBB = 1024;          // threads per workgroup of the batched solver
+// lanes per site of the four-lane engines in the batched solver: groups of
+// 4 lanes, R right-hand sides per lane (R = 1 for N = 4, else 2)
+inline int batch_lanes_per_site(int logN) { return logN <= 3 ? 4 : 8; }
 
+// One problem of a batched solve. Two tilings of its (site, rhs) pairs:
+// lane tiles of kBB pairs (BLAS steps, FP64 Dslash, inner Dslash of the lane
+// engine) and, for the four-lane engines, inner-Dslash tiles of
+// kBB / batch_lanes_per_site sites.
 struct BatchProb {
     Geom g;
-    int logN;     // log2 of the number of right-hand sides
-    int tile0;    // first global tile of this problem (a tile = 256 threads)
-    int ntiles;   // tiles of this problem: ceil(V/2 * N / 256)
-    int rhs0;     // first global right-hand-side index
-    double m4;    // 4 m^2
+    int logN;    // log2 of the number of right-hand sides
+    int eng;     // inner Dslash engine (MrhsEngine)
+    int lt0, nlt; // first global lane tile, lane tiles
+    int dt0, ndt; // first global inner-Dslash tile, inner-Dslash tiles
+    int rhs0;    // first global right-hand-side index
+    int pad;
+    double m4;   // 4 m^2
     const void *Ulo, *Uhi;
-    // FP64 multi-RHS vectors
-    const double *b64;
-    double *x64, *t64, *q64;
-    // inner-precision multi-RHS vectors (FP32 for F32/BF16 links, FP64 otherwise)
-    void *r, *pa, *pb, *Ap, *t, *xlo;
-    CgState *st; // N states
+    const double *b64;          // FP64 multi-RHS vectors
+    double *x64, *t64;
+    void *r, *pa, *pb, *Ap, *t, *xlo; // inner-precision multi-RHS vectors (xlo = x64 for FP64)
 };
 
 // Control words of a persistent launch (device memory, zeroed by the host).
+// Arrival counters only grow: the last arrival of a barrier is the one that
+// brings a counter to a multiple of its group size.
 struct BatchCtl {
-    unsigned int bar_count;
-    unsigned int bar_gen;
-    unsigned int err;         // 1: a barrier wait exceeded its spin limit
-    unsigned int iters_done;  // outer loop trips performed
-    unsigned int active[2];   // right-hand sides still iterating, per loop parity
-    unsigned int need_ru[2];  // right-hand sides waiting for an FP64 update
+    unsigned int gen;        // barrier generation
+    unsigned int top;        // group leaders arrived
+    unsigned int err;        // 1: a barrier wait exceeded its spin limit
+    unsigned int iters_done; // outer loop trips performed
+    unsigned int pad[12];
+    unsigned int grp[8][16]; // per-XCD arrival counters, one 64-byte line each
 };
 
 struct BatchArgs {
     BatchProb prob[kMaxProblems];
     int nprob;
-    int total_tiles;
+    int total_lt, total_dt;
     int total_rhs;
     int scheme;
     int ru_interval;
     int max_iter;
-    double *partials; // [total_tiles][kMaxRhs]
+    int pad;
+    double tol, inner;  // relative tolerance; REFINE inner tolerance or RELIABLE factor
+    CgState *states;    // [total_rhs], written at the end of the launch
+    double *rows[2];    // partial-sum rows [grid][total_rhs], two buffers
     BatchCtl *ctl;
     unsigned int spin_limit;
 };
@@ -69,8 +82,9 @@ hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, c
                               hipStream_t s, int engine);
 hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s);
 hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s);
-// Persistent batched CG (cooperative launch). lo = inner link format.
-hipError_t launch_batch_cg(Fmt lo, const BatchArgs *a_host, int grid, hipStream_t s);
+// Persistent batched CG (cooperative launch of `grid` workgroups of kBB
+// threads). lo = inner link format; a_dev = BatchArgs in device memory.
+hipError_t launch_batch_cg(Fmt lo, const BatchArgs *a_dev, int grid, hipStream_t s);
 int batch_cg_max_blocks_per_cu(Fmt lo);
 
 } // namespace lgt

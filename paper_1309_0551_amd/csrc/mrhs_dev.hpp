@@ -1,6 +1,13 @@
-// mrhs4.hpp -- multi-RHS Dslash with four lanes per site.
+// mrhs_dev.hpp -- device building blocks of the multi-RHS Dslash.
 //
-// A wavefront covers 16 sites; each of a site's 4 lanes owns R = N/4
+// Multi-RHS vectors hold N right-hand sides of one parity as [3][V/2][N]
+// complex (right-hand side fastest).
+//
+// One lane per (site, rhs): dslash_mrhs. The N lanes of a site read one
+// contiguous run of each input and issue the same link address, which the
+// load unit serves once.
+//
+// Four lanes per site: dslash_site4. A wavefront covers 16 sites; each of a site's 4 lanes owns R = N/4
 // consecutive right-hand sides (rhs = lane*R + r). The 4 lanes share
 // every link load and each lane's inputs are R contiguous complex numbers per
 // colour. Two engines compute the 3x3 complex products:
@@ -26,6 +33,59 @@
 #include "geom.hpp"
 
 namespace lgt {
+
+constexpr int kEven = 0, kOdd = 1; // output parity of a half-Dslash
+
+template <typename T> struct V2of;
+template <> struct V2of<double> { using type = dv2; };
+template <> struct V2of<float> { using type = fv2; };
+
+// element (colour c, site, rhs) of a multi-RHS vector; the plane base is uniform
+template <typename T>
+__device__ __forceinline__ void ldm(const void *v, size_t Vh, int logN, unsigned site, unsigned rhs, cx<T> o[3])
+{
+    using V2 = typename V2of<T>::type;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const V2 w = ld<false>((const V2 *)v + ((size_t)c * Vh << logN), (site << logN) + rhs);
+        o[c].re = w.x;
+        o[c].im = w.y;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void stm(void *v, size_t Vh, int logN, unsigned site, unsigned rhs, const cx<T> o[3])
+{
+    using V2 = typename V2of<T>::type;
+#pragma unroll
+    for (int c = 0; c < 3; c++) st<false>((V2 *)v + ((size_t)c * Vh << logN), (site << logN) + rhs, V2{o[c].re, o[c].im});
+}
+
+// D on one (site, rhs): the input at a neighbour comes from `in(site, v)`.
+template <class LF, class In>
+__device__ __forceinline__ void dslash_mrhs(const Geom &g, int par, const void *U, int cb, In in,
+                                            cx<typename LF::real> acc[3])
+{
+    using T = typename LF::real;
+    const size_t Vh = (size_t)g.Vh;
+    int c[4];
+    decode(g, par, cb, c);
+#pragma unroll
+    for (int i = 0; i < 3; i++) acc[i].re = acc[i].im = T(0);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; mu++) {
+        const Hop h = hop_rt(g, c, cb, mu);
+        cx<T> u[9], v[3];
+        LF::template load<false>(U, Vh, par * 4 + mu, cb, u);
+        in(h.f, v);
+        negate_if(h.fneg, v);
+        mv_add(u, v, acc);
+        LF::template load<false>(U, Vh, (1 - par) * 4 + mu, h.b, u);
+        in(h.b, v);
+        negate_if(h.bneg, v);
+        amv_sub(u, v, acc);
+    }
+}
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 

@@ -3,11 +3,17 @@
 Workload: 32^4 lattice, Haar-random SU(3) links, m = 0.01, one Gaussian source
 on the even sites, x0 = 0, stop at 1e-10 true relative residual.
 
-One step = the whole hot path on that workload:
+One step = the whole hot path:
   1. FP64 even-odd CG (FP64 links and vectors),
   2. mixed CG: FP32 12-real links, FP32 vectors, FP64 reliable update every 50,
   3. mixed CG: BF16 12-real links, FP32 vectors, FP64 iterative refinement
-     (inner relative tolerance 0.1).
+     (inner relative tolerance 0.1),
+  4. batched CG in one persistent launch: 24^3x48 with 16 right-hand sides,
+     then 8^4, 12^4 and 16^3x32 with 4 each (Haar links, m = 0.02, FP32-12
+     with FP64 reliable updates every 50; multi-RHS Dslash on MFMA),
+  5. S = phi^dag A^-1 phi and dS/dU at 16^3x32 (links exp(0.5 i H),
+     m = 0.05) through the autograd function: FP64 CG forward, fermion-force
+     kernel backward.
 `value` is the FP64 Dslash bandwidth in algorithmic bytes (8 links + the
 input vector read once + the output written once per site) over the kernel
 time, where the kernel time is measured with HIP events that the library
@@ -121,6 +127,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in Dslash variants")
+    ap.add_argument("--no-singles", action="store_true",
+                    help="skip the one-time comparison of the batched solves with single solves")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave the batched solves out of the step (short runs under hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (the domain-decomposed "
@@ -169,6 +179,46 @@ def main():
                         "tune_us": {"%d/%d" % k: round(v, 2) for k, v in tune.items()} if tune else None}
         log(f"dslash {name}: {dslash[name]}")
 
+    # ---- batching workload (row a8)
+    c4, c4m = li.CONFIGS["c4_24x24x24x48"], li.CONFIGS["c4_mixed"]
+    batch_lat = []
+
+    def batch_problem(Lb, link_seed, src_seed, nrhs):
+        lb = P.Lattice(Lb, device=0)
+        Ub = torch.from_numpy(li.links(Lb, "haar", link_seed)).to(dev)
+        bb = torch.from_numpy(li.vectors(Lb, src_seed, nrhs)).to(dev)
+        uh, ul = lb.pack_links(Ub, P.LGT_F64, P.LGT_R18), lb.pack_links(Ub, P.LGT_F32, P.LGT_R12)
+        batch_lat.append(lb)
+        return (lb, uh, ul, bb)
+
+    big = [batch_problem(c4["L"], c4["link_seed"], c4["src_seed"], c4["nrhs"])]
+    mixed = [batch_problem(Lm, sd, sd + c4m["src_seed_offset"], c4m["nrhs"]) for Lm, sd in c4m["members"]]
+    torch.cuda.synchronize()
+
+    def batched():
+        out = {}
+        for key, probs in (("24x24x24x48_x16", big), ("mixed_8x8x8x8_12x12x12x12_16x16x16x32_x4", mixed)):
+            t0 = time.perf_counter()
+            _, res = P.cg_solve_batch(probs, c4["mass"], tol=c4["tol"], scheme=P.LGT_CG_RELIABLE, ru_interval=50)
+            out[key] = (time.perf_counter() - t0, res)
+        return out
+
+    # ---- differentiation workload (row a9)
+    c5 = li.CONFIGS["c5_16x16x16x32"]
+    flat = P.Lattice(c5["L"], device=0)
+    Uf = torch.from_numpy(li.links(c5["L"], c5["kind"], c5["link_seed"], c5["c"])).to(dev)
+    phi = torch.from_numpy(li.vector(c5["L"], c5["src_seed"])).to(dev)
+
+    def action_and_force():
+        U = Uf.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        S = P.PseudofermionAction.apply(U, phi, flat, c5["mass"])
+        t1 = time.perf_counter()
+        S.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return {"S": float(S), "forward_s": t1 - t0, "backward_s": t2 - t1, "grad_norm": float(U.grad.norm())}
+
     def solves():
         out = {}
         _, out["fp64"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
@@ -176,6 +226,9 @@ def main():
                                                  scheme=P.LGT_CG_RELIABLE, U_lo=packed["f32r12"], ru_interval=50)
         _, out["bf16r12_refine"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10,
                                                 scheme=P.LGT_CG_REFINE, U_lo=packed["bf16r12"], inner_tol=0.1)
+        if not args.no_batch:
+            out["batch"] = batched()
+        out["force"] = action_and_force()
         return out
 
     lat.set_timing(True)
@@ -207,6 +260,47 @@ def main():
     cg["speedup_f32_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["f32r12_reliable"]["seconds_median"], 3)
     cg["speedup_bf16_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["bf16r12_refine"]["seconds_median"], 3)
 
+    # batching: wall time of each batched launch vs the same right-hand sides solved one by one
+    # (the single solves run once, outside the timed steps)
+    singles = {}
+    for key, probs in (("24x24x24x48_x16", big), ("mixed_8x8x8x8_12x12x12x12_16x16x16x32_x4", mixed)):
+        if args.no_batch:
+            break
+        if args.no_singles:
+            singles[key] = None
+            continue
+        tot = 0.0
+        for lb, uh, ul, bb in probs:
+            for j in range(bb.shape[0]):
+                _, r = lb.cg_solve(uh, bb[j].contiguous(), c4["mass"], tol=c4["tol"], scheme=P.LGT_CG_RELIABLE,
+                                   U_lo=ul, ru_interval=50)
+                tot += r.seconds
+        singles[key] = tot
+    batch = {}
+    for key in singles:
+        rs = [s["batch"][key] for s in steps]
+        last = [r for per in rs[-1][1] for r in per]
+        med = statistics.median(r[0] for r in rs)
+        sg = singles[key]
+        batch[key] = {"seconds_median": round(med, 4), "sum_of_single_solves_s": None if sg is None else round(sg, 4),
+                      "speedup_vs_single_solves": None if sg is None else round(sg / med, 3),
+                      "iters_max": max(r.iters for r in last), "updates_max": max(r.updates for r in last),
+                      "true_rel_resid_max": max(r.true_rel_resid for r in last),
+                      "status_all_ok": all(r.status == 0 for r in last)}
+    # differentiation: whole S and dS/dU per step, and the force kernel alone
+    fs = [s["force"] for s in steps]
+    Upf = flat.pack_links(Uf, P.LGT_F64, P.LGT_R18)
+    Xf, _ = flat.cg_solve(Upf, phi, c5["mass"], tol=1e-12)
+    fk = statistics.median(event_times(flat, lambda: flat.force(Upf, Xf), 10, 3))
+    Vf = int(np.prod(c5["L"]))
+    force_bytes = (Vf // 2) * 96 + (Vf // 2) * alg_bytes_per_site(P.LGT_F64, P.LGT_R18) + 4 * Vf * 144 + Vf * 48
+    force = {"lattice": list(c5["L"]), "S": fs[-1]["S"],
+             "forward_s_median": round(statistics.median(f["forward_s"] for f in fs), 4),
+             "backward_s_median": round(statistics.median(f["backward_s"] for f in fs), 4),
+             # lgt_force = pack X + Y = D_oe X + outer-product kernel writing G (4 V x 144 B)
+             "lgt_force_us": round(fk * 1e3, 2),
+             "lgt_force_GBps": round(force_bytes / (fk * 1e-3) / 1e9, 1), "lgt_force_alg_bytes": force_bytes}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -223,7 +317,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"staggered Dslash in even-odd CG, {'x'.join(map(str, L))} lattice, Haar SU(3) "
                                f"links, m={args.mass}, tol 1e-10; step = FP64 CG + FP32-12 reliable-update CG "
-                               f"+ BF16-12 refinement CG", "lattice": list(L), "mass": args.mass},
+                               f"+ BF16-12 refinement CG + batched CG (24^3x48 x16; 8^4, 12^4, 16^3x32 x4) "
+                               f"+ S and dS/dU at 16^3x32", "lattice": list(L), "mass": args.mass},
         "gflops": round(gflops, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -233,11 +328,16 @@ def main():
                      "alg_bytes_per_launch": by64, "avg_launch_us": round(avg_ms * 1e3, 2),
                      "launches_timed": n_hi, "measured_ceiling_GBps": ceil},
         "cg": cg,
+        "batch": batch,
+        "force": force,
         "dslash_standalone": dslash,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     lat.close()
+    flat.close()
+    for lb in batch_lat:
+        lb.close()
 
 
 if __name__ == "__main__":

@@ -165,7 +165,7 @@ CONFIGS = {
                            link_seed=4001, src_seed=4010, nrhs=16, tol=1e-10),
     "c4_mixed": dict(members=[((8, 8, 8, 8), 4101), ((12, 12, 12, 12), 4201),
                               ((16, 16, 16, 32), 4301)],
-                     kind="haar", mass=0.02, nrhs=4, tol=1e-10),
+                     kind="haar", mass=0.02, nrhs=4, src_seed_offset=10, tol=1e-10),
     "c5_16x16x16x32": dict(L=(16, 16, 16, 32), kind="expih", c=0.5, mass=0.05,
                            link_seed=5001, src_seed=5002, fd_seed=5004, tol=1e-10),
 }

@@ -17,8 +17,8 @@ One step = the whole hot path:
 `value` is the FP64 Dslash bandwidth in algorithmic bytes (8 links + the
 input vector read once + the output written once per site) over the kernel
 time, where the kernel time is measured with HIP events that the library
-records on its own stream around every FP64 Dslash launch inside the timed
-FP64 solves. Inputs are resident in HBM before the timed region; link packing
+records on its own stream around the FP64 Dslash launches of every 16th
+iteration (and of every FP64 update) inside the timed FP64 solves. Inputs are resident in HBM before the timed region; link packing
 is done once per gauge field, outside it.
 """
 from __future__ import annotations
@@ -36,6 +36,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Dslash GB/s & GFLOP/s at 32^4; mixed-vs-FP64 CG time to 1e-10 residual"
 HBM_PEAK_GBS = 8000.0
+# Dslash kernel times come from HIP events around the Dslash pair of every
+# TIMING_EVERY-th CG iteration: each event costs a few microseconds of stream
+# time, so timing every launch would inflate the solve times it sits in.
+TIMING_EVERY = 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f64r18_32x32x32x32_traffic.txt")
 KERNEL_SOURCES = ["paper_1309_0551_amd/csrc/dslash.hip", "paper_1309_0551_amd/csrc/fields.hpp",
                   "paper_1309_0551_amd/csrc/geom.hpp", "paper_1309_0551_amd/csrc/reduce.hpp"]
@@ -231,7 +235,7 @@ def main():
         out["force"] = action_and_force()
         return out
 
-    lat.set_timing(True)
+    lat.set_timing(TIMING_EVERY)
     for _ in range(args.warmup):
         solves()
     torch.cuda.synchronize()
@@ -244,17 +248,31 @@ def main():
     ms_hi = sum(s["fp64"].dslash_ms_hi for s in steps)
     n_hi = sum(s["fp64"].dslash_timed_hi for s in steps)
     avg_ms = ms_hi / max(n_hi, 1)
-    by64 = alg_bytes_per_site(P.LGT_F64, P.LGT_R18) * Vh
+    # Algorithmic bytes of the timed FP64 launches (per output site): a CG
+    # iteration's pair is a plain D_oe and a D_eo that also reads p for 4m^2 p
+    # (+48 B); an FP64 update's pair is a plain D_oe and a D_eo reading x and b
+    # (+96 B). One update pair is timed per update.
+    base = alg_bytes_per_site(P.LGT_F64, P.LGT_R18)
+    vb = P.vec_bytes_per_site(P.LGT_F64)
+    it_pair, ru_pair = base + (base + vb), base + (base + 2 * vb)
+    n_ru = sum(s["fp64"].updates for s in steps)
+    n_it = n_hi // 2 - n_ru
+    by64 = (n_it * it_pair + n_ru * ru_pair) * Vh / max(n_hi, 1)
     gbs = by64 / (avg_ms * 1e-3) / 1e9
     gflops = P.DSLASH_FLOP_PER_SITE * Vh / (avg_ms * 1e-3) / 1e9
 
     def summ(key):
         rs = [s[key] for s in steps]
-        n = max(1, sum(r.dslash_timed_lo + r.dslash_timed_hi for r in rs))
-        return {"seconds_median": round(statistics.median(r.seconds for r in rs), 4),
-                "iters": rs[-1].iters, "updates": rs[-1].updates, "dslash_calls": rs[-1].dslash_calls,
-                "true_rel_resid": rs[-1].true_rel_resid, "status": rs[-1].status,
-                "dslash_us_avg": round(1e3 * sum(r.dslash_ms_lo + r.dslash_ms_hi for r in rs) / n, 2)}
+        nlo, nhi = sum(r.dslash_timed_lo for r in rs), sum(r.dslash_timed_hi for r in rs)
+        out = {"seconds_median": round(statistics.median(r.seconds for r in rs), 4),
+               "iters": rs[-1].iters, "updates": rs[-1].updates, "dslash_calls": rs[-1].dslash_calls,
+               "true_rel_resid": rs[-1].true_rel_resid, "status": rs[-1].status}
+        # sampled kernel times: inner-precision Dslash and FP64 Dslash (CG or FP64 updates)
+        if nlo:
+            out["dslash_lo_us_avg"] = round(1e3 * sum(r.dslash_ms_lo for r in rs) / nlo, 2)
+        if nhi:
+            out["dslash_f64_us_avg"] = round(1e3 * sum(r.dslash_ms_hi for r in rs) / nhi, 2)
+        return out
 
     cg = {k: summ(k) for k in ("fp64", "f32r12_reliable", "bf16r12_refine")}
     cg["speedup_f32_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["f32r12_reliable"]["seconds_median"], 3)
@@ -305,10 +323,10 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         n, el = cpu_baseline(L, U, b, args.cpu_budget)
-        cpu = {"value": round(by64 * n / el / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(),
+        cpu = {"value": round(base * Vh * n / el / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(),
                "kind": "oracle",
                "sample": f"{n} FP64 D_oe applications of the C oracle (OpenMP) at {'x'.join(map(str, L))} "
-                         f"in {el:.1f} s; same algorithmic bytes per application as the GPU kernel"}
+                         f"in {el:.1f} s; algorithmic bytes of a plain Dslash (1248 B/site)"}
 
     traffic = measured_traffic()
     line = {
@@ -324,8 +342,10 @@ def main():
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic,
-                     "kernel": "k_dslash<LinkF64R18,*> (FP64 D_oe and D_eo+<p,Ap>) inside the FP64 CG",
-                     "alg_bytes_per_launch": by64, "avg_launch_us": round(avg_ms * 1e3, 2),
+                     "kernel": "k_dslash<LinkF64R18,*> inside the FP64 CG: plain D_oe (1248 B/site) and "
+                               "D_eo with 4m^2 p and <p,Ap> (1296 B/site)",
+                     "alg_bytes_per_launch": round(by64), "alg_bytes_per_site": round(by64 / Vh, 1),
+                     "avg_launch_us": round(avg_ms * 1e3, 2),
                      "launches_timed": n_hi, "measured_ceiling_GBps": ceil},
         "cg": cg,
         "batch": batch,

@@ -104,9 +104,13 @@ lgt_status lgt_vec_bytes(const lgt_geom *g, int32_t prec, size_t *bytes);
  * gfx950 part (LGT_ERR_UNSUPPORTED). */
 lgt_status lgt_create(const lgt_geom *g, int32_t device, void *hip_stream, lgt_ctx **out);
 lgt_status lgt_destroy(lgt_ctx *ctx);
-/* Record HIP events around every Dslash launch inside lgt_cg_solve and report
- * the summed kernel time in lgt_cg_result (0 = off, the default). */
-lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t enable);
+/* Dslash kernel timing inside lgt_cg_solve: with every > 0, HIP events are
+ * recorded around the two Dslash launches of every `every`-th iteration of
+ * each chunk and around every FP64 update's Dslash pair, and the summed times
+ * and counts are reported in lgt_cg_result. Each recorded event costs a few
+ * microseconds of stream time, so sampling (every = 16, say) keeps the solve
+ * time representative. 0 = off (the default); negative is LGT_ERR_ARG. */
+lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t every);
 
 /* ---- kernel variants and autotuning ---------------------------------------- */
 

@@ -233,10 +233,11 @@ lgt_status lgt_destroy(lgt_ctx *c)
     return LGT_OK;
 }
 
-lgt_status lgt_set_timing(lgt_ctx *c, int32_t enable)
+lgt_status lgt_set_timing(lgt_ctx *c, int32_t every)
 {
     CHECK_CTX(c);
-    c->timing = enable != 0;
+    if (every < 0) return fail(LGT_ERR_ARG, "timing interval must be >= 0");
+    c->timing = every;
     return LGT_OK;
 }
 

@@ -28,16 +28,40 @@ __global__ __launch_bounds__(kBS) void k_xpay(VecArgs a)
     VecFmt<T>::template store<false>(a.p, (size_t)a.Vh, cb, p);
 }
 
-// x += alpha p ; r -= alpha Ap ; partial |r|^2 (FP64)
+hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
+{
+    if (f64) hipLaunchKernelGGL(k_xpay<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    else hipLaunchKernelGGL(k_xpay<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    return hipGetLastError();
+}
+
+// alpha = rho / <p, Ap>, then x += alpha p ; r -= alpha Ap ; partial |r|^2
+// (FP64). Every workgroup sums the partials of the preceding D_eo itself, in
+// k_finalize's order, so all of them get the same alpha bit for bit without a
+// launch of their own; workgroup 0 records the step in the solver state
+// (fields no other workgroup reads in this kernel). A breakdown (<p, Ap> not
+// positive or not finite) marks the state failed and skips the update.
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
 {
     if (!gate_open(a.gate, a.st)) return;
+    __shared__ double lds[kBS / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.nparts_in; i += kBS) acc += a.parts_in[i];
+    const double pAp = block_sum_all(acc, lds);
+    const bool bad = !(pAp > 0.0) || !isfinite(pAp);
+    const double alpha64 = a.st->rho / pAp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.st->pAp = pAp;
+        if (bad) a.st->state = ST_FAIL;
+        else a.st->alpha = alpha64;
+    }
+    if (bad) return;
     const int blk = blockIdx.x;
     const int cb = blk * kBS + threadIdx.x;
     double part = 0.0;
     if (cb < a.Vh) {
-        const T alpha = (T)a.st->alpha;
+        const T alpha = (T)alpha64;
         cx<T> x[3], r[3], p[3], q[3];
         VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
         VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
@@ -55,13 +79,6 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
         VecFmt<T>::template store<false>(a.r, (size_t)a.Vh, cb, r);
     }
     write_partial(part, a.partials, blk);
-}
-
-hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
-{
-    if (f64) hipLaunchKernelGGL(k_xpay<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
-    else hipLaunchKernelGGL(k_xpay<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
-    return hipGetLastError();
 }
 
 hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s)

@@ -14,7 +14,7 @@ struct lgt_ctx {
     lgt::Geom g;
     int device = 0;
     hipStream_t stream = nullptr;
-    int timing = 0;
+    int timing = 0; // Dslash timing inside CG: every n-th iteration (0 = off)
     // Dslash variant per link format: hops whose loads are issued together
     // (8 = fully unrolled, 2 = one direction per loop trip, 1 = one hop).
     // and whether link loads stream past the caches (1) or are cached (0).

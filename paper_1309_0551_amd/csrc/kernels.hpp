@@ -84,7 +84,9 @@ struct VecArgs {
     const void *Ap;
     int Vh;
     Launch l;
-    double *partials;
+    const double *parts_in; // <p, Ap> partials of the preceding D_eo
+    int nparts_in;
+    double *partials;       // |r|^2 partials written by the update
     CgState *st;
     int gate;
 };

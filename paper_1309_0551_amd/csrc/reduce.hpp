@@ -29,6 +29,17 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return s;
 }
 
+// sum over the workgroup in block_sum's order, returned to every thread
+__device__ __forceinline__ double block_sum_all(double v, double *lds)
+{
+    const double s = block_sum(v, lds);
+    if (threadIdx.x == 0) lds[0] = s;
+    __syncthreads();
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ bool gate_open(int gate, const CgState *st)
 {
     if (gate == GATE_NONE) return true;

@@ -4,8 +4,13 @@
 // beta = rho'/rho, p = r + beta p) with every scalar kept in device memory:
 // the kernels compute alpha and beta themselves from FP64 reductions, and a
 // solver state word makes every later kernel of a finished solve exit at
-// once. The host enqueues iterations in chunks and reads the state back once
-// per chunk, one chunk behind, so the GPU never waits for the host.
+// once. An iteration is five launches: p = r + beta p; D_oe; D_eo with 4m^2 p
+// and the partials of <p, Ap>; the update (which sums those partials itself
+// for alpha) with the partials of |r|^2; and the one-workgroup step for beta
+// and the stop tests. (Forming r + beta p inside D_oe instead saves the xpay
+// pass but gathers two vectors at every neighbour, which costs more cache
+// misses than the pass it saves.) The host enqueues iterations in chunks and reads the state
+// back once per chunk, one chunk behind, so the GPU never waits for the host.
 //
 // Precision forms (single precision gains more than double, Sec. 4):
 //  FP64      all in FP64; at inner convergence the true residual b - A x is
@@ -84,13 +89,16 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     void *Ap = workspace(c, "cg.Ap", vlo);
     void *t = workspace(c, "cg.t", vlo);
     void *xlo = mixed ? workspace(c, "cg.xlo", vlo) : x64;
-    double *partials = (double *)workspace(c, "cg.partials", sizeof(double) * (size_t)l.nblk_pad);
+    // two partial-sum buffers: the update reads D_eo's while writing its own
+    double *partials = (double *)workspace(c, "cg.partials", 2 * sizeof(double) * (size_t)l.nblk_pad);
+    double *partials2 = partials ? partials + l.nblk_pad : nullptr;
     CgState *dst = (CgState *)workspace(c, "cg.state", sizeof(CgState));
     CgState *host = (CgState *)pinned(c, 3 * sizeof(CgState));
     if (!b64 || !x64 || !t64 || !q64 || !r || !pp || !Ap || !t || !xlo || !partials || !dst || !host)
         return fail(LGT_ERR_OOM, "cannot allocate the solver workspace");
 
-    const bool timing = c->timing != 0;
+    const bool timing = c->timing > 0;
+    const int every = timing ? c->timing : 1; // iterations of a chunk whose Dslash pair is timed: i % every == 0
     const int pairs = 2 * chunk + 2; // event pairs per chunk: 2 Dslash per iteration + 2 in the update
     Events evs, tev;
     LGT_HIP(evs.make(4)); // 0 start, 1 end, 2/3 chunk slots
@@ -118,7 +126,9 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.ntl = c->ntl[f];
         return launch_dslash(f, epi, a, s);
     };
-    auto F = [&](int fin, int gate, int nparts) { return launch_finalize(partials, nparts, dst, fin, gate, s); };
+    auto F = [&](const double *parts, int fin, int gate, int nparts) {
+        return launch_finalize(parts, nparts, dst, fin, gate, s);
+    };
     auto timed = [&](int slot, int idx, bool begin) -> hipError_t {
         if (!timing) return hipSuccess;
         return hipEventRecord(tev.ev[((size_t)slot * pairs + idx) * 2 + (begin ? 0 : 1)], s);
@@ -130,7 +140,9 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     va.Ap = Ap;
     va.Vh = Vh;
     va.l = l;
-    va.partials = partials;
+    va.parts_in = partials;
+    va.nparts_in = l.nblk_pad;
+    va.partials = partials2;
     va.st = dst;
     va.gate = GATE_ITER;
 
@@ -151,7 +163,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
             e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr);
         if (e != hipSuccess) return e;
         if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, false)) != hipSuccess) return e;
-        return F(fin, gate, l.nblk_pad);
+        return F(partials, fin, gate, l.nblk_pad);
     };
 
     LGT_HIP(hipEventRecord(evs.ev[0], s));
@@ -178,6 +190,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         if (!timing) return hipSuccess;
         const int nreal = std::min(end.iter - prev_iter, chunk);
         for (int i = 0; i < 2 * nreal; i++) {
+            if ((i / 2) % every != 0) continue;
             float ms = 0.f;
             hipError_t e = hipEventElapsedTime(&ms, tev.ev[((size_t)slot * pairs + i) * 2],
                                                tev.ev[((size_t)slot * pairs + i) * 2 + 1]);
@@ -206,17 +219,17 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     while (!finished) {
         const int slot = k & 1;
         for (int i = 0; i < chunk; i++) {
+            const bool ti = i % every == 0;
+            const void *Ui = mixed ? Ulo->ptr : Uhi->ptr;
             LGT_HIP(launch_xpay(lo_is_f64, va, s));
-            LGT_HIP(timed(slot, 2 * i, true));
-            LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, mixed ? Ulo->ptr : Uhi->ptr, pp, t, GATE_ITER, nullptr, nullptr,
-                      nullptr));
-            LGT_HIP(timed(slot, 2 * i, false));
-            LGT_HIP(timed(slot, 2 * i + 1, true));
-            LGT_HIP(D(flo, EPI_A, LGT_EVEN, mixed ? Ulo->ptr : Uhi->ptr, t, Ap, GATE_ITER, pp, nullptr, nullptr));
-            LGT_HIP(timed(slot, 2 * i + 1, false));
-            LGT_HIP(F(FIN_ALPHA, GATE_ITER, l.nblk_pad));
+            if (ti) LGT_HIP(timed(slot, 2 * i, true));
+            LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, Ui, pp, t, GATE_ITER, nullptr, nullptr, nullptr));
+            if (ti) LGT_HIP(timed(slot, 2 * i, false));
+            if (ti) LGT_HIP(timed(slot, 2 * i + 1, true));
+            LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr));
+            if (ti) LGT_HIP(timed(slot, 2 * i + 1, false));
             LGT_HIP(launch_update(lo_is_f64, va, s));
-            LGT_HIP(F(FIN_UPDATE, GATE_ITER, l.nblk));
+            LGT_HIP(F(partials2, FIN_UPDATE, GATE_ITER, l.nblk));
         }
         LGT_HIP(reliable(GATE_RU, timing ? slot : -1, FIN_RU));
         LGT_HIP(hipMemcpyAsync(host + slot, dst, sizeof(CgState), hipMemcpyDeviceToHost, s));

@@ -235,8 +235,9 @@ class Lattice:
     def __exit__(self, *exc):
         self.close()
 
-    def set_timing(self, on: bool):
-        _check(lib().lgt_set_timing(self._ctx, int(bool(on))))
+    def set_timing(self, every):
+        """Time the Dslash launches of every `every`-th CG iteration (True = every one, 0/False = off)."""
+        _check(lib().lgt_set_timing(self._ctx, int(every)))
 
     def set_dslash_variant(self, prec: int, recon: int, hops: int, streaming: int = 1):
         _check(lib().lgt_set_dslash_variant(self._ctx, prec, recon, hops, streaming))

@@ -197,6 +197,21 @@ def main():
 
     big = [batch_problem(c4["L"], c4["link_seed"], c4["src_seed"], c4["nrhs"])]
     mixed = [batch_problem(Lm, sd, sd + c4m["src_seed_offset"], c4m["nrhs"]) for Lm, sd in c4m["members"]]
+    # autotuner: the multi-RHS tile shape of each batched lattice (its inner Dslash)
+    names = {(P.LGT_MRHS_LANE, 1): "lane", (P.LGT_MRHS_VALU4, 1): "valu4_g1", (P.LGT_MRHS_VALU4, 2): "valu4_g2",
+             (P.LGT_MRHS_VALU4, 4): "valu4_g4", (P.LGT_MRHS_MFMA, 1): "mfma_g1", (P.LGT_MRHS_MFMA, 2): "mfma_g2",
+             (P.LGT_MRHS_MFMA, 4): "mfma_g4"}
+    mrhs_tune = {}
+    for lb, uh, ul, bb in big + mixed:
+        n = int(bb.shape[0])
+        key = f"{'x'.join(map(str, lb.L))}_f32r12_N{n}"
+        if args.no_tune:
+            mrhs_tune[key] = {"chosen": names[lb.mrhs_variant(P.LGT_F32, P.LGT_R12, n)]}
+            continue
+        t = lb.tune_dslash_mrhs(ul, n)
+        mrhs_tune[key] = {"chosen": names[lb.mrhs_variant(P.LGT_F32, P.LGT_R12, n)],
+                          "us": {names[k]: round(v, 2) for k, v in t.items()}}
+        log(f"mrhs tune {key}: {mrhs_tune[key]}")
     torch.cuda.synchronize()
 
     def batched():
@@ -349,6 +364,7 @@ def main():
                      "launches_timed": n_hi, "measured_ceiling_GBps": ceil},
         "cg": cg,
         "batch": batch,
+        "mrhs_tune": mrhs_tune,
         "force": force,
         "dslash_standalone": dslash,
         "cpu_baseline": cpu,

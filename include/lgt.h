@@ -225,8 +225,29 @@ lgt_status lgt_dslash_mrhs(lgt_ctx *ctx, const lgt_links *U, int32_t out_parity,
  * per (site, right-hand side). FP64 links and nrhs < 4 always use
  * LGT_MRHS_LANE. Speed only: results agree to rounding. */
 enum { LGT_MRHS_LANE = 0, LGT_MRHS_VALU4 = 1, LGT_MRHS_MFMA = 2 };
+/* Sets the engine for every link format and nrhs, with one group of four
+ * lanes per site (R = nrhs / 4 right-hand sides per lane). */
 lgt_status lgt_set_mrhs_engine(lgt_ctx *ctx, int32_t engine);
 lgt_status lgt_get_mrhs_engine(lgt_ctx *ctx, int32_t *engine);
+/* Variant for one (link format, nrhs): the engine and, for the four-lane
+ * engines, `groups` = 1, 2 or 4 groups of four lanes per site, each lane then
+ * holding R = nrhs / (4 groups) >= 1 right-hand sides (otherwise LGT_ERR_ARG).
+ * The get call reports the variant lgt_dslash_mrhs actually runs on this
+ * lattice (LGT_MRHS_LANE, groups 1, where the engine does not apply). The
+ * batched solver runs the four-lane engines with 1 group for nrhs = 4, 1 or 2
+ * for 8, and 2 or 4 for 16 (a request for 1 group at 16 runs 2). */
+lgt_status lgt_set_mrhs_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t engine,
+                                int32_t groups);
+lgt_status lgt_get_mrhs_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t *engine,
+                                int32_t *groups);
+/* Autotuner of the multi-RHS tile shape: times every variant that applies to
+ * U's format and nrhs on this lattice (10 launches each, alternating output
+ * parity, zero input), keeps the fastest for that (format, nrhs) in the
+ * context, and with LGT_TUNE_CACHE set caches it like lgt_tune_dslash.
+ * times_us: NULL, or 7 doubles in this order: lane; VALU with 1, 2, 4 groups;
+ * MFMA with 1, 2, 4 groups (-1 where a variant does not apply). Uses scratch
+ * vectors of the context; synchronous. */
+lgt_status lgt_tune_dslash_mrhs(lgt_ctx *ctx, const lgt_links *U, int32_t nrhs, double times_us[7]);
 
 typedef struct {
     lgt_ctx *ctx;          /* the problem's lattice; all problems on one device */

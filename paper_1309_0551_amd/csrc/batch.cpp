@@ -61,6 +61,46 @@ lgt_status lgt_set_mrhs_engine(lgt_ctx *c, int32_t engine)
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
     if (engine < LGT_MRHS_LANE || engine > LGT_MRHS_MFMA) return fail(LGT_ERR_ARG, "bad engine %d", engine);
     c->mrhs_engine = engine;
+    for (int f = 0; f < FMT_COUNT; f++)
+        for (int l = 0; l < 5; l++) {
+            c->mrhs_eng[f][l] = engine;
+            c->mrhs_gps[f][l] = 1;
+        }
+    return LGT_OK;
+}
+
+lgt_status lgt_set_mrhs_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t nrhs, int32_t engine,
+                                int32_t groups)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (engine < LGT_MRHS_LANE || engine > LGT_MRHS_MFMA) return fail(LGT_ERR_ARG, "bad engine %d", engine);
+    if (engine != LGT_MRHS_LANE && !mrhs_groups_valid(logN, groups))
+        return fail(LGT_ERR_ARG, "groups must be 1, 2 or 4 with 4 * groups <= nrhs");
+    c->mrhs_eng[f][logN] = engine;
+    c->mrhs_gps[f][logN] = engine == LGT_MRHS_LANE ? 1 : groups;
+    return LGT_OK;
+}
+
+lgt_status lgt_get_mrhs_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t nrhs, int32_t *engine,
+                                int32_t *groups)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (!engine || !groups) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    // the variant lgt_dslash_mrhs runs on this lattice
+    const int e = c->mrhs_eng[f][logN];
+    const bool four = mrhs_engine_applies(f, logN, c->g.Vh, e);
+    *engine = four ? e : LGT_MRHS_LANE;
+    *groups = four && mrhs_groups_valid(logN, c->mrhs_gps[f][logN]) ? c->mrhs_gps[f][logN] : 1;
     return LGT_OK;
 }
 
@@ -88,7 +128,8 @@ lgt_status lgt_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t out_parity, i
     if ((s = check_ptr(out, "out")) != LGT_OK) return s;
     if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
     DeviceScope ds(c->device);
-    LGT_HIP(launch_dslash_mrhs(f, U->ptr, in, out, c->g, out_parity, logN, c->stream, c->mrhs_engine));
+    LGT_HIP(launch_dslash_mrhs(f, U->ptr, in, out, c->g, out_parity, logN, c->stream, c->mrhs_eng[f][logN],
+                               c->mrhs_gps[f][logN]));
     return LGT_OK;
 }
 
@@ -157,15 +198,23 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         P.g = c->g;
         P.logN = logN;
         // inner Dslash engine: four-lane groups for F32/BF16 links and N >= 4
+        // (the variant this problem's context keeps for the inner format and N)
         P.eng = MRHS_LANE;
-        if (mixed && logN >= 2 && c0->mrhs_engine != MRHS_LANE)
-            P.eng = (c0->mrhs_engine == MRHS_MFMA && c->g.Vh % 16 == 0) ? MRHS_MFMA : MRHS_VALU4;
+        P.gps = 1;
+        if (mixed && mrhs_engine_applies(flo, logN, c->g.Vh, c->mrhs_eng[flo][logN])) {
+            P.eng = c->mrhs_eng[flo][logN];
+            P.gps = batch_groups(logN, c->mrhs_gps[flo][logN]);
+        } else if (mixed && c->mrhs_eng[flo][logN] == MRHS_MFMA &&
+                   mrhs_engine_applies(flo, logN, c->g.Vh, MRHS_VALU4)) {
+            P.eng = MRHS_VALU4; // MFMA needs V/2 % 16 == 0
+            P.gps = batch_groups(logN, c->mrhs_gps[flo][logN]);
+        }
         P.lt0 = lt;
         P.nlt = (int)((n + kBB - 1) / kBB);
         P.dt0 = dt;
         if (P.eng == MRHS_LANE) P.ndt = P.nlt;
         else {
-            const int sites = kBB / batch_lanes_per_site(logN);
+            const int sites = kBB / (4 * P.gps);
             P.ndt = (c->g.Vh + sites - 1) / sites;
         }
         P.rhs0 = rhs0;

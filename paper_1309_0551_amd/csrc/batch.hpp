@@ -18,22 +18,29 @@ constexpr int kMaxRhs = 16;        // right-hand sides per problem (power of two
 constexpr int kMaxProblems = 64;   // problems per batched launch
 constexpr int kMaxTotalRhs = 256;  // right-hand sides per batched launch
 constexpr int kBB = 1024;          // threads per workgroup of the batched solver
-// lanes per site of the four-lane engines in the batched solver: groups of
-// 4 lanes, R right-hand sides per lane (R = 1 for N = 4, else 2)
-inline int batch_lanes_per_site(int logN) { return logN <= 3 ? 4 : 8; }
+// Groups of four lanes per site the batched solver can run for N = 2^logN
+// right-hand sides (R = N / (4 groups) per lane): N = 4: 1; N = 8: 1 or 2;
+// N = 16: 2 or 4 (R = 4 needs more registers than its 1024-thread
+// workgroups leave, so a request for 1 group at N = 16 becomes 2).
+inline int batch_groups(int logN, int gps)
+{
+    if (logN <= 2) return 1;
+    if (logN == 3) return gps == 2 ? 2 : 1;
+    return gps == 4 ? 4 : 2;
+}
 
 // One problem of a batched solve. Two tilings of its (site, rhs) pairs:
 // lane tiles of kBB pairs (BLAS steps, FP64 Dslash, inner Dslash of the lane
 // engine) and, for the four-lane engines, inner-Dslash tiles of
-// kBB / batch_lanes_per_site sites.
+// kBB / (4 gps) sites.
 struct BatchProb {
     Geom g;
     int logN;    // log2 of the number of right-hand sides
     int eng;     // inner Dslash engine (MrhsEngine)
+    int gps;     // four-lane engines: groups of four lanes per site (batch_groups)
     int lt0, nlt; // first global lane tile, lane tiles
     int dt0, ndt; // first global inner-Dslash tile, inner-Dslash tiles
     int rhs0;    // first global right-hand-side index
-    int pad;
     double m4;   // 4 m^2
     const void *Ulo, *Uhi;
     const double *b64;          // FP64 multi-RHS vectors
@@ -76,10 +83,13 @@ struct BatchArgs {
 enum MrhsEngine { MRHS_LANE = 0, MRHS_VALU4 = 1, MRHS_MFMA = 2 };
 inline bool fmt_is_f64_fmt(Fmt f) { return f == F64R18 || f == F64R12; }
 bool mrhs_engine_applies(Fmt f, int logN, int Vh, int engine);
+// groups of four lanes per site for the four-lane engines: 1, 2 or 4, with
+// R = N / (4 groups) >= 1 right-hand sides per lane
+bool mrhs_groups_valid(int logN, int gps);
 
 // Standalone multi-RHS Dslash (plain epilogue): out = D in, N right-hand sides.
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                              hipStream_t s, int engine);
+                              hipStream_t s, int engine, int gps);
 hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s);
 hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s);
 // Persistent batched CG (cooperative launch of `grid` workgroups of kBB

@@ -149,13 +149,12 @@ template <int R> __device__ __forceinline__ void flush_acc(Shared &S, double v[4
     for (int r = 0; r < 4; r++) v[r] = 0.0;
 }
 
-// flush for problem P: groups of four lanes (R right-hand sides per lane:
-// 1 for N = 4, else 2; 4 R lanes per group) or one lane per rhs
+// flush for problem P: groups of four lanes (R = N / (4 gps) right-hand sides
+// per lane, N / R lanes per site) or one lane per rhs
 __device__ __forceinline__ void flush_prob(Shared &S, double v[4], const BatchProb &P, bool four)
 {
     const int N = 1 << P.logN;
-    if (!four) flush_acc<1>(S, v, N, P.rhs0);
-    else if (N == 4) flush_acc<1>(S, v, 4, P.rhs0);
+    if (!four || N == 4 * P.gps) flush_acc<1>(S, v, N, P.rhs0);
     else flush_acc<2>(S, v, N / 2, P.rhs0);
 }
 
@@ -353,9 +352,11 @@ __device__ __forceinline__ void step1(const BatchProb &P, const Shared &S, int d
     if constexpr (!std::is_same<typename LF::real, double>::value) {
         if (P.eng != MRHS_LANE) {
             const bool mf = P.eng == MRHS_MFMA;
-            if (P.logN == 2) mf ? step1_four<LF, 1, 1, true>(P, S, dt, pold, pnew) : step1_four<LF, 1, 1, false>(P, S, dt, pold, pnew);
-            else if (P.logN == 3) mf ? step1_four<LF, 2, 1, true>(P, S, dt, pold, pnew) : step1_four<LF, 2, 1, false>(P, S, dt, pold, pnew);
-            else mf ? step1_four<LF, 2, 2, true>(P, S, dt, pold, pnew) : step1_four<LF, 2, 2, false>(P, S, dt, pold, pnew);
+#define LGT_STEP1(R, G) (mf ? step1_four<LF, R, G, true>(P, S, dt, pold, pnew) : step1_four<LF, R, G, false>(P, S, dt, pold, pnew))
+            if (P.logN == 2) LGT_STEP1(1, 1);
+            else if (P.logN == 3) P.gps == 2 ? LGT_STEP1(1, 2) : LGT_STEP1(2, 1);
+            else P.gps == 4 ? LGT_STEP1(1, 4) : LGT_STEP1(2, 2);
+#undef LGT_STEP1
             return;
         }
     }
@@ -368,9 +369,11 @@ __device__ __forceinline__ void step2(const BatchProb &P, const Shared &S, int d
     if constexpr (!std::is_same<typename LF::real, double>::value) {
         if (P.eng != MRHS_LANE) {
             const bool mf = P.eng == MRHS_MFMA;
-            if (P.logN == 2) mf ? step2_four<LF, 1, 1, true>(P, S, dt, pnew, v) : step2_four<LF, 1, 1, false>(P, S, dt, pnew, v);
-            else if (P.logN == 3) mf ? step2_four<LF, 2, 1, true>(P, S, dt, pnew, v) : step2_four<LF, 2, 1, false>(P, S, dt, pnew, v);
-            else mf ? step2_four<LF, 2, 2, true>(P, S, dt, pnew, v) : step2_four<LF, 2, 2, false>(P, S, dt, pnew, v);
+#define LGT_STEP2(R, G) (mf ? step2_four<LF, R, G, true>(P, S, dt, pnew, v) : step2_four<LF, R, G, false>(P, S, dt, pnew, v))
+            if (P.logN == 2) LGT_STEP2(1, 1);
+            else if (P.logN == 3) P.gps == 2 ? LGT_STEP2(1, 2) : LGT_STEP2(2, 1);
+            else P.gps == 4 ? LGT_STEP2(1, 4) : LGT_STEP2(2, 2);
+#undef LGT_STEP2
             return;
         }
     }

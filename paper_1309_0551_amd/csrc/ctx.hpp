@@ -24,8 +24,15 @@ struct lgt_ctx {
     // 256 MB Infinity Cache: FP32x12 42 -> 34 us, BF16x12 25 -> 20 us).
     int hpi[lgt::FMT_COUNT] = {2, 2, 8, 8, 8};
     int ntl[lgt::FMT_COUNT] = {1, 1, 0, 0, 0};
-    // multi-RHS Dslash engine (0 lane per RHS, 1 four-lane VALU, 2 four-lane MFMA)
+    // multi-RHS Dslash: engine (0 lane per RHS, 1 four-lane VALU, 2 four-lane
+    // MFMA) last set for all cases, and the variant per (link format, log2 N):
+    // engine and groups of four lanes per site. Set by lgt_set_mrhs_engine,
+    // lgt_set_mrhs_variant or lgt_tune_dslash_mrhs.
     int mrhs_engine = 2;
+    int mrhs_eng[lgt::FMT_COUNT][5] = {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2},
+                                       {2, 2, 2, 2, 2}};
+    int mrhs_gps[lgt::FMT_COUNT][5] = {{1, 1, 1, 1, 1}, {1, 1, 1, 1, 1}, {1, 1, 1, 1, 1}, {1, 1, 1, 1, 1},
+                                       {1, 1, 1, 1, 1}};
     struct Buf {
         void *ptr = nullptr;
         size_t bytes = 0;

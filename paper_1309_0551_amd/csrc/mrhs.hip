@@ -28,47 +28,53 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs(const void *__restrict__ U,
     stm<T>(out, Vh, logN, site, rhs, acc);
 }
 
-// four lanes per site, R right-hand sides per lane, VALU or MFMA engine
-template <class LF, int R, bool MFMA>
+// GPS groups of four lanes per site, R right-hand sides per lane (N = 4 GPS R),
+// VALU or MFMA engine. Lane l of a site's 4 GPS lanes owns right-hand sides
+// l R .. l R + R - 1; each group of four is one MFMA block.
+template <class LF, int R, int GPS, bool MFMA>
 __global__ __launch_bounds__(kBS) void k_dslash_mrhs4(const void *__restrict__ U, const void *__restrict__ in,
                                                       void *__restrict__ out, Geom g, int par, int logN, int nblk_pad)
 {
+    constexpr unsigned LPS = 4 * GPS;
     const unsigned idx = (unsigned)xcd_block(blockIdx.x, nblk_pad) * kBS + threadIdx.x;
-    const unsigned site = idx >> 2, lane4 = idx & 3u;
-    // the 4 lanes of a site and the 16 sites of a wavefront stay together, and
-    // a wavefront is never split by the bound below (Vh is a multiple of 16
+    const unsigned site = idx / LPS, lane4 = idx & 3u;
+    // the lanes of a site and the 64 / LPS sites of a wavefront stay together,
+    // and a wavefront is never split by the bound below (Vh is a multiple of 16
     // whenever the MFMA engine is used: checked on the host)
     if (site >= (unsigned)g.Vh) return;
     const size_t Vh = (size_t)g.Vh;
-    const unsigned rhs0 = lane4 * R;
+    const unsigned rhs0 = (idx % LPS) * R;
     auto IN = [=](int s, cx<float> v[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(in, Vh, logN, s, rhs0, v); };
     cx<float> acc[R][3];
     dslash_site4<LF, R, MFMA>(g, par, U, site, lane4, IN, acc);
     stm_r<float, R>(out, Vh, logN, site, rhs0, acc);
 }
 
-template <class LF>
-static hipError_t launch_mrhs4(int engine, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                               hipStream_t s)
+template <class LF, int R, int GPS>
+static void launch_mrhs4_rg(bool mf, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
+                            hipStream_t s)
 {
-    const int64_t n = (int64_t)g.Vh * 4;
+    const int64_t n = (int64_t)g.Vh * 4 * GPS;
     const int nblk = (int)((n + kBS - 1) / kBS);
     const int pad = (nblk + 7) / 8 * 8;
     const dim3 grid(pad), block(kBS);
+    if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+    else hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+}
+
+template <class LF>
+static hipError_t launch_mrhs4(int engine, int gps, const void *U, const void *in, void *out, const Geom &g, int par,
+                               int logN, hipStream_t s)
+{
     const bool mf = engine == MRHS_MFMA;
-    switch (logN) {
-    case 2:
-        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, 1, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-        else hipLaunchKernelGGL((k_dslash_mrhs4<LF, 1, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-        break;
-    case 3:
-        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, 2, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-        else hipLaunchKernelGGL((k_dslash_mrhs4<LF, 2, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-        break;
-    case 4:
-        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, 4, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-        else hipLaunchKernelGGL((k_dslash_mrhs4<LF, 4, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-        break;
+    const int key = logN * 8 + gps;
+    switch (key) {
+    case 2 * 8 + 1: launch_mrhs4_rg<LF, 1, 1>(mf, U, in, out, g, par, logN, s); break;
+    case 3 * 8 + 1: launch_mrhs4_rg<LF, 2, 1>(mf, U, in, out, g, par, logN, s); break;
+    case 3 * 8 + 2: launch_mrhs4_rg<LF, 1, 2>(mf, U, in, out, g, par, logN, s); break;
+    case 4 * 8 + 1: launch_mrhs4_rg<LF, 4, 1>(mf, U, in, out, g, par, logN, s); break;
+    case 4 * 8 + 2: launch_mrhs4_rg<LF, 2, 2>(mf, U, in, out, g, par, logN, s); break;
+    case 4 * 8 + 4: launch_mrhs4_rg<LF, 1, 4>(mf, U, in, out, g, par, logN, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -80,14 +86,20 @@ bool mrhs_engine_applies(Fmt f, int logN, int Vh, int engine)
     return engine == MRHS_VALU4 || (Vh % 16) == 0;
 }
 
+bool mrhs_groups_valid(int logN, int gps)
+{
+    return (gps == 1 || gps == 2 || gps == 4) && 4 * gps <= (1 << logN);
+}
+
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                              hipStream_t s, int engine)
+                              hipStream_t s, int engine, int gps)
 {
     if (mrhs_engine_applies(f, logN, g.Vh, engine)) {
+        if (!mrhs_groups_valid(logN, gps)) gps = 1;
         switch (f) {
-        case F32R18: return launch_mrhs4<LinkF32R18>(engine, U, in, out, g, par, logN, s);
-        case F32R12: return launch_mrhs4<LinkF32R12>(engine, U, in, out, g, par, logN, s);
-        case BF16R12: return launch_mrhs4<LinkBF16R12>(engine, U, in, out, g, par, logN, s);
+        case F32R18: return launch_mrhs4<LinkF32R18>(engine, gps, U, in, out, g, par, logN, s);
+        case F32R12: return launch_mrhs4<LinkF32R12>(engine, gps, U, in, out, g, par, logN, s);
+        case BF16R12: return launch_mrhs4<LinkBF16R12>(engine, gps, U, in, out, g, par, logN, s);
         default: break;
         }
     }

@@ -9,6 +9,12 @@
 // environment variable LGT_TUNE_CACHE naming a file, results persist per
 // (device architecture, lattice, format) and later contexts reuse them
 // (LGT_TUNE=force re-times).
+//
+// The multi-RHS Dslash is tuned the same way per (format, N): one lane per
+// (site, rhs), or groups of four lanes per site (1, 2 or 4 groups, R = N / (4
+// groups) right-hand sides per lane) on the VALU or on MFMA -- the tile shape
+// trades link-load instructions per site (fewer groups) against registers per
+// lane (larger R).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -18,6 +24,7 @@
 #include <sstream>
 #include <string>
 
+#include "batch.hpp"
 #include "ctx.hpp"
 
 using namespace lgt;
@@ -53,8 +60,8 @@ std::string cache_key(lgt_ctx *c, Fmt f)
     return k.str();
 }
 
-// "<key> <hops> <stream> ..." ; the last matching line wins
-bool cache_lookup(const std::string &key, int *hops, int *stream)
+// "<key> <a> <b> ..." with (a, b) accepted by ok(a, b); the last matching line wins
+template <class Ok> bool cache_lookup_pair(const std::string &key, int *pa, int *pb, Ok ok)
 {
     const char *path = std::getenv("LGT_TUNE_CACHE");
     if (!path) return false;
@@ -64,25 +71,37 @@ bool cache_lookup(const std::string &key, int *hops, int *stream)
     while (std::getline(in, line)) {
         if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
         std::istringstream rest(line.substr(key.size() + 1));
-        int h = 0, s = -1;
-        rest >> h >> s;
-        if ((h == 1 || h == 2 || h == 8) && (s == 0 || s == 1)) {
-            *hops = h;
-            *stream = s;
+        int a = -1, b = -1;
+        rest >> a >> b;
+        if (ok(a, b)) {
+            *pa = a;
+            *pb = b;
             found = true;
         }
     }
     return found;
 }
 
-void cache_store(const std::string &key, int hops, int stream, const double *t)
+void cache_store_pair(const std::string &key, int a, int b, const double *t, int n)
 {
     const char *path = std::getenv("LGT_TUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << hops << " " << stream << " us:";
-    for (int i = 0; i < kNumVariants; i++) out << (i ? "," : "") << t[i];
+    out << key << " " << a << " " << b << " us:";
+    for (int i = 0; i < n; i++) out << (i ? "," : "") << t[i];
     out << "\n";
+}
+
+// "<key> <hops> <stream> ..." ; the last matching line wins
+bool cache_lookup(const std::string &key, int *hops, int *stream)
+{
+    return cache_lookup_pair(key, hops, stream,
+                             [](int h, int st) { return (h == 1 || h == 2 || h == 8) && (st == 0 || st == 1); });
+}
+
+void cache_store(const std::string &key, int hops, int stream, const double *t)
+{
+    cache_store_pair(key, hops, stream, t, kNumVariants);
 }
 
 } // namespace
@@ -189,6 +208,108 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[6])
     cache_store(key, kHops[best], kStream[best], t);
     if (times_us)
         for (int i = 0; i < kNumVariants; i++) times_us[i] = t[i];
+    return LGT_OK;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------- multi-RHS ---
+
+namespace {
+
+constexpr int kNumMrhs = 7;
+const int kMrhsEngine[kNumMrhs] = {MRHS_LANE, MRHS_VALU4, MRHS_VALU4, MRHS_VALU4, MRHS_MFMA, MRHS_MFMA, MRHS_MFMA};
+const int kMrhsGroups[kNumMrhs] = {1, 1, 2, 4, 1, 2, 4};
+
+int log2_n(int32_t n)
+{
+    for (int l = 0; l <= 4; l++)
+        if (n == (1 << l)) return l;
+    return -1;
+}
+
+bool mrhs_variant_runs(Fmt f, int logN, int Vh, int v)
+{
+    if (kMrhsEngine[v] == MRHS_LANE) return true;
+    return mrhs_engine_applies(f, logN, Vh, kMrhsEngine[v]) && mrhs_groups_valid(logN, kMrhsGroups[v]);
+}
+
+} // namespace
+
+extern "C" {
+
+lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, double times_us[7])
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    lgt_status st = check_links(U, false, &f);
+    if (st != LGT_OK) return st;
+    const int logN = log2_n(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    DeviceScope ds(c->device);
+    std::ostringstream kk;
+    kk << cache_key(c, f) << " mrhs" << nrhs;
+    const std::string key = kk.str();
+    const char *force = std::getenv("LGT_TUNE");
+    const bool forced = force && std::strcmp(force, "force") == 0;
+    if (!forced && !times_us) {
+        int e, gr;
+        const int Vh = c->g.Vh;
+        auto ok = [&](int a, int b) {
+            for (int v = 0; v < kNumMrhs; v++)
+                if (kMrhsEngine[v] == a && kMrhsGroups[v] == b) return mrhs_variant_runs(f, logN, Vh, v);
+            return false;
+        };
+        if (cache_lookup_pair(key, &e, &gr, ok)) {
+            c->mrhs_eng[f][logN] = e;
+            c->mrhs_gps[f][logN] = gr;
+            return LGT_OK;
+        }
+    }
+    const size_t vb = ((size_t)c->g.Vh << logN) * (fmt_is_f64(f) ? 48 : 24);
+    void *in = workspace(c, "tune.mrhs_in", vb);
+    void *out = workspace(c, "tune.mrhs_out", vb);
+    if (!in || !out) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
+    LGT_HIP(launch_zero(in, vb, c->stream));
+    hipEvent_t e0, e1;
+    LGT_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LGT_ERR_DEVICE, "hipEventCreate failed");
+    }
+    double t[kNumMrhs];
+    int best = 0;
+    double best_t = 1e300;
+    const int reps = 10;
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < kNumMrhs && e == hipSuccess; v++) {
+        t[v] = -1.0;
+        if (!mrhs_variant_runs(f, logN, c->g.Vh, v)) continue;
+        auto run = [&](int par) {
+            return launch_dslash_mrhs(f, U->ptr, in, out, c->g, par, logN, c->stream, kMrhsEngine[v], kMrhsGroups[v]);
+        };
+        for (int w = 0; w < 2 && e == hipSuccess; w++) e = run(w & 1);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = run(r & 1);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        t[v] = 1e3 * ms / reps;
+        if (e == hipSuccess && t[v] < best_t) {
+            best_t = t[v];
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(LGT_ERR_DEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+    c->mrhs_eng[f][logN] = kMrhsEngine[best];
+    c->mrhs_gps[f][logN] = kMrhsGroups[best];
+    cache_store_pair(key, kMrhsEngine[best], kMrhsGroups[best], t, kNumMrhs);
+    if (times_us)
+        for (int v = 0; v < kNumMrhs; v++) times_us[v] = t[v];
     return LGT_OK;
 }
 

@@ -84,6 +84,78 @@ def test_dslash_mrhs_engines(dev, engine, fmt, nrhs, L):
                 assert _rel(got[r], ref) <= tol, (engine, fmt, nrhs, L, par, r)
 
 
+VARIANTS = [(e, g) for e in ("valu4", "mfma") for g in (1, 2, 4)]
+
+
+@pytest.mark.parametrize("engine,groups", VARIANTS)
+@pytest.mark.parametrize("fmt", ["f32r12", "bf16r12"])
+@pytest.mark.parametrize("nrhs", [4, 8, 16])
+def test_dslash_mrhs_groups(dev, engine, groups, fmt, nrhs):
+    """Every tile shape (groups of four lanes per site) of both four-lane
+    engines against the oracle, at 8^3x12 (48+ workgroups)."""
+    if 4 * groups > nrhs:
+        pytest.skip("needs at least one right-hand side per lane")
+    prec, recon, tol = FMTS[fmt]
+    L, bc = (8, 8, 8, 12), (1, 1, 1, -1)
+    U = li.links(L, "haar", 161)
+    chis = li.vectors(L, 162, nrhs)
+    with P.Lattice(L, bc) as lat:
+        lat.set_mrhs_variant(prec, recon, nrhs, ENGINES[engine], groups)
+        assert lat.mrhs_variant(prec, recon, nrhs) == (ENGINES[engine], groups)
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        x = lat.pack_vec_mrhs(_t(chis, dev), P.LGT_F32)
+        for par in (0, 1):
+            got = lat.unpack_vec_mrhs(lat.dslash_mrhs(Up, x, par), P.LGT_F32).cpu().numpy()
+            for r in range(nrhs):
+                ref = oracle.dslash(L, U, chis[r], par, bc)
+                assert _rel(got[r], ref) <= tol, (engine, groups, fmt, nrhs, par, r)
+
+
+def test_mrhs_variant_arguments(dev):
+    with P.Lattice((4, 4, 4, 4)) as lat:
+        for bad in ((P.LGT_F32, P.LGT_R12, 8, ENGINES["mfma"], 4),   # 4 groups need 16 rhs
+                    (P.LGT_F32, P.LGT_R12, 16, ENGINES["mfma"], 3),  # groups 1, 2 or 4
+                    (P.LGT_F32, P.LGT_R12, 6, ENGINES["mfma"], 1),   # nrhs a power of two <= 16
+                    (P.LGT_F32, P.LGT_R12, 16, 5, 1)):               # unknown engine
+            with pytest.raises(P.LgtError):
+                lat.set_mrhs_variant(*bad)
+        # FP64 links and nrhs < 4 always run one lane per (site, rhs)
+        lat.set_mrhs_variant(P.LGT_F64, P.LGT_R18, 16, ENGINES["mfma"], 2)
+        assert lat.mrhs_variant(P.LGT_F64, P.LGT_R18, 16) == (ENGINES["lane"], 1)
+        assert lat.mrhs_variant(P.LGT_F32, P.LGT_R12, 2) == (ENGINES["lane"], 1)
+
+
+def test_tune_dslash_mrhs(dev, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LGT_TUNE_CACHE", str(cache))
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 171)
+    chis = li.vectors(L, 172, 16)
+    with P.Lattice(L) as lat:
+        Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        times = lat.tune_dslash_mrhs(Up, 16)
+        # all seven shapes apply at N = 16 with V/2 a multiple of 16
+        assert set(times) == set(P.Lattice.MRHS_VARIANTS) and all(t > 0 for t in times.values())
+        best = min(times, key=times.get)
+        assert lat.mrhs_variant(P.LGT_F32, P.LGT_R12, 16) == best
+        x = lat.pack_vec_mrhs(_t(chis, dev), P.LGT_F32)
+        got = lat.unpack_vec_mrhs(lat.dslash_mrhs(Up, x, 1), P.LGT_F32).cpu().numpy()
+        for r in range(16):
+            assert _rel(got[r], oracle.dslash(L, U, chis[r], 1)) <= 32 * U32
+        # N = 4 on a lattice with V/2 = 648 (not a multiple of 16): no MFMA shapes
+        lat2 = P.Lattice((6, 6, 6, 6))
+        U2 = lat2.pack_links(_t(li.links((6, 6, 6, 6), "haar", 173), dev), P.LGT_F32, P.LGT_R12)
+        t2 = lat2.tune_dslash_mrhs(U2, 4)
+        assert set(t2) == {(ENGINES["lane"], 1), (ENGINES["valu4"], 1)}
+        lat2.close()
+    assert "mrhs16" in cache.read_text()
+    # a new context picks the cached choice without timing
+    with P.Lattice(L) as lat:
+        Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        lat.tune_dslash_mrhs(Up, 16, report=False)
+        assert lat.mrhs_variant(P.LGT_F32, P.LGT_R12, 16) == best
+
+
 def test_mrhs_engine_rejects_unknown(dev):
     with P.Lattice((4, 4, 4, 4)) as lat:
         with pytest.raises(P.LgtError):
@@ -179,3 +251,21 @@ def test_batch_iteration_cap_and_determinism(dev):
         x2, r2 = P.cg_solve_batch([(lat, Uh, None, _t(b, dev))], 0.1, scheme=P.LGT_CG_FP64)
         assert torch.equal(x1[0], x2[0])
         assert [r.iters for r in r1[0]] == [r.iters for r in r2[0]]
+
+
+@pytest.mark.parametrize("nrhs,engine,groups", [(8, "valu4", 1), (8, "mfma", 2), (16, "valu4", 4),
+                                                (16, "mfma", 2), (16, "mfma", 4), (16, "lane", 1)])
+def test_batch_inner_shapes(dev, nrhs, engine, groups):
+    """The batched solver with each inner-Dslash shape it runs: every right-hand
+    side's oracle-recomputed residual within the tolerance."""
+    L, mass, tol = (8, 8, 8, 12), 0.1, 1e-10
+    U = li.links(L, "haar", 181)
+    bs = li.vectors(L, 182, nrhs)
+    with P.Lattice(L) as lat:
+        lat.set_mrhs_variant(P.LGT_F32, P.LGT_R12, nrhs, ENGINES[engine], groups)
+        Ut = _t(U, dev)
+        uh, ul = lat.pack_links(Ut, P.LGT_F64, P.LGT_R18), lat.pack_links(Ut, P.LGT_F32, P.LGT_R12)
+        xs, res = P.cg_solve_batch([(lat, uh, ul, _t(bs, dev))], mass, tol=tol, scheme=P.LGT_CG_RELIABLE)
+    xg = xs[0].cpu().numpy()
+    for j in range(nrhs):
+        _check_solution(L, U, mass, bs[j], xg[j], res[0][j], tol)

@@ -42,6 +42,7 @@ __all__ = [
     "expih_su3",
     "gaussian_cvec",
     "links",
+    "improved_links",
     "vector",
     "vectors",
     "to_real",
@@ -136,6 +137,22 @@ def links(L, kind: str = "haar", seed: int = 1, c: float = 0.3) -> np.ndarray:
     return to_real(u).reshape(4, V, 3, 3, 2)
 
 
+def improved_links(L, seed: int, c1: float = 9.0 / 8.0, c3: float = -1.0 / 24.0, w: float = 0.1):
+    """Link fields of the improved operator, canonical float64 [4][V][3][3][2] each:
+    fat one-link F = c1 U + w Z (U Haar SU(3), Z complex Gaussian: a general
+    complex 3x3 matrix, as a sum of smeared paths is) and Naik three-link
+    N = c3 W (W Haar SU(3)); the tree-level coefficients c1 = 9/8, c3 = -1/24
+    by default. One stream: U, then Z, then W."""
+    V = volume(L)
+    g = rng(seed)
+    U = haar_su3(4 * V, g)
+    Z = _complex_gaussian(g, (4 * V, 3, 3))
+    W = haar_su3(4 * V, g)
+    F = (c1 * U + w * Z).reshape(4, V, 3, 3)
+    N = (c3 * W).reshape(4, V, 3, 3)
+    return to_real(F), to_real(N)
+
+
 def vector(L, seed: int) -> np.ndarray:
     """Canonical float64 colour vector on one parity, [V/2][3][2]."""
     Vh = volume(L) // 2
@@ -168,4 +185,6 @@ CONFIGS = {
                      kind="haar", mass=0.02, nrhs=4, src_seed_offset=10, tol=1e-10),
     "c5_16x16x16x32": dict(L=(16, 16, 16, 32), kind="expih", c=0.5, mass=0.05,
                            link_seed=5001, src_seed=5002, fd_seed=5004, tol=1e-10),
+    # improved (fat + Naik) operator at the headline lattice size
+    "imp_32x32x32x32": dict(L=(32, 32, 32, 32), mass=0.01, link_seed=6001, src_seed=6002, tol=1e-10),
 }

@@ -48,6 +48,11 @@ def _setup(l):
     l.or_cg.argtypes = [_ip, _ip, _dp, C.c_double, _dp, _dp, C.c_double, C.c_int,
                         C.POINTER(C.c_int), _dp]
     l.or_force.argtypes = [_ip, _ip, _dp, _dp, _dp]
+    l.or_dslash_imp.argtypes = [_ip, _ip, _dp, _dp, _dp, _dp, C.c_int]
+    l.or_apply_A_imp.argtypes = [_ip, _ip, _dp, _dp, C.c_double, _dp, _dp]
+    l.or_cg_imp.restype = C.c_int
+    l.or_cg_imp.argtypes = [_ip, _ip, _dp, _dp, C.c_double, _dp, _dp, C.c_double, C.c_int,
+                            C.POINTER(C.c_int), C.POINTER(C.c_double)]
     l.or_action_variational.restype = C.c_double
     l.or_action_variational.argtypes = [_ip, _ip, _dp, C.c_double, _dp, _dp]
     cx = C.c_void_p
@@ -144,6 +149,41 @@ def cg(L, U, mass, b, tol=1e-10, max_iter=100000, bc=None):
     rr = C.c_double()
     st = lib().or_cg(_iptr(L), _iptr(_bc(bc)), _dptr(U), float(mass), _dptr(b), _dptr(x),
                      float(tol), int(max_iter), C.byref(it), C.byref(rr))
+    return int(st), x, int(it.value), float(rr.value)
+
+
+def dslash_imp(L, F, N, chi, out_parity: int, bc=None):
+    """Improved operator: fat one-link field F plus Naik three-link field N."""
+    L = _i4(L)
+    F = _f64(F)
+    N = _f64(N)
+    chi = _f64(chi)
+    out = np.empty_like(chi)
+    lib().or_dslash_imp(_iptr(L), _iptr(_bc(bc)), _dptr(F), _dptr(N), _dptr(chi), _dptr(out), int(out_parity))
+    return out
+
+
+def apply_A_imp(L, F, N, mass, v, bc=None):
+    L = _i4(L)
+    F = _f64(F)
+    N = _f64(N)
+    v = _f64(v)
+    out = np.empty_like(v)
+    lib().or_apply_A_imp(_iptr(L), _iptr(_bc(bc)), _dptr(F), _dptr(N), float(mass), _dptr(v), _dptr(out))
+    return out
+
+
+def cg_imp(L, F, N, mass, b, tol=1e-10, max_iter=100000, bc=None):
+    """CG with the improved operator. Returns (status, x, iters, true_rel_resid)."""
+    L = _i4(L)
+    F = _f64(F)
+    N = _f64(N)
+    b = _f64(b)
+    x = np.empty_like(b)
+    it = C.c_int()
+    rr = C.c_double()
+    st = lib().or_cg_imp(_iptr(L), _iptr(_bc(bc)), _dptr(F), _dptr(N), float(mass), _dptr(b), _dptr(x),
+                         float(tol), int(max_iter), C.byref(it), C.byref(rr))
     return int(st), x, int(it.value), float(rr.value)
 
 

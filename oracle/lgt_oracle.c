@@ -22,6 +22,14 @@
  *  - M = 2m + D, D anti-Hermitian, A = (M^dag M)_ee = 4 m^2 - D_eo D_oe.
  *  - CG: textbook Hestenes-Stiefel on A x = b.
  *  - Force: the outer product su3_projector (Table 1) of X and Y = D_oe X.
+ *  - Improved operator: the paper's application uses the improved staggered
+ *    action (Table 4), whose operator the paper does not write out either.
+ *    Reading used (fat one-link plus Naik three-link hops, path coefficients
+ *    folded into the two link fields F and N, general complex 3x3):
+ *      (D chi)(x) = sum_mu eta_mu(x) [ s+ F_mu(x) chi(x+mu) - s- F_mu(x-mu)^dag chi(x-mu)
+ *                       + s3+ N_mu(x) chi(x+3mu) - s3- N_mu(x-3mu)^dag chi(x-3mu) ]
+ *    with s3+- = bc_mu to the number of boundary crossings of the three-step
+ *    hop; 16 mat-vecs and 15 vector sums, 16*66 + 15*6 = 1146 flop per site.
  */
 #include "lgt_oracle.h"
 
@@ -303,8 +311,60 @@ static void scale3(or_cx *v, double s)
     }
 }
 
+/* one-link part of the operator at output site (out_par, cb) with coordinates c */
+static void onelink_site(const int32_t L[4], const int32_t bc[4], const double *U, const or_cx *chi,
+                         int out_par, int64_t cb, const int c[4], or_cx fwd[3])
+{
+    const int64_t V = vol(L), Vh = V / 2;
+    const int in_par = 1 - out_par;
+    or_cx A4[36], b4[12], back[12];
+    for (int mu = 0; mu < 4; mu++) {
+        const double e = eta(c, mu);
+        /* forward hop: U_mu(x) chi(x+mu) */
+        memcpy(A4 + 9 * mu, link_at(U, V, mu, out_par * Vh + cb), 9 * sizeof(or_cx));
+        memcpy(b4 + 3 * mu, chi + 3 * nbr_cb(L, c, mu, +1), 3 * sizeof(or_cx));
+        scale3(b4 + 3 * mu, e * s_plus(L, bc, c, mu));
+        /* backward hop: U_mu(x-mu)^dag chi(x-mu), the link lives on the neighbour */
+        const int64_t cbm = nbr_cb(L, c, mu, -1);
+        or_mult_adj_su3_mat_vec(link_at(U, V, mu, in_par * Vh + cbm), chi + 3 * cbm,
+                                back + 3 * mu);
+        scale3(back + 3 * mu, e * s_minus(bc, c, mu));
+    }
+    or_mult_su3_mat_vec_sum_4dir(A4, b4, fwd);
+    or_sub_four_su3_vecs(fwd, back);
+}
+
 void or_dslash(const int32_t L[4], const int32_t bc[4], const double *U,
                const double *in, double *out, int out_par)
+{
+    const int64_t Vh = vol(L) / 2;
+    const or_cx *chi = (const or_cx *)in;
+    or_cx *res = (or_cx *)out;
+#pragma omp parallel for schedule(static) num_threads(or_get_threads())
+    for (int64_t cb = 0; cb < Vh; cb++) {
+        int c[4];
+        coords_of_cb(L, out_par, cb, c);
+        onelink_site(L, bc, U, chi, out_par, cb, c, res + 3 * cb);
+    }
+}
+
+/* cb index of x + 3 mu (dir = +1) or x - 3 mu (dir = -1), periodic */
+static int64_t nbr3_cb(const int32_t L[4], const int c[4], int mu, int dir)
+{
+    int d[4] = {c[0], c[1], c[2], c[3]};
+    d[mu] = ((d[mu] + 3 * dir) % L[mu] + L[mu]) % L[mu];
+    return lex_of_coords(L, d) >> 1;
+}
+
+/* bc_mu to the number of times a three-step hop from c along dir crosses the boundary */
+static double s3(const int32_t L[4], const int32_t bc[4], const int c[4], int mu, int dir)
+{
+    const int crossings = dir > 0 ? (c[mu] + 3) / L[mu] : (L[mu] - 1 - c[mu] + 3) / L[mu];
+    return ((crossings & 1) && bc[mu] < 0) ? -1.0 : 1.0;
+}
+
+void or_dslash_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N,
+                   const double *in, double *out, int out_par)
 {
     const int64_t V = vol(L), Vh = V / 2;
     const int in_par = 1 - out_par;
@@ -314,35 +374,52 @@ void or_dslash(const int32_t L[4], const int32_t bc[4], const double *U,
     for (int64_t cb = 0; cb < Vh; cb++) {
         int c[4];
         coords_of_cb(L, out_par, cb, c);
-        or_cx A4[36], b4[12], back[12], fwd[3];
+        or_cx acc[3], t[3];
+        onelink_site(L, bc, F, chi, out_par, cb, c, acc);
         for (int mu = 0; mu < 4; mu++) {
             const double e = eta(c, mu);
-            /* forward hop: U_mu(x) chi(x+mu) */
-            memcpy(A4 + 9 * mu, link_at(U, V, mu, out_par * Vh + cb), 9 * sizeof(or_cx));
-            memcpy(b4 + 3 * mu, chi + 3 * nbr_cb(L, c, mu, +1), 3 * sizeof(or_cx));
-            scale3(b4 + 3 * mu, e * s_plus(L, bc, c, mu));
-            /* backward hop: U_mu(x-mu)^dag chi(x-mu), the link lives on the neighbour */
-            const int64_t cbm = nbr_cb(L, c, mu, -1);
-            or_mult_adj_su3_mat_vec(link_at(U, V, mu, in_par * Vh + cbm), chi + 3 * cbm,
-                                    back + 3 * mu);
-            scale3(back + 3 * mu, e * s_minus(bc, c, mu));
+            /* Naik forward hop: N_mu(x) chi(x+3mu) */
+            or_mult_su3_mat_vec(link_at(N, V, mu, out_par * Vh + cb), chi + 3 * nbr3_cb(L, c, mu, +1), t);
+            or_scalar_mult_add_su3_vector(acc, t, e * s3(L, bc, c, mu, +1), acc);
+            /* Naik backward hop: N_mu(x-3mu)^dag chi(x-3mu), the link lives at x-3mu */
+            const int64_t cbm3 = nbr3_cb(L, c, mu, -1);
+            or_mult_adj_su3_mat_vec(link_at(N, V, mu, in_par * Vh + cbm3), chi + 3 * cbm3, t);
+            or_scalar_mult_add_su3_vector(acc, t, -e * s3(L, bc, c, mu, -1), acc);
         }
-        or_mult_su3_mat_vec_sum_4dir(A4, b4, fwd);
-        or_sub_four_su3_vecs(fwd, back);
-        memcpy(res + 3 * cb, fwd, 3 * sizeof(or_cx));
+        memcpy(res + 3 * cb, acc, 3 * sizeof(or_cx));
     }
+}
+
+/* D with the one-link field U, plus the Naik field N when N != NULL */
+static void dslash_op(const int32_t L[4], const int32_t bc[4], const double *U, const double *N,
+                      const double *in, double *out, int out_par)
+{
+    if (N) or_dslash_imp(L, bc, U, N, in, out, out_par);
+    else or_dslash(L, bc, U, in, out, out_par);
+}
+
+static void apply_A_op(const int32_t L[4], const int32_t bc[4], const double *U, const double *N,
+                       double mass, const double *in, double *out)
+{
+    const int64_t n = vol(L) / 2 * 6;
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    dslash_op(L, bc, U, N, in, tmp, 1);  /* D_oe: even -> odd */
+    dslash_op(L, bc, U, N, tmp, out, 0); /* D_eo: odd -> even */
+    const double m4 = 4.0 * mass * mass;
+    for (int64_t k = 0; k < n; k++) out[k] = m4 * in[k] - out[k];
+    free(tmp);
 }
 
 void or_apply_A(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
                 const double *in, double *out)
 {
-    const int64_t n = vol(L) / 2 * 6;
-    double *tmp = (double *)malloc(sizeof(double) * n);
-    or_dslash(L, bc, U, in, tmp, 1);  /* D_oe: even -> odd */
-    or_dslash(L, bc, U, tmp, out, 0); /* D_eo: odd -> even */
-    const double m4 = 4.0 * mass * mass;
-    for (int64_t k = 0; k < n; k++) out[k] = m4 * in[k] - out[k];
-    free(tmp);
+    apply_A_op(L, bc, U, NULL, mass, in, out);
+}
+
+void or_apply_A_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N,
+                    double mass, const double *in, double *out)
+{
+    apply_A_op(L, bc, F, N, mass, in, out);
 }
 
 void or_cdot(int64_t n_real, const double *a, const double *b, double *re, double *im)
@@ -367,9 +444,9 @@ double or_norm2(int64_t n_real, const double *a)
 /* CG                                                                        */
 /* ------------------------------------------------------------------------ */
 
-int or_cg(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
-          const double *b, double *x, double tol, int max_iter,
-          int *iters, double *true_rel_resid)
+static int cg_op(const int32_t L[4], const int32_t bc[4], const double *U, const double *N,
+                 double mass, const double *b, double *x, double tol, int max_iter,
+                 int *iters, double *true_rel_resid)
 {
     const int64_t n = vol(L) / 2 * 6;
     double *r = (double *)malloc(sizeof(double) * n);
@@ -387,7 +464,7 @@ int or_cg(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
         goto done;
     }
     while (k < max_iter) {
-        or_apply_A(L, bc, U, mass, p, Ap);
+        apply_A_op(L, bc, U, N, mass, p, Ap);
         double pAp, im;
         or_cdot(n, p, Ap, &pAp, &im);
         if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -407,7 +484,7 @@ int or_cg(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
         }
         if (rho_new <= stop) {
             /* true residual r = b - A x */
-            or_apply_A(L, bc, U, mass, x, Ap);
+            apply_A_op(L, bc, U, N, mass, x, Ap);
             for (int64_t i = 0; i < n; i++) r[i] = b[i] - Ap[i];
             rho_new = or_norm2(n, r);
             if (rho_new <= stop) {
@@ -420,7 +497,7 @@ int or_cg(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
         rho = rho_new;
     }
 done:
-    or_apply_A(L, bc, U, mass, x, Ap);
+    apply_A_op(L, bc, U, N, mass, x, Ap);
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - Ap[i];
     if (iters) *iters = k;
     if (true_rel_resid) *true_rel_resid = bb > 0.0 ? sqrt(or_norm2(n, r) / bb) : 0.0;
@@ -428,6 +505,19 @@ done:
     free(p);
     free(Ap);
     return status;
+}
+
+int or_cg(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
+          const double *b, double *x, double tol, int max_iter,
+          int *iters, double *true_rel_resid)
+{
+    return cg_op(L, bc, U, NULL, mass, b, x, tol, max_iter, iters, true_rel_resid);
+}
+
+int or_cg_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N, double mass,
+              const double *b, double *x, double tol, int max_iter, int *iters, double *true_rel_resid)
+{
+    return cg_op(L, bc, F, N, mass, b, x, tol, max_iter, iters, true_rel_resid);
 }
 
 /* ------------------------------------------------------------------------ */

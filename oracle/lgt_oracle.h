@@ -68,6 +68,16 @@ int or_cg(const int32_t L[4], const int32_t bc[4], const double *U, double mass,
           const double *b, double *x, double tol, int max_iter,
           int *iters, double *true_rel_resid);
 
+/* --- improved operator: fat one-link field F plus Naik three-link field N,
+ * both canonical [4][V][3][3][2], general complex 3x3 (coefficients folded in):
+ * D = sum_mu eta_mu [s+ F fwd - s- F^dag bwd + s3+ N fwd3 - s3- N^dag bwd3] */
+void or_dslash_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N,
+                   const double *in, double *out, int out_par);
+void or_apply_A_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N,
+                    double mass, const double *in, double *out);
+int or_cg_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N, double mass,
+              const double *b, double *x, double tol, int max_iter, int *iters, double *true_rel_resid);
+
 /* --- force: G[4][V][3][3][2] = dS/d(Re U, Im U) of S = phi^dag A^-1 phi, from X = A^-1 phi */
 void or_force(const int32_t L[4], const int32_t bc[4], const double *U,
               const double *X, double *G);

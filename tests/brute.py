@@ -64,6 +64,40 @@ def dense_D(L, U, bc=(1, 1, 1, 1)):
     return D
 
 
+def shift_signed(L, c, mu, steps, bc):
+    """Site reached by |steps| single steps along +-mu, and the product of the
+    boundary signs picked up each time a step wraps around."""
+    c = list(c)
+    sign = 1.0
+    d = 1 if steps > 0 else -1
+    for _ in range(abs(steps)):
+        n = c[mu] + d
+        if n == L[mu] or n < 0:
+            sign *= bc[mu]
+        c[mu] = n % L[mu]
+    return tuple(c), sign
+
+
+def dense_D_imp(L, F, N, bc=(1, 1, 1, 1)):
+    """Dense improved operator: one-link hops with F, three-link hops with N
+    (N_mu(x) joins x to x + 3 mu), both canonical [4][V][3][3][2]."""
+    V = int(np.prod(L))
+    Fc = F[..., 0] + 1j * F[..., 1]
+    Nc = N[..., 0] + 1j * N[..., 1]
+    D = np.zeros((3 * V, 3 * V), dtype=np.complex128)
+    for _, c in sites(L):
+        i = eo_index(L, c)
+        for mu in range(4):
+            e = eta(c, mu)
+            for steps, W in ((1, Fc), (3, Nc)):
+                cf, sf = shift_signed(L, c, mu, +steps, bc)
+                cb, sb = shift_signed(L, c, mu, -steps, bc)
+                jf, jb = eo_index(L, cf), eo_index(L, cb)
+                D[3 * i:3 * i + 3, 3 * jf:3 * jf + 3] += e * sf * W[mu, i]
+                D[3 * i:3 * i + 3, 3 * jb:3 * jb + 3] -= e * sb * W[mu, jb].conj().T
+    return D
+
+
 def blocks(L, D):
     """(D_eo, D_oe) blocks of the dense D: D_eo maps odd -> even, D_oe even -> odd."""
     n = 3 * int(np.prod(L)) // 2
@@ -72,6 +106,12 @@ def blocks(L, D):
 
 def dense_A(L, U, mass, bc=(1, 1, 1, 1)):
     Deo, Doe = blocks(L, dense_D(L, U, bc))
+    n = Deo.shape[0]
+    return 4.0 * mass * mass * np.eye(n) - Deo @ Doe
+
+
+def dense_A_imp(L, F, N, mass, bc=(1, 1, 1, 1)):
+    Deo, Doe = blocks(L, dense_D_imp(L, F, N, bc))
     n = Deo.shape[0]
     return 4.0 * mass * mass * np.eye(n) - Deo @ Doe
 

@@ -14,6 +14,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_improved as ipins
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lgt_oracle.c")
@@ -40,6 +41,18 @@ MUTANTS = {
     "mass_factor": ("const double m4 = 4.0 * mass * mass;", "const double m4 = 2.0 * mass * mass;"),
     # force: sign of the odd-site term
     "force_sign": ("const double sg = par == 0 ? s : -s;", "const double sg = s;"),
+    # improved operator: Naik backward link taken at the output site
+    "naik_bwd_link": ("link_at(N, V, mu, in_par * Vh + cbm3)", "link_at(N, V, mu, out_par * Vh + cb)"),
+    # improved operator: one crossing too few counted for the forward three-step hop
+    "naik_crossings": ("(c[mu] + 3) / L[mu]", "(c[mu] + 2) / L[mu]"),
+    # improved operator: dropped Naik backward hop
+    "naik_drop_bwd": ("or_scalar_mult_add_su3_vector(acc, t, -e * s3(L, bc, c, mu, -1), acc);",
+                      "or_scalar_mult_add_su3_vector(acc, t, 0.0 * e, acc);"),
+    # improved operator: two-step instead of three-step neighbours
+    "naik_distance": ("d[mu] = ((d[mu] + 3 * dir) % L[mu] + L[mu]) % L[mu];",
+                      "d[mu] = ((d[mu] + 2 * dir) % L[mu] + L[mu]) % L[mu];"),
+    # improved operator: backward Naik hop without the adjoint
+    "naik_no_adjoint": ("or_mult_adj_su3_mat_vec(link_at(N, V", "or_mult_su3_mat_vec(link_at(N, V"),
 }
 
 
@@ -67,6 +80,11 @@ def _pins():
     yield lambda: pins.test_dslash_dense_brute_force((2, 4, 2, 6), (1, 1, 1, -1))
     yield lambda: pins.test_cg_vs_dense_solve((2, 4, 2, 6), 0.05, "expih")
     yield lambda: pins.test_force_vs_dense_central_differences((2, 4, 2, 4), (1, 1, 1, 1))
+    yield lambda: ipins.test_improved_antihermitian((8, 4, 6, 4), (1, 1, 1, -1))
+    yield lambda: ipins.test_improved_free_field_plane_wave((8, 8, 8, 8), (1, 2, 0, 1.5), (1, 1, 1, -1))
+    yield lambda: ipins.test_improved_gauge_covariance((1, -1, 1, -1))
+    yield lambda: ipins.test_improved_dense_brute_force((8, 4, 2, 8), (1, 1, 1, -1))
+    yield ipins.test_improved_cg_vs_dense_solve
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

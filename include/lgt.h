@@ -205,6 +205,25 @@ lgt_status lgt_cg_solve(lgt_ctx *ctx, const lgt_links *U_hi, const lgt_links *U_
                         const lgt_cg_params *p, const double *b, double *x,
                         lgt_cg_result *res);
 
+/* ---- improved (fat + Naik) operator ----------------------------------------
+ * The improved staggered action of the paper's application (Table 4), with
+ * its path coefficients folded into two link fields, both general complex
+ * 3x3 and packed with lgt_pack_links in one 18-real format (F64 or F32):
+ *   (D chi)(x) = sum_mu eta_mu(x) [ s+ F_mu(x) chi(x+mu) - s- F_mu(x-mu)^dag chi(x-mu)
+ *                    + s3+ N_mu(x) chi(x+3mu) - s3- N_mu(x-3mu)^dag chi(x-3mu) ]
+ * with N_mu(x) the Naik link joining x to x+3mu and s3+- the boundary sign
+ * raised to the number of boundary crossings of the three-step hop. 16
+ * neighbours, 1146 flop per site; still anti-Hermitian, so A = 4m^2 - D_eo D_oe
+ * and the solver are unchanged. Other formats: LGT_ERR_UNSUPPORTED; fat and
+ * Naik in different formats: LGT_ERR_ARG. */
+lgt_status lgt_dslash_improved(lgt_ctx *ctx, const lgt_links *fat, const lgt_links *naik, int32_t out_parity,
+                               const void *in, void *out);
+/* lgt_cg_solve for the improved operator: fat_hi and naik_hi F64 x 18; for
+ * RELIABLE and REFINE, fat_lo and naik_lo F32 x 18 (ignored for FP64). */
+lgt_status lgt_cg_solve_improved(lgt_ctx *ctx, const lgt_links *fat_hi, const lgt_links *naik_hi,
+                                 const lgt_links *fat_lo, const lgt_links *naik_lo, const lgt_cg_params *p,
+                                 const double *b, double *x, lgt_cg_result *res);
+
 /* ---- many right-hand sides and lattices ------------------------------------ */
 
 /* Multi-RHS native vectors hold nrhs (1, 2, 4, 8 or 16) right-hand sides of

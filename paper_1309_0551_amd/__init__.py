@@ -13,7 +13,7 @@ from .lgt import (  # noqa: F401
     LGT_MRHS_LANE, LGT_MRHS_VALU4, LGT_MRHS_MFMA, LgtError,
     Lattice, PackedLinks, CgResult, PseudofermionAction, cg_solve_batch,
     lib, lib_path, exported_symbols, links_bytes, vec_bytes, geom_check,
-    DSLASH_FLOP_PER_SITE, link_bytes_per_dir, vec_bytes_per_site,
+    DSLASH_FLOP_PER_SITE, IMPROVED_FLOP_PER_SITE, link_bytes_per_dir, vec_bytes_per_site,
 )
 
 lib()  # load liblgt.so now: a missing library fails the import, not a later call

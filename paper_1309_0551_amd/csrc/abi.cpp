@@ -325,10 +325,10 @@ lgt_status lgt_dslash(lgt_ctx *c, const lgt_links *U, int32_t out_parity, const 
     return LGT_OK;
 }
 
-lgt_status lgt_cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
-                        const double *b, double *x, lgt_cg_result *res)
+namespace {
+
+lgt_status check_cg_params(const lgt_cg_params *p)
 {
-    CHECK_CTX(c);
     if (!p) return fail(LGT_ERR_ARG, "params is NULL");
     if (!(p->mass > 0.0)) return fail(LGT_ERR_ARG, "mass must be > 0");
     if (!(p->tol > 0.0)) return fail(LGT_ERR_ARG, "tol must be > 0");
@@ -340,11 +340,81 @@ lgt_status lgt_cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, 
     if (p->scheme != LGT_CG_REFINE && (p->inner_tol < 0.0 || p->inner_tol > 1.0))
         return fail(LGT_ERR_ARG, "inner_tol must be in [0, 1]");
     if (p->check_interval < 0) return fail(LGT_ERR_ARG, "check_interval must be >= 0");
+    return LGT_OK;
+}
+
+// improved operator: fat and Naik fields in one 18-real format
+lgt_status check_improved(const lgt_links *F, const lgt_links *N, bool need_f64, Fmt *f)
+{
     lgt_status s;
+    Fmt ff, fn;
+    if ((s = check_links(F, need_f64, &ff)) != LGT_OK) return s;
+    if ((s = check_links(N, need_f64, &fn)) != LGT_OK) return s;
+    if (ff != fn) return fail(LGT_ERR_ARG, "fat and Naik links must have the same format");
+    if (ff != F64R18 && ff != F32R18)
+        return fail(LGT_ERR_UNSUPPORTED, "the improved operator takes 18-real links (F64 or F32)");
+    *f = ff;
+    return LGT_OK;
+}
+
+} // namespace
+
+lgt_status lgt_cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
+                        const double *b, double *x, lgt_cg_result *res)
+{
+    CHECK_CTX(c);
+    lgt_status s;
+    if ((s = check_cg_params(p)) != LGT_OK) return s;
     if ((s = check_ptr(b, "b")) != LGT_OK) return s;
     if ((s = check_ptr(x, "x")) != LGT_OK) return s;
     DeviceScope ds(c->device);
     return cg_solve(c, Uhi, Ulo, p, b, x, res);
+}
+
+lgt_status lgt_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_links *naik, int32_t out_parity,
+                               const void *in, void *out)
+{
+    CHECK_CTX(c);
+    Fmt f;
+    lgt_status s;
+    if ((s = check_improved(fat, naik, false, &f)) != LGT_OK) return s;
+    if (out_parity != LGT_EVEN && out_parity != LGT_ODD) return fail(LGT_ERR_ARG, "bad parity %d", out_parity);
+    if ((s = check_ptr(in, "in")) != LGT_OK) return s;
+    if ((s = check_ptr(out, "out")) != LGT_OK) return s;
+    if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
+    DeviceScope ds(c->device);
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.U = fat->ptr;
+    a.U3 = naik->ptr;
+    a.in = in;
+    a.out = out;
+    a.g = c->g;
+    a.par = out_parity;
+    a.gate = GATE_NONE;
+    a.l = site_launch(c->g.Vh);
+    a.ntl = c->ntl[f];
+    LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_cg_solve_improved(lgt_ctx *c, const lgt_links *fat_hi, const lgt_links *naik_hi,
+                                 const lgt_links *fat_lo, const lgt_links *naik_lo, const lgt_cg_params *p,
+                                 const double *b, double *x, lgt_cg_result *res)
+{
+    CHECK_CTX(c);
+    lgt_status s;
+    if ((s = check_cg_params(p)) != LGT_OK) return s;
+    Fmt f;
+    if ((s = check_improved(fat_hi, naik_hi, true, &f)) != LGT_OK) return s;
+    if (p->scheme != LGT_CG_FP64) {
+        if ((s = check_improved(fat_lo, naik_lo, false, &f)) != LGT_OK) return s;
+        if (f != F32R18) return fail(LGT_ERR_ARG, "the inner links of a mixed scheme must be F32 x 18");
+    }
+    if ((s = check_ptr(b, "b")) != LGT_OK) return s;
+    if ((s = check_ptr(x, "x")) != LGT_OK) return s;
+    DeviceScope ds(c->device);
+    return cg_solve(c, fat_hi, fat_lo, p, b, x, res, naik_hi, naik_lo);
 }
 
 lgt_status lgt_cdot(lgt_ctx *c, int64_t n, const double *a, const double *b, double out[2])

@@ -74,8 +74,11 @@ struct DeviceScope {
     }
 };
 
+// Even-odd CG. With U3hi (and U3lo for the mixed schemes) set, the operator is
+// the improved one: Uhi/Ulo are its fat fields and U3hi/U3lo its Naik fields.
 lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
-                    const double *b, double *x, lgt_cg_result *res);
+                    const double *b, double *x, lgt_cg_result *res, const lgt_links *U3hi = nullptr,
+                    const lgt_links *U3lo = nullptr);
 
 } // namespace lgt
 

@@ -19,7 +19,9 @@ namespace lgt {
 // basic block in which the backend hoists all 96 loads of the FP64 kernel
 // (256 VGPRs, one wave per SIMD); a runtime loop over directions (HPI = 2) or
 // over single hops (HPI = 1) bounds the loads in flight per thread and lets
-// more waves share each SIMD.
+// more waves share each SIMD. HPI = 0 is the improved operator: a runtime loop
+// over the 8 hop pairs (one-link and Naik three-link per direction), 16 links
+// per site from two link fields of the same format.
 template <class LF, int EPI, int HPI, bool NTL>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
 {
@@ -36,7 +38,24 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
         cx<T> acc[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) acc[i].re = acc[i].im = T(0);
-        if constexpr (HPI == 8) {
+        if constexpr (HPI == 0) {
+#pragma unroll 1
+            for (int k = 0; k < 8; k++) {
+                const int mu = k >> 1;
+                const bool naik = k & 1;
+                const Hop h = naik ? hop3_rt(a.g, c, cb, mu) : hop_rt(a.g, c, cb, mu);
+                const void *W = naik ? a.U3 : a.U;
+                cx<T> u[9], v[3], w[9], z[3];
+                LF::template load<NTL>(W, Vh, a.par * 4 + mu, cb, u);
+                VF::template load<false>(a.in, Vh, h.f, v);
+                LF::template load<NTL>(W, Vh, (1 - a.par) * 4 + mu, h.b, w);
+                VF::template load<false>(a.in, Vh, h.b, z);
+                negate_if(h.fneg, v);
+                mv_add(u, v, acc);
+                negate_if(h.bneg, z);
+                amv_sub(w, z, acc);
+            }
+        } else if constexpr (HPI == 8) {
 #pragma unroll
             for (int mu = 0; mu < 4; mu++) {
                 cx<T> u[9], v[3];
@@ -150,6 +169,12 @@ static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
 template <class LF, bool NTL>
 static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s)
 {
+    if (a.U3) {
+        // improved operator: fat and Naik fields are general complex 3x3 (18 reals)
+        if constexpr (std::is_same<LF, LinkF64R18>::value || std::is_same<LF, LinkF32R18>::value)
+            return launch_fmt<LF, 0, NTL>(epi, a, s);
+        else return hipErrorInvalidValue;
+    }
     switch (a.hpi) {
     case 1: return launch_fmt<LF, 1, NTL>(epi, a, s);
     case 2: return launch_fmt<LF, 2, NTL>(epi, a, s);

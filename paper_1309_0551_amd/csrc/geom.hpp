@@ -105,6 +105,37 @@ __host__ __device__ __forceinline__ Hop hop_rt(const Geom &g, const int c[4], in
     return h;
 }
 
+// Three-step neighbours x + 3 mu and x - 3 mu (improved operator's Naik hops)
+// for a runtime mu, and their signs: eta_mu times bc_mu to the number of
+// boundary crossings of the hop (twice for an extent of 2). On the x axis
+// cb = (lex >> 1) moves by the change of x >> 1; on the others by the change
+// of the coordinate times the cb stride.
+__host__ __device__ __forceinline__ Hop hop3_rt(const Geom &g, const int c[4], int cb, int mu)
+{
+    const int c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
+    const int b0 = g.bc[0], b1 = g.bc[1], b2 = g.bc[2], b3 = g.bc[3];
+    const int s1 = g.str[1], s2 = g.str[2], s3 = g.str[3];
+    const int cm = mu == 0 ? c0 : mu == 1 ? c1 : mu == 2 ? c2 : c3;
+    const int Lm = mu == 0 ? L0 : mu == 1 ? L1 : mu == 2 ? L2 : L3;
+    const int bcm = mu == 0 ? b0 : mu == 1 ? b1 : mu == 2 ? b2 : b3;
+    const int sm = mu == 1 ? s1 : mu == 2 ? s2 : s3;
+    const int ep = (mu > 0 ? c0 : 0) + (mu > 1 ? c1 : 0) + (mu > 2 ? c2 : 0);
+    const int cf = (cm + 3) / Lm, xf = cm + 3 - cf * Lm;          // crossings, new coordinate
+    const int cbk = (Lm + 2 - cm) / Lm, xb = cm - 3 + cbk * Lm;   // going down
+    Hop h;
+    if (mu == 0) {
+        h.f = cb - (cm >> 1) + (xf >> 1);
+        h.b = cb - (cm >> 1) + (xb >> 1);
+    } else {
+        h.f = cb + (xf - cm) * sm;
+        h.b = cb + (xb - cm) * sm;
+    }
+    h.fneg = (ep & 1) ^ ((cf & 1) && bcm < 0);
+    h.bneg = (ep & 1) ^ ((cbk & 1) && bcm < 0);
+    return h;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs. Remap so that each
 // XCD walks a contiguous range of sites: neighbours in y, z and t then fall in
 // the same XCD's L2. nblk_pad is a multiple of 8; blocks beyond nblk idle.

@@ -53,7 +53,8 @@ inline Launch site_launch(int Vh)
 enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3 };
 
 struct DslashArgs {
-    const void *U;   // packed links
+    const void *U;   // packed links (the fat one-link field of the improved operator)
+    const void *U3;  // improved operator: packed Naik three-link field, same format; else null
     const void *in;  // vector on parity 1-par
     void *out;       // vector on parity par
     Geom g;

@@ -55,7 +55,8 @@ struct Events {
 } // namespace
 
 lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
-                    const double *b, double *x, lgt_cg_result *res)
+                    const double *b, double *x, lgt_cg_result *res, const lgt_links *U3hi,
+                    const lgt_links *U3lo)
 {
     const Geom g = c->g;
     const int Vh = g.Vh;
@@ -110,6 +111,8 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                  const void *aux1, void *out_lo) {
         DslashArgs a;
         a.U = U;
+        // the improved operator's Naik field that goes with this fat field
+        a.U3 = !U3hi ? nullptr : (U == Uhi->ptr ? U3hi->ptr : U3lo->ptr);
         a.in = in;
         a.out = out;
         a.g = g;

@@ -33,6 +33,7 @@ STATUS = {
 # 8 complex 3x3 mat-vecs of 66 flop (36 mul + 30 add) and 7 three-complex vector
 # additions of 6 flop per output site
 DSLASH_FLOP_PER_SITE = 8 * 66 + 7 * 6
+IMPROVED_FLOP_PER_SITE = 16 * 66 + 15 * 6  # one-link and Naik hops: 1146
 
 
 def link_bytes_per_dir(prec: int, recon: int) -> int:
@@ -127,6 +128,9 @@ def _setup(l):
         "lgt_get_mrhs_variant": (st, [vp, i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "lgt_tune_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, C.POINTER(C.c_double)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
+        "lgt_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), i32, vp, vp]),
+        "lgt_cg_solve_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), C.POINTER(_Links),
+                                       C.POINTER(_Links), C.POINTER(_CgParams), vp, vp, C.POINTER(_CgResult)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -363,6 +367,41 @@ class Lattice:
         dlo = U_lo.desc() if U_lo is not None else None
         st = lib().lgt_cg_solve(self._ctx, C.byref(dhi), C.byref(dlo) if dlo is not None else None,
                                 C.byref(prm), pb, px, C.byref(res))
+        r = CgResult(*(getattr(res, f[0]) for f in _CgResult._fields_))
+        if st != 0 and (raise_on_fail or st not in (-5, -6)):
+            _check(st)
+        return x, r
+
+    # -- improved (fat + Naik) operator
+    def dslash_improved(self, F: PackedLinks, N: PackedLinks, x: torch.Tensor, out_parity: int,
+                        out: torch.Tensor | None = None):
+        """out = D x with the improved operator (fat F, Naik N: same 18-real format)."""
+        dt = torch.float64 if F.prec == LGT_F64 else torch.float32
+        p = self._dev(x, dt, (3, self.Vh, 2), "input vector")
+        if out is None:
+            out = torch.empty_like(x)
+        q = self._dev(out, dt, (3, self.Vh, 2), "output vector")
+        df, dn = F.desc(), N.desc()
+        _check(lib().lgt_dslash_improved(self._ctx, C.byref(df), C.byref(dn), int(out_parity), p, q))
+        return out
+
+    def cg_solve_improved(self, F_hi: PackedLinks, N_hi: PackedLinks, b: torch.Tensor, mass: float,
+                          tol: float = 1e-10, scheme: int = LGT_CG_FP64, F_lo: PackedLinks | None = None,
+                          N_lo: PackedLinks | None = None, ru_interval: int = 50, inner_tol: float = 0.0,
+                          max_iter: int = 100000, raise_on_fail: bool = True):
+        pb = self._dev(b, torch.float64, self.vec_shape(), "b")
+        x = torch.zeros_like(b)
+        px = self._dev(x, torch.float64, self.vec_shape(), "x")
+        prm = _CgParams(float(mass), float(tol), int(max_iter), int(scheme), int(ru_interval), 0,
+                        float(inner_tol), 0, 0)
+        res = _CgResult()
+        dfh, dnh = F_hi.desc(), N_hi.desc()
+        dfl = F_lo.desc() if F_lo is not None else None
+        dnl = N_lo.desc() if N_lo is not None else None
+        st = lib().lgt_cg_solve_improved(self._ctx, C.byref(dfh), C.byref(dnh),
+                                         C.byref(dfl) if dfl is not None else None,
+                                         C.byref(dnl) if dnl is not None else None, C.byref(prm), pb, px,
+                                         C.byref(res))
         r = CgResult(*(getattr(res, f[0]) for f in _CgResult._fields_))
         if st != 0 and (raise_on_fail or st not in (-5, -6)):
             _check(st)

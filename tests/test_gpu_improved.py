@@ -1,0 +1,115 @@
+"""Improved (fat one-link + Naik three-link) staggered operator on the GPU
+against the FP64 oracle: Dslash element by element, the CG in every scheme,
+and the argument checks of its entry points."""
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+import oracle
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1309_0551_amd")
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+FMTS = {"f64r18": (P.LGT_F64, 1e-12), "f32r18": (P.LGT_F32, 32 * U32)}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+@pytest.mark.parametrize("L,bc", [((2, 4, 2, 6), (1, 1, 1, -1)),    # extents 2, 4, 6: hops coincide
+                                  ((4, 2, 6, 4), (-1, 1, -1, 1)),
+                                  ((8, 4, 6, 8), (1, 1, 1, -1)),
+                                  ((10, 8, 12, 6), (1, -1, 1, -1)),  # several workgroups, ragged tail
+                                  ((16, 16, 16, 32), (1, 1, 1, 1))])
+def test_improved_dslash_parity(dev, fmt, L, bc):
+    prec, tol = FMTS[fmt]
+    F, N = li.improved_links(L, 401)
+    vp = prec
+    with P.Lattice(L, bc) as lat:
+        Fp = lat.pack_links(_t(F, dev), prec, P.LGT_R18)
+        Np = lat.pack_links(_t(N, dev), prec, P.LGT_R18)
+        for par in (0, 1):
+            chi = li.vector(L, 402 + par)
+            x = lat.pack_vec(_t(chi, dev), vp)
+            got = lat.unpack_vec(lat.dslash_improved(Fp, Np, x, par), vp).cpu().numpy()
+            ref = oracle.dslash_imp(L, F, N, chi, par, bc)
+            assert _rel(got, ref) <= tol, (fmt, L, par)
+            if prec == P.LGT_F64:
+                assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_improved_dslash_full_size_32(dev):
+    """32^4, the benchmark's lattice and launch configuration: every output site."""
+    L = li.CONFIGS["imp_32x32x32x32"]["L"]
+    F, N = li.improved_links(L, li.CONFIGS["imp_32x32x32x32"]["link_seed"])
+    chi = li.vector(L, 411)
+    with P.Lattice(L) as lat:
+        Fp = lat.pack_links(_t(F, dev), P.LGT_F64, P.LGT_R18)
+        Np = lat.pack_links(_t(N, dev), P.LGT_F64, P.LGT_R18)
+        x = lat.pack_vec(_t(chi, dev))
+        got = lat.unpack_vec(lat.dslash_improved(Fp, Np, x, 1)).cpu().numpy()
+    ref = oracle.dslash_imp(L, F, N, chi, 1)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+CG_CASES = [("fp64", P.LGT_CG_FP64), ("reliable_f32r18", P.LGT_CG_RELIABLE), ("refine_f32r18", P.LGT_CG_REFINE)]
+
+
+@pytest.mark.parametrize("name,scheme", CG_CASES, ids=[c[0] for c in CG_CASES])
+def test_improved_cg_parity(dev, name, scheme):
+    L, mass, tol = (8, 8, 8, 8), 0.1, 1e-10
+    F, N = li.improved_links(L, 421)
+    b = li.vector(L, 422)
+    st, xo, it_o, rr_o = oracle.cg_imp(L, F, N, mass, b, tol=tol)
+    assert st == 0
+    with P.Lattice(L) as lat:
+        Ft, Nt = _t(F, dev), _t(N, dev)
+        Fh, Nh = lat.pack_links(Ft, P.LGT_F64, P.LGT_R18), lat.pack_links(Nt, P.LGT_F64, P.LGT_R18)
+        lo = {}
+        if scheme != P.LGT_CG_FP64:
+            lo = dict(F_lo=lat.pack_links(Ft, P.LGT_F32, P.LGT_R18), N_lo=lat.pack_links(Nt, P.LGT_F32, P.LGT_R18))
+        x, res = lat.cg_solve_improved(Fh, Nh, _t(b, dev), mass, tol=tol, scheme=scheme,
+                                       inner_tol=0.1 if scheme == P.LGT_CG_REFINE else 0.0, **lo)
+    xg = x.cpu().numpy()
+    rr = float(np.linalg.norm(b - oracle.apply_A_imp(L, F, N, mass, xg)) / np.linalg.norm(b))
+    print(f"\nimproved {name}: iters {res.iters} (oracle {it_o}) updates {res.updates} resid {rr:.3e}", flush=True)
+    assert res.status == 0
+    assert rr <= 1.05 * tol
+    assert abs(res.true_rel_resid - rr) <= 1e-3 * tol + 0.05 * rr
+    assert np.linalg.norm(xg - xo) <= (1.05 * tol + rr_o) * np.linalg.norm(b) / (4 * mass * mass)
+    if scheme == P.LGT_CG_FP64:
+        assert abs(res.iters - it_o) <= 3
+
+
+def test_improved_argument_checks(dev):
+    L = (4, 4, 4, 4)
+    F, N = li.improved_links(L, 431)
+    with P.Lattice(L) as lat:
+        Ft, Nt = _t(F, dev), _t(N, dev)
+        F64, N64 = lat.pack_links(Ft, P.LGT_F64, P.LGT_R18), lat.pack_links(Nt, P.LGT_F64, P.LGT_R18)
+        N32 = lat.pack_links(Nt, P.LGT_F32, P.LGT_R18)
+        F12 = lat.pack_links(Ft, P.LGT_F32, P.LGT_R12)
+        x = lat.pack_vec(_t(li.vector(L, 432), dev))
+        with pytest.raises(P.LgtError):          # fat and Naik in different formats
+            lat.dslash_improved(F64, N32, x, 0)
+        with pytest.raises(P.LgtError):          # 12-real fields cannot hold general matrices
+            lat.dslash_improved(F12, lat.pack_links(Nt, P.LGT_F32, P.LGT_R12),
+                                lat.pack_vec(_t(li.vector(L, 433), dev), P.LGT_F32), 0)
+        with pytest.raises(P.LgtError):          # mixed scheme without F32 x 18 inner fields
+            lat.cg_solve_improved(F64, N64, _t(li.vector(L, 434), dev), 0.1, scheme=P.LGT_CG_RELIABLE)

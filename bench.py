@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in Dslash variants")
     ap.add_argument("--no-singles", action="store_true",
                     help="skip the one-time comparison of the batched solves with single solves")
+    ap.add_argument("--no-improved", action="store_true",
+                    help="skip the improved (fat + Naik) operator measurement after the timed steps")
     ap.add_argument("--no-batch", action="store_true",
                     help="leave the batched solves out of the step (short runs under hardware counters)")
     args = ap.parse_args()
@@ -334,6 +336,56 @@ def main():
              "lgt_force_us": round(fk * 1e3, 2),
              "lgt_force_GBps": round(force_bytes / (fk * 1e-3) / 1e9, 1), "lgt_force_alg_bytes": force_bytes}
 
+    # improved (fat + Naik) operator at 32^4, measured after the timed steps:
+    # standalone Dslash per format and link-load kind, FP64 vs FP32 reliable-update CG
+    improved = None
+    if not args.no_improved:
+        ci = li.CONFIGS["imp_32x32x32x32"]
+        Fi, Ni = li.improved_links(L, ci["link_seed"])
+        bi = torch.from_numpy(li.vector(L, ci["src_seed"])).to(dev)
+        Ft, Nt = torch.from_numpy(Fi).to(dev), torch.from_numpy(Ni).to(dev)
+        del Fi, Ni
+        imp_packed = {"f64r18": (lat.pack_links(Ft, P.LGT_F64, P.LGT_R18), lat.pack_links(Nt, P.LGT_F64, P.LGT_R18)),
+                      "f32r18": (lat.pack_links(Ft, P.LGT_F32, P.LGT_R18), lat.pack_links(Nt, P.LGT_F32, P.LGT_R18))}
+        del Ft, Nt
+        improved = {"lattice": list(L), "flop_per_site": P.IMPROVED_FLOP_PER_SITE, "dslash": {}}
+        for name, (Fp, Np) in imp_packed.items():
+            prec = Fp.prec
+            hops0, st0 = lat.dslash_variant(prec, P.LGT_R18)
+            vb = P.vec_bytes_per_site(prec)
+            by = (16 * P.link_bytes_per_dir(prec, P.LGT_R18) + 2 * vb) * Vh
+            xi = lat.pack_vec(bi, prec)
+            oi = lat.native_vec(prec)
+            t = {}
+            for streaming in (1, 0):
+                lat.set_dslash_variant(prec, P.LGT_R18, hops0, streaming)
+                t[streaming] = statistics.median(event_times(lat, lambda: lat.dslash_improved(Fp, Np, xi, 1, oi), 20, 5))
+            best = min(t, key=t.get)
+            lat.set_dslash_variant(prec, P.LGT_R18, hops0, best)
+            ms = t[best]
+            improved["dslash"][name] = {"us": round(ms * 1e3, 2), "GBps": round(by / (ms * 1e-3) / 1e9, 1),
+                                        "GFLOPs": round(P.IMPROVED_FLOP_PER_SITE * Vh / (ms * 1e-3) / 1e9, 1),
+                                        "alg_bytes": by, "streaming_links": best,
+                                        "us_streaming_cached": [round(t[1] * 1e3, 2), round(t[0] * 1e3, 2)]}
+            log(f"improved dslash {name}: {improved['dslash'][name]}")
+        (F64p, N64p), (F32p, N32p) = imp_packed["f64r18"], imp_packed["f32r18"]
+        lat.set_timing(TIMING_EVERY)
+        cgs = {}
+        for key, kw in (("fp64", dict(scheme=P.LGT_CG_FP64)),
+                        ("f32r18_reliable", dict(scheme=P.LGT_CG_RELIABLE, F_lo=F32p, N_lo=N32p, ru_interval=50))):
+            _, r = lat.cg_solve_improved(F64p, N64p, bi, ci["mass"], tol=ci["tol"], **kw)
+            cgs[key] = {"seconds": round(r.seconds, 4), "iters": r.iters, "updates": r.updates,
+                        "true_rel_resid": r.true_rel_resid, "status": r.status}
+            if r.dslash_timed_hi:
+                cgs[key]["dslash_f64_us_avg"] = round(1e3 * r.dslash_ms_hi / r.dslash_timed_hi, 2)
+            if r.dslash_timed_lo:
+                cgs[key]["dslash_lo_us_avg"] = round(1e3 * r.dslash_ms_lo / r.dslash_timed_lo, 2)
+            log(f"improved cg {key}: {cgs[key]}")
+        lat.set_timing(0)
+        cgs["speedup_f32_vs_fp64"] = round(cgs["fp64"]["seconds"] / cgs["f32r18_reliable"]["seconds"], 3)
+        improved["cg"] = cgs
+        del imp_packed, F64p, N64p, F32p, N32p
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -365,6 +417,7 @@ def main():
         "cg": cg,
         "batch": batch,
         "mrhs_tune": mrhs_tune,
+        "improved": improved,
         "force": force,
         "dslash_standalone": dslash,
         "cpu_baseline": cpu,

@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in Dslash variants")
     ap.add_argument("--no-singles", action="store_true",
                     help="skip the one-time comparison of the batched solves with single solves")
+    ap.add_argument("--no-routines", action="store_true",
+                    help="skip the per-routine (Table 1) measurement after the timed steps")
     ap.add_argument("--no-improved", action="store_true",
                     help="skip the improved (fat + Naik) operator measurement after the timed steps")
     ap.add_argument("--no-batch", action="store_true",
@@ -386,6 +388,40 @@ def main():
         improved["cg"] = cgs
         del imp_packed, F64p, N64p, F32p, N32p
 
+    # Table 1 routines one at a time (the paper times each routine on its own,
+    # Table 2): n independent calls per launch, 20 launches back to back between
+    # the events. "hbm": n = 2^24 calls, operands streamed from HBM; "cache":
+    # operands of about 128 MB (n <= 2^20), which stay in the 256 MB Infinity
+    # Cache from one launch to the next.
+    routines = None
+    if not args.no_routines:
+        routines = {}
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7001)
+        reps = 20
+        for name, (rid, ka, kb, kc, fl) in P.ROUTINES.items():
+            routines[name] = {"flop_per_call": fl}
+            for prec, dt, eb in (("f64", torch.float64, 16), ("f32", torch.float32, 8)):
+                per_call = (P.PLANES[ka] + P.PLANES[kb] + P.PLANES[kc]) * eb
+                row = {}
+                for label, n in (("hbm", 1 << 24), ("cache", min(1 << 20, (128 << 20) // per_call // 256 * 256))):
+                    ra = torch.randn((P.PLANES[ka], n, 2), generator=gen, device=dev, dtype=dt)
+                    rb = torch.randn((P.PLANES[kb], n, 2), generator=gen, device=dev, dtype=dt)
+                    rc = torch.empty((P.PLANES[kc], n, 2), device=dev, dtype=dt)
+
+                    def burst():
+                        for _ in range(reps):
+                            P.routine(lat, name, ra, rb, 0.5, out=rc)
+
+                    ms = statistics.median(event_times(lat, burst, 5, 1)) / reps
+                    row[label] = {"n": n, "ns_per_call": round(ms * 1e6 / n, 4),
+                                  "GBps": round(per_call * n / (ms * 1e-3) / 1e9, 1),
+                                  "GFLOPs": round(fl * n / (ms * 1e-3) / 1e9, 1)}
+                    del ra, rb, rc
+                routines[name][prec] = row
+            log(f"routine {name}: {routines[name]}")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -418,6 +454,7 @@ def main():
         "batch": batch,
         "mrhs_tune": mrhs_tune,
         "improved": improved,
+        "routines": routines,
         "force": force,
         "dslash_standalone": dslash,
         "cpu_baseline": cpu,

@@ -224,6 +224,48 @@ lgt_status lgt_cg_solve_improved(lgt_ctx *ctx, const lgt_links *fat_hi, const lg
                                  const lgt_links *fat_lo, const lgt_links *naik_lo, const lgt_cg_params *p,
                                  const double *b, double *x, lgt_cg_result *res);
 
+/* ---- Table 1 routines, one at a time --------------------------------------- *
+ * lgt_routine applies one SU(3) routine of Table 1 to n independent operand
+ * sets (one GPU thread per call), for microbenchmarks of each routine on its
+ * own and for checking each against its definition. Operands are
+ * structure-of-arrays planes of complex numbers in the precision prec
+ * (LGT_F64: double pairs, LGT_F32: float pairs), device memory:
+ *   vec = [3][n], mat = [9][n] (element 3 i + j), vec4 = [4][3][n], mat4 = [4][9][n].
+ * Operands in the routine's argument order (c is the output):
+ *   1 add_su3_vector             a vec, b vec          -> c vec  = a + b
+ *   3 mult_adj_su3_mat_vec       a mat, b vec          -> c vec  = a^dag b (Eqs (1.1)-(2.3))
+ *   4 mult_adj_su3_mat_vec_4dir  a vec, b mat4         -> c vec4 = b_k^dag a
+ *   5 mult_adj_su3_mat_4vec      a mat4, b vec         -> c vec4 = a_k^dag b
+ *   6 mult_su3_an                a mat, b mat          -> c mat  = a^dag b
+ *   8 mult_su3_na                a mat, b mat          -> c mat  = a b^dag
+ *   9 mult_su3_nn                a mat, b mat          -> c mat  = a b
+ *  10 mult_su3_mat_vec           a mat, b vec          -> c vec  = a b
+ *  11 mult_su3_mat_vec_sum_4dir  a mat4, b vec4        -> c vec  = sum_k a_k b_k
+ *  12 scalar_mult_add_su3_matrix a mat, b mat, s       -> c mat  = a + s b
+ *  13 scalar_mult_add_su3_vector a vec, b vec, s       -> c vec  = a + s b
+ *  14 su3_projector              a vec, b vec          -> c mat, c_ij = a_i conj(b_j)
+ *  15 sub_four_su3_vecs          a vec, b vec4         -> c vec  = a - sum_k b_k
+ * (2 and 7, the Wilson half-vector routines, are not built: LGT_ERR_UNSUPPORTED.)
+ * c must not overlap a or b, except that c may be a for 1, 12, 13 and 15.
+ * n = 0 does nothing. Asynchronous on the context's stream. */
+enum {
+    LGT_R_ADD_SU3_VECTOR = 1,
+    LGT_R_MULT_ADJ_SU3_MAT_VEC = 3,
+    LGT_R_MULT_ADJ_SU3_MAT_VEC_4DIR = 4,
+    LGT_R_MULT_ADJ_SU3_MAT_4VEC = 5,
+    LGT_R_MULT_SU3_AN = 6,
+    LGT_R_MULT_SU3_NA = 8,
+    LGT_R_MULT_SU3_NN = 9,
+    LGT_R_MULT_SU3_MAT_VEC = 10,
+    LGT_R_MULT_SU3_MAT_VEC_SUM_4DIR = 11,
+    LGT_R_SCALAR_MULT_ADD_SU3_MATRIX = 12,
+    LGT_R_SCALAR_MULT_ADD_SU3_VECTOR = 13,
+    LGT_R_SU3_PROJECTOR = 14,
+    LGT_R_SUB_FOUR_SU3_VECS = 15
+};
+lgt_status lgt_routine(lgt_ctx *ctx, int32_t routine, int32_t prec, int64_t n, const void *a, const void *b,
+                       void *c, double s);
+
 /* ---- many right-hand sides and lattices ------------------------------------ */
 
 /* Multi-RHS native vectors hold nrhs (1, 2, 4, 8 or 16) right-hand sides of

@@ -417,6 +417,31 @@ lgt_status lgt_cg_solve_improved(lgt_ctx *c, const lgt_links *fat_hi, const lgt_
     return cg_solve(c, fat_hi, fat_lo, p, b, x, res, naik_hi, naik_lo);
 }
 
+lgt_status lgt_routine(lgt_ctx *c, int32_t routine, int32_t prec, int64_t n, const void *a, const void *b,
+                       void *out, double s)
+{
+    CHECK_CTX(c);
+    switch (routine) {
+    case LGT_R_ADD_SU3_VECTOR: case LGT_R_MULT_ADJ_SU3_MAT_VEC: case LGT_R_MULT_ADJ_SU3_MAT_VEC_4DIR:
+    case LGT_R_MULT_ADJ_SU3_MAT_4VEC: case LGT_R_MULT_SU3_AN: case LGT_R_MULT_SU3_NA: case LGT_R_MULT_SU3_NN:
+    case LGT_R_MULT_SU3_MAT_VEC: case LGT_R_MULT_SU3_MAT_VEC_SUM_4DIR: case LGT_R_SCALAR_MULT_ADD_SU3_MATRIX:
+    case LGT_R_SCALAR_MULT_ADD_SU3_VECTOR: case LGT_R_SU3_PROJECTOR: case LGT_R_SUB_FOUR_SU3_VECS: break;
+    case 2: case 7: return fail(LGT_ERR_UNSUPPORTED, "routine %d works on Wilson half-vectors", routine);
+    default: return fail(LGT_ERR_ARG, "unknown routine %d", routine);
+    }
+    if (prec != LGT_F64 && prec != LGT_F32) return fail(LGT_ERR_ARG, "precision must be LGT_F64 or LGT_F32");
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(LGT_ERR_ARG, "bad n %lld", (long long)n);
+    if (n == 0) return LGT_OK;
+    lgt_status st;
+    if ((st = check_ptr(a, "a")) != LGT_OK) return st;
+    if ((st = check_ptr(b, "b")) != LGT_OK) return st;
+    if ((st = check_ptr(out, "c")) != LGT_OK) return st;
+    if (!std::isfinite(s)) return fail(LGT_ERR_ARG, "s must be finite");
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_routine(routine, prec == LGT_F64, a, b, out, n, s, c->stream));
+    return LGT_OK;
+}
+
 lgt_status lgt_cdot(lgt_ctx *c, int64_t n, const double *a, const double *b, double out[2])
 {
     CHECK_CTX(c);

@@ -103,6 +103,10 @@ hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *part
 // sum n partials in order and run the scalar step `fin` (one workgroup)
 hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s);
 
+// ---- Table 1 routines (routines.hip) ---------------------------------------
+hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, void *c, int64_t n, double s,
+                          hipStream_t st);
+
 // ---- force (force.hip) -----------------------------------------------------
 hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,
                         hipStream_t s);

@@ -129,6 +129,7 @@ def _setup(l):
         "lgt_tune_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, C.POINTER(C.c_double)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
         "lgt_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), i32, vp, vp]),
+        "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
         "lgt_cg_solve_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), C.POINTER(_Links),
                                        C.POINTER(_Links), C.POINTER(_CgParams), vp, vp, C.POINTER(_CgResult)]),
     }
@@ -467,6 +468,46 @@ class Lattice:
         d = U.desc()
         _check(lib().lgt_force(self._ctx, C.byref(d), px, float(scale), G.data_ptr()))
         return G
+
+
+# Table 1 routines: id, operand kinds (a, b, c) and flop per call (a mat-vec
+# is 36 multiplications + 30 additions = 66 flop, Sec. 4)
+ROUTINES = {
+    "add_su3_vector": (1, "vec", "vec", "vec", 6),
+    "mult_adj_su3_mat_vec": (3, "mat", "vec", "vec", 66),
+    "mult_adj_su3_mat_vec_4dir": (4, "vec", "mat4", "vec4", 264),
+    "mult_adj_su3_mat_4vec": (5, "mat4", "vec", "vec4", 264),
+    "mult_su3_an": (6, "mat", "mat", "mat", 198),
+    "mult_su3_na": (8, "mat", "mat", "mat", 198),
+    "mult_su3_nn": (9, "mat", "mat", "mat", 198),
+    "mult_su3_mat_vec": (10, "mat", "vec", "vec", 66),
+    "mult_su3_mat_vec_sum_4dir": (11, "mat4", "vec4", "vec", 282),
+    "scalar_mult_add_su3_matrix": (12, "mat", "mat", "mat", 36),
+    "scalar_mult_add_su3_vector": (13, "vec", "vec", "vec", 12),
+    "su3_projector": (14, "vec", "vec", "mat", 54),
+    "sub_four_su3_vecs": (15, "vec", "vec4", "vec", 24),
+}
+# complex numbers per call of each operand kind
+PLANES = {"vec": 3, "mat": 9, "vec4": 12, "mat4": 36}
+
+
+def routine(lat: "Lattice", name: str, a: torch.Tensor, b: torch.Tensor, s: float = 0.0,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    """One Table 1 routine over n calls: operands are [planes][n][2] real tensors
+    (float64 or float32) on the lattice's device; returns c."""
+    rid, ka, kb, kc, _ = ROUTINES[name]
+    n = int(a.shape[1])
+    dt = a.dtype
+    if dt not in (torch.float64, torch.float32):
+        raise LgtError(-1, "operands must be float64 or float32")
+    pa = lat._dev(a, dt, (PLANES[ka], n, 2), "a")
+    pb = lat._dev(b, dt, (PLANES[kb], n, 2), "b")
+    if out is None:
+        out = torch.empty((PLANES[kc], n, 2), dtype=dt, device=lat.device)
+    pc = lat._dev(out, dt, (PLANES[kc], n, 2), "c")
+    prec = LGT_F64 if dt == torch.float64 else LGT_F32
+    _check(lib().lgt_routine(lat._ctx, rid, prec, n, pa, pb, pc, float(s)))
+    return out
 
 
 def cg_solve_batch(problems, mass: float, tol: float = 1e-10, scheme: int = LGT_CG_RELIABLE,

@@ -43,6 +43,8 @@ __all__ = [
     "gaussian_cvec",
     "links",
     "improved_links",
+    "momenta",
+    "uniform",
     "vector",
     "vectors",
     "to_real",
@@ -153,6 +155,23 @@ def improved_links(L, seed: int, c1: float = 9.0 / 8.0, c3: float = -1.0 / 24.0,
     return to_real(F), to_real(N)
 
 
+def momenta(L, seed: int) -> np.ndarray:
+    """Gaussian HMC momenta, complex [4][V][3][3]: P = i H with H the traceless
+    part of (Z + Z^dag)/2, Z complex Gaussian with E|Z_ij|^2 = 1. H then has the
+    distribution of sum_a p^a lambda^a / 2 with p^a ~ N(0, 1) (off-diagonal
+    parts N(0, 1/4) each, diagonal covariance (delta_ij - 1/3)/2)."""
+    V = volume(L)
+    Z = _complex_gaussian(rng(seed), (4, V, 3, 3))
+    H = 0.5 * (Z + np.conj(np.swapaxes(Z, -1, -2)))
+    H = H - (np.trace(H, axis1=-2, axis2=-1) / 3.0)[..., None, None] * np.eye(3)
+    return 1j * H
+
+
+def uniform(seed: int) -> float:
+    """One uniform number in [0, 1) (the Metropolis test's)."""
+    return float(rng(seed).random())
+
+
 def vector(L, seed: int) -> np.ndarray:
     """Canonical float64 colour vector on one parity, [V/2][3][2]."""
     Vh = volume(L) // 2
@@ -185,6 +204,10 @@ CONFIGS = {
                      kind="haar", mass=0.02, nrhs=4, src_seed_offset=10, tol=1e-10),
     "c5_16x16x16x32": dict(L=(16, 16, 16, 32), kind="expih", c=0.5, mass=0.05,
                            link_seed=5001, src_seed=5002, fd_seed=5004, tol=1e-10),
+    # HMC trajectory around the solve (links, momenta, pseudofermion R_e, R_o, Metropolis u)
+    "hmc_16x16x16x16": dict(L=(16, 16, 16, 16), kind="expih", c=0.3, beta=5.6, mass=0.05, eps=0.02,
+                            nsteps=10, link_seed=8001, mom_seed=8002, re_seed=8003, ro_seed=8004,
+                            u_seed=8005, tol=1e-10),
     # improved (fat + Naik) operator at the headline lattice size
     "imp_32x32x32x32": dict(L=(32, 32, 32, 32), mass=0.01, link_seed=6001, src_seed=6002, tol=1e-10),
 }

@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in Dslash variants")
     ap.add_argument("--no-singles", action="store_true",
                     help="skip the one-time comparison of the batched solves with single solves")
+    ap.add_argument("--no-hmc", action="store_true",
+                    help="skip the HMC trajectory measurement after the timed steps")
     ap.add_argument("--no-routines", action="store_true",
                     help="skip the per-routine (Table 1) measurement after the timed steps")
     ap.add_argument("--no-improved", action="store_true",
@@ -388,6 +390,31 @@ def main():
         improved["cg"] = cgs
         del imp_packed, F64p, N64p, F32p, N32p
 
+    # HMC trajectory around the solve (the paper's application-level comparison,
+    # Table 4): FP64 CG vs FP32-12 reliable-update CG inside the same trajectory
+    hmc_res = None
+    if not args.no_hmc:
+        ch = li.CONFIGS["hmc_16x16x16x16"]
+        hl = P.Lattice(ch["L"], device=0)
+        U0 = torch.from_numpy(li.links(ch["L"], ch["kind"], ch["link_seed"], ch["c"])).to(dev)
+        Pm = li.momenta(ch["L"], ch["mom_seed"])
+        P0 = torch.from_numpy(np.ascontiguousarray(np.stack([Pm.real, Pm.imag], -1))).to(dev)
+        Re = torch.from_numpy(li.vector(ch["L"], ch["re_seed"])).to(dev)
+        Ro = torch.from_numpy(li.vector(ch["L"], ch["ro_seed"])).to(dev)
+        u = li.uniform(ch["u_seed"])
+        kw = dict(beta=ch["beta"], mass=ch["mass"], eps=ch["eps"], nsteps=ch["nsteps"], u=u, tol=ch["tol"])
+        hl.hmc_trajectory(U0.clone(), P0.clone(), Re, Ro, **dict(kw, nsteps=1))  # allocate workspace
+        hmc_res = {"lattice": list(ch["L"]), "beta": ch["beta"], "mass": ch["mass"], "eps": ch["eps"],
+                   "nsteps": ch["nsteps"], "tol": ch["tol"]}
+        for key, sch in (("fp64", P.LGT_CG_FP64), ("f32r12_reliable", P.LGT_CG_RELIABLE)):
+            r = hl.hmc_trajectory(U0.clone(), P0.clone(), Re, Ro, scheme=sch, **kw)
+            hmc_res[key] = {"seconds": round(r["seconds"], 4), "dH": r["dH"], "accepted": r["accepted"],
+                            "cg_solves": r["cg_solves"], "cg_iters": r["cg_iters"]}
+            log(f"hmc {key}: {hmc_res[key]}")
+        hmc_res["speedup_f32_vs_fp64"] = round(hmc_res["fp64"]["seconds"] / hmc_res["f32r12_reliable"]["seconds"], 3)
+        hl.close()
+        del U0, P0, Re, Ro
+
     # Table 1 routines one at a time (the paper times each routine on its own,
     # Table 2): n independent calls per launch, 20 launches back to back between
     # the events. "hbm": n = 2^24 calls, operands streamed from HBM; "cache":
@@ -454,6 +481,7 @@ def main():
         "batch": batch,
         "mrhs_tune": mrhs_tune,
         "improved": improved,
+        "hmc": hmc_res,
         "routines": routines,
         "force": force,
         "dslash_standalone": dslash,

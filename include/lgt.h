@@ -224,6 +224,55 @@ lgt_status lgt_cg_solve_improved(lgt_ctx *ctx, const lgt_links *fat_hi, const lg
                                  const lgt_links *fat_lo, const lgt_links *naik_lo, const lgt_cg_params *p,
                                  const double *b, double *x, lgt_cg_result *res);
 
+/* ---- the HMC step around the solve ----------------------------------------- *
+ * Fields in the canonical layout [4][V][3][3][2] float64, eo site order, device
+ * memory: links U, momenta P (traceless anti-Hermitian), derivatives G with
+ * dS = sum Re tr(G^dag dU) (lgt_force's convention). Wilson gauge action
+ * S_g = beta sum_{x, mu<nu} (1 - Re tr U_mu,nu(x)/3); molecular dynamics
+ * dU/dt = P U, dP/dt = TA(U G^dag)/2 with TA the traceless anti-Hermitian part,
+ * which conserves H = -sum tr P^2 + S_g + S_f. The paper's application runs
+ * this (Table 4); its gauge side uses the Table 1 matrix products. */
+/* G (+)= scale * dS_g/dU = scale * (-(beta/3)) Sigma^dag, Sigma_mu(x) the staple
+ * sum; accumulate = 0 overwrites G. Asynchronous. */
+lgt_status lgt_gauge_force(lgt_ctx *ctx, const double *U, double beta, double scale, int32_t accumulate, double *G);
+/* P += eps TA(U G^dag) / 2. Asynchronous. */
+lgt_status lgt_momentum_update(lgt_ctx *ctx, const double *U, const double *G, double eps, double *P);
+/* U = exp(eps P) U (degree-12 Taylor series; accurate to rounding for
+ * |eps P| of a molecular-dynamics step). Asynchronous. */
+lgt_status lgt_link_update(lgt_ctx *ctx, const double *P, double eps, double *U);
+/* sum over x and mu < nu of Re tr U_mu,nu(x) (FP64, fixed summation order); synchronous */
+lgt_status lgt_plaquette(lgt_ctx *ctx, const double *U, double *sum);
+/* K = -sum tr P^2 (FP64, fixed order); synchronous */
+lgt_status lgt_kinetic_energy(lgt_ctx *ctx, const double *P, double *K);
+
+typedef struct {
+    double beta, mass;
+    double eps;       /* leapfrog step */
+    double tol;       /* CG relative residual for the action and every force */
+    double u;         /* uniform in [0, 1) for the Metropolis test */
+    int32_t nsteps;   /* leapfrog steps */
+    int32_t scheme;   /* LGT_CG_FP64, or LGT_CG_RELIABLE with F32 x 12 inner links */
+    int32_t reserved[2];
+} lgt_hmc_params;
+
+typedef struct {
+    double H0, H1, dH;          /* H = K + S_g + S_f at the start and end */
+    double Sg0, Sg1, Sf0, Sf1, K0, K1;
+    double seconds;             /* wall time of the call */
+    int32_t accepted;           /* 1: u < exp(-dH) */
+    int32_t cg_iters, cg_solves;
+    int32_t reserved;
+} lgt_hmc_result;
+
+/* One HMC trajectory: pseudofermion phi_e = 2m R_e - D_eo R_o from the Gaussian
+ * canonical vectors R_e (even) and R_o (odd) at the starting links; leapfrog
+ * with nsteps steps of eps (half momentum steps at both ends), every force
+ * from a fresh CG (x0 = 0) and lgt_force plus lgt_gauge_force; Metropolis test
+ * with u. U and P (device, canonical) are updated in place, or restored when
+ * the trajectory is rejected. Uses context workspace; synchronous. */
+lgt_status lgt_hmc_trajectory(lgt_ctx *ctx, double *U, double *P, const double *R_e, const double *R_o,
+                              const lgt_hmc_params *p, lgt_hmc_result *res);
+
 /* ---- Table 1 routines, one at a time --------------------------------------- *
  * lgt_routine applies one SU(3) routine of Table 1 to n independent operand
  * sets (one GPU thread per call), for microbenchmarks of each routine on its

@@ -1,0 +1,246 @@
+// hmc_abi.cpp -- C ABI of the HMC step: the gauge-side kernels one by one and a
+// native driver for one leapfrog trajectory with a Metropolis test, built on
+// the library's own CG (FP64 or mixed precision) and fermion force.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ctx.hpp"
+
+namespace lgt {
+hipError_t launch_gauge_force(const double *U, double *G, const Geom &g, double beta, double scale, int accumulate,
+                              hipStream_t s);
+hipError_t launch_momentum(const double *U, const double *G, double *P, int64_t V, double eps, hipStream_t s);
+hipError_t launch_links(const double *P, double *U, int64_t V, double eps, hipStream_t s);
+hipError_t launch_plaquette(const double *U, const Geom &g, double *partials, double *out, hipStream_t s);
+hipError_t launch_kinetic(const double *P, int64_t V, double *partials, double *out, hipStream_t s);
+hipError_t launch_phi(const double *Re, const double *t, double *phi, int64_t n, double m2, hipStream_t s);
+} // namespace lgt
+
+using namespace lgt;
+
+namespace {
+
+#define CHECK(c)                                                     \
+    do {                                                             \
+        clear_error();                                               \
+        if (!(c)) return fail(LGT_ERR_ARG, "context is NULL");       \
+    } while (0)
+
+int64_t volume(const lgt_ctx *c) { return 2 * (int64_t)c->g.Vh; }
+
+// scalar reduction result of a launch_* kernel pair, read back synchronously
+lgt_status reduce_to_host(lgt_ctx *c, double *dev_out, double *host_out)
+{
+    double *h = (double *)pinned(c, 3 * sizeof(CgState));
+    if (!h) return fail(LGT_ERR_OOM, "cannot allocate pinned staging");
+    LGT_HIP(hipMemcpyAsync(h, dev_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LGT_HIP(hipStreamSynchronize(c->stream));
+    *host_out = h[0];
+    return LGT_OK;
+}
+
+lgt_status plaquette(lgt_ctx *c, const double *U, double *sum)
+{
+    const int64_t nb = (volume(c) + kBS - 1) / kBS;
+    double *part = (double *)workspace(c, "hmc.partials", sizeof(double) * (size_t)(4 * nb + 8));
+    double *out = (double *)workspace(c, "hmc.scalar", 64);
+    if (!part || !out) return fail(LGT_ERR_OOM, "cannot allocate the reduction workspace");
+    LGT_HIP(launch_plaquette(U, c->g, part, out, c->stream));
+    return reduce_to_host(c, out, sum);
+}
+
+lgt_status kinetic(lgt_ctx *c, const double *P, double *K)
+{
+    const int64_t nb = (4 * volume(c) + kBS - 1) / kBS;
+    double *part = (double *)workspace(c, "hmc.partials", sizeof(double) * (size_t)(nb + 8));
+    double *out = (double *)workspace(c, "hmc.scalar", 64);
+    if (!part || !out) return fail(LGT_ERR_OOM, "cannot allocate the reduction workspace");
+    LGT_HIP(launch_kinetic(P, volume(c), part, out, c->stream));
+    return reduce_to_host(c, out, K);
+}
+
+} // namespace
+
+extern "C" {
+
+lgt_status lgt_gauge_force(lgt_ctx *c, const double *U, double beta, double scale, int32_t accumulate, double *G)
+{
+    CHECK(c);
+    lgt_status s;
+    if ((s = check_ptr(U, "U")) != LGT_OK) return s;
+    if ((s = check_ptr(G, "G")) != LGT_OK) return s;
+    if (U == G) return fail(LGT_ERR_ARG, "U and G alias");
+    if (!std::isfinite(beta) || !std::isfinite(scale)) return fail(LGT_ERR_ARG, "beta and scale must be finite");
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_gauge_force(U, G, c->g, beta, scale, accumulate != 0, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_momentum_update(lgt_ctx *c, const double *U, const double *G, double eps, double *P)
+{
+    CHECK(c);
+    lgt_status s;
+    if ((s = check_ptr(U, "U")) != LGT_OK) return s;
+    if ((s = check_ptr(G, "G")) != LGT_OK) return s;
+    if ((s = check_ptr(P, "P")) != LGT_OK) return s;
+    if (P == U || P == G) return fail(LGT_ERR_ARG, "P aliases U or G");
+    if (!std::isfinite(eps)) return fail(LGT_ERR_ARG, "eps must be finite");
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_momentum(U, G, P, volume(c), eps, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_link_update(lgt_ctx *c, const double *P, double eps, double *U)
+{
+    CHECK(c);
+    lgt_status s;
+    if ((s = check_ptr(U, "U")) != LGT_OK) return s;
+    if ((s = check_ptr(P, "P")) != LGT_OK) return s;
+    if (P == U) return fail(LGT_ERR_ARG, "P and U alias");
+    if (!std::isfinite(eps)) return fail(LGT_ERR_ARG, "eps must be finite");
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_links(P, U, volume(c), eps, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_plaquette(lgt_ctx *c, const double *U, double *sum)
+{
+    CHECK(c);
+    lgt_status s;
+    if ((s = check_ptr(U, "U")) != LGT_OK) return s;
+    if (!sum) return fail(LGT_ERR_ARG, "sum is NULL");
+    DeviceScope ds(c->device);
+    return plaquette(c, U, sum);
+}
+
+lgt_status lgt_kinetic_energy(lgt_ctx *c, const double *P, double *K)
+{
+    CHECK(c);
+    lgt_status s;
+    if ((s = check_ptr(P, "P")) != LGT_OK) return s;
+    if (!K) return fail(LGT_ERR_ARG, "K is NULL");
+    DeviceScope ds(c->device);
+    return kinetic(c, P, K);
+}
+
+lgt_status lgt_hmc_trajectory(lgt_ctx *c, double *U, double *P, const double *R_e, const double *R_o,
+                              const lgt_hmc_params *hp, lgt_hmc_result *hr)
+{
+    CHECK(c);
+    lgt_status s;
+    if (!hp || !hr) return fail(LGT_ERR_ARG, "params or result is NULL");
+    if ((s = check_ptr(U, "U")) != LGT_OK) return s;
+    if ((s = check_ptr(P, "P")) != LGT_OK) return s;
+    if ((s = check_ptr(R_e, "R_e")) != LGT_OK) return s;
+    if ((s = check_ptr(R_o, "R_o")) != LGT_OK) return s;
+    if (!(hp->mass > 0.0) || !std::isfinite(hp->beta) || !(hp->eps > 0.0) || hp->nsteps < 1 || !(hp->tol > 0.0))
+        return fail(LGT_ERR_ARG, "need mass > 0, finite beta, eps > 0, nsteps >= 1, tol > 0");
+    if (hp->scheme != LGT_CG_FP64 && hp->scheme != LGT_CG_RELIABLE)
+        return fail(LGT_ERR_ARG, "scheme must be LGT_CG_FP64 or LGT_CG_RELIABLE");
+    if (!(hp->u >= 0.0 && hp->u < 1.0)) return fail(LGT_ERR_ARG, "u must be in [0, 1)");
+    DeviceScope ds(c->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    const hipStream_t st = c->stream;
+    const int64_t V = volume(c);
+    const size_t fb = (size_t)4 * V * 18 * sizeof(double);
+    const size_t v64 = (size_t)c->g.Vh * 48;
+    const bool mixed = hp->scheme == LGT_CG_RELIABLE;
+    size_t lb_hi = 0, lb_lo = 0;
+    (void)lgt_links_bytes(&c->geom, LGT_F64, LGT_R18, &lb_hi);
+    if (mixed) (void)lgt_links_bytes(&c->geom, LGT_F32, LGT_R12, &lb_lo);
+    double *U0 = (double *)workspace(c, "hmc.U0", fb);
+    double *P0 = (double *)workspace(c, "hmc.P0", fb);
+    double *G = (double *)workspace(c, "hmc.G", fb);
+    void *Uhi = workspace(c, "hmc.Uhi", lb_hi);
+    void *Ulo = mixed ? workspace(c, "hmc.Ulo", lb_lo) : nullptr;
+    double *phi = (double *)workspace(c, "hmc.phi", v64);
+    double *X = (double *)workspace(c, "hmc.X", v64);
+    double *t = (double *)workspace(c, "hmc.t", v64);
+    void *nv_in = workspace(c, "hmc.nv_in", v64);
+    void *nv_out = workspace(c, "hmc.nv_out", v64);
+    if (!U0 || !P0 || !G || !Uhi || (mixed && !Ulo) || !phi || !X || !t || !nv_in || !nv_out)
+        return fail(LGT_ERR_OOM, "cannot allocate the HMC workspace");
+    LGT_HIP(hipMemcpyAsync(U0, U, fb, hipMemcpyDeviceToDevice, st));
+    LGT_HIP(hipMemcpyAsync(P0, P, fb, hipMemcpyDeviceToDevice, st));
+
+    lgt_links lhi{Uhi, LGT_F64, LGT_R18}, llo{Ulo, LGT_F32, LGT_R12};
+    auto pack = [&]() -> lgt_status {
+        lgt_status r = lgt_pack_links(c, U, LGT_F64, LGT_R18, Uhi);
+        if (r == LGT_OK && mixed) r = lgt_pack_links(c, U, LGT_F32, LGT_R12, Ulo);
+        return r;
+    };
+    lgt_cg_params cp;
+    std::memset(&cp, 0, sizeof(cp));
+    cp.mass = hp->mass;
+    cp.tol = hp->tol;
+    cp.max_iter = 100000;
+    cp.scheme = hp->scheme;
+    cp.ru_interval = 50;
+    std::memset(hr, 0, sizeof(*hr));
+    // X = A^-1 phi from x0 = 0; S_f = Re <phi, X>
+    auto solve = [&](double *Sf) -> lgt_status {
+        lgt_cg_result r;
+        lgt_status q = cg_solve(c, &lhi, mixed ? &llo : nullptr, &cp, phi, X, &r);
+        hr->cg_iters += r.iters;
+        hr->cg_solves += 1;
+        if (q != LGT_OK) return q;
+        if (Sf) {
+            double d[2];
+            // V/2 sites x 3 colours complex numbers
+            if ((q = lgt_cdot(c, (int64_t)c->g.Vh * 3, phi, X, d)) != LGT_OK) return q;
+            *Sf = d[0];
+        }
+        return LGT_OK;
+    };
+    // P += h * TA(U G^dag) / 2 with G = G_fermion + G_gauge at the current U
+    auto kick = [&](double h) -> lgt_status {
+        lgt_status q = solve(nullptr);
+        if (q != LGT_OK) return q;
+        if ((q = lgt_force(c, &lhi, X, 1.0, G)) != LGT_OK) return q;
+        LGT_HIP(launch_gauge_force(U, G, c->g, hp->beta, 1.0, 1, st));
+        LGT_HIP(launch_momentum(U, G, P, V, h, st));
+        return LGT_OK;
+    };
+    auto energy = [&](double *Sg, double *Sf, double *K) -> lgt_status {
+        double pl;
+        lgt_status q;
+        if ((q = plaquette(c, U, &pl)) != LGT_OK) return q;
+        *Sg = hp->beta * (6.0 * (double)V - pl / 3.0);
+        if ((q = kinetic(c, P, K)) != LGT_OK) return q;
+        return solve(Sf);
+    };
+
+    // pseudofermion phi_e = 2m R_e - D_eo R_o at the starting links
+    if ((s = pack()) != LGT_OK) return s;
+    if ((s = lgt_pack_vec(c, LGT_F64, R_o, nv_in)) != LGT_OK) return s;
+    if ((s = lgt_dslash(c, &lhi, LGT_EVEN, nv_in, nv_out)) != LGT_OK) return s;
+    if ((s = lgt_unpack_vec(c, LGT_F64, nv_out, t)) != LGT_OK) return s;
+    LGT_HIP(launch_phi(R_e, t, phi, (int64_t)c->g.Vh * 6, 2.0 * hp->mass, st));
+
+    if ((s = energy(&hr->Sg0, &hr->Sf0, &hr->K0)) != LGT_OK) return s;
+    // leapfrog: half kick, (drift, kick) x nsteps with the last kick halved
+    if ((s = kick(0.5 * hp->eps)) != LGT_OK) return s;
+    for (int k = 0; k < hp->nsteps; k++) {
+        LGT_HIP(launch_links(P, U, V, hp->eps, st));
+        if ((s = pack()) != LGT_OK) return s;
+        if ((s = kick(k < hp->nsteps - 1 ? hp->eps : 0.5 * hp->eps)) != LGT_OK) return s;
+    }
+    if ((s = energy(&hr->Sg1, &hr->Sf1, &hr->K1)) != LGT_OK) return s;
+    hr->H0 = hr->K0 + hr->Sg0 + hr->Sf0;
+    hr->H1 = hr->K1 + hr->Sg1 + hr->Sf1;
+    hr->dH = hr->H1 - hr->H0;
+    if (!std::isfinite(hr->dH)) return fail(LGT_ERR_NONFINITE, "non-finite energy change");
+    hr->accepted = hp->u < std::exp(-hr->dH) ? 1 : 0;
+    if (!hr->accepted) {
+        LGT_HIP(hipMemcpyAsync(U, U0, fb, hipMemcpyDeviceToDevice, st));
+        LGT_HIP(hipMemcpyAsync(P, P0, fb, hipMemcpyDeviceToDevice, st));
+    }
+    LGT_HIP(hipStreamSynchronize(st));
+    hr->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return LGT_OK;
+}
+
+} // extern "C"

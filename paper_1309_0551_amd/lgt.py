@@ -94,6 +94,18 @@ def lib():
     return _lib
 
 
+class _HmcParams(C.Structure):
+    _fields_ = [("beta", C.c_double), ("mass", C.c_double), ("eps", C.c_double), ("tol", C.c_double),
+                ("u", C.c_double), ("nsteps", C.c_int32), ("scheme", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+class _HmcResult(C.Structure):
+    _fields_ = [("H0", C.c_double), ("H1", C.c_double), ("dH", C.c_double), ("Sg0", C.c_double),
+                ("Sg1", C.c_double), ("Sf0", C.c_double), ("Sf1", C.c_double), ("K0", C.c_double),
+                ("K1", C.c_double), ("seconds", C.c_double), ("accepted", C.c_int32), ("cg_iters", C.c_int32),
+                ("cg_solves", C.c_int32), ("reserved", C.c_int32)]
+
+
 def _setup(l):
     vp, i32, st = C.c_void_p, C.c_int32, C.c_int32
     sig = {
@@ -130,6 +142,12 @@ def _setup(l):
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
         "lgt_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), i32, vp, vp]),
         "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
+        "lgt_gauge_force": (st, [vp, vp, C.c_double, C.c_double, i32, vp]),
+        "lgt_momentum_update": (st, [vp, vp, vp, C.c_double, vp]),
+        "lgt_link_update": (st, [vp, vp, C.c_double, vp]),
+        "lgt_plaquette": (st, [vp, vp, C.POINTER(C.c_double)]),
+        "lgt_kinetic_energy": (st, [vp, vp, C.POINTER(C.c_double)]),
+        "lgt_hmc_trajectory": (st, [vp, vp, vp, vp, vp, C.POINTER(_HmcParams), C.POINTER(_HmcResult)]),
         "lgt_cg_solve_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), C.POINTER(_Links),
                                        C.POINTER(_Links), C.POINTER(_CgParams), vp, vp, C.POINTER(_CgResult)]),
     }
@@ -372,6 +390,51 @@ class Lattice:
         if st != 0 and (raise_on_fail or st not in (-5, -6)):
             _check(st)
         return x, r
+
+    # -- HMC step: fields are canonical [4][V][3][3][2] float64 tensors
+    def _field(self, t, what):
+        return self._dev(t, torch.float64, (4, self.V, 3, 3, 2), what)
+
+    def gauge_force(self, U: torch.Tensor, beta: float, scale: float = 1.0, G: torch.Tensor | None = None,
+                    accumulate: bool = False) -> torch.Tensor:
+        """G (+)= scale * dS_g/dU for the Wilson action with coupling beta."""
+        pu = self._field(U, "U")
+        if G is None:
+            G = torch.zeros_like(U) if accumulate else torch.empty_like(U)
+        pg = self._field(G, "G")
+        _check(lib().lgt_gauge_force(self._ctx, pu, float(beta), float(scale), int(bool(accumulate)), pg))
+        return G
+
+    def momentum_update(self, U: torch.Tensor, G: torch.Tensor, eps: float, P: torch.Tensor) -> torch.Tensor:
+        _check(lib().lgt_momentum_update(self._ctx, self._field(U, "U"), self._field(G, "G"), float(eps),
+                                         self._field(P, "P")))
+        return P
+
+    def link_update(self, P: torch.Tensor, eps: float, U: torch.Tensor) -> torch.Tensor:
+        _check(lib().lgt_link_update(self._ctx, self._field(P, "P"), float(eps), self._field(U, "U")))
+        return U
+
+    def plaquette(self, U: torch.Tensor) -> float:
+        out = C.c_double()
+        _check(lib().lgt_plaquette(self._ctx, self._field(U, "U"), C.byref(out)))
+        return float(out.value)
+
+    def kinetic_energy(self, P: torch.Tensor) -> float:
+        out = C.c_double()
+        _check(lib().lgt_kinetic_energy(self._ctx, self._field(P, "P"), C.byref(out)))
+        return float(out.value)
+
+    def hmc_trajectory(self, U: torch.Tensor, P: torch.Tensor, R_e: torch.Tensor, R_o: torch.Tensor, beta: float,
+                       mass: float, eps: float, nsteps: int, u: float, tol: float = 1e-10,
+                       scheme: int = LGT_CG_FP64) -> dict:
+        """One HMC trajectory; U and P are updated in place (restored if rejected)."""
+        prm = _HmcParams(float(beta), float(mass), float(eps), float(tol), float(u), int(nsteps), int(scheme))
+        res = _HmcResult()
+        _check(lib().lgt_hmc_trajectory(self._ctx, self._field(U, "U"), self._field(P, "P"),
+                                        self._dev(R_e, torch.float64, self.vec_shape(), "R_e"),
+                                        self._dev(R_o, torch.float64, self.vec_shape(), "R_o"),
+                                        C.byref(prm), C.byref(res)))
+        return {f[0]: getattr(res, f[0]) for f in _HmcResult._fields_ if f[0] != "reserved"}
 
     # -- improved (fat + Naik) operator
     def dslash_improved(self, F: PackedLinks, N: PackedLinks, x: torch.Tensor, out_parity: int,

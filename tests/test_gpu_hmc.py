@@ -1,0 +1,108 @@
+"""The HMC step on the GPU against the HMC oracle: gauge force, momentum and
+link updates, plaquette and kinetic energy element by element, then whole
+leapfrog trajectories (FP64 and mixed-precision CG) and the Metropolis test."""
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+import oracle.hmc as hmc
+
+torch = pytest.importorskip("torch")
+P_ = pytest.importorskip("paper_1309_0551_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("L", [(4, 2, 6, 4), (8, 8, 8, 8)])
+def test_gauge_force_plaquette_vs_oracle(dev, L):
+    beta = 5.7
+    U = li.links(L, "haar", 601)
+    with P_.Lattice(L) as lat:
+        Ut = _t(U, dev)
+        G = lat.gauge_force(Ut, beta).cpu().numpy()
+        ref = hmc.gauge_force_G(L, U, beta)
+        assert np.abs(G - ref).max() <= 1e-13 * np.abs(ref).max()
+        # accumulate: G0 + 0.5 G_gauge
+        G0 = li.links(L, "haar", 602)
+        Ga = lat.gauge_force(Ut, beta, scale=0.5, G=_t(G0, dev), accumulate=True).cpu().numpy()
+        np.testing.assert_allclose(Ga, G0 + 0.5 * ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        pl = lat.plaquette(Ut)
+        assert pl == pytest.approx(hmc.plaquette_sum(L, U), rel=1e-13)
+
+
+def test_momentum_link_kinetic_vs_oracle(dev):
+    L, eps = (4, 4, 6, 4), 0.03
+    U = li.links(L, "haar", 611)
+    G = li.links(L, "haar", 612)  # any complex field serves as G here
+    Pc = li.momenta(L, 613)
+    P = hmc.real(Pc)
+    with P_.Lattice(L) as lat:
+        Ut, Pt = _t(U, dev), _t(P, dev)
+        assert lat.kinetic_energy(Pt) == pytest.approx(hmc.kinetic(Pc), rel=1e-13)
+        lat.momentum_update(Ut, _t(G, dev), eps, Pt)
+        Pref = Pc + eps * hmc.md_force(U, G)
+        np.testing.assert_allclose(Pt.cpu().numpy(), hmc.real(Pref), rtol=0, atol=1e-14)
+        lat.link_update(_t(hmc.real(Pref), dev), eps, Ut)
+        Uref = hmc.real(hmc.expm_su3(eps * Pref) @ hmc.cplx(U))
+        np.testing.assert_allclose(Ut.cpu().numpy(), Uref, rtol=0, atol=2e-14)
+
+
+def _traj_inputs(L, seed):
+    U = li.links(L, "expih", seed, c=0.3)
+    Pc = li.momenta(L, seed + 1)
+    return U, Pc, li.vector(L, seed + 2), li.vector(L, seed + 3)
+
+
+@pytest.mark.parametrize("scheme", ["fp64", "reliable_f32r12"])
+def test_trajectory_vs_oracle(dev, scheme):
+    L, beta, mass, eps, nsteps, tol = (4, 4, 4, 4), 5.5, 0.2, 0.025, 8, 1e-12
+    U, Pc, Re, Ro = _traj_inputs(L, 621)
+    ref = hmc.trajectory(L, U, Pc, Re, Ro, beta, mass, eps, nsteps, tol=tol)
+    sch = P_.LGT_CG_FP64 if scheme == "fp64" else P_.LGT_CG_RELIABLE
+    with P_.Lattice(L) as lat:
+        Ut, Pt = _t(U, dev), _t(hmc.real(Pc), dev)
+        r = lat.hmc_trajectory(Ut, Pt, _t(Re, dev), _t(Ro, dev), beta, mass, eps, nsteps, u=0.0, tol=tol,
+                               scheme=sch)
+        Ug, Pg = Ut.cpu().numpy(), Pt.cpu().numpy()
+    print(f"\nhmc {scheme}: dH gpu {r['dH']:.10f} oracle {ref['dH']:.10f}; H0 {r['H0']:.6f}; "
+          f"cg {r['cg_solves']} solves {r['cg_iters']} iters", flush=True)
+    assert r["accepted"] == 1  # u = 0 accepts every finite trajectory
+    for k in ("H0", "Sg0", "Sf0", "K0", "H1", "Sg1", "Sf1", "K1"):
+        assert r[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-9), k
+    assert abs(r["dH"] - ref["dH"]) <= 1e-8
+    assert np.abs(Ug - ref["U"]).max() <= 1e-10
+    assert np.abs(Pg - hmc.real(ref["P"])).max() <= 1e-9
+    assert r["cg_solves"] == nsteps + 3
+
+
+def test_trajectory_rejected_restores_fields(dev):
+    L, beta, mass, eps, nsteps = (4, 4, 4, 4), 5.5, 0.2, 0.05, 4
+    # coarse steps: the first seed whose oracle trajectory raises H by > 0.05,
+    # which u close to 1 must reject
+    for seed in range(631, 661, 3):
+        U, Pc, Re, Ro = _traj_inputs(L, seed)
+        if hmc.trajectory(L, U, Pc, Re, Ro, beta, mass, eps, nsteps)["dH"] > 0.05:
+            break
+    else:
+        pytest.fail("no seed with dH > 0.05")
+    P = hmc.real(Pc)
+    with P_.Lattice(L) as lat:
+        Ut, Pt = _t(U, dev), _t(P, dev)
+        r = lat.hmc_trajectory(Ut, Pt, _t(Re, dev), _t(Ro, dev), beta, mass, eps, nsteps, u=1.0 - 1e-12)
+        assert r["dH"] > 0.05
+        assert r["accepted"] == 0
+        np.testing.assert_array_equal(Ut.cpu().numpy(), U)
+        np.testing.assert_array_equal(Pt.cpu().numpy(), P)
+        with pytest.raises(P_.LgtError):
+            lat.hmc_trajectory(Ut, Pt, _t(Re, dev), _t(Ro, dev), beta, mass, 0.05, 4, u=1.5)

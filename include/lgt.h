@@ -319,7 +319,9 @@ lgt_status lgt_routine(lgt_ctx *ctx, int32_t routine, int32_t prec, int64_t n, c
 
 /* Multi-RHS native vectors hold nrhs (1, 2, 4, 8 or 16) right-hand sides of
  * one parity, right-hand side fastest; canonical multi-RHS vectors are
- * float64 [nrhs][V/2][3][2]. Byte size: nrhs * lgt_vec_bytes. */
+ * float64 [nrhs][V/2][3][2]. Byte size: nrhs * lgt_vec_bytes. Every multi-RHS
+ * call (and lgt_cg_solve_batch) needs V/2 * 16 < 2^31, else
+ * LGT_ERR_UNSUPPORTED. */
 lgt_status lgt_pack_vec_mrhs(lgt_ctx *ctx, int32_t prec, int32_t nrhs, const double *src, void *dst);
 lgt_status lgt_unpack_vec_mrhs(lgt_ctx *ctx, int32_t prec, int32_t nrhs, const void *src, double *dst);
 /* out = D in for nrhs right-hand sides at once (native multi-RHS vectors in

@@ -31,6 +31,7 @@ lgt_status lgt_pack_vec_mrhs(lgt_ctx *c, int32_t prec, int32_t nrhs, const doubl
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
     const int logN = log2_rhs(nrhs);
     if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (!mrhs_size_ok(c->g.Vh)) return fail(LGT_ERR_UNSUPPORTED, "lattice too large for multi-RHS vectors");
     if (prec != LGT_F64 && prec != LGT_F32 && prec != LGT_BF16) return fail(LGT_ERR_ARG, "bad precision %d", prec);
     lgt_status s;
     if ((s = check_ptr(src, "src")) != LGT_OK) return s;
@@ -46,6 +47,7 @@ lgt_status lgt_unpack_vec_mrhs(lgt_ctx *c, int32_t prec, int32_t nrhs, const voi
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
     const int logN = log2_rhs(nrhs);
     if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (!mrhs_size_ok(c->g.Vh)) return fail(LGT_ERR_UNSUPPORTED, "lattice too large for multi-RHS vectors");
     if (prec != LGT_F64 && prec != LGT_F32 && prec != LGT_BF16) return fail(LGT_ERR_ARG, "bad precision %d", prec);
     lgt_status s;
     if ((s = check_ptr(src, "src")) != LGT_OK) return s;
@@ -124,6 +126,7 @@ lgt_status lgt_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t out_parity, i
     if (out_parity != LGT_EVEN && out_parity != LGT_ODD) return fail(LGT_ERR_ARG, "bad parity %d", out_parity);
     const int logN = log2_rhs(nrhs);
     if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (!mrhs_size_ok(c->g.Vh)) return fail(LGT_ERR_UNSUPPORTED, "lattice too large for multi-RHS vectors");
     if ((s = check_ptr(in, "in")) != LGT_OK) return s;
     if ((s = check_ptr(out, "out")) != LGT_OK) return s;
     if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
@@ -158,6 +161,7 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         if (!q.ctx) return fail(LGT_ERR_ARG, "problem %d has no context", i);
         if (q.ctx->device != c0->device) return fail(LGT_ERR_ARG, "problem %d is on another device", i);
         if (log2_rhs(q.nrhs) < 0) return fail(LGT_ERR_ARG, "problem %d: nrhs must be 1, 2, 4, 8 or 16", i);
+        if (!mrhs_size_ok(q.ctx->g.Vh)) return fail(LGT_ERR_UNSUPPORTED, "problem %d: lattice too large", i);
         Fmt fh, fl;
         lgt_status s = check_links(q.U_hi, true, &fh);
         if (s != LGT_OK) return s;

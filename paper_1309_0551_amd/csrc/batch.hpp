@@ -86,6 +86,9 @@ bool mrhs_engine_applies(Fmt f, int logN, int Vh, int engine);
 // groups of four lanes per site for the four-lane engines: 1, 2 or 4, with
 // R = N / (4 groups) >= 1 right-hand sides per lane
 bool mrhs_groups_valid(int logN, int gps);
+// The multi-RHS kernels index (site, rhs) and (site, lane) pairs, up to 16 per
+// site, in 32 bits: lattices with V/2 * 16 >= 2^31 are rejected.
+inline bool mrhs_size_ok(int Vh) { return (int64_t)Vh * 16 < ((int64_t)1 << 31); }
 
 // Standalone multi-RHS Dslash (plain epilogue): out = D in, N right-hand sides.
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,

@@ -247,6 +247,7 @@ lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, do
     if (st != LGT_OK) return st;
     const int logN = log2_n(nrhs);
     if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (!mrhs_size_ok(c->g.Vh)) return fail(LGT_ERR_UNSUPPORTED, "lattice too large for multi-RHS vectors");
     DeviceScope ds(c->device);
     std::ostringstream kk;
     kk << cache_key(c, f) << " mrhs" << nrhs;

@@ -118,8 +118,13 @@ lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t every);
  * together (more loads in flight per thread against more waves per SIMD), with
  * link loads that either stream past the caches (streaming = 1, the default)
  * or are cached (0: a link field that fits in the Infinity Cache may be served
- * from it on the next call). The choice is per link format and per context;
- * it changes speed only, never results. hops_per_group must be 1, 2 or 8. */
+ * from it on the next call). hops_per_group = 4 (LGT_HOPS_LDS) is the 2-hop
+ * variant with the input vector's sites around each workgroup's own (its x and
+ * y neighbours) copied once into LDS and read from there; where that range
+ * would exceed 1024 sites (Lx > 768) it runs as 2. The choice is per link format
+ * and per context; it changes speed only, never results. hops_per_group must
+ * be 1, 2, 4 or 8. */
+#define LGT_HOPS_LDS 4
 lgt_status lgt_set_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t hops_per_group,
                                   int32_t streaming);
 lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *hops_per_group,
@@ -127,12 +132,12 @@ lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int
 /* Time every variant on U (2 warm-up and 10 timed launches each, alternating
  * the output parity, on the context's stream; synchronises) and keep the
  * fastest for U's format. times_us (host, may be NULL) receives the mean
- * launch time of the variants (hops, streaming) = (8,1) (2,1) (1,1) (8,0)
- * (2,0) (1,0). When the environment variable LGT_TUNE_CACHE names a file and
+ * launch time of the variants (hops, streaming) = (8,1) (2,1) (1,1) (4,1)
+ * (8,0) (2,0) (1,0) (4,0). When the environment variable LGT_TUNE_CACHE names a file and
  * times_us is NULL, a cached choice for (device architecture, lattice,
  * format) is used without timing unless LGT_TUNE=force; new results are
  * appended to that file. */
-lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[6]);
+lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[8]);
 
 /* ---- geometry export (Sec. 1: unique 4-tuple per site, 8 neighbours) ------- */
 

@@ -22,15 +22,41 @@ namespace lgt {
 // more waves share each SIMD. HPI = 0 is the improved operator: a runtime loop
 // over the 8 hop pairs (one-link and Naik three-link per direction), 16 links
 // per site from two link fields of the same format.
+//
+// HPI = 4 is the direction loop of HPI = 2 with the input vector staged in LDS:
+// a workgroup's 256 output sites are consecutive cb indices, whole x rows
+// (Lx/2 sites each) of a few y values, so their x and y neighbours of the
+// other parity lie in the cb range [first - Lx/2, last + Lx/2]. The workgroup
+// copies that range (256 + Lx sites) into LDS once with coalesced loads; every
+// hop whose neighbour falls in it reads LDS, the others (z and t, and wrapped
+// x/y hops) read global memory.
+extern __shared__ __align__(16) unsigned char lds_dyn[];
+
+// sites of the staged cb range of one workgroup
+__host__ __device__ __forceinline__ int staged_sites(const Geom &g) { return kBS + 2 * g.hx; }
+
 template <class LF, int EPI, int HPI, bool NTL>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
 {
     using T = typename LF::real;
     using VF = VecFmt<T>;
+    using S2 = typename VF::store_t;
     if (!gate_open(a.gate, a.st)) return;
     const int blk = xcd_block(blockIdx.x, a.l.nblk_pad);
     const int cb = blk * kBS + threadIdx.x;
     const size_t Vh = (size_t)a.g.Vh;
+    [[maybe_unused]] const int s0 = blk * kBS - a.g.hx, ns = staged_sites(a.g);
+    [[maybe_unused]] S2 *lds = (S2 *)lds_dyn; // [3][ns]
+    if constexpr (HPI == 4) {
+        for (int i = threadIdx.x; i < ns; i += kBS) {
+            const int n = s0 + i;
+            if (n >= 0 && n < a.g.Vh) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) lds[k * ns + i] = ((const S2 *)a.in)[k * Vh + n];
+            }
+        }
+        __syncthreads();
+    }
     double part = 0.0;
     if (cb < a.g.Vh) {
         int c[4];
@@ -70,6 +96,42 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 VF::template load<false>(a.in, Vh, b, v);
                 negate_if(bwd_neg(a.g, c, mu), v);
                 amv_sub(u, v, acc);
+            }
+        } else if constexpr (HPI == 4) {
+            // a neighbour in the staged range (every x hop, y hops except across
+            // the y wrap) is read from LDS, any other from global memory, through
+            // one generic pointer so the two cases share the instruction stream
+            const S2 *gin = (const S2 *)a.in;
+            auto vsrc = [&](int n, size_t &stride) -> const S2 * {
+                const unsigned j = (unsigned)(n - s0);
+                const bool staged = j < (unsigned)ns;
+                stride = staged ? (size_t)ns : Vh;
+                return staged ? lds + j : gin + n;
+            };
+#pragma unroll 1
+            for (int mu = 0; mu < 4; mu++) {
+                const Hop h = hop_rt(a.g, c, cb, mu);
+                cx<T> u[9], v[3], w[9], z[3];
+                size_t sf, sb;
+                const S2 *pf = vsrc(h.f, sf), *pb = vsrc(h.b, sb);
+                LF::template load<NTL>(a.U, Vh, a.par * 4 + mu, cb, u);
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const S2 x = pf[k * sf];
+                    v[k].re = x.x;
+                    v[k].im = x.y;
+                }
+                LF::template load<NTL>(a.U, Vh, (1 - a.par) * 4 + mu, h.b, w);
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const S2 x = pb[k * sb];
+                    z[k].re = x.x;
+                    z[k].im = x.y;
+                }
+                negate_if(h.fneg, v);
+                mv_add(u, v, acc);
+                negate_if(h.bneg, z);
+                amv_sub(w, z, acc);
             }
         } else if constexpr (HPI == 2) {
 #pragma unroll 1
@@ -144,18 +206,19 @@ template <class LF, int HPI, bool NTL>
 static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
 {
     const dim3 grid(a.l.nblk_pad), block(kBS);
+    const size_t shm = HPI == 4 ? (size_t)3 * staged_sites(a.g) * sizeof(typename VecFmt<typename LF::real>::store_t) : 0;
     switch (epi) {
     case EPI_PLAIN:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, HPI, NTL>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, HPI, NTL>), grid, block, shm, s, a);
         break;
     case EPI_A:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_A, HPI, NTL>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<LF, EPI_A, HPI, NTL>), grid, block, shm, s, a);
         break;
     case EPI_RES:
     case EPI_RES_LO:
         if constexpr (std::is_same<typename LF::real, double>::value) {
-            if (epi == EPI_RES) hipLaunchKernelGGL((k_dslash<LF, EPI_RES, HPI, NTL>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, HPI, NTL>), grid, block, 0, s, a);
+            if (epi == EPI_RES) hipLaunchKernelGGL((k_dslash<LF, EPI_RES, HPI, NTL>), grid, block, shm, s, a);
+            else hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, HPI, NTL>), grid, block, shm, s, a);
         } else {
             return hipErrorInvalidValue;
         }
@@ -178,6 +241,10 @@ static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s)
     switch (a.hpi) {
     case 1: return launch_fmt<LF, 1, NTL>(epi, a, s);
     case 2: return launch_fmt<LF, 2, NTL>(epi, a, s);
+    case 4:
+        // the staged range must fit the LDS budget of a workgroup
+        if (staged_sites(a.g) > kMaxStagedSites) return launch_fmt<LF, 2, NTL>(epi, a, s);
+        return launch_fmt<LF, 4, NTL>(epi, a, s);
     case 8: return launch_fmt<LF, 8, NTL>(epi, a, s);
     default: return hipErrorInvalidValue;
     }

@@ -9,6 +9,8 @@
 namespace lgt {
 
 constexpr int kBS = 256; // threads per workgroup of the site-parallel kernels
+// LDS-staged Dslash: at most this many input sites per workgroup (48 KB at FP64)
+constexpr int kMaxStagedSites = 1024;
 
 // Link storage formats (see fields.hpp)
 enum Fmt { F64R18 = 0, F64R12 = 1, F32R18 = 2, F32R12 = 3, BF16R12 = 4, FMT_COUNT = 5 };
@@ -69,7 +71,7 @@ struct DslashArgs {
     double m4;
     double *partials;
     CgState *st;
-    int hpi; // hops whose loads are issued together: 1, 2 or 8
+    int hpi; // hops whose loads are issued together: 1, 2 or 8; 4 = 2 with the input staged in LDS
     int ntl; // 1: streaming (non-temporal) link loads, 0: cached
 };
 

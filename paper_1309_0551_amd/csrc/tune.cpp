@@ -31,9 +31,9 @@ using namespace lgt;
 
 namespace {
 
-constexpr int kNumVariants = 6;
-const int kHops[kNumVariants] = {8, 2, 1, 8, 2, 1};
-const int kStream[kNumVariants] = {1, 1, 1, 0, 0, 0};
+constexpr int kNumVariants = 8;
+const int kHops[kNumVariants] = {8, 2, 1, 4, 8, 2, 1, 4};
+const int kStream[kNumVariants] = {1, 1, 1, 1, 0, 0, 0, 0};
 
 const char *fmt_name(Fmt f)
 {
@@ -96,7 +96,7 @@ void cache_store_pair(const std::string &key, int a, int b, const double *t, int
 bool cache_lookup(const std::string &key, int *hops, int *stream)
 {
     return cache_lookup_pair(key, hops, stream,
-                             [](int h, int st) { return (h == 1 || h == 2 || h == 8) && (st == 0 || st == 1); });
+                             [](int h, int st) { return (h == 1 || h == 2 || h == 4 || h == 8) && (st == 0 || st == 1); });
 }
 
 void cache_store(const std::string &key, int hops, int stream, const double *t)
@@ -114,7 +114,8 @@ lgt_status lgt_set_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
     Fmt f;
     if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
-    if (hops != 1 && hops != 2 && hops != 8) return fail(LGT_ERR_ARG, "hops per group must be 1, 2 or 8");
+    if (hops != 1 && hops != 2 && hops != 4 && hops != 8)
+        return fail(LGT_ERR_ARG, "hops per group must be 1, 2, 4 (LDS-staged) or 8");
     if (streaming != 0 && streaming != 1) return fail(LGT_ERR_ARG, "streaming must be 0 or 1");
     c->hpi[f] = hops;
     c->ntl[f] = streaming;
@@ -133,7 +134,7 @@ lgt_status lgt_get_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32
     return LGT_OK;
 }
 
-lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[6])
+lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[8])
 {
     clear_error();
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
@@ -171,7 +172,7 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[6])
     a.g = c->g;
     a.gate = GATE_NONE;
     a.l = site_launch(c->g.Vh);
-    double t[kNumVariants] = {0, 0, 0, 0, 0, 0};
+    double t[kNumVariants] = {};
     int best = 0;
     double best_t = 1e300;
     const int reps = 10;

@@ -306,7 +306,7 @@ class Lattice:
         _check(lib().lgt_tune_dslash_mrhs(self._ctx, C.byref(d), int(nrhs), t))
         return {v: t[i] for i, v in enumerate(self.MRHS_VARIANTS) if t[i] >= 0}
 
-    TUNE_VARIANTS = ((8, 1), (2, 1), (1, 1), (8, 0), (2, 0), (1, 0))
+    TUNE_VARIANTS = ((8, 1), (2, 1), (1, 1), (4, 1), (8, 0), (2, 0), (1, 0), (4, 0))
 
     def tune_dslash(self, U: "PackedLinks", report: bool = True):
         """Time every variant on U and keep the fastest; returns {(hops, streaming): us} or None."""
@@ -314,7 +314,7 @@ class Lattice:
         if not report:
             _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), None))
             return None
-        t = (C.c_double * 6)()
+        t = (C.c_double * len(self.TUNE_VARIANTS))()
         _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), t))
         return {v: t[i] for i, v in enumerate(self.TUNE_VARIANTS)}
 

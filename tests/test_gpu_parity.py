@@ -92,10 +92,11 @@ def test_dslash_parity(dev, fmt, L, bc, kind):
 
 
 @pytest.mark.parametrize("fmt", sorted(FMTS))
-@pytest.mark.parametrize("hops,streaming", [(1, 1), (2, 1), (8, 1), (1, 0), (2, 0), (8, 0)])
+@pytest.mark.parametrize("hops,streaming", [(1, 1), (2, 1), (8, 1), (4, 1), (1, 0), (2, 0), (8, 0), (4, 0)])
 def test_dslash_every_variant(dev, fmt, hops, streaming):
-    """Each kernel variant (loads of 1, 2 or 8 hops issued together; streaming or
-    cached link loads) gives the same operator."""
+    """Each kernel variant (loads of 1, 2 or 8 hops issued together, or 2 with
+    the input staged in LDS; streaming or cached link loads) gives the same
+    operator."""
     prec, recon, tol = FMTS[fmt]
     L, bc = (6, 4, 6, 8), (1, 1, 1, -1)
     U = li.links(L, "haar", 121)
@@ -113,6 +114,31 @@ def test_dslash_every_variant(dev, fmt, hops, streaming):
     assert _rel(got, ref) <= tol
     if prec == P.LGT_F64:
         assert _rel(got, ref8) <= 1e-15
+
+
+@pytest.mark.parametrize("fmt", ["f64r18", "f32r12"])
+@pytest.mark.parametrize("L,bc", [((2, 2, 2, 2), (1, 1, 1, 1)),        # every neighbour inside the staged range
+                                  ((4, 6, 2, 4), (1, -1, 1, -1)),
+                                  ((32, 4, 4, 6), (1, 1, 1, -1)),      # 8 rows per workgroup, ragged tail
+                                  ((768, 2, 2, 2), (-1, 1, 1, 1)),     # staged range at its 1024-site limit
+                                  ((776, 2, 2, 2), (1, 1, 1, -1))])    # beyond it: runs the 2-hop kernel
+def test_dslash_lds_variant_bitwise(dev, fmt, L, bc):
+    """The LDS-staged variant does the 2-hop variant's arithmetic in the same
+    order: bit-identical output, and the oracle's within the format's bound."""
+    prec, recon, tol = FMTS[fmt]
+    U = li.links(L, "haar", 141)
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        for par in (0, 1):
+            chi = li.vector(L, 142 + par)
+            x = lat.pack_vec(_t(chi, dev), vp)
+            out = {}
+            for hops in (4, 2):
+                lat.set_dslash_variant(prec, recon, hops, 1)
+                out[hops] = lat.unpack_vec(lat.dslash(Up, x, par), vp).cpu().numpy()
+            np.testing.assert_array_equal(out[4], out[2])
+            assert _rel(out[4], oracle.dslash(L, U, chi, par, bc)) <= tol
 
 
 def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):

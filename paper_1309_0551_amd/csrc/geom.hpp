@@ -145,4 +145,37 @@ __host__ __device__ __forceinline__ int xcd_block(int bid, int nblk_pad)
     return (bid & 7) * per + (bid >> 3);
 }
 
+// z-blocked XCD order of site tiles, for kernels whose input vector is too
+// large for an XCD's L2 to hold the three t-slices a slab walk reuses (many
+// right-hand sides per site). Tiles are runs of `T` consecutive cb sites; when
+// a t-slice (V/2 / Lt sites) holds a whole number n_ts >= 8 of them, XCD x
+// takes, for every t, the tiles at positions [x n_ts / 8, (x+1) n_ts / 8) of
+// the slice -- a range of z planes -- and walks them t-major. The input a tile
+// reads from t +- 1 was then loaded a few tiles earlier by the same XCD; only
+// the two z planes bounding the range come from another XCD's share.
+struct TileOrder {
+    int n_ts; // tiles per t-slice; 0: plain slab order (xcd_block)
+    int Lt;
+    int per;  // blocks launched per XCD: Lt * ceil(n_ts / 8)
+};
+
+__host__ __device__ __forceinline__ TileOrder tile_order(const Geom &g, int T)
+{
+    TileOrder o{0, g.L[3], 0};
+    const int slice = g.Vh / g.L[3];
+    if (T <= 0 || slice % T != 0 || slice / T < 8) return o;
+    o.n_ts = slice / T;
+    o.per = g.L[3] * ((o.n_ts + 7) / 8);
+    return o;
+}
+
+// tile of the k-th block of XCD x under order o, or -1 past its share
+__host__ __device__ __forceinline__ int zorder_tile(const TileOrder &o, int x, int k)
+{
+    const int lo = (x * o.n_ts) >> 3, hi = ((x + 1) * o.n_ts) >> 3, ns = hi - lo;
+    if (k >= o.Lt * ns) return -1;
+    const int t = k / ns;
+    return t * o.n_ts + lo + (k - t * ns);
+}
+
 } // namespace lgt

@@ -13,12 +13,28 @@ namespace lgt {
 
 // ------------------------------------------------------- standalone ---
 
+// logical block (a tile of consecutive sites) of this workgroup, or -1
+__device__ __forceinline__ int mrhs_block(const TileOrder &o, int nblk_pad)
+{
+    if (o.n_ts) return zorder_tile(o, blockIdx.x & 7, blockIdx.x >> 3);
+    return xcd_block(blockIdx.x, nblk_pad);
+}
+
+// blocks to launch for nblk tiles under order o
+static int mrhs_grid(const TileOrder &o, int nblk)
+{
+    return o.n_ts ? 8 * o.per : (nblk + 7) / 8 * 8;
+}
+
 template <class LF>
 __global__ __launch_bounds__(kBS) void k_dslash_mrhs(const void *__restrict__ U, const void *__restrict__ in,
-                                                     void *__restrict__ out, Geom g, int par, int logN, int nblk_pad)
+                                                     void *__restrict__ out, Geom g, int par, int logN, int nblk_pad,
+                                                     TileOrder o)
 {
     using T = typename LF::real;
-    const unsigned idx = (unsigned)xcd_block(blockIdx.x, nblk_pad) * kBS + threadIdx.x;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return;
+    const unsigned idx = (unsigned)blk * kBS + threadIdx.x;
     const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
     if (site >= (unsigned)g.Vh) return;
     const size_t Vh = (size_t)g.Vh;
@@ -33,10 +49,13 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs(const void *__restrict__ U,
 // l R .. l R + R - 1; each group of four is one MFMA block.
 template <class LF, int R, int GPS, bool MFMA>
 __global__ __launch_bounds__(kBS) void k_dslash_mrhs4(const void *__restrict__ U, const void *__restrict__ in,
-                                                      void *__restrict__ out, Geom g, int par, int logN, int nblk_pad)
+                                                      void *__restrict__ out, Geom g, int par, int logN, int nblk_pad,
+                                                      TileOrder o)
 {
     constexpr unsigned LPS = 4 * GPS;
-    const unsigned idx = (unsigned)xcd_block(blockIdx.x, nblk_pad) * kBS + threadIdx.x;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return;
+    const unsigned idx = (unsigned)blk * kBS + threadIdx.x;
     const unsigned site = idx / LPS, lane4 = idx & 3u;
     // the lanes of a site and the 64 / LPS sites of a wavefront stay together,
     // and a wavefront is never split by the bound below (Vh is a multiple of 16
@@ -57,9 +76,10 @@ static void launch_mrhs4_rg(bool mf, const void *U, const void *in, void *out, c
     const int64_t n = (int64_t)g.Vh * 4 * GPS;
     const int nblk = (int)((n + kBS - 1) / kBS);
     const int pad = (nblk + 7) / 8 * 8;
-    const dim3 grid(pad), block(kBS);
-    if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, true>), grid, block, 0, s, U, in, out, g, par, logN, pad);
-    else hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, false>), grid, block, 0, s, U, in, out, g, par, logN, pad);
+    const TileOrder o = tile_order(g, kBS / (4 * GPS));
+    const dim3 grid(mrhs_grid(o, nblk)), block(kBS);
+    if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, true>), grid, block, 0, s, U, in, out, g, par, logN, pad, o);
+    else hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, false>), grid, block, 0, s, U, in, out, g, par, logN, pad, o);
 }
 
 template <class LF>
@@ -106,13 +126,14 @@ hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, c
     const int64_t n = (int64_t)g.Vh << logN;
     const int nblk = (int)((n + kBS - 1) / kBS);
     const int pad = (nblk + 7) / 8 * 8;
-    const dim3 grid(pad), block(kBS);
+    const TileOrder o = tile_order(g, kBS >> logN);
+    const dim3 grid(mrhs_grid(o, nblk)), block(kBS);
     switch (f) {
-    case F64R18: hipLaunchKernelGGL(k_dslash_mrhs<LinkF64R18>, grid, block, 0, s, U, in, out, g, par, logN, pad); break;
-    case F64R12: hipLaunchKernelGGL(k_dslash_mrhs<LinkF64R12>, grid, block, 0, s, U, in, out, g, par, logN, pad); break;
-    case F32R18: hipLaunchKernelGGL(k_dslash_mrhs<LinkF32R18>, grid, block, 0, s, U, in, out, g, par, logN, pad); break;
-    case F32R12: hipLaunchKernelGGL(k_dslash_mrhs<LinkF32R12>, grid, block, 0, s, U, in, out, g, par, logN, pad); break;
-    case BF16R12: hipLaunchKernelGGL(k_dslash_mrhs<LinkBF16R12>, grid, block, 0, s, U, in, out, g, par, logN, pad); break;
+    case F64R18: hipLaunchKernelGGL(k_dslash_mrhs<LinkF64R18>, grid, block, 0, s, U, in, out, g, par, logN, pad, o); break;
+    case F64R12: hipLaunchKernelGGL(k_dslash_mrhs<LinkF64R12>, grid, block, 0, s, U, in, out, g, par, logN, pad, o); break;
+    case F32R18: hipLaunchKernelGGL(k_dslash_mrhs<LinkF32R18>, grid, block, 0, s, U, in, out, g, par, logN, pad, o); break;
+    case F32R12: hipLaunchKernelGGL(k_dslash_mrhs<LinkF32R12>, grid, block, 0, s, U, in, out, g, par, logN, pad, o); break;
+    case BF16R12: hipLaunchKernelGGL(k_dslash_mrhs<LinkBF16R12>, grid, block, 0, s, U, in, out, g, par, logN, pad, o); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -304,6 +304,27 @@ def test_cg_deterministic(dev):
             assert torch.equal(x1, x2) and r1.iters == r2.iters
 
 
+@pytest.mark.parametrize("L", [(8, 8, 8, 8), (32, 4, 4, 6)])
+def test_cg_lds_variant_bit_identical(dev, L):
+    """The CG's Dslash launches (plain, 4m^2 p - D with <p,Ap>, and the FP64
+    residual epilogues of the reliable updates) give bit-identical solves with
+    the LDS-staged variant and the 2-hop variant it repeats."""
+    U = li.links(L, "haar", 411)
+    b = li.vector(L, 412)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev))
+        Ul = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        for scheme, lo in ((P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, Ul)):
+            out = []
+            for hops in (4, 2):
+                lat.set_dslash_variant(P.LGT_F64, P.LGT_R18, hops, 1)
+                lat.set_dslash_variant(P.LGT_F32, P.LGT_R12, hops, 0)
+                out.append(lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo))
+            assert torch.equal(out[0][0], out[1][0]) and out[0][1].iters == out[1][1].iters
+            assert out[0][1].updates == out[1][1].updates
+    assert _true_resid(L, U, 0.1, b, out[0][0].cpu().numpy()) <= 1.05e-10
+
+
 # ---------------------------------------------------------------- force ---
 
 @pytest.mark.parametrize("L,bc", [((4, 4, 4, 4), (1, 1, 1, 1)), ((6, 4, 6, 8), (1, 1, 1, -1)),

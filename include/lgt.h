@@ -129,11 +129,12 @@ lgt_status lgt_set_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int
                                   int32_t streaming);
 lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *hops_per_group,
                                   int32_t *streaming);
-/* Time every variant on U (2 warm-up and 10 timed launches each, alternating
- * the output parity, on the context's stream; synchronises) and keep the
- * fastest for U's format. times_us (host, may be NULL) receives the mean
- * launch time of the variants (hops, streaming) = (8,1) (2,1) (1,1) (4,1)
- * (8,0) (2,0) (1,0) (4,0). When the environment variable LGT_TUNE_CACHE names a file and
+/* Time every variant on U as the CG runs it (1 warm-up and 5 timed pairs of a
+ * plain D_oe and a D_eo with the 4m^2 p epilogue and its partial sums, on the
+ * context's stream; synchronises) and keep, for U's format, the first variant
+ * in the order below whose time is within 1 % of the fastest. times_us (host,
+ * may be NULL) receives the mean launch time of the variants (hops,
+ * streaming) = (8,1) (2,1) (1,1) (4,1) (8,0) (2,0) (1,0) (4,0). When the environment variable LGT_TUNE_CACHE names a file and
  * times_us is NULL, a cached choice for (device architecture, lattice,
  * format) is used without timing unless LGT_TUNE=force; new results are
  * appended to that file. */

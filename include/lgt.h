@@ -104,12 +104,13 @@ lgt_status lgt_vec_bytes(const lgt_geom *g, int32_t prec, size_t *bytes);
  * gfx950 part (LGT_ERR_UNSUPPORTED). */
 lgt_status lgt_create(const lgt_geom *g, int32_t device, void *hip_stream, lgt_ctx **out);
 lgt_status lgt_destroy(lgt_ctx *ctx);
-/* Dslash kernel timing inside lgt_cg_solve: with every > 0, HIP events are
- * recorded around the two Dslash launches of every `every`-th iteration of
- * each chunk and around every FP64 update's Dslash pair, and the summed times
- * and counts are reported in lgt_cg_result. Each recorded event costs a few
- * microseconds of stream time, so sampling (every = 16, say) keeps the solve
- * time representative. 0 = off (the default); negative is LGT_ERR_ARG. */
+/* Dslash kernel timing inside lgt_cg_solve: with every > 0, the two Dslash
+ * launches of every `every`-th iteration of each chunk and every FP64
+ * update's Dslash pair carry start and stop events on their own dispatch
+ * packets (the kernel's execution alone, as a kernel trace reports it), and
+ * the summed times and counts are reported in lgt_cg_result. Sampling
+ * (every = 16, say) keeps the host's event bookkeeping small. 0 = off (the
+ * default); negative is LGT_ERR_ARG. */
 lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t every);
 
 /* ---- kernel variants and autotuning ---------------------------------------- */

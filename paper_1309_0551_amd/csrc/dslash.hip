@@ -9,6 +9,8 @@
 // the plane set of the other parity. Every link is read exactly once per call
 // and the kernel is bound by HBM bandwidth: link loads are marked
 // non-temporal so they do not evict the reused input vector from L2.
+#include <hip/hip_ext.h>
+
 #include "fields.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
@@ -202,23 +204,31 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
     if constexpr (EPI != EPI_PLAIN) write_partial(part, a.partials, blk);
 }
 
+// One Dslash launch. With events, they are carried by the kernel's own
+// dispatch packet (hipExtLaunchKernel) and time the kernel alone -- what a
+// kernel trace reports -- without the marker packets (and their stream time)
+// that separate event records add around it.
+template <class K>
+static void launch_k(K kernel, dim3 grid, dim3 block, size_t shm, hipStream_t s, const DslashArgs &a, hipEvent_t e0,
+                     hipEvent_t e1)
+{
+    if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, s, e0, e1, 0u, a);
+    else hipLaunchKernelGGL(kernel, grid, block, shm, s, a);
+}
+
 template <class LF, int HPI, bool NTL>
-static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
+static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid(a.l.nblk_pad), block(kBS);
     const size_t shm = HPI == 4 ? (size_t)3 * staged_sites(a.g) * sizeof(typename VecFmt<typename LF::real>::store_t) : 0;
     switch (epi) {
-    case EPI_PLAIN:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_PLAIN, HPI, NTL>), grid, block, shm, s, a);
-        break;
-    case EPI_A:
-        hipLaunchKernelGGL((k_dslash<LF, EPI_A, HPI, NTL>), grid, block, shm, s, a);
-        break;
+    case EPI_PLAIN: launch_k(k_dslash<LF, EPI_PLAIN, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
+    case EPI_A: launch_k(k_dslash<LF, EPI_A, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_RES:
     case EPI_RES_LO:
         if constexpr (std::is_same<typename LF::real, double>::value) {
-            if (epi == EPI_RES) hipLaunchKernelGGL((k_dslash<LF, EPI_RES, HPI, NTL>), grid, block, shm, s, a);
-            else hipLaunchKernelGGL((k_dslash<LF, EPI_RES_LO, HPI, NTL>), grid, block, shm, s, a);
+            if (epi == EPI_RES) launch_k(k_dslash<LF, EPI_RES, HPI, NTL>, grid, block, shm, s, a, e0, e1);
+            else launch_k(k_dslash<LF, EPI_RES_LO, HPI, NTL>, grid, block, shm, s, a, e0, e1);
         } else {
             return hipErrorInvalidValue;
         }
@@ -230,22 +240,22 @@ static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s)
 }
 
 template <class LF, bool NTL>
-static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s)
+static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.U3) {
         // improved operator: fat and Naik fields are general complex 3x3 (18 reals)
         if constexpr (std::is_same<LF, LinkF64R18>::value || std::is_same<LF, LinkF32R18>::value)
-            return launch_fmt<LF, 0, NTL>(epi, a, s);
+            return launch_fmt<LF, 0, NTL>(epi, a, s, e0, e1);
         else return hipErrorInvalidValue;
     }
     switch (a.hpi) {
-    case 1: return launch_fmt<LF, 1, NTL>(epi, a, s);
-    case 2: return launch_fmt<LF, 2, NTL>(epi, a, s);
+    case 1: return launch_fmt<LF, 1, NTL>(epi, a, s, e0, e1);
+    case 2: return launch_fmt<LF, 2, NTL>(epi, a, s, e0, e1);
     case 4:
         // the staged range must fit the LDS budget of a workgroup
-        if (staged_sites(a.g) > kMaxStagedSites) return launch_fmt<LF, 2, NTL>(epi, a, s);
-        return launch_fmt<LF, 4, NTL>(epi, a, s);
-    case 8: return launch_fmt<LF, 8, NTL>(epi, a, s);
+        if (staged_sites(a.g) > kMaxStagedSites) return launch_fmt<LF, 2, NTL>(epi, a, s, e0, e1);
+        return launch_fmt<LF, 4, NTL>(epi, a, s, e0, e1);
+    case 8: return launch_fmt<LF, 8, NTL>(epi, a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -256,19 +266,19 @@ static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s)
 // 256 MB Infinity Cache (FP32/BF16 12-real at 32^4) may instead stay there
 // from one Dslash to the next with cached loads.
 template <class LF>
-static hipError_t launch_hpi(int epi, const DslashArgs &a, hipStream_t s)
+static hipError_t launch_hpi(int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    return a.ntl ? launch_hpi_ntl<LF, true>(epi, a, s) : launch_hpi_ntl<LF, false>(epi, a, s);
+    return a.ntl ? launch_hpi_ntl<LF, true>(epi, a, s, e0, e1) : launch_hpi_ntl<LF, false>(epi, a, s, e0, e1);
 }
 
-hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s)
+hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     switch (f) {
-    case F64R18: return launch_hpi<LinkF64R18>(epi, a, s);
-    case F64R12: return launch_hpi<LinkF64R12>(epi, a, s);
-    case F32R18: return launch_hpi<LinkF32R18>(epi, a, s);
-    case F32R12: return launch_hpi<LinkF32R12>(epi, a, s);
-    case BF16R12: return launch_hpi<LinkBF16R12>(epi, a, s);
+    case F64R18: return launch_hpi<LinkF64R18>(epi, a, s, e0, e1);
+    case F64R12: return launch_hpi<LinkF64R12>(epi, a, s, e0, e1);
+    case F32R18: return launch_hpi<LinkF32R18>(epi, a, s, e0, e1);
+    case F32R12: return launch_hpi<LinkF32R12>(epi, a, s, e0, e1);
+    case BF16R12: return launch_hpi<LinkBF16R12>(epi, a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }

@@ -75,7 +75,9 @@ struct DslashArgs {
     int ntl; // 1: streaming (non-temporal) link loads, 0: cached
 };
 
-hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s);
+// e0 / e1 (may be null): events set to the start and end of the kernel itself
+hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 hipError_t launch_pack_links(Fmt f, const double *Ucanon, void *Upacked, const Geom &g, hipStream_t s);
 hipError_t launch_pack_vec(bool f64, const double *src, void *dst, const Geom &g, hipStream_t s);
 hipError_t launch_unpack_vec(bool f64, const void *src, double *dst, const Geom &g, hipStream_t s);

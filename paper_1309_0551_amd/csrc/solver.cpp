@@ -108,7 +108,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     // Dslash launch; the reducing epilogues (EPI_A, EPI_RES*) leave one
     // partial sum per workgroup for the finalize kernel that follows.
     auto D = [&](Fmt f, int epi, int par, const void *U, const void *in, void *out, int gate, const void *aux0,
-                 const void *aux1, void *out_lo) {
+                 const void *aux1, void *out_lo, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
         DslashArgs a;
         a.U = U;
         // the improved operator's Naik field that goes with this fat field
@@ -127,14 +127,15 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.st = dst;
         a.hpi = c->hpi[f];
         a.ntl = c->ntl[f];
-        return launch_dslash(f, epi, a, s);
+        return launch_dslash(f, epi, a, s, e0, e1);
     };
     auto F = [&](const double *parts, int fin, int gate, int nparts) {
         return launch_finalize(parts, nparts, dst, fin, gate, s);
     };
-    auto timed = [&](int slot, int idx, bool begin) -> hipError_t {
-        if (!timing) return hipSuccess;
-        return hipEventRecord(tev.ev[((size_t)slot * pairs + idx) * 2 + (begin ? 0 : 1)], s);
+    // start / stop events of timed Dslash launch idx of a chunk slot (null: untimed)
+    auto ev = [&](int slot, int idx, bool begin) -> hipEvent_t {
+        if (!timing || slot < 0) return nullptr;
+        return tev.ev[((size_t)slot * pairs + idx) * 2 + (begin ? 0 : 1)];
     };
     VecArgs va;
     va.x = xlo;
@@ -153,19 +154,17 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     auto reliable = [&](int gate, int slot, int fin) -> hipError_t {
         hipError_t e = hipSuccess;
         if (mixed && (e = launch_ru_accum(x64, xlo, Vh, dst, gate, s)) != hipSuccess) return e;
-        if (slot >= 0 && (e = timed(slot, 2 * chunk, true)) != hipSuccess) return e;
-        if ((e = D(fhi, EPI_PLAIN, LGT_ODD, Uhi->ptr, x64, t64, gate, nullptr, nullptr, nullptr)) != hipSuccess)
+        if ((e = D(fhi, EPI_PLAIN, LGT_ODD, Uhi->ptr, x64, t64, gate, nullptr, nullptr, nullptr,
+                   ev(slot, 2 * chunk, true), ev(slot, 2 * chunk, false))) != hipSuccess)
             return e;
-        if (slot >= 0 && (e = timed(slot, 2 * chunk, false)) != hipSuccess) return e;
-        if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, true)) != hipSuccess) return e;
+        hipEvent_t r0 = ev(slot, 2 * chunk + 1, true), r1 = ev(slot, 2 * chunk + 1, false);
         if (fin == FIN_FINAL)
-            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, q64, gate, x64, b64, nullptr);
+            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, q64, gate, x64, b64, nullptr, r0, r1);
         else if (mixed)
-            e = D(fhi, EPI_RES_LO, LGT_EVEN, Uhi->ptr, t64, nullptr, gate, x64, b64, r);
+            e = D(fhi, EPI_RES_LO, LGT_EVEN, Uhi->ptr, t64, nullptr, gate, x64, b64, r, r0, r1);
         else
-            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr);
+            e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr, r0, r1);
         if (e != hipSuccess) return e;
-        if (slot >= 0 && (e = timed(slot, 2 * chunk + 1, false)) != hipSuccess) return e;
         return F(partials, fin, gate, l.nblk_pad);
     };
 
@@ -222,15 +221,13 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     while (!finished) {
         const int slot = k & 1;
         for (int i = 0; i < chunk; i++) {
-            const bool ti = i % every == 0;
+            const int ts = i % every == 0 ? slot : -1;
             const void *Ui = mixed ? Ulo->ptr : Uhi->ptr;
             LGT_HIP(launch_xpay(lo_is_f64, va, s));
-            if (ti) LGT_HIP(timed(slot, 2 * i, true));
-            LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, Ui, pp, t, GATE_ITER, nullptr, nullptr, nullptr));
-            if (ti) LGT_HIP(timed(slot, 2 * i, false));
-            if (ti) LGT_HIP(timed(slot, 2 * i + 1, true));
-            LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr));
-            if (ti) LGT_HIP(timed(slot, 2 * i + 1, false));
+            LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, Ui, pp, t, GATE_ITER, nullptr, nullptr, nullptr, ev(ts, 2 * i, true),
+                      ev(ts, 2 * i, false)));
+            LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
+                      ev(ts, 2 * i + 1, false)));
             LGT_HIP(launch_update(lo_is_f64, va, s));
             LGT_HIP(F(partials2, FIN_UPDATE, GATE_ITER, l.nblk));
         }

@@ -150,7 +150,9 @@ def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):
         Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
         t = lat.tune_dslash(Up)
         assert set(t) == set(P.Lattice.TUNE_VARIANTS) and all(v > 0 for v in t.values())
-        best = min(t, key=t.get)
+        # the first variant in list order within 1 % of the fastest
+        fastest = min(t.values())
+        best = next(v for v in P.Lattice.TUNE_VARIANTS if t[v] <= 1.01 * fastest)
         assert lat.dslash_variant(P.LGT_F32, P.LGT_R12) == best
     assert "f32r12" in cache.read_text()
     with P.Lattice(L) as lat2:

@@ -168,6 +168,15 @@ lgt_status lgt_unpack_vec(lgt_ctx *ctx, int32_t prec, const void *src, double *d
 lgt_status lgt_dslash(lgt_ctx *ctx, const lgt_links *U, int32_t out_parity,
                       const void *in, void *out);
 
+/* The even-site normal operator the CG solves with, applied once:
+ * out = A in = 4 mass^2 in - D_eo D_oe in (M = 2m + D, A = (M^dag M)_ee).
+ * in and out are native even-parity vectors in the vector precision of
+ * U->prec and must not alias; mass >= 0. When pAp is not NULL it receives
+ * Re <in, A in>, summed in FP64 in a fixed order (deterministic), and the call
+ * synchronises the context's stream; otherwise it only enqueues. */
+lgt_status lgt_apply_normal(lgt_ctx *ctx, const lgt_links *U, double mass, const void *in, void *out,
+                            double *pAp);
+
 /* ---- even-odd CG on A = 4 m^2 - D_eo D_oe ------------------------------------ */
 
 enum {

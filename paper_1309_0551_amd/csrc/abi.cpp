@@ -325,6 +325,52 @@ lgt_status lgt_dslash(lgt_ctx *c, const lgt_links *U, int32_t out_parity, const 
     return LGT_OK;
 }
 
+lgt_status lgt_apply_normal(lgt_ctx *c, const lgt_links *U, double mass, const void *in, void *out, double *pAp)
+{
+    CHECK_CTX(c);
+    Fmt f;
+    lgt_status s;
+    if ((s = check_links(U, false, &f)) != LGT_OK) return s;
+    if (!(mass >= 0.0) || !std::isfinite(mass)) return fail(LGT_ERR_ARG, "mass must be finite and >= 0");
+    if ((s = check_ptr(in, "in")) != LGT_OK) return s;
+    if ((s = check_ptr(out, "out")) != LGT_OK) return s;
+    if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
+    DeviceScope ds(c->device);
+    const size_t vb = (size_t)c->g.Vh * (fmt_is_f64(f) ? 48 : 24);
+    const Launch l = site_launch(c->g.Vh);
+    void *t = workspace(c, "apply.t", vb);
+    double *parts = (double *)workspace(c, "apply.partials", sizeof(double) * (size_t)l.nblk_pad);
+    double *host = pAp ? (double *)pinned(c, sizeof(double) * (size_t)l.nblk_pad) : nullptr;
+    if (!t || !parts || (pAp && !host)) return fail(LGT_ERR_OOM, "cannot allocate the workspace");
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.U = U->ptr;
+    a.g = c->g;
+    a.gate = GATE_NONE;
+    a.l = l;
+    a.hpi = c->hpi[f];
+    a.ntl = c->ntl[f];
+    a.par = LGT_ODD; // t = D_oe in
+    a.in = in;
+    a.out = t;
+    LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
+    a.par = LGT_EVEN; // out = 4m^2 in - D_eo t, one partial <in, out> per workgroup
+    a.in = t;
+    a.out = out;
+    a.aux0 = in;
+    a.m4 = 4.0 * mass * mass;
+    a.partials = parts;
+    LGT_HIP(launch_dslash(f, EPI_A, a, c->stream));
+    if (pAp) {
+        LGT_HIP(hipMemcpyAsync(host, parts, sizeof(double) * (size_t)l.nblk_pad, hipMemcpyDeviceToHost, c->stream));
+        LGT_HIP(hipStreamSynchronize(c->stream));
+        double sum = 0.0;
+        for (int i = 0; i < l.nblk_pad; i++) sum += host[i];
+        *pAp = sum;
+    }
+    return LGT_OK;
+}
+
 namespace {
 
 lgt_status check_cg_params(const lgt_cg_params *p)

@@ -129,6 +129,7 @@ def _setup(l):
         "lgt_set_dslash_variant": (st, [vp, i32, i32, i32, i32]),
         "lgt_get_dslash_variant": (st, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),
+        "lgt_apply_normal": (st, [vp, C.POINTER(_Links), C.c_double, vp, vp, C.POINTER(C.c_double)]),
         "lgt_stream_copy": (st, [vp, vp, vp, C.c_size_t]),
         "lgt_stream_read": (st, [vp, vp, C.c_size_t, vp]),
         "lgt_pack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
@@ -371,6 +372,18 @@ class Lattice:
         d = U.desc()
         _check(lib().lgt_dslash(self._ctx, C.byref(d), int(out_parity), p, q))
         return out
+
+    def apply_normal(self, U: PackedLinks, x: torch.Tensor, mass: float, out: torch.Tensor | None = None):
+        """(A x, Re <x, A x>) with A = 4 mass^2 - D_eo D_oe on native even vectors."""
+        dt = torch.float64 if U.prec == LGT_F64 else torch.float32
+        p = self._dev(x, dt, (3, self.Vh, 2), "input vector")
+        if out is None:
+            out = torch.empty_like(x)
+        q = self._dev(out, dt, (3, self.Vh, 2), "output vector")
+        d = U.desc()
+        pap = C.c_double()
+        _check(lib().lgt_apply_normal(self._ctx, C.byref(d), float(mass), p, q, C.byref(pap)))
+        return out, float(pap.value)
 
     def cg_solve(self, U_hi: PackedLinks, b: torch.Tensor, mass: float, tol: float = 1e-10,
                  scheme: int = LGT_CG_FP64, U_lo: PackedLinks | None = None, ru_interval: int = 50,

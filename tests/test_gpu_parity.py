@@ -141,6 +141,33 @@ def test_dslash_lds_variant_bitwise(dev, fmt, L, bc):
             assert _rel(out[4], oracle.dslash(L, U, chi, par, bc)) <= tol
 
 
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+@pytest.mark.parametrize("L,bc", [((4, 4, 4, 4), (1, 1, 1, 1)), ((6, 4, 6, 8), (1, 1, 1, -1)),
+                                  ((10, 8, 12, 6), (-1, 1, 1, -1))])
+def test_apply_normal_parity(dev, fmt, L, bc):
+    """A = 4m^2 - D_eo D_oe applied once, and Re <x, A x>, against the oracle
+    (two Dslash applications: twice the single-Dslash bound)."""
+    prec, recon, tol = FMTS[fmt]
+    mass = 0.07
+    U = li.links(L, "haar", 151)
+    chi = li.vector(L, 152)
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        x = lat.pack_vec(_t(chi, dev), vp)
+        out, pap = lat.apply_normal(Up, x, mass)
+        got = lat.unpack_vec(out, vp).cpu().numpy()
+        with pytest.raises(P.LgtError):
+            lat.apply_normal(Up, x, mass, out=x)       # in and out alias
+        with pytest.raises(P.LgtError):
+            lat.apply_normal(Up, x, -1.0)
+    ref = oracle.apply_A(L, U, mass, chi, bc)
+    assert _rel(got, ref) <= 2 * tol
+    ref_pap = float(np.sum(chi * ref))  # Re <chi, A chi> over the real layout
+    assert ref_pap > 4 * mass * mass * float(np.sum(chi * chi))
+    assert pap == pytest.approx(ref_pap, rel=2 * tol)
+
+
 def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):
     L = (8, 8, 8, 8)
     U = li.links(L, "haar", 131)

@@ -132,7 +132,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in Dslash variants")
     ap.add_argument("--no-singles", action="store_true",
-                    help="skip the one-time comparison of the batched solves with single solves")
+                    help="skip the one-time comparisons outside the timed steps (batched vs single solves, "
+                         "BF16 links under reliable updates)")
     ap.add_argument("--no-hmc", action="store_true",
                     help="skip the HMC trajectory measurement after the timed steps")
     ap.add_argument("--no-routines", action="store_true",
@@ -298,6 +299,13 @@ def main():
     cg = {k: summ(k) for k in ("fp64", "f32r12_reliable", "bf16r12_refine")}
     cg["speedup_f32_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["f32r12_reliable"]["seconds_median"], 3)
     cg["speedup_bf16_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["bf16r12_refine"]["seconds_median"], 3)
+    if not args.no_singles:
+        # why BF16 links take refinement: the same reliable-update scheme as FP32 (once, untimed)
+        _, r = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE,
+                            U_lo=packed["bf16r12"], ru_interval=50, max_iter=60000, raise_on_fail=False)
+        cg["bf16r12_reliable_untimed"] = {"seconds": round(r.seconds, 4), "iters": r.iters, "updates": r.updates,
+                                          "true_rel_resid": r.true_rel_resid, "status": r.status}
+        log(f"bf16 reliable updates: {cg['bf16r12_reliable_untimed']}")
 
     # batching: wall time of each batched launch vs the same right-hand sides solved one by one
     # (the single solves run once, outside the timed steps)

@@ -45,6 +45,16 @@ template <typename T>
 __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
 {
     if (!gate_open(a.gate, a.st)) return;
+    const int blk = blockIdx.x;
+    const int cb = blk * kBS + threadIdx.x;
+    // the vector loads do not depend on alpha: issue them before the sum
+    cx<T> x[3], r[3], p[3], q[3];
+    if (cb < a.Vh) {
+        VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
+        VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
+        VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
+        VecFmt<T>::template load<false>(a.Ap, (size_t)a.Vh, cb, q);
+    }
     __shared__ double lds[kBS / 64];
     double acc = 0.0;
     for (int i = threadIdx.x; i < a.nparts_in; i += kBS) acc += a.parts_in[i];
@@ -57,16 +67,9 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
         else a.st->alpha = alpha64;
     }
     if (bad) return;
-    const int blk = blockIdx.x;
-    const int cb = blk * kBS + threadIdx.x;
     double part = 0.0;
     if (cb < a.Vh) {
         const T alpha = (T)alpha64;
-        cx<T> x[3], r[3], p[3], q[3];
-        VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
-        VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
-        VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
-        VecFmt<T>::template load<false>(a.Ap, (size_t)a.Vh, cb, q);
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             x[i].re = fma(alpha, p[i].re, x[i].re);

@@ -15,36 +15,48 @@ namespace lgt {
 __global__ __launch_bounds__(kBS) void k_force(const double *__restrict__ X, const double *__restrict__ Y,
                                                double scale, double *__restrict__ G, Geom g)
 {
+    // A workgroup's 256 links are consecutive in [4][V], so its gradients are
+    // one contiguous 36 KB run: each thread writes its 3x3 matrix into LDS,
+    // and the workgroup then stores the run with fully coalesced 16-byte
+    // stores (a direct store of 144 bytes per thread spreads every store
+    // instruction of a wavefront over 64 places 144 bytes apart).
+    __shared__ dv2 buf[kBS * 9];
     const int64_t V = 2 * (int64_t)g.Vh;
-    const int64_t idx = (int64_t)blockIdx.x * kBS + threadIdx.x; // mu*V + eo
-    if (idx >= 4 * V) return;
-    const int mu = (int)(idx / V);
-    const int64_t eo = idx - mu * V;
-    const int par = eo >= g.Vh;
-    const int cb = (int)(eo - par * (int64_t)g.Vh);
-    int c[4];
-    decode(g, par, cb, c);
-    const int f = nbr_fwd(g, c, cb, mu);
-    // a: the vector at x, b: the vector at x+mu (other parity)
-    cx<double> a[3], b[3];
-    if (par == 0) {
-        VecFmt<double>::load<false>(X, (size_t)g.Vh, cb, a);
-        VecFmt<double>::load<false>(Y, (size_t)g.Vh, f, b);
-    } else {
-        VecFmt<double>::load<false>(Y, (size_t)g.Vh, cb, a);
-        VecFmt<double>::load<false>(X, (size_t)g.Vh, f, b);
-    }
-    const bool neg = eta_neg(c, mu) ^ (c[mu] == g.L[mu] - 1 && g.bc[mu] < 0) ^ (par == 1);
-    const double s = neg ? -2.0 * scale : 2.0 * scale;
-    dv2 *out = (dv2 *)(G + idx * 18);
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            const double re = a[i].re * b[j].re + a[i].im * b[j].im;
-            const double im = a[i].im * b[j].re - a[i].re * b[j].im;
-            out[3 * i + j] = dv2{s * re, s * im};
+    const int64_t first = (int64_t)blockIdx.x * kBS;
+    const int64_t idx = first + threadIdx.x; // mu*V + eo
+    if (idx < 4 * V) {
+        const int mu = (int)(idx / V);
+        const int64_t eo = idx - mu * V;
+        const int par = eo >= g.Vh;
+        const int cb = (int)(eo - par * (int64_t)g.Vh);
+        int c[4];
+        decode(g, par, cb, c);
+        const int f = nbr_fwd(g, c, cb, mu);
+        // a: the vector at x, b: the vector at x+mu (other parity)
+        cx<double> a[3], b[3];
+        if (par == 0) {
+            VecFmt<double>::load<false>(X, (size_t)g.Vh, cb, a);
+            VecFmt<double>::load<false>(Y, (size_t)g.Vh, f, b);
+        } else {
+            VecFmt<double>::load<false>(Y, (size_t)g.Vh, cb, a);
+            VecFmt<double>::load<false>(X, (size_t)g.Vh, f, b);
         }
+        const bool neg = eta_neg(c, mu) ^ (c[mu] == g.L[mu] - 1 && g.bc[mu] < 0) ^ (par == 1);
+        const double s = neg ? -2.0 * scale : 2.0 * scale;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const double re = a[i].re * b[j].re + a[i].im * b[j].im;
+                const double im = a[i].im * b[j].re - a[i].re * b[j].im;
+                buf[threadIdx.x * 9 + 3 * i + j] = dv2{s * re, s * im};
+            }
+    }
+    __syncthreads();
+    const int64_t left = 4 * V - first;
+    const int n = 9 * (int)(left < kBS ? left : kBS);
+    dv2 *out = (dv2 *)G + first * 9;
+    for (int k = threadIdx.x; k < n; k += kBS) st<true>(out, (unsigned)k, buf[k]); // streamed: no reuse
 }
 
 hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,

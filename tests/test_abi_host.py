@@ -93,3 +93,17 @@ def test_param_struct_layout_matches_header():
 
 def test_flop_constant():
     assert P.DSLASH_FLOP_PER_SITE == 570
+
+
+def test_build_entry_resolves_both_builders():
+    """build() compiles the library and the oracle; its two steps resolve to
+    the module functions (not a same-named package attribute)."""
+    import importlib
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), ".."))
+    ge = importlib.import_module("__graft_entry__")
+    lib_b, or_b = ge._builders()
+    assert callable(lib_b) and callable(or_b)
+    assert lib_b.__module__ == "paper_1309_0551_amd.build" and or_b.__module__ == "oracle.build"
+    assert callable(ge.smoke)

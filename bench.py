@@ -45,6 +45,31 @@ KERNEL_SOURCES = ["paper_1309_0551_amd/csrc/dslash.hip", "paper_1309_0551_amd/cs
                   "paper_1309_0551_amd/csrc/geom.hpp", "paper_1309_0551_amd/csrc/reduce.hpp"]
 
 
+# The paper's own measurements, quoted as context (Pentium 4 class hardware):
+# seconds for 10^6 cache-warm calls of each routine, SSE2 vs optimised plain C
+# (Table 2), and MILC ks_imp_dyn1 application seconds (Table 4).
+PAPER_TABLE2 = {"mult_su3_mat_vec": (4.05, 7.13), "mult_adj_su3_mat_vec": (4.03, 5.68),
+                "mult_su3_mat_vec_sum_4dir": (17.49, 30.01), "mult_adj_su3_mat_vec_4dir": (15.75, 25.0),
+                "sub_four_su3_vecs": (2.33, 4.44), "su3_projector": (4.09, 16.14)}
+PAPER_TABLE4 = {"4^4 serial FP64": {"plain": 220, "sse2_aligned": 135},
+                "4^4 serial FP32": {"plain": 153, "sse_aligned": 89},
+                "16^4 parallel FP64": {"plain": 17290, "sse2_unaligned": 16614},
+                "16^4 parallel FP32": {"plain": 5367, "sse_unaligned": 4044}}
+
+
+def paper_context():
+    t4 = {k: {**v, "speedup": round(v["plain"] / min(x for n, x in v.items() if n != "plain"), 2)}
+          for k, v in PAPER_TABLE4.items()}
+    return {"hardware": "2.4 GHz Pentium 4, 8 KB L1D, 256 KB L2, 533 MHz bus, 2 GB RAM, gcc -O3 (Table 4); "
+                        "routine timings gcc -O2, 10^6 cache-warm calls (Table 2)",
+            "routine_speedup_sse2_table2": {k: round(b / a, 2) for k, (a, b) in PAPER_TABLE2.items()},
+            "application_table4_s": t4,
+            "single_over_double_plain_table4": {"4^4 serial": round(220 / 153, 2),
+                                                "16^4 parallel": round(17290 / 5367, 2)},
+            "note": "context only: other hardware, other quantities; the comparable figure here is "
+                    "cg.speedup_f32_vs_fp64 (mixed precision over FP64 on one MI355X)"}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -494,6 +519,7 @@ def main():
         "force": force,
         "dslash_standalone": dslash,
         "cpu_baseline": cpu,
+        "paper_context": paper_context(),
     }
     print(json.dumps(line), flush=True)
     lat.close()

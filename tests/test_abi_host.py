@@ -107,3 +107,44 @@ def test_build_entry_resolves_both_builders():
     assert callable(lib_b) and callable(or_b)
     assert lib_b.__module__ == "paper_1309_0551_amd.build" and or_b.__module__ == "oracle.build"
     assert callable(ge.smoke)
+
+
+def test_every_context_call_rejects_a_null_context():
+    """Every entry point that takes a context returns LGT_ERR_ARG for NULL,
+    on the host, before any device work."""
+    l = P.lib()
+    d = C.c_double()
+    i = C.c_int32()
+    calls = {
+        "lgt_index_maps": (None, None, None),
+        "lgt_pack_links": (None, None, 0, 18, None),
+        "lgt_pack_vec": (None, 0, None, None),
+        "lgt_unpack_vec": (None, 0, None, None),
+        "lgt_set_dslash_variant": (None, 0, 18, 8, 1),
+        "lgt_get_dslash_variant": (None, 0, 18, C.byref(i), C.byref(i)),
+        "lgt_tune_dslash": (None, None, None),
+        "lgt_apply_normal": (None, None, 0.1, None, None, C.byref(d)),
+        "lgt_stream_copy": (None, None, None, 16),
+        "lgt_stream_read": (None, None, 16, None),
+        "lgt_pack_vec_mrhs": (None, 1, 4, None, None),
+        "lgt_unpack_vec_mrhs": (None, 1, 4, None, None),
+        "lgt_dslash_mrhs": (None, None, 0, 4, None, None),
+        "lgt_set_mrhs_engine": (None, 0),
+        "lgt_get_mrhs_engine": (None, C.byref(i)),
+        "lgt_set_mrhs_variant": (None, 1, 12, 4, 0, 1),
+        "lgt_get_mrhs_variant": (None, 1, 12, 4, C.byref(i), C.byref(i)),
+        "lgt_tune_dslash_mrhs": (None, None, 4, None),
+        "lgt_dslash_improved": (None, None, None, 0, None, None),
+        "lgt_cg_solve_improved": (None, None, None, None, None, None, None, None, None),
+        "lgt_routine": (None, 1, 0, 16, None, None, None, 1.0),
+        "lgt_gauge_force": (None, None, 5.6, 1.0, 0, None),
+        "lgt_momentum_update": (None, None, None, 0.1, None),
+        "lgt_link_update": (None, None, 0.1, None),
+        "lgt_plaquette": (None, None, C.byref(d)),
+        "lgt_kinetic_energy": (None, None, C.byref(d)),
+        "lgt_hmc_trajectory": (None, None, None, None, None, None, None),
+    }
+    for name, args in calls.items():
+        assert getattr(l, name)(*args) == -1, name
+    # no problems / a NULL problem list
+    assert l.lgt_cg_solve_batch(None, 0, None) == -1

@@ -169,8 +169,8 @@ def main():
                     help="leave the batched solves out of the step (short runs under hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this library has no multi-GPU path (the domain-decomposed "
-              "design is described in DESIGN.md); run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path (its domain decomposition "
+              "over several GPUs is a design only); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

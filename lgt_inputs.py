@@ -205,8 +205,10 @@ CONFIGS = {
     "c5_16x16x16x32": dict(L=(16, 16, 16, 32), kind="expih", c=0.5, mass=0.05,
                            link_seed=5001, src_seed=5002, fd_seed=5004, tol=1e-10),
     # HMC trajectory around the solve (links, momenta, pseudofermion R_e, R_o, Metropolis u)
-    "hmc_16x16x16x16": dict(L=(16, 16, 16, 16), kind="expih", c=0.3, beta=5.6, mass=0.05, eps=0.02,
-                            nsteps=10, link_seed=8001, mom_seed=8002, re_seed=8003, ro_seed=8004,
+    # trajectory length 0.2 in 80 leapfrog steps: |dH| of order 1 from these
+    # (non-equilibrium) links, so the Metropolis test can go either way
+    "hmc_16x16x16x16": dict(L=(16, 16, 16, 16), kind="expih", c=0.3, beta=5.6, mass=0.05, eps=0.0025,
+                            nsteps=80, link_seed=8001, mom_seed=8002, re_seed=8003, ro_seed=8004,
                             u_seed=8005, tol=1e-10),
     # improved (fat + Naik) operator at the headline lattice size
     "imp_32x32x32x32": dict(L=(32, 32, 32, 32), mass=0.01, link_seed=6001, src_seed=6002, tol=1e-10),

@@ -325,6 +325,11 @@ def main():
     cg["speedup_f32_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["f32r12_reliable"]["seconds_median"], 3)
     cg["speedup_bf16_vs_fp64"] = round(cg["fp64"]["seconds_median"] / cg["bf16r12_refine"]["seconds_median"], 3)
     if not args.no_singles:
+        # FP64 with 12-real links (third row rebuilt in FP64): a third fewer link bytes (once, untimed)
+        _, r = lat.cg_solve(packed["f64r12"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
+        cg["fp64_r12_untimed"] = {"seconds": round(r.seconds, 4), "iters": r.iters,
+                                  "true_rel_resid": r.true_rel_resid, "status": r.status}
+        log(f"fp64 with 12-real links: {cg['fp64_r12_untimed']}")
         # why BF16 links take refinement: the same reliable-update scheme as FP32 (once, untimed)
         _, r = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE,
                             U_lo=packed["bf16r12"], ru_interval=50, max_iter=60000, raise_on_fail=False)

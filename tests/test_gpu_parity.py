@@ -271,6 +271,27 @@ def test_cg_parity(dev, case):
         assert abs(res.iters - it_o) <= 3
 
 
+@pytest.mark.parametrize("scheme", [P.LGT_CG_FP64, P.LGT_CG_RELIABLE], ids=["fp64", "rel_f32r12"])
+def test_cg_fp64_12real_links(dev, scheme):
+    """FP64 links stored as 12 reals (third row rebuilt in FP64) in the FP64
+    solve and in the FP64 residuals of reliable updates: same bound as with 18
+    reals, and the same iteration count to within a few."""
+    L, mass, tol = (8, 8, 8, 8), 0.1, 1e-10
+    U = li.links(L, "haar", 211)
+    b = li.vector(L, 212)
+    st, xo, it_o, rr_o = oracle.cg(L, U, mass, b, tol=tol)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev), P.LGT_F64, P.LGT_R12)
+        Ul = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12) if scheme == P.LGT_CG_RELIABLE else None
+        x, res = lat.cg_solve(Uh, _t(b, dev), mass, tol=tol, scheme=scheme, U_lo=Ul)
+    xg = x.cpu().numpy()
+    rr = _true_resid(L, U, mass, b, xg)
+    assert res.status == 0 and rr <= 1.05 * tol
+    assert np.linalg.norm(xg - xo) <= (1.05 * tol + rr_o) * np.linalg.norm(b) / (4 * mass * mass)
+    if scheme == P.LGT_CG_FP64:
+        assert abs(res.iters - it_o) <= 3
+
+
 def test_cg_free_field_plane_wave(dev):
     """Unit links: b is an eigenvector of A with eigenvalue 4 (m^2 + sum sin^2 p)."""
     L = (8, 4, 6, 4)

@@ -377,6 +377,23 @@ def main():
              # lgt_force = pack X + Y = D_oe X + outer-product kernel writing G (4 V x 144 B)
              "lgt_force_us": round(fk * 1e3, 2),
              "lgt_force_GBps": round(force_bytes / (fk * 1e-3) / 1e9, 1), "lgt_force_alg_bytes": force_bytes}
+    # the same action with the mixed-precision forward solve (once, untimed)
+    grads = {}
+    for mixed in (False, True):
+        Ug = Uf.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sg = P.PseudofermionAction.apply(Ug, phi, flat, c5["mass"], 1e-12, 100000, mixed)
+        torch.cuda.synchronize()
+        grads[mixed] = (float(Sg), time.perf_counter() - t0)
+        Sg.backward()
+        grads[mixed] += (Ug.grad.detach().clone(),)
+        del Ug
+    force["mixed_forward"] = {"seconds": round(grads[True][1], 4), "fp64_seconds": round(grads[False][1], 4),
+                              "S_rel_diff": abs(grads[True][0] - grads[False][0]) / abs(grads[False][0]),
+                              "grad_rel_diff": float((grads[True][2] - grads[False][2]).norm()
+                                                     / grads[False][2].norm())}
+    del grads
 
     # improved (fat + Naik) operator at 32^4, measured after the timed steps:
     # standalone Dslash per format and link-load kind, FP64 vs FP32 reliable-update CG

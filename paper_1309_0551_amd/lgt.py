@@ -625,15 +625,24 @@ def cg_solve_batch(problems, mass: float, tol: float = 1e-10, scheme: int = LGT_
 class PseudofermionAction(torch.autograd.Function):
     """S = phi^dag A^-1 phi with A = 4 m^2 - D_eo D_oe, differentiable in U (and phi).
 
-    forward: X = A^-1 phi by the FP64 CG of the library, S = Re <phi, X>.
+    forward: X = A^-1 phi by the library's CG, S = Re <phi, X>; the FP64 CG by
+    default, or with mixed=True the FP32 x 12 inner CG with FP64 reliable
+    updates (same FP64 true-residual stop, so S and dS/dU agree to O(tol)).
     backward: dS/dU from the fermion-force kernel, reusing the saved X.
     U: float64 [4][V][3][3][2] (real view of the complex links), phi: [V/2][3][2].
     """
 
     @staticmethod
-    def forward(ctx, U, phi, lat: Lattice, mass: float, tol: float = 1e-12, max_iter: int = 100000):
+    def forward(ctx, U, phi, lat: Lattice, mass: float, tol: float = 1e-12, max_iter: int = 100000,
+                mixed: bool = False):
         Up = lat.pack_links(U.detach(), LGT_F64, LGT_R18)
-        X, res = lat.cg_solve(Up, phi.detach(), mass, tol=tol, max_iter=max_iter)
+        if mixed:
+            Ul = lat.pack_links(U.detach(), LGT_F32, LGT_R12)
+            X, res = lat.cg_solve(Up, phi.detach(), mass, tol=tol, max_iter=max_iter, scheme=LGT_CG_RELIABLE,
+                                  U_lo=Ul)
+            del Ul
+        else:
+            X, res = lat.cg_solve(Up, phi.detach(), mass, tol=tol, max_iter=max_iter)
         S = lat.cdot(phi.detach(), X).real
         ctx.lat = lat
         ctx.Up = Up
@@ -648,4 +657,4 @@ class PseudofermionAction(torch.autograd.Function):
         gU = ctx.lat.force(ctx.Up, X, scale=g) if ctx.needs_input_grad[0] else None
         # dS/d(Re phi, Im phi) = 2 (Re X, Im X)
         gphi = (2.0 * g) * X if ctx.needs_input_grad[1] else None
-        return gU, gphi, None, None, None, None
+        return gU, gphi, None, None, None, None, None

@@ -408,6 +408,24 @@ def test_autograd_action_vs_oracle(dev):
     np.testing.assert_allclose(pt.grad.cpu().numpy(), 2.5 * 2 * Xo, atol=1e-8 * np.abs(Xo).max())
 
 
+def test_autograd_action_mixed_precision(dev):
+    """The action's forward solve with FP32 x 12 links and FP64 reliable
+    updates: S and dS/dU against the oracle to the same O(kappa tol) bound."""
+    L, mass, tol = (4, 4, 4, 8), 0.05, 1e-12
+    U = li.links(L, "expih", 611, c=0.5)
+    phi = li.vector(L, 612)
+    st, Xo, _, _ = oracle.cg(L, U, mass, phi, tol=1e-13)
+    Go = oracle.force(L, U, Xo)
+    S_o = oracle.cdot(phi, Xo).real
+    with P.Lattice(L) as lat:
+        Ut = _t(U, dev).requires_grad_(True)
+        S = P.PseudofermionAction.apply(Ut, _t(phi, dev), lat, mass, tol, 100000, True)
+        S.backward()
+    kappa = (4 * (mass ** 2) + 64) / (4 * mass ** 2)
+    assert abs(S.item() - S_o) <= kappa * tol * abs(S_o)
+    assert _rel(Ut.grad.cpu().numpy(), Go) <= kappa * tol * 10
+
+
 def test_stream_copy(dev):
     with P.Lattice((4, 4, 4, 4)) as lat:
         src = torch.randn(1 << 20, dtype=torch.float64, device=dev)

@@ -106,3 +106,64 @@ def test_trajectory_rejected_restores_fields(dev):
         np.testing.assert_array_equal(Pt.cpu().numpy(), P)
         with pytest.raises(P_.LgtError):
             lat.hmc_trajectory(Ut, Pt, _t(Re, dev), _t(Ro, dev), beta, mass, 0.05, 4, u=1.5)
+
+
+def _leapfrog_gauge(lat, U, P, beta, eps, n):
+    """Pure-gauge leapfrog from the library's kernels: half momentum steps at
+    both ends, U = exp(eps P) U in between."""
+    lat.momentum_update(U, lat.gauge_force(U, beta), 0.5 * eps, P)
+    for k in range(n):
+        lat.link_update(P, eps, U)
+        lat.momentum_update(U, lat.gauge_force(U, beta), eps if k < n - 1 else 0.5 * eps, P)
+
+
+def _h_gauge(lat, U, P, beta, V):
+    return lat.kinetic_energy(P) + beta * (6 * V - lat.plaquette(U) / 3.0)
+
+
+def test_gauge_leapfrog_reversible(dev):
+    """Integrate, flip the momenta, integrate again: the GPU kernels bring U
+    and -P back to the start (a pin independent of the oracle)."""
+    L, beta, eps, n = (4, 4, 4, 6), 5.6, 0.02, 10
+    U0 = li.links(L, "expih", 641, c=0.3)
+    P0 = hmc.real(li.momenta(L, 642))
+    with P_.Lattice(L) as lat:
+        U, P = _t(U0, dev), _t(P0, dev)
+        _leapfrog_gauge(lat, U, P, beta, eps, n)
+        assert np.abs(U.cpu().numpy() - U0).max() > 1e-3  # it did move
+        P.neg_()
+        _leapfrog_gauge(lat, U, P, beta, eps, n)
+        np.testing.assert_allclose(U.cpu().numpy(), U0, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(P.cpu().numpy(), -P0, rtol=0, atol=1e-11)
+
+
+def test_gauge_leapfrog_energy_error_is_second_order(dev):
+    """Same trajectory length, half the step: |dH| falls by 4 (leapfrog)."""
+    L, beta = (8, 8, 8, 8), 5.6
+    U0 = li.links(L, "expih", 651, c=0.3)
+    P0 = hmc.real(li.momenta(L, 652))
+    V = int(np.prod(L))
+    dH = []
+    with P_.Lattice(L) as lat:
+        for eps, n in ((0.02, 10), (0.01, 20)):
+            U, P = _t(U0, dev), _t(P0, dev)
+            h0 = _h_gauge(lat, U, P, beta, V)
+            _leapfrog_gauge(lat, U, P, beta, eps, n)
+            dH.append(_h_gauge(lat, U, P, beta, V) - h0)
+    print(f"\npure gauge dH: {dH}", flush=True)
+    assert 3.5 <= abs(dH[0] / dH[1]) <= 4.5
+
+
+def test_trajectory_energy_error_is_second_order(dev):
+    """Whole trajectories with the fermion force (FP64 CG): same length, half
+    the step, |dH| falls by 4."""
+    L, beta, mass = (4, 4, 4, 4), 5.5, 0.2
+    U, Pc, Re, Ro = _traj_inputs(L, 661)
+    dH = []
+    with P_.Lattice(L) as lat:
+        for eps, n in ((0.04, 5), (0.02, 10)):
+            r = lat.hmc_trajectory(_t(U, dev), _t(hmc.real(Pc), dev), _t(Re, dev), _t(Ro, dev), beta, mass, eps, n,
+                                   u=0.0, tol=1e-12)
+            dH.append(r["dH"])
+    print(f"\nhmc dH: {dH}", flush=True)
+    assert 3.5 <= abs(dH[0] / dH[1]) <= 4.5

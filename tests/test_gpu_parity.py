@@ -16,6 +16,7 @@ import math
 import numpy as np
 import pytest
 
+import brute
 import lgt_inputs as li
 import oracle
 
@@ -139,6 +140,58 @@ def test_dslash_lds_variant_bitwise(dev, fmt, L, bc):
                 out[hops] = lat.unpack_vec(lat.dslash(Up, x, par), vp).cpu().numpy()
             np.testing.assert_array_equal(out[4], out[2])
             assert _rel(out[4], oracle.dslash(L, U, chi, par, bc)) <= tol
+
+
+def _gpu_dslash(lat, Up, vp, chi, par, dev):
+    return lat.unpack_vec(lat.dslash(Up, lat.pack_vec(_t(chi, dev), vp), par), vp).cpu().numpy()
+
+
+@pytest.mark.parametrize("fmt", ["f64r18", "f64r12", "f32r12"])
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (-1, 1, 1, -1)])
+def test_gpu_dslash_antihermitian(dev, fmt, bc):
+    """<phi_e, D_eo psi_o> = -<D_oe phi_e, psi_o> on the GPU operator itself."""
+    prec, recon, tol = FMTS[fmt]
+    L = (6, 4, 8, 4)
+    U = li.links(L, "haar", 161)
+    phi, psi = li.vector(L, 162), li.vector(L, 163)
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        Dpsi = li.to_complex(_gpu_dslash(lat, Up, vp, psi, 0, dev))
+        Dphi = li.to_complex(_gpu_dslash(lat, Up, vp, phi, 1, dev))
+    lhs = np.vdot(li.to_complex(phi), Dpsi)
+    rhs = -np.vdot(Dphi, li.to_complex(psi))
+    assert abs(lhs - rhs) <= 4 * tol * np.linalg.norm(Dpsi) * np.linalg.norm(phi)
+
+
+@pytest.mark.parametrize("fmt", ["f64r18", "f64r12", "f32r12"])
+def test_gpu_dslash_gauge_covariance(dev, fmt):
+    """D[U^g] (g chi) = g (D[U] chi) for a random SU(3) gauge transform g, on
+    the GPU operator (12-real fields hold the transformed links exactly too)."""
+    prec, recon, tol = FMTS[fmt]
+    L, bc = (4, 6, 4, 6), (1, 1, 1, -1)
+    V = int(np.prod(L))
+    Vh = V // 2
+    U = li.links(L, "haar", 171)
+    G = li.haar_su3(V, li.rng(173))
+    Uc = li.to_complex(U)
+    UG = np.empty_like(Uc)
+    for lex, c in brute.sites(L):
+        e = brute.eo_index(L, c)
+        for mu in range(4):
+            f = brute.eo_index(L, brute.shift(L, c, mu, +1))
+            UG[mu, e] = G[e] @ Uc[mu, e] @ G[f].conj().T
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    with P.Lattice(L, bc) as lat:
+        Up = lat.pack_links(_t(U, dev), prec, recon)
+        UGp = lat.pack_links(_t(li.to_real(UG), dev), prec, recon)
+        for par in (0, 1):
+            chi = li.vector(L, 172 + par)
+            Gin, Gout = G[(1 - par) * Vh:(2 - par) * Vh], G[par * Vh:(par + 1) * Vh]
+            lhs = li.to_complex(_gpu_dslash(lat, UGp, vp, li.to_real(np.einsum("nij,nj->ni", Gin,
+                                                                               li.to_complex(chi))), par, dev))
+            rhs = np.einsum("nij,nj->ni", Gout, li.to_complex(_gpu_dslash(lat, Up, vp, chi, par, dev)))
+            assert np.linalg.norm(lhs - rhs) <= 4 * tol * np.linalg.norm(rhs), (fmt, par)
 
 
 @pytest.mark.parametrize("fmt", sorted(FMTS))

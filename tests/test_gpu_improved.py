@@ -113,3 +113,23 @@ def test_improved_argument_checks(dev):
                                 lat.pack_vec(_t(li.vector(L, 433), dev), P.LGT_F32), 0)
         with pytest.raises(P.LgtError):          # mixed scheme without F32 x 18 inner fields
             lat.cg_solve_improved(F64, N64, _t(li.vector(L, 434), dev), 0.1, scheme=P.LGT_CG_RELIABLE)
+
+
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+def test_improved_dslash_antihermitian(dev, fmt):
+    """<phi_e, D_eo psi_o> = -<D_oe phi_e, psi_o> for the GPU improved operator
+    (antiperiodic t, Naik hops crossing the boundary)."""
+    prec, tol = FMTS[fmt]
+    L, bc = (8, 4, 6, 8), (1, 1, 1, -1)
+    F, N = li.improved_links(L, 441)
+    phi, psi = li.vector(L, 442), li.vector(L, 443)
+    with P.Lattice(L, bc) as lat:
+        Fp = lat.pack_links(_t(F, dev), prec, P.LGT_R18)
+        Np = lat.pack_links(_t(N, dev), prec, P.LGT_R18)
+        Dpsi = li.to_complex(lat.unpack_vec(lat.dslash_improved(Fp, Np, lat.pack_vec(_t(psi, dev), prec), 0),
+                                            prec).cpu().numpy())
+        Dphi = li.to_complex(lat.unpack_vec(lat.dslash_improved(Fp, Np, lat.pack_vec(_t(phi, dev), prec), 1),
+                                            prec).cpu().numpy())
+    lhs = np.vdot(li.to_complex(phi), Dpsi)
+    rhs = -np.vdot(Dphi, li.to_complex(psi))
+    assert abs(lhs - rhs) <= 4 * tol * np.linalg.norm(Dpsi) * np.linalg.norm(phi)

@@ -53,6 +53,7 @@ def _setup(l):
     l.or_cg_imp.restype = C.c_int
     l.or_cg_imp.argtypes = [_ip, _ip, _dp, _dp, C.c_double, _dp, _dp, C.c_double, C.c_int,
                             C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    l.or_force_imp.argtypes = [_ip, _ip, _dp, _dp, _dp, _dp, _dp]
     l.or_action_variational.restype = C.c_double
     l.or_action_variational.argtypes = [_ip, _ip, _dp, C.c_double, _dp, _dp]
     cx = C.c_void_p
@@ -195,6 +196,16 @@ def force(L, U, X, bc=None):
     G = np.empty_like(U)
     lib().or_force(_iptr(L), _iptr(_bc(bc)), _dptr(U), _dptr(X), _dptr(G))
     return G
+
+
+def force_imp(L, F, N, X, bc=None):
+    """(GF, GN) = dS/d(Re, Im) of the fat and Naik fields for the improved
+    operator's S = phi^dag A^-1 phi, given X = A^-1 phi (or_force_imp)."""
+    L = _i4(L)
+    F, N, X = _f64(F), _f64(N), _f64(X)
+    GF, GN = np.empty_like(F), np.empty_like(N)
+    lib().or_force_imp(_iptr(L), _iptr(_bc(bc)), _dptr(F), _dptr(N), _dptr(X), _dptr(GF), _dptr(GN))
+    return GF, GN
 
 
 def action_variational(L, U, mass, phi, x, bc=None):

@@ -564,6 +564,43 @@ void or_force(const int32_t L[4], const int32_t bc[4], const double *U,
     free(Y);
 }
 
+/* The same derivative for the improved operator, with respect to both link
+ * fields: dS = sum Re tr(GF^dag dF) + Re tr(GN^dag dN). Y = D_oe X now has
+ * the Naik hops too; a Naik link N_mu(x) joins x to x + 3 mu with the sign
+ * eta_mu(x) s3 of that hop, so its term is the one-link term with x + mu
+ * replaced by x + 3 mu. */
+void or_force_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N,
+                  const double *X, double *GF, double *GN)
+{
+    const int64_t V = vol(L), Vh = V / 2;
+    double *Y = (double *)malloc(sizeof(double) * Vh * 6);
+    or_dslash_imp(L, bc, F, N, X, Y, 1);
+    const or_cx *Xe = (const or_cx *)X, *Yo = (const or_cx *)Y;
+#pragma omp parallel for schedule(static) num_threads(or_get_threads())
+    for (int64_t eo = 0; eo < V; eo++) {
+        const int par = eo >= Vh;
+        const int64_t cb = eo - par * Vh;
+        int c[4];
+        coords_of_cb(L, par, cb, c);
+        for (int mu = 0; mu < 4; mu++) {
+            for (int naik = 0; naik < 2; naik++) {
+                const int64_t cbp = naik ? nbr3_cb(L, c, mu, +1) : nbr_cb(L, c, mu, +1);
+                const double s = 2.0 * eta(c, mu) * (naik ? s3(L, bc, c, mu, +1) : s_plus(L, bc, c, mu));
+                or_cx P[9];
+                if (par == 0) or_su3_projector(Xe + 3 * cb, Yo + 3 * cbp, P);
+                else or_su3_projector(Yo + 3 * cb, Xe + 3 * cbp, P);
+                const double sgn = par == 0 ? s : -s; /* odd sites: the D_oe half */
+                double *g = (naik ? GN : GF) + ((int64_t)mu * V + eo) * 18;
+                for (int k = 0; k < 9; k++) {
+                    g[2 * k] = sgn * P[k].re;
+                    g[2 * k + 1] = sgn * P[k].im;
+                }
+            }
+        }
+    }
+    free(Y);
+}
+
 double or_action_variational(const int32_t L[4], const int32_t bc[4], const double *U,
                              double mass, const double *phi, const double *x)
 {

@@ -82,6 +82,9 @@ int or_cg_imp(const int32_t L[4], const int32_t bc[4], const double *F, const do
 void or_force(const int32_t L[4], const int32_t bc[4], const double *U,
               const double *X, double *G);
 /* S estimate 2 Re<phi,x> - <x, A x>: error is -r^dag A^-1 r, quadratic in the residual */
+/* dS/dF and dS/dN for the improved operator (GF, GN: [4][V][3][3][2]) */
+void or_force_imp(const int32_t L[4], const int32_t bc[4], const double *F, const double *N,
+                  const double *X, double *GF, double *GN);
 double or_action_variational(const int32_t L[4], const int32_t bc[4], const double *U,
                              double mass, const double *phi, const double *x);
 

@@ -127,3 +127,41 @@ def test_improved_cg_vs_dense_solve():
     xs = np.linalg.solve(brute.dense_A_imp(L, F, N, mass), brute.cvec(b))
     bound = rr * np.linalg.norm(brute.cvec(b)) / (4 * mass * mass)
     assert np.linalg.norm(brute.cvec(x) - xs) <= 1.01 * bound + 1e-12
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (1, 1, 1, -1)])
+def test_improved_force_central_differences(bc):
+    """dS/dF and dS/dN of S = Re phi^dag A^-1 phi (improved operator) from
+    or_force_imp against central differences of S computed by a dense solve of
+    the brute-force matrix, along random directions in F only and in N only.
+    Extent 8 in t keeps the Naik hops apart from the one-link hops there."""
+    L, mass, h = (4, 2, 2, 8), 0.1, 1e-5
+    F, N = li.improved_links(L, 471)
+    phi = brute.cvec(li.vector(L, 472))
+    Vh = int(np.prod(L)) // 2
+
+    def S(Fx, Nx):
+        return float(np.vdot(phi, np.linalg.solve(brute.dense_A_imp(L, Fx, Nx, mass, bc), phi)).real)
+
+    X = brute.rvec(np.linalg.solve(brute.dense_A_imp(L, F, N, mass, bc), phi), Vh)
+    GF, GN = oracle.force_imp(L, F, N, X, bc)
+    rng = np.random.default_rng(473)
+    for which in ("F", "N"):
+        for _ in range(3):
+            E = rng.standard_normal(F.shape)
+            if which == "F":
+                fd = (S(F + h * E, N) - S(F - h * E, N)) / (2 * h)
+                an = float(np.sum(GF * E))
+            else:
+                fd = (S(F, N + h * E) - S(F, N - h * E)) / (2 * h)
+                an = float(np.sum(GN * E))
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (which, fd, an)
+
+
+def test_improved_force_reduces_to_one_link_force():
+    """With the Naik field zero the fat-link derivative is the one-link force."""
+    L = (4, 4, 6, 4)
+    F, N = li.improved_links(L, 481)
+    X = li.vector(L, 482)
+    GF, GN = oracle.force_imp(L, F, np.zeros_like(N), X)
+    np.testing.assert_allclose(GF, oracle.force(L, F, X), rtol=0, atol=1e-13 * np.abs(GF).max())

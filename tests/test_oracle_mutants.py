@@ -52,6 +52,10 @@ MUTANTS = {
     "naik_distance": ("d[mu] = ((d[mu] + 3 * dir) % L[mu] + L[mu]) % L[mu];",
                       "d[mu] = ((d[mu] + 2 * dir) % L[mu] + L[mu]) % L[mu];"),
     # improved operator: backward Naik hop without the adjoint
+    "naik_force_sign": ("const double s = 2.0 * eta(c, mu) * (naik ? s3(L, bc, c, mu, +1) : s_plus(L, bc, c, mu));",
+                        "const double s = 2.0 * eta(c, mu) * (naik ? -s3(L, bc, c, mu, +1) : s_plus(L, bc, c, mu));"),
+    "naik_force_distance": ("const int64_t cbp = naik ? nbr3_cb(L, c, mu, +1) : nbr_cb(L, c, mu, +1);",
+                            "const int64_t cbp = nbr_cb(L, c, mu, +1);"),
     "naik_no_adjoint": ("or_mult_adj_su3_mat_vec(link_at(N, V", "or_mult_su3_mat_vec(link_at(N, V"),
 }
 
@@ -85,6 +89,7 @@ def _pins():
     yield lambda: ipins.test_improved_gauge_covariance((1, -1, 1, -1))
     yield lambda: ipins.test_improved_dense_brute_force((8, 4, 2, 8), (1, 1, 1, -1))
     yield ipins.test_improved_cg_vs_dense_solve
+    yield lambda: ipins.test_improved_force_central_differences((1, 1, 1, -1))
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

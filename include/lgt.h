@@ -240,6 +240,16 @@ lgt_status lgt_cg_solve_improved(lgt_ctx *ctx, const lgt_links *fat_hi, const lg
                                  const lgt_links *fat_lo, const lgt_links *naik_lo, const lgt_cg_params *p,
                                  const double *b, double *x, lgt_cg_result *res);
 
+/* The fermion force of the improved operator, for both link fields: with
+ * X = A^-1 phi (A built from fat and naik, both F64 x 18), G_fat and G_naik
+ * (canonical [4][V][3][3][2], device) receive scale * dS/d(Re, Im) of each
+ * field, dS = sum Re tr(G_fat^dag dF) + Re tr(G_naik^dag dN). The Naik link
+ * N_mu(x) joins x to x + 3 mu, so its derivative is the one-link formula of
+ * lgt_force with x + mu replaced by x + 3 mu and that hop's sign. X is a
+ * canonical even vector. Asynchronous. */
+lgt_status lgt_force_improved(lgt_ctx *ctx, const lgt_links *fat, const lgt_links *naik, const double *X,
+                              double scale, double *G_fat, double *G_naik);
+
 /* ---- the HMC step around the solve ----------------------------------------- *
  * Fields in the canonical layout [4][V][3][3][2] float64, eo site order, device
  * memory: links U, momenta P (traceless anti-Hermitian), derivatives G with

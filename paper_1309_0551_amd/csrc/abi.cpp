@@ -542,4 +542,40 @@ lgt_status lgt_force(lgt_ctx *c, const lgt_links *U, const double *X, double sca
     return LGT_OK;
 }
 
+lgt_status lgt_force_improved(lgt_ctx *c, const lgt_links *fat, const lgt_links *naik, const double *X, double scale,
+                              double *G_fat, double *G_naik)
+{
+    CHECK_CTX(c);
+    Fmt f;
+    lgt_status s;
+    if ((s = check_improved(fat, naik, true, &f)) != LGT_OK) return s;
+    if ((s = check_ptr(X, "X")) != LGT_OK) return s;
+    if ((s = check_ptr(G_fat, "G_fat")) != LGT_OK) return s;
+    if ((s = check_ptr(G_naik, "G_naik")) != LGT_OK) return s;
+    if (G_fat == G_naik) return fail(LGT_ERR_ARG, "G_fat and G_naik alias");
+    if (!std::isfinite(scale)) return fail(LGT_ERR_ARG, "scale must be finite");
+    DeviceScope ds(c->device);
+    const size_t v64 = (size_t)c->g.Vh * 48;
+    double *Xn = (double *)workspace(c, "force.X", v64);
+    double *Yn = (double *)workspace(c, "force.Y", v64);
+    if (!Xn || !Yn) return fail(LGT_ERR_OOM, "cannot allocate the force workspace");
+    LGT_HIP(launch_pack_vec(true, X, Xn, c->g, c->stream));
+    DslashArgs a; // Y = D_oe X with the one-link and three-link hops
+    std::memset(&a, 0, sizeof(a));
+    a.U = fat->ptr;
+    a.U3 = naik->ptr;
+    a.in = Xn;
+    a.out = Yn;
+    a.g = c->g;
+    a.par = LGT_ODD;
+    a.gate = GATE_NONE;
+    a.l = site_launch(c->g.Vh);
+    a.hpi = c->hpi[f];
+    a.ntl = c->ntl[f];
+    LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
+    LGT_HIP(launch_force(Xn, Yn, scale, G_fat, c->g, c->stream, false));
+    LGT_HIP(launch_force(Xn, Yn, scale, G_naik, c->g, c->stream, true));
+    return LGT_OK;
+}
+
 } // extern "C"

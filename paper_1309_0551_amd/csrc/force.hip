@@ -12,6 +12,9 @@
 
 namespace lgt {
 
+// NAIK: the derivative for the three-link field of the improved operator:
+// the link N_mu(x) joins x to x + 3 mu, with that hop's sign.
+template <bool NAIK>
 __global__ __launch_bounds__(kBS) void k_force(const double *__restrict__ X, const double *__restrict__ Y,
                                                double scale, double *__restrict__ G, Geom g)
 {
@@ -31,7 +34,16 @@ __global__ __launch_bounds__(kBS) void k_force(const double *__restrict__ X, con
         const int cb = (int)(eo - par * (int64_t)g.Vh);
         int c[4];
         decode(g, par, cb, c);
-        const int f = nbr_fwd(g, c, cb, mu);
+        int f;
+        bool hop_neg;
+        if constexpr (NAIK) {
+            const Hop h = hop3_rt(g, c, cb, mu);
+            f = h.f;
+            hop_neg = h.fneg; // eta_mu(x) times the boundary sign of the three-step hop
+        } else {
+            f = nbr_fwd(g, c, cb, mu);
+            hop_neg = fwd_neg(g, c, mu);
+        }
         // a: the vector at x, b: the vector at x+mu (other parity)
         cx<double> a[3], b[3];
         if (par == 0) {
@@ -41,7 +53,7 @@ __global__ __launch_bounds__(kBS) void k_force(const double *__restrict__ X, con
             VecFmt<double>::load<false>(Y, (size_t)g.Vh, cb, a);
             VecFmt<double>::load<false>(X, (size_t)g.Vh, f, b);
         }
-        const bool neg = eta_neg(c, mu) ^ (c[mu] == g.L[mu] - 1 && g.bc[mu] < 0) ^ (par == 1);
+        const bool neg = hop_neg ^ (par == 1);
         const double s = neg ? -2.0 * scale : 2.0 * scale;
 #pragma unroll
         for (int i = 0; i < 3; i++)
@@ -60,10 +72,12 @@ __global__ __launch_bounds__(kBS) void k_force(const double *__restrict__ X, con
 }
 
 hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,
-                        hipStream_t s)
+                        hipStream_t s, bool naik)
 {
     const int64_t n = 8 * (int64_t)g.Vh;
-    hipLaunchKernelGGL(k_force, dim3((unsigned)((n + kBS - 1) / kBS)), dim3(kBS), 0, s, Xnat, Ynat, scale, G, g);
+    const dim3 grid((unsigned)((n + kBS - 1) / kBS)), block(kBS);
+    if (naik) hipLaunchKernelGGL(k_force<true>, grid, block, 0, s, Xnat, Ynat, scale, G, g);
+    else hipLaunchKernelGGL(k_force<false>, grid, block, 0, s, Xnat, Ynat, scale, G, g);
     return hipGetLastError();
 }
 

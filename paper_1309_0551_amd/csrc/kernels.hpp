@@ -112,7 +112,8 @@ hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, v
                           hipStream_t st);
 
 // ---- force (force.hip) -----------------------------------------------------
+// fermion force of one link field (naik: the three-link field of the improved operator)
 hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,
-                        hipStream_t s);
+                        hipStream_t s, bool naik = false);
 
 } // namespace lgt

@@ -142,6 +142,7 @@ def _setup(l):
         "lgt_tune_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, C.POINTER(C.c_double)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
         "lgt_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), i32, vp, vp]),
+        "lgt_force_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), vp, C.c_double, vp, vp]),
         "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
         "lgt_gauge_force": (st, [vp, vp, C.c_double, C.c_double, i32, vp]),
         "lgt_momentum_update": (st, [vp, vp, vp, C.c_double, vp]),
@@ -545,6 +546,16 @@ class Lattice:
         _check(lib().lgt_force(self._ctx, C.byref(d), px, float(scale), G.data_ptr()))
         return G
 
+    def force_improved(self, F: PackedLinks, N: PackedLinks, X: torch.Tensor, scale: float = 1.0):
+        """(G_fat, G_naik) = scale * dS/d(Re, Im) of the improved operator's two link fields."""
+        px = self._dev(X, torch.float64, self.vec_shape(), "X")
+        GF = torch.empty((4, self.V, 3, 3, 2), dtype=torch.float64, device=self.device)
+        GN = torch.empty_like(GF)
+        df, dn = F.desc(), N.desc()
+        _check(lib().lgt_force_improved(self._ctx, C.byref(df), C.byref(dn), px, float(scale), GF.data_ptr(),
+                                        GN.data_ptr()))
+        return GF, GN
+
 
 # Table 1 routines: id, operand kinds (a, b, c) and flop per call (a mat-vec
 # is 36 multiplications + 30 additions = 66 flop, Sec. 4)
@@ -658,3 +669,32 @@ class PseudofermionAction(torch.autograd.Function):
         # dS/d(Re phi, Im phi) = 2 (Re X, Im X)
         gphi = (2.0 * g) * X if ctx.needs_input_grad[1] else None
         return gU, gphi, None, None, None, None, None
+
+
+class ImprovedPseudofermionAction(torch.autograd.Function):
+    """S = phi^dag A^-1 phi for the improved operator (fat F + Naik N),
+    differentiable in F, N (and phi): the forward solve by the library's FP64
+    improved CG, the backward from its improved fermion-force kernel with the
+    saved X. F, N: float64 [4][V][3][3][2]; phi: [V/2][3][2]."""
+
+    @staticmethod
+    def forward(ctx, F, N, phi, lat: Lattice, mass: float, tol: float = 1e-12, max_iter: int = 100000):
+        Fp = lat.pack_links(F.detach(), LGT_F64, LGT_R18)
+        Np = lat.pack_links(N.detach(), LGT_F64, LGT_R18)
+        X, res = lat.cg_solve_improved(Fp, Np, phi.detach(), mass, tol=tol, max_iter=max_iter)
+        S = lat.cdot(phi.detach(), X).real
+        ctx.lat, ctx.Fp, ctx.Np, ctx.res = lat, Fp, Np, res
+        ctx.save_for_backward(X)
+        return torch.tensor(S, dtype=torch.float64, device=F.device)
+
+    @staticmethod
+    def backward(ctx, gS):
+        (X,) = ctx.saved_tensors
+        g = float(gS.item())
+        gF = gN = None
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            gF, gN = ctx.lat.force_improved(ctx.Fp, ctx.Np, X, scale=g)
+            gF = gF if ctx.needs_input_grad[0] else None
+            gN = gN if ctx.needs_input_grad[1] else None
+        gphi = (2.0 * g) * X if ctx.needs_input_grad[2] else None
+        return gF, gN, gphi, None, None, None, None

@@ -133,3 +133,75 @@ def test_improved_dslash_antihermitian(dev, fmt):
     lhs = np.vdot(li.to_complex(phi), Dpsi)
     rhs = -np.vdot(Dphi, li.to_complex(psi))
     assert abs(lhs - rhs) <= 4 * tol * np.linalg.norm(Dpsi) * np.linalg.norm(phi)
+
+
+@pytest.mark.parametrize("L,bc", [((8, 4, 6, 8), (1, 1, 1, -1)), ((10, 8, 12, 6), (-1, 1, 1, 1))])
+def test_improved_force_vs_oracle(dev, L, bc):
+    """dS/dF and dS/dN on the GPU against the oracle given the same X."""
+    F, N = li.improved_links(L, 451)
+    X = li.vector(L, 452)
+    GFo, GNo = oracle.force_imp(L, F, N, X, bc)
+    with P.Lattice(L, bc) as lat:
+        Fp = lat.pack_links(_t(F, dev), P.LGT_F64, P.LGT_R18)
+        Np = lat.pack_links(_t(N, dev), P.LGT_F64, P.LGT_R18)
+        GF, GN = lat.force_improved(Fp, Np, _t(X, dev), scale=0.5)
+        GF, GN = GF.cpu().numpy(), GN.cpu().numpy()
+        with pytest.raises(P.LgtError):  # 32-bit fields are not accepted for the force
+            lat.force_improved(lat.pack_links(_t(F, dev), P.LGT_F32, P.LGT_R18),
+                               lat.pack_links(_t(N, dev), P.LGT_F32, P.LGT_R18), _t(X, dev))
+    assert np.abs(GF - 0.5 * GFo).max() <= 1e-12 * np.abs(GFo).max()
+    assert np.abs(GN - 0.5 * GNo).max() <= 1e-12 * np.abs(GNo).max()
+
+
+def test_improved_force_central_differences_gpu(dev):
+    """The GPU improved force from the GPU improved CG's X against central
+    differences of the GPU action S = Re <phi, A^-1 phi> (variational
+    estimator), along random directions in F and in N."""
+    L, mass, h = (8, 4, 4, 8), 0.1, 1e-5
+    F, N = li.improved_links(L, 461)
+    phi = li.vector(L, 462)
+    rng = np.random.default_rng(463)
+    with P.Lattice(L) as lat:
+        ph = _t(phi, dev)
+
+        def solve(Fx, Nx):
+            Fp = lat.pack_links(_t(Fx, dev), P.LGT_F64, P.LGT_R18)
+            Np = lat.pack_links(_t(Nx, dev), P.LGT_F64, P.LGT_R18)
+            x, _ = lat.cg_solve_improved(Fp, Np, ph, mass, tol=1e-13)
+            return Fp, Np, x
+
+        def S(Fx, Nx):
+            Fp, Np, x = solve(Fx, Nx)
+            xa = x.cpu().numpy()
+            Ax = oracle.apply_A_imp(L, Fx, Nx, mass, xa)
+            return 2.0 * float(np.sum(phi * xa)) - float(np.sum(xa * Ax))
+
+        Fp, Np, X = solve(F, N)
+        GF, GN = (g.cpu().numpy() for g in lat.force_improved(Fp, Np, X))
+        for which in ("F", "N"):
+            E = rng.standard_normal(F.shape)
+            if which == "F":
+                fd = (S(F + h * E, N) - S(F - h * E, N)) / (2 * h)
+                an = float(np.sum(GF * E))
+            else:
+                fd = (S(F, N + h * E) - S(F, N - h * E)) / (2 * h)
+                an = float(np.sum(GN * E))
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (which, fd, an)
+
+
+def test_improved_autograd_action(dev):
+    """ImprovedPseudofermionAction: S and dS/dF, dS/dN, dS/dphi against the
+    oracle's solve and force."""
+    L, mass = (8, 4, 6, 4), 0.1
+    F, N = li.improved_links(L, 491)
+    phi = li.vector(L, 492)
+    st, Xo, _, _ = oracle.cg_imp(L, F, N, mass, phi, tol=1e-13)
+    GFo, GNo = oracle.force_imp(L, F, N, Xo)
+    with P.Lattice(L) as lat:
+        Ft, Nt, pt = (_t(a, dev).requires_grad_(True) for a in (F, N, phi))
+        S = P.ImprovedPseudofermionAction.apply(Ft, Nt, pt, lat, mass, 1e-13)
+        (1.5 * S).backward()
+    assert abs(S.item() - float(np.sum(phi * Xo))) <= 1e-10 * abs(S.item())
+    assert _rel(Ft.grad.cpu().numpy(), 1.5 * GFo) <= 1e-8
+    assert _rel(Nt.grad.cpu().numpy(), 1.5 * GNo) <= 1e-8
+    assert _rel(pt.grad.cpu().numpy(), 1.5 * 2 * Xo) <= 1e-8

@@ -8,7 +8,10 @@
 // plane set of parity `par`; the backward link U_mu(x-mu) at the neighbour, in
 // the plane set of the other parity. Every link is read exactly once per call
 // and the kernel is bound by HBM bandwidth: link loads are marked
-// non-temporal so they do not evict the reused input vector from L2.
+// non-temporal so they do not evict the reused input vector from L2 (or cached,
+// for fields that the Infinity Cache holds between calls), and so are the
+// output stores, which no thread of the kernel reads back: write-allocating
+// them in L2 would evict input lines that neighbouring sites still gather.
 #include <hip/hip_ext.h>
 
 #include "fields.hpp"
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
             }
         }
         if constexpr (EPI == EPI_PLAIN) {
-            VF::template store<false>(a.out, Vh, cb, acc);
+            VF::template store<true>(a.out, Vh, cb, acc);
         } else if constexpr (EPI == EPI_A) {
             // out = m4 p - D in ; partial Re <p, out>
             cx<T> p[3];
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 acc[i].im = m4 * p[i].im - acc[i].im;
                 part += (double)p[i].re * (double)acc[i].re + (double)p[i].im * (double)acc[i].im;
             }
-            VF::template store<false>(a.out, Vh, cb, acc);
+            VF::template store<true>(a.out, Vh, cb, acc);
         } else {
             // r = b - (m4 x - D in), FP64 only; partial |r|^2
             cx<double> x[3], bb[3];
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 part += acc[i].re * acc[i].re + acc[i].im * acc[i].im;
             }
             if constexpr (EPI == EPI_RES) {
-                VF::template store<false>(a.out, Vh, cb, acc);
+                VF::template store<true>(a.out, Vh, cb, acc);
             } else {
                 cx<float> lo[3];
 #pragma unroll
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                     lo[i].re = (float)acc[i].re;
                     lo[i].im = (float)acc[i].im;
                 }
-                VecFmt<float>::store<false>(a.out_lo, Vh, cb, lo);
+                VecFmt<float>::store<true>(a.out_lo, Vh, cb, lo);
             }
         }
     }

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs(const void *__restrict__ U,
     auto IN = [=](int s, cx<T> v[3]) __attribute__((always_inline)) { ldm<T>(in, Vh, logN, s, rhs, v); };
     cx<T> acc[3];
     dslash_mrhs<LF>(g, par, U, site, IN, acc);
-    stm<T>(out, Vh, logN, site, rhs, acc);
+    stm<T, true>(out, Vh, logN, site, rhs, acc);
 }
 
 // GPS groups of four lanes per site, R right-hand sides per lane (N = 4 GPS R),
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs4(const void *__restrict__ U
     auto IN = [=](int s, cx<float> v[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(in, Vh, logN, s, rhs0, v); };
     cx<float> acc[R][3];
     dslash_site4<LF, R, MFMA>(g, par, U, site, lane4, IN, acc);
-    stm_r<float, R>(out, Vh, logN, site, rhs0, acc);
+    stm_r<float, R, true>(out, Vh, logN, site, rhs0, acc);
 }
 
 template <class LF, int R, int GPS>

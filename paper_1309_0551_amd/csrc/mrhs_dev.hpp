@@ -53,12 +53,15 @@ __device__ __forceinline__ void ldm(const void *v, size_t Vh, int logN, unsigned
     }
 }
 
-template <typename T>
+// NT: non-temporal store, for an output the same kernel never reads back (the
+// standalone multi-RHS Dslash): write-allocating it would evict the input
+// that the neighbouring sites' gathers are about to reuse.
+template <typename T, bool NT = false>
 __device__ __forceinline__ void stm(void *v, size_t Vh, int logN, unsigned site, unsigned rhs, const cx<T> o[3])
 {
     using V2 = typename V2of<T>::type;
 #pragma unroll
-    for (int c = 0; c < 3; c++) st<false>((V2 *)v + ((size_t)c * Vh << logN), (site << logN) + rhs, V2{o[c].re, o[c].im});
+    for (int c = 0; c < 3; c++) st<NT>((V2 *)v + ((size_t)c * Vh << logN), (site << logN) + rhs, V2{o[c].re, o[c].im});
 }
 
 // D on one (site, rhs): the input at a neighbour comes from `in(site, v)`.
@@ -118,7 +121,7 @@ __device__ __forceinline__ void ldm_r(const void *v, size_t Vh, int logN, unsign
     }
 }
 
-template <typename T, int R>
+template <typename T, int R, bool NT = false>
 __device__ __forceinline__ void stm_r(void *v, size_t Vh, int logN, unsigned site, unsigned rhs0, const cx<T> o[R][3])
 {
 #pragma unroll
@@ -128,12 +131,12 @@ __device__ __forceinline__ void stm_r(void *v, size_t Vh, int logN, unsigned sit
         if constexpr (std::is_same<T, float>::value && R % 2 == 0) {
 #pragma unroll
             for (int q = 0; q < R / 2; q++)
-                st<false>((fv4 *)((fv2 *)v + plane + i) + q, 0u,
+                st<NT>((fv4 *)((fv2 *)v + plane + i) + q, 0u,
                           fv4{o[2 * q][c].re, o[2 * q][c].im, o[2 * q + 1][c].re, o[2 * q + 1][c].im});
         } else {
             using V2 = typename std::conditional<std::is_same<T, double>::value, dv2, fv2>::type;
 #pragma unroll
-            for (int r = 0; r < R; r++) st<false>((V2 *)v + plane, i + r, V2{o[r][c].re, o[r][c].im});
+            for (int r = 0; r < R; r++) st<NT>((V2 *)v + plane, i + r, V2{o[r][c].re, o[r][c].im});
         }
     }
 }

@@ -220,7 +220,12 @@ typedef struct {
 /* Solve A x = b on even sites. U_hi: F64 links (recon 18 or 12). U_lo: the
  * low-precision links for RELIABLE / REFINE (F32 or BF16), ignored (may be
  * NULL) for FP64. b, x: canonical float64 even-parity vectors (device).
- * NOT_CONVERGED and NONFINITE still write the best x and fill *res. */
+ * NOT_CONVERGED and NONFINITE still write the best x and fill *res.
+ * An iteration is five launches while the Dslash has at most 3584
+ * workgroups of 256 sites (the update kernel then sums the <p, Ap> partials
+ * in every workgroup), six beyond (one workgroup computes alpha first); the
+ * environment variable LGT_FUSE_ALPHA_MAX moves that limit. The results are
+ * the same bit for bit either way. */
 lgt_status lgt_cg_solve(lgt_ctx *ctx, const lgt_links *U_hi, const lgt_links *U_lo,
                         const lgt_cg_params *p, const double *b, double *x,
                         lgt_cg_result *res);

@@ -24,6 +24,9 @@ Sec. 4; the random ensembles below are synthetic stand-ins):
   principal cube root of det(Q) lands in SU(3) and keeps left invariance.
 * ``expih``: exp(i c H) with H = (A + A^dag)/2 - tr(.)/3, A complex Gaussian
   with Re, Im ~ N(0, 1/2); computed as V diag(exp(i c w)) V^dag from eigh.
+* ``haar_pool``: every link an independent uniform draw from a seeded pool of
+  2^16 Haar matrices (each link is Haar-distributed; for lattices whose
+  per-link QR would take minutes on the host).
 * ``gaussian`` vectors: Re, Im ~ N(0, 1/2) per component.
 
 Seeds: numpy ``Generator(PCG64(seed))``; whole arrays are drawn in canonical
@@ -124,9 +127,16 @@ def to_complex(a: np.ndarray) -> np.ndarray:
 def links(L, kind: str = "haar", seed: int = 1, c: float = 0.3) -> np.ndarray:
     """Canonical float64 link field [4][V][3][3][2] in eo site order.
 
-    kind: 'haar' | 'expih' | 'unit'.
+    kind: 'haar' | 'expih' | 'unit' | 'haar_pool'.
     """
     V = volume(L)
+    if kind == "haar_pool":
+        g = rng(seed)
+        pool = to_real(haar_su3(1 << 16, g))
+        idx = g.integers(0, pool.shape[0], size=4 * V)
+        out = np.empty((4 * V, 3, 3, 2), dtype=np.float64)
+        np.take(pool, idx, axis=0, out=out)
+        return out.reshape(4, V, 3, 3, 2)
     if kind == "unit":
         u = np.zeros((4 * V, 3, 3), dtype=np.complex128)
         u[:, 0, 0] = u[:, 1, 1] = u[:, 2, 2] = 1.0

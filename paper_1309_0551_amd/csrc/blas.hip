@@ -36,11 +36,13 @@ hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
 }
 
 // alpha = rho / <p, Ap>, then x += alpha p ; r -= alpha Ap ; partial |r|^2
-// (FP64). Every workgroup sums the partials of the preceding D_eo itself, in
-// k_finalize's order, so all of them get the same alpha bit for bit without a
-// launch of their own; workgroup 0 records the step in the solver state
-// (fields no other workgroup reads in this kernel). A breakdown (<p, Ap> not
-// positive or not finite) marks the state failed and skips the update.
+// (FP64). With nparts_in > 0 every workgroup sums the partials of the
+// preceding D_eo itself, in k_finalize's order, so all of them get the same
+// alpha bit for bit without a launch of their own; workgroup 0 records the
+// step in the solver state (fields no other workgroup reads in this kernel).
+// A breakdown (<p, Ap> not positive or not finite) marks the state failed and
+// skips the update. With nparts_in == 0 a FIN_ALPHA finalize has already done
+// all of that, and a breakdown has closed this kernel's gate.
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
 {
@@ -55,18 +57,23 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
         VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
         VecFmt<T>::template load<false>(a.Ap, (size_t)a.Vh, cb, q);
     }
-    __shared__ double lds[kBS / 64];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < a.nparts_in; i += kBS) acc += a.parts_in[i];
-    const double pAp = block_sum_all(acc, lds);
-    const bool bad = !(pAp > 0.0) || !isfinite(pAp);
-    const double alpha64 = a.st->rho / pAp;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.st->pAp = pAp;
-        if (bad) a.st->state = ST_FAIL;
-        else a.st->alpha = alpha64;
+    double alpha64;
+    if (a.nparts_in > 0) {
+        __shared__ double lds[kBS / 64];
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < a.nparts_in; i += kBS) acc += a.parts_in[i];
+        const double pAp = block_sum_all(acc, lds);
+        const bool bad = !(pAp > 0.0) || !isfinite(pAp);
+        alpha64 = a.st->rho / pAp;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.st->pAp = pAp;
+            if (bad) a.st->state = ST_FAIL;
+            else a.st->alpha = alpha64;
+        }
+        if (bad) return;
+    } else {
+        alpha64 = a.st->alpha;
     }
-    if (bad) return;
     double part = 0.0;
     if (cb < a.Vh) {
         const T alpha = (T)alpha64;

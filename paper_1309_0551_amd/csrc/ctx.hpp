@@ -19,9 +19,10 @@ struct lgt_ctx {
     // (8 = fully unrolled, 2 = one direction per loop trip, 1 = one hop).
     // and whether link loads stream past the caches (1) or are cached (0).
     // Set by lgt_set_dslash_variant or lgt_tune_dslash.
-    // Defaults measured on MI355X at 32^4: FP64 fields (604 / 403 MB) stream;
-    // FP32 and BF16 fields are cached (at 32^4 the 12-real ones fit in the
-    // 256 MB Infinity Cache: FP32x12 42 -> 34 us, BF16x12 25 -> 20 us).
+    // Defaults measured on MI355X: FP64 fields (604 / 403 MB at 32^4) stream;
+    // FP32 and BF16 fields are cached while they (mostly) fit in the 256 MB
+    // Infinity Cache (32^4 12-real: FP32x12 42 -> 34 us, BF16x12 25 -> 20 us)
+    // and stream beyond 384 MB (lgt_create sets ntl from the field size).
     int hpi[lgt::FMT_COUNT] = {2, 2, 8, 8, 8};
     int ntl[lgt::FMT_COUNT] = {1, 1, 0, 0, 0};
     // multi-RHS Dslash: engine (0 lane per RHS, 1 four-lane VALU, 2 four-lane

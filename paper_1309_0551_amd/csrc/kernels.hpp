@@ -11,6 +11,19 @@ namespace lgt {
 constexpr int kBS = 256; // threads per workgroup of the site-parallel kernels
 // LDS-staged Dslash: at most this many input sites per workgroup (48 KB at FP64)
 constexpr int kMaxStagedSites = 1024;
+// MI355X Infinity Cache (memory-side, shared by the 8 XCDs)
+constexpr size_t kMallBytes = (size_t)256 << 20;
+// CG: up to this many <p, Ap> partials (one per Dslash workgroup), every
+// workgroup of the update kernel sums them itself, which saves a launch per
+// iteration; the work of those redundant sums grows with the square of the
+// workgroup count, so on larger lattices one finalize workgroup computes
+// alpha once instead. Both give the same bits. Measured on MI355X: the fused
+// sums win at 2048 workgroups (32^4), the extra launch from 5000 (40^4) on,
+// by 7 % (FP64) and 17 % (FP32) of the iteration at 64^4.
+#ifndef LGT_FUSE_ALPHA_MAX
+#define LGT_FUSE_ALPHA_MAX 3584
+#endif
+constexpr int kFuseAlphaMaxParts = LGT_FUSE_ALPHA_MAX;
 
 // Link storage formats (see fields.hpp)
 enum Fmt { F64R18 = 0, F64R12 = 1, F32R18 = 2, F32R12 = 3, BF16R12 = 4, FMT_COUNT = 5 };
@@ -90,7 +103,7 @@ struct VecArgs {
     int Vh;
     Launch l;
     const double *parts_in; // <p, Ap> partials of the preceding D_eo
-    int nparts_in;
+    int nparts_in;          // 0: alpha is already in the state (FIN_ALPHA ran)
     double *partials;       // |r|^2 partials written by the update
     CgState *st;
     int gate;

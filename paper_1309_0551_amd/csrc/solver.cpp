@@ -7,7 +7,10 @@
 // once. An iteration is five launches: p = r + beta p; D_oe; D_eo with 4m^2 p
 // and the partials of <p, Ap>; the update (which sums those partials itself
 // for alpha) with the partials of |r|^2; and the one-workgroup step for beta
-// and the stop tests. (Forming r + beta p inside D_oe instead saves the xpay
+// and the stop tests. On lattices with more than kFuseAlphaMaxParts Dslash
+// workgroups a one-workgroup alpha step runs before the update instead (six
+// launches), since the redundant sums grow with the square of the lattice
+// size. (Forming r + beta p inside D_oe instead saves the xpay
 // pass but gathers two vectors at every neighbour, which costs more cache
 // misses than the pass it saves.) The host enqueues iterations in chunks and reads the state
 // back once per chunk, one chunk behind, so the GPU never waits for the host.
@@ -26,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -51,6 +55,18 @@ struct Events {
         return hipSuccess;
     }
 };
+
+// Largest partial count for which the update kernel sums the <p, Ap>
+// partials itself; LGT_FUSE_ALPHA_MAX overrides the built-in value (both
+// paths give the same bits, so this only moves work between launches).
+int fuse_alpha_max()
+{
+    const char *e = std::getenv("LGT_FUSE_ALPHA_MAX");
+    if (!e || !*e) return kFuseAlphaMaxParts;
+    char *end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    return (end && *end == 0 && v >= 0 && v <= (1L << 30)) ? (int)v : kFuseAlphaMaxParts;
+}
 
 } // namespace
 
@@ -144,8 +160,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     va.Ap = Ap;
     va.Vh = Vh;
     va.l = l;
-    va.parts_in = partials;
-    va.nparts_in = l.nblk_pad;
+    // partial slots from nblk on belong to idle workgroups (zeros): sum nblk
+    const bool fuse_alpha = l.nblk <= fuse_alpha_max();
+    va.parts_in = fuse_alpha ? partials : nullptr;
+    va.nparts_in = fuse_alpha ? l.nblk : 0;
     va.partials = partials2;
     va.st = dst;
     va.gate = GATE_ITER;
@@ -165,7 +183,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         else
             e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr, r0, r1);
         if (e != hipSuccess) return e;
-        return F(partials, fin, gate, l.nblk_pad);
+        return F(partials, fin, gate, l.nblk);
     };
 
     LGT_HIP(hipEventRecord(evs.ev[0], s));
@@ -228,6 +246,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                       ev(ts, 2 * i, false)));
             LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
                       ev(ts, 2 * i + 1, false)));
+            if (!fuse_alpha) LGT_HIP(F(partials, FIN_ALPHA, GATE_ITER, l.nblk));
             LGT_HIP(launch_update(lo_is_f64, va, s));
             LGT_HIP(F(partials2, FIN_UPDATE, GATE_ITER, l.nblk));
         }

@@ -242,6 +242,19 @@ def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):
         assert lat2.dslash_variant(P.LGT_F32, P.LGT_R12) == best
 
 
+@pytest.mark.parametrize("L,f32r18,f32r12,bf16r12", [((32, 32, 32, 32), 0, 0, 0), ((40, 40, 40, 40), 1, 1, 0),
+                                                       ((48, 48, 48, 48), 1, 1, 1), ((24, 24, 24, 48), 0, 0, 0)])
+def test_default_link_loads_follow_field_size(dev, L, f32r18, f32r12, bf16r12):
+    """FP32/BF16 link loads default to cached while the field (mostly) fits
+    in the 256 MB Infinity Cache -- up to 384 MB -- and to streaming beyond;
+    FP64 fields stream."""
+    with P.Lattice(L) as lat:
+        assert lat.dslash_variant(P.LGT_F32, P.LGT_R18)[1] == f32r18
+        assert lat.dslash_variant(P.LGT_F32, P.LGT_R12)[1] == f32r12
+        assert lat.dslash_variant(P.LGT_BF16, P.LGT_R12)[1] == bf16r12
+        assert lat.dslash_variant(P.LGT_F64, P.LGT_R18)[1] == 1
+
+
 def test_dslash_full_size_32(dev):
     """32^4 Haar, FP64, the benchmark's launch configuration: every output site."""
     L = (32, 32, 32, 32)
@@ -405,6 +418,38 @@ def test_cg_deterministic(dev):
             x1, r1 = lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo)
             x2, r2 = lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo)
             assert torch.equal(x1, x2) and r1.iters == r2.iters
+
+
+@pytest.mark.parametrize("L", [(8, 8, 8, 8), (16, 16, 16, 32)])
+def test_cg_alpha_step_fused_or_separate(dev, L, monkeypatch):
+    """alpha = rho / <p, Ap> summed by every update workgroup (small
+    lattices) or by one finalize workgroup first (large lattices; forced here
+    with LGT_FUSE_ALPHA_MAX=0): the same solve bit for bit, in every scheme,
+    and a non-finite source still ends in LGT_ERR_NONFINITE."""
+    U = li.links(L, "haar", 421)
+    b = li.vector(L, 422)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev))
+        Ul = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        Ub = lat.pack_links(_t(U, dev), P.LGT_BF16, P.LGT_R12)
+        for scheme, lo, itol in ((P.LGT_CG_FP64, None, 0.0), (P.LGT_CG_RELIABLE, Ul, 0.0),
+                                 (P.LGT_CG_REFINE, Ub, 0.1)):
+            out = []
+            for limit in ("1073741824", "0"):
+                monkeypatch.setenv("LGT_FUSE_ALPHA_MAX", limit)
+                out.append(lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo, inner_tol=itol))
+            assert torch.equal(out[0][0], out[1][0])
+            assert out[0][1].iters == out[1][1].iters and out[0][1].updates == out[1][1].updates
+            assert out[0][1].true_rel_resid == out[1][1].true_rel_resid
+            assert out[1][1].true_rel_resid <= 1e-10
+        # a NaN source: both paths stop with LGT_ERR_NONFINITE
+        bn = b.copy()
+        bn[3, 1, 0] = np.nan
+        for limit in ("1073741824", "0"):
+            monkeypatch.setenv("LGT_FUSE_ALPHA_MAX", limit)
+            _, r = lat.cg_solve(Uh, _t(bn, dev), 0.1, raise_on_fail=False)
+            assert r.status == -6
+    assert _true_resid(L, U, 0.1, b, out[1][0].cpu().numpy()) <= 1.05e-10
 
 
 @pytest.mark.parametrize("L", [(8, 8, 8, 8), (32, 4, 4, 6)])

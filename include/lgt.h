@@ -400,7 +400,7 @@ typedef struct {
     lgt_ctx *ctx;          /* the problem's lattice; all problems on one device */
     const lgt_links *U_hi; /* F64 x 18 links */
     const lgt_links *U_lo; /* inner links, one format for all problems; ignored for FP64 */
-    int32_t nrhs;          /* 1, 2, 4, 8 or 16 */
+    int32_t nrhs;          /* 1..16 (padded inside to 1, 2, 4, 8 or 16 with zero sources) */
     const double *b;       /* canonical multi-RHS even vectors [nrhs][V/2][3][2], device */
     double *x;             /* same layout; initial guess when x0_is_guess */
     lgt_cg_result *res;    /* host array of nrhs results */
@@ -417,8 +417,10 @@ typedef struct {
  * Schemes and parameters as lgt_cg_solve (shared by all problems); res[j].seconds
  * is the time of the whole batch. Returns LGT_OK when every right-hand side
  * converged, else the first failing status (every res is filled either way).
- * nprob <= 64, sum of nrhs <= 256; a context may appear in several problems.
- * Synchronous. */
+ * nprob <= 64; the sum over problems of nrhs rounded up to a power of two
+ * is <= 256 (a padding right-hand side costs the work of a real one but
+ * converges at once and is never reported); a context may appear in several
+ * problems. Synchronous. */
 lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p);
 
 /* ---- reductions ------------------------------------------------------------ */

@@ -21,6 +21,14 @@ int log2_rhs(int32_t n)
     return -1;
 }
 
+// the batched solver pads 1..16 right-hand sides to the next power of two
+int log2_rhs_padded(int32_t n)
+{
+    for (int l = 0; l <= 4; l++)
+        if (n >= 1 && n <= (1 << l)) return l;
+    return -1;
+}
+
 } // namespace
 
 extern "C" {
@@ -160,7 +168,8 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         const lgt_cg_problem &q = probs[i];
         if (!q.ctx) return fail(LGT_ERR_ARG, "problem %d has no context", i);
         if (q.ctx->device != c0->device) return fail(LGT_ERR_ARG, "problem %d is on another device", i);
-        if (log2_rhs(q.nrhs) < 0) return fail(LGT_ERR_ARG, "problem %d: nrhs must be 1, 2, 4, 8 or 16", i);
+        const int logN = log2_rhs_padded(q.nrhs);
+        if (logN < 0) return fail(LGT_ERR_ARG, "problem %d: nrhs must be in 1..16", i);
         if (!mrhs_size_ok(q.ctx->g.Vh)) return fail(LGT_ERR_UNSUPPORTED, "problem %d: lattice too large", i);
         Fmt fh, fl;
         lgt_status s = check_links(q.U_hi, true, &fh);
@@ -175,9 +184,11 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         if ((s = check_ptr(q.b, "b")) != LGT_OK) return s;
         if ((s = check_ptr(q.x, "x")) != LGT_OK) return s;
         if (!q.res) return fail(LGT_ERR_ARG, "problem %d: res is NULL", i);
-        total_rhs += q.nrhs;
+        total_rhs += 1 << logN; // padding right-hand sides (zero sources) included
     }
-    if (total_rhs > kMaxTotalRhs) return fail(LGT_ERR_ARG, "at most %d right-hand sides per batch", kMaxTotalRhs);
+    if (total_rhs > kMaxTotalRhs)
+        return fail(LGT_ERR_ARG, "at most %d right-hand sides per batch (each nrhs rounded up to a power of two)",
+                    kMaxTotalRhs);
     DeviceScope ds(c0->device);
     const hipStream_t s = c0->stream;
 
@@ -195,7 +206,7 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     for (int i = 0; i < nprob; i++) {
         const lgt_cg_problem &q = probs[i];
         lgt_ctx *c = q.ctx;
-        const int logN = log2_rhs(q.nrhs);
+        const int logN = log2_rhs_padded(q.nrhs);
         const size_t n = (size_t)c->g.Vh << logN;
         const size_t v64 = n * 48, vlo = mixed ? n * 24 : n * 48;
         BatchProb &P = ha->prob[i];
@@ -244,7 +255,7 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
             return fail(LGT_ERR_OOM, "cannot allocate the batch workspace of problem %d", i);
         lt += P.nlt;
         dt += P.ndt;
-        rhs0 += q.nrhs;
+        rhs0 += 1 << logN;
     }
     int grid = ncu;
     const int most = lt > dt ? lt : dt;
@@ -291,8 +302,9 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         const BatchProb &P = ha->prob[i];
         const size_t n = (size_t)q.ctx->g.Vh << P.logN;
         const size_t vlo = mixed ? n * 24 : n * 48;
-        LGT_HIP(launch_pack_mrhs(true, q.b, (void *)P.b64, q.ctx->g, P.logN, s));
-        if (p->x0_is_guess) LGT_HIP(launch_pack_mrhs(true, q.x, P.x64, q.ctx->g, P.logN, s));
+        // right-hand sides q.nrhs..2^logN-1 get zero sources: converged at the start
+        LGT_HIP(launch_pack_mrhs(true, q.b, (void *)P.b64, q.ctx->g, P.logN, s, q.nrhs));
+        if (p->x0_is_guess) LGT_HIP(launch_pack_mrhs(true, q.x, P.x64, q.ctx->g, P.logN, s, q.nrhs));
         else LGT_HIP(launch_zero(P.x64, n * 48, s));
         if (mixed) LGT_HIP(launch_zero(P.xlo, vlo, s));
         LGT_HIP(launch_zero(P.pa, vlo, s));
@@ -303,7 +315,7 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     LGT_HIP(launch_batch_cg(mixed ? flo : F64R18, da, grid, s));
     for (int i = 0; i < nprob; i++) {
         const lgt_cg_problem &q = probs[i];
-        LGT_HIP(launch_unpack_mrhs(true, ha->prob[i].x64, q.x, q.ctx->g, ha->prob[i].logN, s));
+        LGT_HIP(launch_unpack_mrhs(true, ha->prob[i].x64, q.x, q.ctx->g, ha->prob[i].logN, s, q.nrhs));
     }
     LGT_HIP(hipEventRecord(e1, s));
     std::vector<CgState> st((size_t)total_rhs);

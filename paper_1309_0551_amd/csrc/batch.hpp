@@ -93,8 +93,11 @@ inline bool mrhs_size_ok(int Vh) { return (int64_t)Vh * 16 < ((int64_t)1 << 31);
 // Standalone multi-RHS Dslash (plain epilogue): out = D in, N right-hand sides.
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
                               hipStream_t s, int engine, int gps);
-hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s);
-hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s);
+// nsrc: canonical right-hand sides present (the rest of the 2^logN are zero-padded / not written); -1: all
+hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s,
+                            int nsrc = -1);
+hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s,
+                              int nsrc = -1);
 // Persistent batched CG (cooperative launch of `grid` workgroups of kBB
 // threads). lo = inner link format; a_dev = BatchArgs in device memory.
 hipError_t launch_batch_cg(Fmt lo, const BatchArgs *a_dev, int grid, hipStream_t s);

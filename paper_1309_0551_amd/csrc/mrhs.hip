@@ -139,32 +139,40 @@ hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, c
     return hipGetLastError();
 }
 
-// canonical [N][V/2][3][2] float64 <-> multi-RHS [3][V/2][N] of T
+// canonical [nsrc][V/2][3][2] float64 <-> multi-RHS [3][V/2][N] of T, N =
+// 2^logN >= nsrc: packing fills right-hand sides nsrc..N-1 with zeros, and
+// unpacking writes only the first nsrc
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_pack_mrhs(const double *__restrict__ src, void *__restrict__ dst, int Vh,
-                                                   int logN)
+                                                   int logN, int nsrc)
 {
     const int64_t idx = (int64_t)blockIdx.x * kBS + threadIdx.x; // (site << logN) + rhs
     if (idx >= ((int64_t)Vh << logN)) return;
     const unsigned site = (unsigned)(idx >> logN), rhs = (unsigned)(idx & ((1 << logN) - 1));
-    const dv2 *p = (const dv2 *)src + ((size_t)rhs * Vh + site) * 3;
     cx<T> v[3];
+    if (rhs < (unsigned)nsrc) {
+        const dv2 *p = (const dv2 *)src + ((size_t)rhs * Vh + site) * 3;
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        const dv2 w = p[c];
-        v[c].re = (T)w.x;
-        v[c].im = (T)w.y;
+        for (int c = 0; c < 3; c++) {
+            const dv2 w = p[c];
+            v[c].re = (T)w.x;
+            v[c].im = (T)w.y;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; c++) v[c].re = v[c].im = T(0);
     }
     stm<T>(dst, (size_t)Vh, logN, site, rhs, v);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_unpack_mrhs(const void *__restrict__ src, double *__restrict__ dst, int Vh,
-                                                     int logN)
+                                                     int logN, int nsrc)
 {
     const int64_t idx = (int64_t)blockIdx.x * kBS + threadIdx.x;
     if (idx >= ((int64_t)Vh << logN)) return;
     const unsigned site = (unsigned)(idx >> logN), rhs = (unsigned)(idx & ((1 << logN) - 1));
+    if (rhs >= (unsigned)nsrc) return;
     cx<T> v[3];
     ldm<T>(src, (size_t)Vh, logN, site, rhs, v);
     dv2 *p = (dv2 *)dst + ((size_t)rhs * Vh + site) * 3;
@@ -172,21 +180,24 @@ __global__ __launch_bounds__(kBS) void k_unpack_mrhs(const void *__restrict__ sr
     for (int c = 0; c < 3; c++) p[c] = dv2{(double)v[c].re, (double)v[c].im};
 }
 
-hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s)
+hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s, int nsrc)
 {
     const int64_t n = (int64_t)g.Vh << logN;
+    if (nsrc < 0 || nsrc > (1 << logN)) nsrc = 1 << logN;
     const dim3 grid((unsigned)((n + kBS - 1) / kBS)), block(kBS);
-    if (f64) hipLaunchKernelGGL(k_pack_mrhs<double>, grid, block, 0, s, src, dst, g.Vh, logN);
-    else hipLaunchKernelGGL(k_pack_mrhs<float>, grid, block, 0, s, src, dst, g.Vh, logN);
+    if (f64) hipLaunchKernelGGL(k_pack_mrhs<double>, grid, block, 0, s, src, dst, g.Vh, logN, nsrc);
+    else hipLaunchKernelGGL(k_pack_mrhs<float>, grid, block, 0, s, src, dst, g.Vh, logN, nsrc);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s)
+hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom &g, int logN, hipStream_t s,
+                              int nsrc)
 {
     const int64_t n = (int64_t)g.Vh << logN;
+    if (nsrc < 0 || nsrc > (1 << logN)) nsrc = 1 << logN;
     const dim3 grid((unsigned)((n + kBS - 1) / kBS)), block(kBS);
-    if (f64) hipLaunchKernelGGL(k_unpack_mrhs<double>, grid, block, 0, s, src, dst, g.Vh, logN);
-    else hipLaunchKernelGGL(k_unpack_mrhs<float>, grid, block, 0, s, src, dst, g.Vh, logN);
+    if (f64) hipLaunchKernelGGL(k_unpack_mrhs<double>, grid, block, 0, s, src, dst, g.Vh, logN, nsrc);
+    else hipLaunchKernelGGL(k_unpack_mrhs<float>, grid, block, 0, s, src, dst, g.Vh, logN, nsrc);
     return hipGetLastError();
 }
 

@@ -603,7 +603,7 @@ def cg_solve_batch(problems, mass: float, tol: float = 1e-10, scheme: int = LGT_
     """Independent CGs for every right-hand side of every problem in one persistent launch.
 
     problems: list of (lattice, U_hi, U_lo, b) with b a float64 tensor [N][V/2][3][2]
-    (N = 1, 2, 4, 8 or 16). Returns ([x per problem], [[CgResult per rhs] per problem]).
+    (1 <= N <= 16). Returns ([x per problem], [[CgResult per rhs] per problem]).
     """
     keep, descs, xs, results = [], [], [], []
     arr = (_CgProblem * len(problems))()

@@ -212,6 +212,56 @@ def test_batch_heterogeneous(dev, scheme, lo):
         lat.close()
 
 
+@pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12))],
+                         ids=["fp64", "rel_f32r12"])
+def test_batch_ragged_rhs_counts(dev, scheme, lo):
+    """1, 3, 5 and 13 right-hand sides (padded inside to 1, 4, 8 and 16 with
+    zero sources): every solution meets the tolerance by the oracle's residual,
+    and the first three of a 3-RHS problem are bit-identical to the same three
+    solved in a 4-RHS problem (right-hand sides never mix)."""
+    mass, tol = 0.1, 1e-10
+    specs = [((8, 8, 8, 8), 3, 4501), ((6, 4, 6, 8), 5, 4511), ((4, 4, 4, 4), 13, 4521), ((4, 4, 4, 6), 1, 4531)]
+    lats, probs, data = [], [], []
+    for L, n, seed in specs:
+        U = li.links(L, "haar", seed)
+        b = li.vectors(L, seed + 1, n)
+        lat = P.Lattice(L)
+        Uh = lat.pack_links(_t(U, dev), P.LGT_F64, P.LGT_R18)
+        Ul = lat.pack_links(_t(U, dev), *lo) if lo else None
+        lats.append(lat)
+        probs.append((lat, Uh, Ul, _t(b, dev)))
+        data.append((L, U, b))
+    print("batch ragged", scheme, flush=True)
+    xs, res = P.cg_solve_batch(probs, mass, tol=tol, scheme=scheme)
+    for (L, U, b), x, rs in zip(data, xs, res):
+        assert x.shape[0] == b.shape[0] and len(rs) == b.shape[0]
+        xg = x.cpu().numpy()
+        for j in range(len(rs)):
+            _check_solution(L, U, mass, b[j], xg[j], rs[j], tol)
+    # the 3-RHS problem again with a fourth right-hand side in place of the padding
+    L, U, b = data[0]
+    b4 = np.concatenate([b, li.vectors(L, 4509, 1)])
+    lat, Uh, Ul, _ = probs[0]
+    x4, r4 = P.cg_solve_batch([(lat, Uh, Ul, _t(b4, dev))], mass, tol=tol, scheme=scheme)
+    x3, r3 = P.cg_solve_batch([(lat, Uh, Ul, _t(b, dev))], mass, tol=tol, scheme=scheme)
+    assert torch.equal(x3[0], x4[0][:3])
+    assert [r.iters for r in r3[0]] == [r.iters for r in r4[0][:3]]
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_rejects_bad_rhs_counts(dev):
+    L = (4, 4, 4, 4)
+    U = li.links(L, "haar", 4541)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev))
+        for n in (0, 17, 20):
+            b = _t(li.vectors(L, 4542, n), dev)
+            with pytest.raises(P.LgtError) as e:
+                P.cg_solve_batch([(lat, Uh, None, b)], 0.1, scheme=P.LGT_CG_FP64)
+            assert e.value.status == -1
+
+
 def test_batch_matches_single_solves_c4_shape(dev):
     """24^3 x 48 is too large for a quick oracle solve: compare the 16-RHS batch
     with the single-RHS solver on the same lattice, right-hand side by right-hand

@@ -281,6 +281,65 @@ def test_dslash_run_twice_bit_identical(dev):
         assert torch.equal(a, b)
 
 
+def test_dslash_on_a_side_stream(dev):
+    """A context on a non-default stream (default priority) orders its work on
+    that stream: results read there without a device-wide sync are the
+    default-stream results bit for bit."""
+    L = (8, 8, 8, 12)
+    U = li.links(L, "haar", 121)
+    chi = li.vector(L, 122)
+    with P.Lattice(L) as lat:
+        ref = lat.dslash(lat.pack_links(_t(U, dev)), lat.pack_vec(_t(chi, dev)), 1).clone()
+        b = li.vector(L, 123)
+        xr, _ = lat.cg_solve(lat.pack_links(_t(U, dev)), _t(b, dev), 0.1)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        with P.Lattice(L, stream=side) as lat:
+            Up = lat.pack_links(_t(U, dev))
+            out = lat.dslash(Up, lat.pack_vec(_t(chi, dev)), 1)
+            got = out.clone()  # ordered after the Dslash on the same stream
+            x, _ = lat.cg_solve(Up, _t(b, dev), 0.1)
+            xs = x.clone()
+    side.synchronize()
+    assert torch.equal(got, ref)
+    assert torch.equal(xs, xr)
+
+
+def test_dslash_graph_capture_replay(dev):
+    """lgt_dslash is only a kernel launch, so it can be captured in a HIP graph:
+    every replay (with new input written eagerly between replays) equals the
+    eager call bit for bit."""
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 131)
+    side = torch.cuda.Stream(dev)
+    with P.Lattice(L, stream=side) as lat:
+        with torch.cuda.stream(side):
+            Up = lat.pack_links(_t(U, dev))
+            x = lat.pack_vec(_t(li.vector(L, 132), dev))
+            out = torch.empty_like(x)
+            lat.dslash(Up, x, 0, out)  # warm-up outside the capture
+        side.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            lat.dslash(Up, x, 0, out)
+        for k in range(4):
+            with torch.cuda.stream(side):
+                x.copy_(lat.pack_vec(_t(li.vector(L, 140 + k), dev)))
+            side.synchronize()
+            g.replay()
+            side.synchronize()
+            with torch.cuda.stream(side):
+                got = out.clone()
+                ref = lat.dslash(Up, x, 0)
+                got64 = lat.unpack_vec(got)
+            side.synchronize()
+            assert torch.equal(got, ref), k
+            want = oracle.dslash(L, U, li.vector(L, 140 + k), 0)
+            assert _rel(got64.cpu().numpy(), want) <= 1e-12
+
+
 def test_pack_unpack_roundtrip(dev):
     L = (4, 6, 4, 8)
     v = li.vector(L, 5)

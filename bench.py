@@ -134,6 +134,86 @@ def probes(lat):
             "bytes": nb}
 
 
+def fd_check(lat, U, phi, mass, G, L, seed, ndir, eps=1e-6):
+    """Central differences of the action along ndir random link directions.
+    S~ = 2 Re <phi, x> - <x, A x> with x from the FP64 CG to 1e-12 (its error is
+    quadratic in the residual) and A x from lgt_apply_normal; the difference of
+    the two S~ is summed element by element so it keeps its own precision.
+    Returns (seconds, largest |FD - <G, E>| relative to max(|<G, E>|, median))."""
+    import lgt_inputs as li
+    import numpy as np
+    import paper_1309_0551_amd as P
+    import torch
+    mus, sites, Es = li.fd_directions(L, seed, ndir)
+
+    def terms(Ut):
+        Up = lat.pack_links(Ut, P.LGT_F64, P.LGT_R18)
+        x, res = lat.cg_solve(Up, phi, mass, tol=1e-12)
+        Ax = lat.unpack_vec(lat.apply_normal(Up, lat.pack_vec(x), mass)[0])
+        return (2.0 * (phi[..., 0] * x[..., 0] + phi[..., 1] * x[..., 1])
+                - (x[..., 0] * Ax[..., 0] + x[..., 1] * Ax[..., 1]))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    an, fd = [], []
+    for mu, site, E in zip(mus, sites, Es):
+        Et = torch.from_numpy(E).to(U.device)
+        Up, Um = U.clone(), U.clone()
+        Up[mu, site] += eps * Et
+        Um[mu, site] -= eps * Et
+        fd.append(float((terms(Up) - terms(Um)).sum()) / (2 * eps))
+        an.append(float((G[mu, site] * Et).sum()))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    an, fd = np.array(an), np.array(fd)
+    scale = np.maximum(np.abs(an), np.median(np.abs(an)))
+    return el, float((np.abs(fd - an) / scale).max())
+
+
+def small_configs(args):
+    """The small workloads, timed after the steps: 4^4 (Haar, m = 0.1) and 16^4
+    (exp(0.3 i H), m = 0.05). FP64 Dslash alone on both parities (mean of 100
+    back-to-back launches between two events, after 10 warm-up launches), the
+    FP64 CG (second of two solves), and the Dslash inside a third solve from
+    events carried on its own dispatch packets."""
+    import lgt_inputs as li
+    import paper_1309_0551_amd as P
+    import torch
+    out = {}
+    for key in ("c1_4x4x4x4", "c2_16x16x16x16"):
+        cfg = li.CONFIGS[key]
+        L = cfg["L"]
+        with P.Lattice(L) as lat:
+            dev = lat.device
+            U = torch.from_numpy(li.links(L, cfg["kind"], cfg["link_seed"], cfg["c"] or 0.3)).to(dev)
+            Up = lat.pack_links(U, P.LGT_F64, P.LGT_R18)
+            b = torch.from_numpy(li.vector(L, cfg["src_seed"])).to(dev)
+            xin = lat.pack_vec(b)
+            y = torch.empty_like(xin)
+            d = {}
+            for par in (0, 1):
+                for _ in range(10):
+                    lat.dslash(Up, xin, par, y)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(lat.stream)
+                for _ in range(100):
+                    lat.dslash(Up, xin, par, y)
+                e1.record(lat.stream)
+                e1.synchronize()
+                d["dslash_us_parity%d" % par] = round(e0.elapsed_time(e1) * 10.0, 2)
+            x, r = lat.cg_solve(Up, b, cfg["mass"], tol=cfg["tol"])  # warm
+            x, r = lat.cg_solve(Up, b, cfg["mass"], tol=cfg["tol"])
+            lat.set_timing(1)
+            _, rt = lat.cg_solve(Up, b, cfg["mass"], tol=cfg["tol"])
+            lat.set_timing(False)
+            d.update({"lattice": list(L), "mass": cfg["mass"], "cg_fp64_s": round(r.seconds, 5), "iters": r.iters,
+                      "true_rel_resid": r.true_rel_resid,
+                      "dslash_in_cg_us": round(1e3 * rt.dslash_ms_hi / max(rt.dslash_timed_hi, 1), 2),
+                      "variant": "hops=%d streaming=%d" % lat.dslash_variant(P.LGT_F64, P.LGT_R18)})
+            out[key[3:]] = d
+    return out
+
+
 def cpu_baseline(L, U, chi, budget_s):
     import oracle
     oracle.dslash(L, U, chi, 1)  # warm: page in, start the thread pool
@@ -268,7 +348,7 @@ def main():
         S.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return {"S": float(S), "forward_s": t1 - t0, "backward_s": t2 - t1, "grad_norm": float(U.grad.norm())}
+        return {"S": float(S.detach()), "forward_s": t1 - t0, "backward_s": t2 - t1, "grad_norm": float(U.grad.norm())}
 
     def solves():
         out = {}
@@ -393,7 +473,12 @@ def main():
                               "S_rel_diff": abs(grads[True][0] - grads[False][0]) / abs(grads[False][0]),
                               "grad_rel_diff": float((grads[True][2] - grads[False][2]).norm()
                                                      / grads[False][2].norm())}
+    # central finite differences over 64 random link directions (128 solves),
+    # against dS/dU of the FP64 forward solve
+    fd_s, fd_err = fd_check(flat, Uf, phi, c5["mass"], grads[False][2], c5["L"], c5["fd_seed"], 64)
+    force["fd_64_directions"] = {"seconds": round(fd_s, 3), "max_rel_dev_from_grad": fd_err, "eps": 1e-6}
     del grads
+    small = small_configs(args)
 
     # improved (fat + Naik) operator at 32^4, measured after the timed steps:
     # standalone Dslash per format and link-load kind, FP64 vs FP32 reliable-update CG
@@ -540,6 +625,7 @@ def main():
         "routines": routines,
         "force": force,
         "dslash_standalone": dslash,
+        "small_configs": small,
         "cpu_baseline": cpu,
         "paper_context": paper_context(),
     }

@@ -48,6 +48,7 @@ __all__ = [
     "improved_links",
     "momenta",
     "uniform",
+    "fd_directions",
     "vector",
     "vectors",
     "to_real",
@@ -180,6 +181,21 @@ def momenta(L, seed: int) -> np.ndarray:
 def uniform(seed: int) -> float:
     """One uniform number in [0, 1) (the Metropolis test's)."""
     return float(rng(seed).random())
+
+
+def fd_directions(L, seed: int, n: int):
+    """n random link directions for finite differences: per direction a uniform
+    mu in 0..3, a uniform eo site, and a Gaussian E in R^18 scaled to unit norm
+    (drawn in that order from one stream). Returns (mu[n], site[n], E[n][3][3][2])."""
+    g = rng(seed)
+    V = volume(L)
+    mus, sites, Es = [], [], []
+    for _ in range(n):
+        mus.append(int(g.integers(4)))
+        sites.append(int(g.integers(V)))
+        e = g.standard_normal(18)
+        Es.append((e / np.linalg.norm(e)).reshape(3, 3, 2))
+    return mus, sites, np.array(Es)
 
 
 def vector(L, seed: int) -> np.ndarray:

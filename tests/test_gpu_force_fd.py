@@ -63,15 +63,11 @@ def test_force_central_differences_64_directions(setup):
     S = P.PseudofermionAction.apply(Ut, phit, lat, MASS, 1e-12)
     S.backward()
     G = Ut.grad.detach()
-    g = li.rng(5004)
-    V = int(np.prod(L))
+    mus, sites, Es = li.fd_directions(L, 5004, NDIR)
     an, fd = [], []
     base = Ut.detach()
-    for k in range(NDIR):
-        mu, s = int(g.integers(4)), int(g.integers(V))
-        E = g.standard_normal(18)
-        E /= np.linalg.norm(E)
-        Et = torch.from_numpy(E.reshape(3, 3, 2)).to(dev)
+    for mu, s, E in zip(mus, sites, Es):
+        Et = torch.from_numpy(E).to(dev)
         Up, Um = base.clone(), base.clone()
         Up[mu, s] += EPS * Et
         Um[mu, s] -= EPS * Et

@@ -229,7 +229,7 @@ def cpu_baseline(L, U, chi, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, nargs=4, default=(32, 32, 32, 32))
     ap.add_argument("--mass", type=float, default=0.01)
@@ -616,7 +616,8 @@ def main():
                                "D_eo with 4m^2 p and <p,Ap> (1296 B/site)",
                      "alg_bytes_per_launch": round(by64), "alg_bytes_per_site": round(by64 / Vh, 1),
                      "avg_launch_us": round(avg_ms * 1e3, 2),
-                     "launches_timed": n_hi, "measured_ceiling_GBps": ceil},
+                     "launches_timed": n_hi, "measured_ceiling_GBps": ceil,
+                     "frac_of_measured_read_ceiling": round(gbs / ceil["read_GBps"], 4)},
         "cg": cg,
         "batch": batch,
         "mrhs_tune": mrhs_tune,

@@ -259,6 +259,31 @@ lgt_status lgt_cg_solve_improved(lgt_ctx *ctx, const lgt_links *fat_hi, const lg
 lgt_status lgt_force_improved(lgt_ctx *ctx, const lgt_links *fat, const lgt_links *naik, const double *X,
                               double scale, double *G_fat, double *G_naik);
 
+/* ---- link fattening for the improved operator -------------------------------- *
+ * The application the paper times (Table 4) uses improved staggered quarks: a
+ * fat one-link field smeared over staple paths built with the Table 1 matrix
+ * products (mult_su3_nn / _na / _an) and a three-link (Naik) field. The paper
+ * gives neither paths nor weights; this library uses the asqtad paths. With
+ * L_{+nu}(y) = U_nu(y), L_{-nu}(y) = U_nu(y-nu)^dag and the staple
+ * S_a[M](x) = L_a(x) M(x+a) L_a(x+mu)^dag along a signed direction a:
+ *   F_mu = one_link U_mu + staple3 sum_a S_a[U_mu] + staple5 sum_{a,b} S_a[S_b[U_mu]]
+ *        + staple7 sum_{a,b,c} S_a[S_b[S_c[U_mu]]] + lepage sum_a S_a[S_a[U_mu]]
+ *   N_mu(x) = naik U_mu(x) U_mu(x+mu) U_mu(x+2mu)
+ * with a, b, c orthogonal to mu on pairwise different axes (6, 24, 48 and 6
+ * terms). Tree-level asqtad weights: 5/8, 1/16, 1/64, 1/384, -1/16, -1/24
+ * (divide each by u0^(path length - 1) for tadpole improvement); unit links
+ * then give F = 9/8, N = -1/24. F and N are the fields lgt_dslash_improved and
+ * lgt_cg_solve_improved take (after lgt_pack_links). */
+typedef struct {
+    double one_link, staple3, staple5, staple7, lepage, naik;
+} lgt_fat_coeffs;
+
+/* F, N from U: canonical [4][V][3][3][2] float64 device fields (periodic gauge
+ * field; fermion boundary signs stay in the Dslash). U, F and N must not
+ * overlap (LGT_ERR_ARG). One thread per link, 168 products of 3x3 complex
+ * matrices each. Asynchronous. */
+lgt_status lgt_fatten_links(lgt_ctx *ctx, const double *U, const lgt_fat_coeffs *coeffs, double *F, double *N);
+
 /* ---- the HMC step around the solve ----------------------------------------- *
  * Fields in the canonical layout [4][V][3][3][2] float64, eo site order, device
  * memory: links U, momenta P (traceless anti-Hermitian), derivatives G with

@@ -12,6 +12,7 @@ from .lgt import (  # noqa: F401
     LGT_CG_FP64, LGT_CG_RELIABLE, LGT_CG_REFINE, STATUS,
     LGT_MRHS_LANE, LGT_MRHS_VALU4, LGT_MRHS_MFMA, LgtError,
     Lattice, PackedLinks, CgResult, PseudofermionAction, ImprovedPseudofermionAction, cg_solve_batch, routine, ROUTINES, PLANES,
+    asqtad_coeffs,
     lib, lib_path, exported_symbols, links_bytes, vec_bytes, geom_check,
     DSLASH_FLOP_PER_SITE, IMPROVED_FLOP_PER_SITE, link_bytes_per_dir, vec_bytes_per_site,
 )

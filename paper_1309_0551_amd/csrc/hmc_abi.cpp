@@ -106,6 +106,30 @@ lgt_status lgt_link_update(lgt_ctx *c, const double *P, double eps, double *U)
     return LGT_OK;
 }
 
+lgt_status lgt_fatten_links(lgt_ctx *c, const double *U, const lgt_fat_coeffs *w, double *F, double *N)
+{
+    CHECK(c);
+    lgt_status s;
+    if ((s = check_ptr(U, "U")) != LGT_OK) return s;
+    if ((s = check_ptr(F, "F")) != LGT_OK) return s;
+    if ((s = check_ptr(N, "N")) != LGT_OK) return s;
+    if (!w) return fail(LGT_ERR_ARG, "coefficients are NULL");
+    // the kernel reads U around every link while it writes F and N: no overlap
+    const size_t bytes = (size_t)volume(c) * 4 * 18 * sizeof(double);
+    auto overlap = [bytes](const void *a, const void *b) {
+        const char *p = (const char *)a, *q = (const char *)b;
+        return p < q + bytes && q < p + bytes;
+    };
+    if (overlap(U, F) || overlap(U, N) || overlap(F, N)) return fail(LGT_ERR_ARG, "U, F and N must not overlap");
+    const double cs[6] = {w->one_link, w->staple3, w->staple5, w->staple7, w->lepage, w->naik};
+    for (double v : cs)
+        if (!std::isfinite(v)) return fail(LGT_ERR_ARG, "coefficients must be finite");
+    DeviceScope ds(c->device);
+    const FatCoeffs fc{w->one_link, w->staple3, w->staple5, w->staple7, w->lepage, w->naik};
+    LGT_HIP(launch_fatten(U, F, N, c->g, fc, c->stream));
+    return LGT_OK;
+}
+
 lgt_status lgt_plaquette(lgt_ctx *c, const double *U, double *sum)
 {
     CHECK(c);

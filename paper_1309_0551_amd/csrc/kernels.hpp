@@ -120,6 +120,13 @@ hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *part
 // sum n partials in order and run the scalar step `fin` (one workgroup)
 hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s);
 
+// ---- link fattening (fatten.hip) --------------------------------------------
+struct FatCoeffs {
+    double c1, c3, c5, c7, cL, cN; // one link, 3-, 5-, 7-link staples, Lepage, Naik
+};
+// F, N (canonical [4][V][3][3][2] float64) from U in the same layout
+hipError_t launch_fatten(const double *U, double *F, double *N, const Geom &g, const FatCoeffs &w, hipStream_t s);
+
 // ---- Table 1 routines (routines.hip) ---------------------------------------
 hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, void *c, int64_t n, double s,
                           hipStream_t st);

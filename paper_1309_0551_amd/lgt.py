@@ -106,6 +106,18 @@ class _HmcResult(C.Structure):
                 ("cg_solves", C.c_int32), ("reserved", C.c_int32)]
 
 
+class _FatCoeffs(C.Structure):
+    _fields_ = [("one_link", C.c_double), ("staple3", C.c_double), ("staple5", C.c_double),
+                ("staple7", C.c_double), ("lepage", C.c_double), ("naik", C.c_double)]
+
+
+def asqtad_coeffs(u0: float = 1.0) -> tuple:
+    """Tree-level asqtad weights (one link, 3-, 5-, 7-link staples, Lepage, Naik),
+    each divided by u0^(path length - 1): for unit links F = 9/8, N = -1/24."""
+    return (5.0 / 8.0, 1.0 / 16.0 / u0 ** 2, 1.0 / 64.0 / u0 ** 4, 1.0 / 384.0 / u0 ** 6,
+            -1.0 / 16.0 / u0 ** 4, -1.0 / 24.0 / u0 ** 2)
+
+
 def _setup(l):
     vp, i32, st = C.c_void_p, C.c_int32, C.c_int32
     sig = {
@@ -145,6 +157,7 @@ def _setup(l):
         "lgt_force_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), vp, C.c_double, vp, vp]),
         "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
         "lgt_gauge_force": (st, [vp, vp, C.c_double, C.c_double, i32, vp]),
+        "lgt_fatten_links": (st, [vp, vp, C.POINTER(_FatCoeffs), vp, vp]),
         "lgt_momentum_update": (st, [vp, vp, vp, C.c_double, vp]),
         "lgt_link_update": (st, [vp, vp, C.c_double, vp]),
         "lgt_plaquette": (st, [vp, vp, C.POINTER(C.c_double)]),
@@ -427,6 +440,18 @@ class Lattice:
     def link_update(self, P: torch.Tensor, eps: float, U: torch.Tensor) -> torch.Tensor:
         _check(lib().lgt_link_update(self._ctx, self._field(P, "P"), float(eps), self._field(U, "U")))
         return U
+
+    def fatten_links(self, U: torch.Tensor, coeffs=None, F: torch.Tensor | None = None,
+                     N: torch.Tensor | None = None):
+        """(F, N), the fat one-link and Naik fields of the improved operator, from
+        the canonical gauge field U; coeffs = (one link, 3-, 5-, 7-link staples,
+        Lepage, Naik), asqtad_coeffs() by default."""
+        w = _FatCoeffs(*(float(c) for c in (coeffs if coeffs is not None else asqtad_coeffs())))
+        pu = self._field(U, "U")
+        F = torch.empty_like(U) if F is None else F
+        N = torch.empty_like(U) if N is None else N
+        _check(lib().lgt_fatten_links(self._ctx, pu, C.byref(w), self._field(F, "F"), self._field(N, "N")))
+        return F, N
 
     def plaquette(self, U: torch.Tensor) -> float:
         out = C.c_double()

@@ -96,17 +96,25 @@ def test_flop_constant():
 
 
 def test_build_entry_resolves_both_builders():
-    """build() compiles the library and the oracle; its two steps resolve to
-    the module functions (not a same-named package attribute)."""
+    """build() compiles the library and the oracle; its two steps are the
+    build scripts' functions, loaded without importing the package (which
+    would load a possibly missing or stale liblgt.so before rebuilding it)."""
     import importlib
     import os
+    import subprocess
     import sys
-    sys.path.insert(0, os.path.join(os.path.dirname(__file__), ".."))
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..")
+    sys.path.insert(0, root)
     ge = importlib.import_module("__graft_entry__")
     lib_b, or_b = ge._builders()
     assert callable(lib_b) and callable(or_b)
-    assert lib_b.__module__ == "paper_1309_0551_amd.build" and or_b.__module__ == "oracle.build"
+    assert lib_b.__globals__["__file__"].endswith(os.path.join("paper_1309_0551_amd", "build.py"))
+    assert or_b.__globals__["__file__"].endswith(os.path.join("oracle", "build.py"))
     assert callable(ge.smoke)
+    code = ("import sys, __graft_entry__ as g; g._builders(); "
+            "print('paper_1309_0551_amd' in sys.modules, 'oracle' in sys.modules)")
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, check=True)
+    assert out.stdout.split() == ["False", "False"]
 
 
 def test_every_context_call_rejects_a_null_context():
@@ -143,6 +151,7 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_plaquette": (None, None, C.byref(d)),
         "lgt_kinetic_energy": (None, None, C.byref(d)),
         "lgt_hmc_trajectory": (None, None, None, None, None, None, None),
+        "lgt_fatten_links": (None, None, None, None, None),
     }
     for name, args in calls.items():
         assert getattr(l, name)(*args) == -1, name

@@ -1,0 +1,103 @@
+"""Link fattening on the GPU (lgt_fatten_links) against the oracle, and the
+improved operator built from it.
+
+Tolerances: F and N are sums of up to 85 path products of FP64 3x3 matrices
+(the kernel nests the sums, the oracle adds level by level), so they agree to
+rounding: 1e-13 norm-wise and per component relative to the largest entry.
+The improved Dslash on the fattened fields: 1e-12 as for the FP64 Dslash; the
+CG: the oracle's true residual of the GPU's x.
+"""
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+import oracle
+import oracle.fatten as ofat
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1309_0551_amd")
+
+pytestmark = pytest.mark.gpu
+
+W = (0.37, -0.11, 0.023, -0.0071, 0.052, -0.29)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _check(got, want, tol=1e-13):
+    assert np.linalg.norm(got - want) <= tol * np.linalg.norm(want)
+    assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+@pytest.mark.parametrize("L,weights", [((4, 4, 4, 4), "generic"), ((4, 4, 4, 4), "asqtad"),
+                                       ((2, 4, 2, 6), "generic"), ((6, 4, 4, 8), "asqtad"),
+                                       ((16, 16, 16, 16), "generic")])
+def test_fatten_vs_oracle(dev, L, weights):
+    print("fatten", L, weights, flush=True)
+    w = W if weights == "generic" else P.asqtad_coeffs(0.87)
+    U = li.links(L, "haar", 7401)
+    Fo, No = ofat.fatten(L, U, w)
+    with P.Lattice(L) as lat:
+        F, N = lat.fatten_links(_t(U, dev), w)
+        _check(F.cpu().numpy(), Fo)
+        _check(N.cpu().numpy(), No)
+
+
+def test_fatten_unit_links_give_the_free_operator(dev):
+    L = (4, 4, 4, 6)
+    with P.Lattice(L) as lat:
+        F, N = lat.fatten_links(_t(li.links(L, "unit", 0), dev))
+        Fc = F[..., 0] + 1j * F[..., 1]
+        Nc = N[..., 0] + 1j * N[..., 1]
+        eye = torch.eye(3, dtype=torch.complex128, device=dev)
+        assert torch.allclose(Fc, 9.0 / 8.0 * eye.expand_as(Fc), atol=1e-15, rtol=0)
+        assert torch.allclose(Nc, -1.0 / 24.0 * eye.expand_as(Nc), atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("L,bc", [((8, 8, 8, 8), (1, 1, 1, 1)), ((6, 4, 6, 8), (1, 1, 1, -1))])
+def test_improved_dslash_and_cg_from_fattened_links(dev, L, bc):
+    """U -> (F, N) on the GPU -> packed -> improved Dslash and CG, against the
+    oracle's improved operator on the oracle's (F, N)."""
+    print("improved from fattened", L, bc, flush=True)
+    w = P.asqtad_coeffs()
+    U = li.links(L, "haar", 7501)
+    Fo, No = ofat.fatten(L, U, w)
+    chi = li.vector(L, 7502)
+    b = li.vector(L, 7503)
+    mass = 0.1
+    with P.Lattice(L, bc) as lat:
+        F, N = lat.fatten_links(_t(U, dev), w)
+        Fp, Np = lat.pack_links(F, P.LGT_F64, P.LGT_R18), lat.pack_links(N, P.LGT_F64, P.LGT_R18)
+        for par in (0, 1):
+            out = lat.unpack_vec(lat.dslash_improved(Fp, Np, lat.pack_vec(_t(chi, dev)), par)).cpu().numpy()
+            ref = oracle.dslash_imp(L, Fo, No, chi, par, bc)
+            assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref)
+        x, res = lat.cg_solve_improved(Fp, Np, _t(b, dev), mass, tol=1e-10)
+        assert res.status == 0
+    r = b - oracle.apply_A_imp(L, Fo, No, mass, x.cpu().numpy(), bc)
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b)
+
+
+def test_fatten_argument_checks(dev):
+    L = (4, 4, 4, 4)
+    with P.Lattice(L) as lat:
+        U = _t(li.links(L, "haar", 7601), dev)
+        with pytest.raises(P.LgtError) as e:
+            lat.fatten_links(U, W, F=U)
+        assert e.value.status == -1
+        F = torch.empty_like(U)
+        with pytest.raises(P.LgtError) as e:
+            lat.fatten_links(U, W, F=F, N=F)
+        assert e.value.status == -1
+        with pytest.raises(P.LgtError) as e:
+            lat.fatten_links(U, (float("nan"),) + W[1:])
+        assert e.value.status == -1

@@ -128,3 +128,56 @@ def rvec(z, Vh):
     out[..., 0] = z.real
     out[..., 1] = z.imag
     return out
+
+
+# ---- link fattening, path by path ------------------------------------------
+
+def walk(L, Uc, x, steps):
+    """Ordered product of the links along a path from x given as signed steps
+    (axis, +1 | -1): a forward step from y uses U_nu(y), a backward step the
+    adjoint of the link that ends at y. Uc: complex [4][V][3][3], eo order."""
+    c = list(x)
+    P = np.eye(3, dtype=complex)
+    for nu, sg in steps:
+        if sg > 0:
+            P = P @ Uc[nu][eo_index(L, c)]
+            c[nu] = (c[nu] + 1) % L[nu]
+        else:
+            c[nu] = (c[nu] - 1) % L[nu]
+            P = P @ Uc[nu][eo_index(L, c)].conj().T
+    return P
+
+
+def fat_link(L, Uc, x, mu, w):
+    """(F_mu(x), N_mu(x)) summed path by path: the link, the 3-, 5- and 7-link
+    staples (out along transverse directions on different axes, one mu step,
+    back in reverse order), the 5-link Lepage path, and the Naik product."""
+    c1, c3, c5, c7, cL, cN = w
+    dirs = [(nu, sg) for nu in range(4) if nu != mu for sg in (1, -1)]
+    back = lambda a: (a[0], -a[1])
+    M = (mu, 1)
+    F = c1 * walk(L, Uc, x, [M])
+    for a in dirs:
+        F = F + c3 * walk(L, Uc, x, [a, M, back(a)])
+        F = F + cL * walk(L, Uc, x, [a, a, M, back(a), back(a)])
+    for a, b in itertools.permutations(dirs, 2):
+        if a[0] != b[0]:
+            F = F + c5 * walk(L, Uc, x, [a, b, M, back(b), back(a)])
+    for a, b, c in itertools.permutations(dirs, 3):
+        if len({a[0], b[0], c[0]}) == 3:
+            F = F + c7 * walk(L, Uc, x, [a, b, c, M, back(c), back(b), back(a)])
+    return F, cN * walk(L, Uc, x, [M, M, M])
+
+
+def coords_of_eo(L, eo):
+    """Coordinates of the site with eo index eo: lex is 2 cb or 2 cb + 1,
+    whichever has the site's parity; checked against eo_index."""
+    Lx, Ly, Lz, Lt = L
+    Vh = Lx * Ly * Lz * Lt // 2
+    par, cb = divmod(int(eo), Vh)
+    for lex in (2 * cb, 2 * cb + 1):
+        c = (lex % Lx, (lex // Lx) % Ly, (lex // (Lx * Ly)) % Lz, lex // (Lx * Ly * Lz))
+        if sum(c) % 2 == par:
+            assert eo_index(L, c) == eo
+            return c
+    raise ValueError(eo)

@@ -10,6 +10,7 @@ CG: the oracle's true residual of the GPU's x.
 import numpy as np
 import pytest
 
+import brute
 import lgt_inputs as li
 import oracle
 import oracle.fatten as ofat
@@ -50,6 +51,30 @@ def test_fatten_vs_oracle(dev, L, weights):
         F, N = lat.fatten_links(_t(U, dev), w)
         _check(F.cpu().numpy(), Fo)
         _check(N.cpu().numpy(), No)
+
+
+def test_fatten_full_size_32_sampled(dev):
+    """32^4 Haar field (the benchmark's): F and N at sampled links against the
+    path-by-path brute force (the whole-lattice oracle is too slow here)."""
+    L = (32, 32, 32, 32)
+    print("fatten 32^4", flush=True)
+    U = li.links(L, "haar", 3001)
+    w = P.asqtad_coeffs(0.9)
+    with P.Lattice(L) as lat:
+        F, N = lat.fatten_links(_t(U, dev), w)
+        g = li.rng(7701)
+        idx = [int(e) for e in g.integers(0, li.volume(L), 6)] + [0, li.volume(L) - 1]
+        Fs = F[:, idx].cpu().numpy()
+        Ns = N[:, idx].cpu().numpy()
+    Uc = U[..., 0] + 1j * U[..., 1]
+    for k, eo in enumerate(idx):
+        x = brute.coords_of_eo(L, eo)
+        for mu in range(4):
+            Fb, Nb = brute.fat_link(L, Uc, x, mu, w)
+            got_F = Fs[mu, k, ..., 0] + 1j * Fs[mu, k, ..., 1]
+            got_N = Ns[mu, k, ..., 0] + 1j * Ns[mu, k, ..., 1]
+            assert np.abs(got_F - Fb).max() <= 1e-13 * np.abs(Fb).max(), (eo, mu)
+            assert np.abs(got_N - Nb).max() <= 1e-13 * np.abs(Nb).max(), (eo, mu)
 
 
 def test_fatten_unit_links_give_the_free_operator(dev):

@@ -15,11 +15,10 @@
 * tree-level asqtad weights give the free improved operator, F = 9/8 and
   N = -1/24.
 """
-import itertools
-
 import numpy as np
 import pytest
 
+import brute
 import lgt_inputs as li
 import oracle.fatten as fat
 import oracle.hmc as hmc
@@ -106,54 +105,6 @@ def test_gauge_covariance():
 
 # ---------------------------------------------------------------- brute force ---
 
-def _eo_of(L, c):
-    lex = c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))
-    V = L[0] * L[1] * L[2] * L[3]
-    return (sum(c) % 2) * (V // 2) + lex // 2
-
-
-def _coords_of_eo(L, eo):
-    V = L[0] * L[1] * L[2] * L[3]
-    for lex in range(V):
-        c = (lex % L[0], (lex // L[0]) % L[1], (lex // (L[0] * L[1])) % L[2], lex // (L[0] * L[1] * L[2]))
-        if _eo_of(L, c) == eo:
-            return list(c)
-    raise ValueError(eo)
-
-
-def _walk(L, Uc, x, steps):
-    """Ordered product of links along the path given as signed steps (axis, +-1)."""
-    c = list(x)
-    P = np.eye(3, dtype=complex)
-    for nu, sg in steps:
-        if sg > 0:
-            P = P @ Uc[nu][_eo_of(L, c)]
-            c[nu] = (c[nu] + 1) % L[nu]
-        else:
-            c[nu] = (c[nu] - 1) % L[nu]
-            P = P @ Uc[nu][_eo_of(L, c)].conj().T
-    return P, c
-
-
-def _brute_fat(L, Uc, x, mu, w):
-    c1, c3, c5, c7, cL, cN = w
-    dirs = [(nu, sg) for nu in range(4) if nu != mu for sg in (1, -1)]
-    back = lambda a: (a[0], -a[1])
-    M = (mu, 1)
-    F = c1 * _walk(L, Uc, x, [M])[0]
-    for a in dirs:
-        F = F + c3 * _walk(L, Uc, x, [a, M, back(a)])[0]
-        F = F + cL * _walk(L, Uc, x, [a, a, M, back(a), back(a)])[0]
-    for a, b in itertools.permutations(dirs, 2):
-        if a[0] != b[0]:
-            F = F + c5 * _walk(L, Uc, x, [a, b, M, back(b), back(a)])[0]
-    for a, b, c in itertools.permutations(dirs, 3):
-        if len({a[0], b[0], c[0]}) == 3:
-            F = F + c7 * _walk(L, Uc, x, [a, b, c, M, back(c), back(b), back(a)])[0]
-    N, end = _walk(L, Uc, x, [M, M, M])
-    return F, cN * N
-
-
 def pin_brute(fatten, L):
     U = _gauss_links(L, 7201 + L[0])
     Uc = hmc.cplx(U)
@@ -162,9 +113,9 @@ def pin_brute(fatten, L):
     V = li.volume(L)
     g = li.rng(7301)
     for eo in g.integers(0, V, 5):
-        x = _coords_of_eo(L, int(eo))
+        x = brute.coords_of_eo(L, int(eo))
         for mu in range(4):
-            Fb, Nb = _brute_fat(L, Uc, x, mu, W)
+            Fb, Nb = brute.fat_link(L, Uc, x, mu, W)
             scale = np.abs(Fb).max()
             assert np.abs(Fc[mu, eo] - Fb).max() <= 1e-13 * scale, (L, eo, mu)
             assert np.abs(Nc[mu, eo] - Nb).max() <= 1e-13 * np.abs(Nb).max(), (L, eo, mu)

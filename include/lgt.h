@@ -32,8 +32,8 @@
  * pointer owned by the caller; the library never frees caller memory. Device
  * pointers must be 16-byte aligned (256 recommended). A context owns only its
  * workspace. Calls are ordered on the context's stream; lgt_dslash*,
- * lgt_pack_*, lgt_unpack_vec*, lgt_index_maps, lgt_force*, lgt_routine and
- * the HMC field updates are asynchronous, as is lgt_apply_normal without its
+ * lgt_pack_*, lgt_unpack_vec*, lgt_index_maps, lgt_force*, lgt_fatten_links,
+ * lgt_routine and the HMC field updates are asynchronous, as is lgt_apply_normal without its
  * dot product; the solves (lgt_cg_solve*, lgt_hmc_trajectory), the tuners and
  * every call that returns a number to the host (lgt_cdot, lgt_plaquette,
  * lgt_kinetic_energy, lgt_apply_normal with pAp) return after the work is

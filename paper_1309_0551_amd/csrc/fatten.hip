@@ -10,11 +10,16 @@
 //        + c7 sum_{a,b,c} S_a[S_b[S_c[U_mu]]] + cL sum_a S_a[S_a[U_mu]]
 //   N_mu(x) = cN U_mu(x) U_mu(x+mu) U_mu(x+2mu)
 // (a, b, c signed directions orthogonal to mu on pairwise different axes). The
-// staple is linear in M, so one thread per link evaluates F nested:
-//   F = c1 U + sum_a S_a[ c3 U + cL S_a[U] + sum_b S_b[ c5 U + c7 sum_c S_c[U] ] ]
-// 168 products of 3x3 complex matrices per link; all link reads come from the
-// caches (each link is read by many threads), so the kernel is bound by FP64
-// arithmetic, not by HBM.
+// staple is linear in M, so F nests:
+//   F = c1 U + sum_a S_a[ c3 U + cL S_a[U] + sum_b S_b[ W_rho ] ],
+//   W_rho = c5 U + c7 (S_{+rho}[U] + S_{-rho}[U]),
+// where rho is the one axis other than mu, a and b: the innermost sum depends
+// on the axis pair only, so per direction mu a first kernel stores the three
+// fields W_rho (8 products per site each) and a second evaluates the outer
+// levels per link from them (72 products, plus 2 for N) instead of
+// recomputing W at every (a, b) of every link (168 products). Link and W
+// reads come from the caches; the kernels are bound by FP64 arithmetic and
+// those gathers, not by HBM.
 #include "fields.hpp"
 #include "kernels.hpp"
 #include "su3.hpp"
@@ -82,44 +87,57 @@ __device__ __forceinline__ M3 staple(const double *U, int64_t V, const Geom &g, 
     return mul<false, true>(mul<false, false>(step_link(U, V, g, y, a, s), M), step_link(U, V, g, ymu, a, s));
 }
 
-__global__ __launch_bounds__(kBS) void k_fatten(const double *__restrict__ U, double *__restrict__ F,
-                                                double *__restrict__ N, Geom g, FatCoeffs w)
+// W_r(y) = c5 U_mu(y) + c7 (S_{+rho}[U_mu](y) + S_{-rho}[U_mu](y)), rho = the r-th
+// axis other than mu; W is [3][V][3][3][2]
+__global__ __launch_bounds__(kBS) void k_fat_inner(const double *__restrict__ U, double *__restrict__ W, Geom g,
+                                                   int mu, double c5, double c7)
 {
     const int64_t V = 2 * (int64_t)g.Vh;
-    const int64_t l = (int64_t)blockIdx.x * kBS + threadIdx.x; // mu * V + x
-    if (l >= 4 * V) return;
-    const int mu = (int)(l / V);
-    const int64_t ex = l - mu * V;
+    const int64_t l = (int64_t)blockIdx.x * kBS + threadIdx.x; // r * V + y
+    if (l >= 3 * V) return;
+    const int r = (int)(l / V);
+    const int64_t ey = l - r * V;
+    const int rho = other_axis(mu, r);
+    int y[4], yp[4], ym[4];
+    site_coords(g, ey, y);
+    step(g, y, rho, 1, yp);
+    step(g, y, rho, -1, ym);
+    M3 w = scaled(c5, ldm3(U, V, mu, ey));
+    axpy(w, c7, staple(U, V, g, y, mu, rho, 1, ldm3(U, V, mu, eo_of(g, yp))));
+    axpy(w, c7, staple(U, V, g, y, mu, rho, -1, ldm3(U, V, mu, eo_of(g, ym))));
+    stm3(W, V, r, ey, w);
+}
+
+// F_mu(x) and N_mu(x) for every site x of direction mu, the innermost level from W
+__global__ __launch_bounds__(kBS) void k_fat_outer(const double *__restrict__ U, const double *__restrict__ W,
+                                                   double *__restrict__ F, double *__restrict__ N, Geom g, int mu,
+                                                   FatCoeffs w)
+{
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const int64_t ex = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    if (ex >= V) return;
     int x[4];
     site_coords(g, ex, x);
 
     M3 acc = scaled(w.c1, ldm3(U, V, mu, ex));
 #pragma unroll 1
     for (int ia = 0; ia < 6; ia++) {
-        const int a = other_axis(mu, ia >> 1), sa = (ia & 1) ? -1 : 1;
+        const int ka = ia >> 1, a = other_axis(mu, ka), sa = (ia & 1) ? -1 : 1;
         int xa[4], xaa[4];
         step(g, x, a, sa, xa);
         step(g, xa, a, sa, xaa);
-        // inner1 at x + a: c3 U + cL S_a[U] + sum_b S_b[inner2]
+        // the field under the outer staple, at x + a: c3 U + cL S_a[U] + sum_b S_b[W]
         M3 in1 = scaled(w.c3, ldm3(U, V, mu, eo_of(g, xa)));
         axpy(in1, w.cL, staple(U, V, g, xa, mu, a, sa, ldm3(U, V, mu, eo_of(g, xaa))));
 #pragma unroll 1
         for (int ib = 0; ib < 6; ib++) {
-            const int b = other_axis(mu, ib >> 1), sb = (ib & 1) ? -1 : 1;
-            if (b == a) continue;
+            const int kb = ib >> 1;
+            if (kb == ka) continue;
+            const int b = other_axis(mu, kb), sb = (ib & 1) ? -1 : 1;
             int xab[4];
             step(g, xa, b, sb, xab);
-            // inner2 at x + a + b: c5 U + c7 sum_c S_c[U]
-            M3 in2 = scaled(w.c5, ldm3(U, V, mu, eo_of(g, xab)));
-#pragma unroll 1
-            for (int ic = 0; ic < 6; ic++) {
-                const int c = other_axis(mu, ic >> 1), sc = (ic & 1) ? -1 : 1;
-                if (c == a || c == b) continue;
-                int xabc[4];
-                step(g, xab, c, sc, xabc);
-                axpy(in2, w.c7, staple(U, V, g, xab, mu, c, sc, ldm3(U, V, mu, eo_of(g, xabc))));
-            }
-            axpy(in1, 1.0, staple(U, V, g, xa, mu, b, sb, in2));
+            // rho: the third axis other than mu (index 3 - ka - kb among mu's others)
+            axpy(in1, 1.0, staple(U, V, g, xa, mu, b, sb, ldm3(W, V, 3 - ka - kb, eo_of(g, xab))));
         }
         axpy(acc, 1.0, staple(U, V, g, x, mu, a, sa, in1));
     }
@@ -135,11 +153,19 @@ __global__ __launch_bounds__(kBS) void k_fatten(const double *__restrict__ U, do
 
 } // namespace
 
-hipError_t launch_fatten(const double *U, double *F, double *N, const Geom &g, const FatCoeffs &w, hipStream_t s)
+hipError_t launch_fatten(const double *U, double *F, double *N, double *W, const Geom &g, const FatCoeffs &w,
+                         hipStream_t s)
 {
-    const int64_t n = 8 * (int64_t)g.Vh;
-    hipLaunchKernelGGL(k_fatten, dim3((unsigned)((n + kBS - 1) / kBS)), dim3(kBS), 0, s, U, F, N, g, w);
-    return hipGetLastError();
+    const int64_t V = 2 * (int64_t)g.Vh;
+    for (int mu = 0; mu < 4; mu++) {
+        hipLaunchKernelGGL(k_fat_inner, dim3((unsigned)((3 * V + kBS - 1) / kBS)), dim3(kBS), 0, s, U, W, g, mu, w.c5,
+                           w.c7);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fat_outer, dim3((unsigned)((V + kBS - 1) / kBS)), dim3(kBS), 0, s, U, W, F, N, g, mu, w);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 } // namespace lgt

@@ -125,8 +125,10 @@ lgt_status lgt_fatten_links(lgt_ctx *c, const double *U, const lgt_fat_coeffs *w
     for (double v : cs)
         if (!std::isfinite(v)) return fail(LGT_ERR_ARG, "coefficients must be finite");
     DeviceScope ds(c->device);
+    double *W = (double *)workspace(c, "fatten.inner", 3 * (size_t)volume(c) * 18 * sizeof(double));
+    if (!W) return fail(LGT_ERR_OOM, "cannot allocate the fattening workspace");
     const FatCoeffs fc{w->one_link, w->staple3, w->staple5, w->staple7, w->lepage, w->naik};
-    LGT_HIP(launch_fatten(U, F, N, c->g, fc, c->stream));
+    LGT_HIP(launch_fatten(U, F, N, W, c->g, fc, c->stream));
     return LGT_OK;
 }
 

@@ -124,8 +124,10 @@ hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, 
 struct FatCoeffs {
     double c1, c3, c5, c7, cL, cN; // one link, 3-, 5-, 7-link staples, Lepage, Naik
 };
-// F, N (canonical [4][V][3][3][2] float64) from U in the same layout
-hipError_t launch_fatten(const double *U, double *F, double *N, const Geom &g, const FatCoeffs &w, hipStream_t s);
+// F, N (canonical [4][V][3][3][2] float64) from U in the same layout; W: workspace
+// of 3 V matrices (the innermost staple fields of one direction at a time)
+hipError_t launch_fatten(const double *U, double *F, double *N, double *W, const Geom &g, const FatCoeffs &w,
+                         hipStream_t s);
 
 // ---- Table 1 routines (routines.hip) ---------------------------------------
 hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, void *c, int64_t n, double s,

@@ -212,8 +212,9 @@ def test_batch_heterogeneous(dev, scheme, lo):
         lat.close()
 
 
-@pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12))],
-                         ids=["fp64", "rel_f32r12"])
+@pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12)),
+                                       (P.LGT_CG_REFINE, (P.LGT_BF16, P.LGT_R12))],
+                         ids=["fp64", "rel_f32r12", "ir_bf16r12"])
 def test_batch_ragged_rhs_counts(dev, scheme, lo):
     """1, 3, 5 and 13 right-hand sides (padded inside to 1, 4, 8 and 16 with
     zero sources): every solution meets the tolerance by the oracle's residual,
@@ -232,7 +233,8 @@ def test_batch_ragged_rhs_counts(dev, scheme, lo):
         probs.append((lat, Uh, Ul, _t(b, dev)))
         data.append((L, U, b))
     print("batch ragged", scheme, flush=True)
-    xs, res = P.cg_solve_batch(probs, mass, tol=tol, scheme=scheme)
+    itol = 0.1 if scheme == P.LGT_CG_REFINE else 0.0
+    xs, res = P.cg_solve_batch(probs, mass, tol=tol, scheme=scheme, inner_tol=itol)
     for (L, U, b), x, rs in zip(data, xs, res):
         assert x.shape[0] == b.shape[0] and len(rs) == b.shape[0]
         xg = x.cpu().numpy()
@@ -242,8 +244,8 @@ def test_batch_ragged_rhs_counts(dev, scheme, lo):
     L, U, b = data[0]
     b4 = np.concatenate([b, li.vectors(L, 4509, 1)])
     lat, Uh, Ul, _ = probs[0]
-    x4, r4 = P.cg_solve_batch([(lat, Uh, Ul, _t(b4, dev))], mass, tol=tol, scheme=scheme)
-    x3, r3 = P.cg_solve_batch([(lat, Uh, Ul, _t(b, dev))], mass, tol=tol, scheme=scheme)
+    x4, r4 = P.cg_solve_batch([(lat, Uh, Ul, _t(b4, dev))], mass, tol=tol, scheme=scheme, inner_tol=itol)
+    x3, r3 = P.cg_solve_batch([(lat, Uh, Ul, _t(b, dev))], mass, tol=tol, scheme=scheme, inner_tol=itol)
     assert torch.equal(x3[0], x4[0][:3])
     assert [r.iters for r in r3[0]] == [r.iters for r in r4[0][:3]]
     for lat in lats:

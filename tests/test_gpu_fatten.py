@@ -7,6 +7,8 @@ rounding: 1e-13 norm-wise and per component relative to the largest entry.
 The improved Dslash on the fattened fields: 1e-12 as for the FP64 Dslash; the
 CG: the oracle's true residual of the GPU's x.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -110,6 +112,39 @@ def test_improved_dslash_and_cg_from_fattened_links(dev, L, bc):
         assert res.status == 0
     r = b - oracle.apply_A_imp(L, Fo, No, mass, x.cpu().numpy(), bc)
     assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b)
+
+
+def _plane_wave(L, n):
+    """e^{ip.x} times a fixed colour vector on the even sites, p_mu = 2 pi n_mu / L_mu"""
+    Vh = int(np.prod(L)) // 2
+    z = np.zeros((Vh, 3), complex)
+    col = np.array([0.3 - 1j, 1.0, 0.25j])
+    for _, c in brute.sites(L):
+        e = brute.eo_index(L, c)
+        if e < Vh:
+            z[e] = np.exp(1j * sum(2 * math.pi * n[mu] * c[mu] / L[mu] for mu in range(4))) * col
+    return li.to_real(z)
+
+
+@pytest.mark.parametrize("L,n,bc", [((8, 6, 8, 8), (1, 2, 3, 1), (1, 1, 1, 1)),
+                                    ((8, 8, 8, 8), (1, 2, 0, 1.5), (1, 1, 1, -1))])
+def test_fattened_free_field_spectrum(dev, L, n, bc):
+    """Unit links -> asqtad fattening -> the improved operator, all on the GPU:
+    on a plane wave A = 4m^2 - D_eo D_oe has the free asqtad eigenvalue
+    4 (m^2 + sum_mu (9/8 sin p_mu - 1/24 sin 3 p_mu)^2) (antiperiodic t:
+    p_t = (2k + 1) pi / L_t)."""
+    m = 0.29
+    psi = _plane_wave(L, n)
+    with P.Lattice(L, bc) as lat:
+        F, N = lat.fatten_links(_t(li.links(L, "unit", 0), dev))
+        Fp, Np = lat.pack_links(F, P.LGT_F64, P.LGT_R18), lat.pack_links(N, P.LGT_F64, P.LGT_R18)
+        v = lat.pack_vec(_t(psi, dev))
+        t = lat.dslash_improved(Fp, Np, v, P.LGT_ODD)
+        Dt = lat.unpack_vec(lat.dslash_improved(Fp, Np, t, P.LGT_EVEN)).cpu().numpy()
+    Apsi = 4 * m * m * psi - Dt
+    p = [2 * math.pi * n[mu] / L[mu] for mu in range(4)]
+    lam = 4 * (m * m + sum((9.0 / 8.0 * math.sin(q) - 1.0 / 24.0 * math.sin(3 * q)) ** 2 for q in p))
+    np.testing.assert_allclose(Apsi, lam * psi, atol=1e-13)
 
 
 def test_fatten_argument_checks(dev):

@@ -531,7 +531,7 @@ def main():
         del imp_packed, F64p, N64p, F32p, N32p
         # link fattening of the headline Haar field with the asqtad weights:
         # median of 5 calls and the FP64 rate at the 20286 flop per link the
-        # kernels execute (94 complex 3x3 products at 216 flop, 8 per complex
+        # kernels execute (86 complex 3x3 products at 216 flop, 8 per complex
         # multiply-add, plus the weighted sums; summing every path separately
         # would take 40320), then the FP64 improved CG on the fattened fields
         Uh = torch.from_numpy(U).to(dev)

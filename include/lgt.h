@@ -282,7 +282,7 @@ typedef struct {
  * field; fermion boundary signs stay in the Dslash). U, F and N must not
  * overlap (LGT_ERR_ARG). Per direction, the innermost staple sums go to a
  * context workspace of 3 V matrices (allocated on first use), then the outer
- * levels run per link: 94 products of 3x3 complex matrices per link in all.
+ * levels run per link: 86 products of 3x3 complex matrices per link in all.
  * Asynchronous. */
 lgt_status lgt_fatten_links(lgt_ctx *ctx, const double *U, const lgt_fat_coeffs *coeffs, double *F, double *N);
 

@@ -15,7 +15,7 @@
 //   W_rho = c5 U + c7 (S_{+rho}[U] + S_{-rho}[U]),
 // where rho is the one axis other than mu, a and b: the innermost sum depends
 // on the axis pair only, so per direction mu a first kernel stores the three
-// fields W_rho (8 products per site each) and a second evaluates the outer
+// fields W_rho (4 products per site each) and a second evaluates the outer
 // levels per link from them (72 products, plus 2 for N) instead of
 // recomputing W at every (a, b) of every link (168 products). Link and W
 // reads come from the caches; the kernels are bound by FP64 arithmetic and

@@ -3,7 +3,8 @@
 Its FP64 18-real link field and the fermion-force gradient are 9.7 GB each,
 so the plane bases of the packed links, of the canonical input and of the
 gradient lie far beyond 4 GiB, and the CG runs with one alpha workgroup per
-iteration (more than 3584 Dslash workgroups). Links are independent draws
+iteration (more than 3584 Dslash workgroups). The improved operator's
+three-link hops are checked on the same field. Links are independent draws
 from a pool of 2^16 Haar matrices (per-link QR would take minutes on the
 host); every output is compared with the FP64 oracle over the whole lattice.
 
@@ -66,6 +67,20 @@ def test_dslash_64(big, fmt, tol):
         assert _rel(out, ref) <= tol
         if fmt == "f64r18":
             assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_improved_dslash_64(big):
+    """The improved operator's 16 hops (one-link and three-link) at 64^4, with the
+    9.7 GB link field serving as both its fat and its Naik field."""
+    dev, lat, U, packs = big
+    Up = packs["f64r18"]
+    for par in (0, 1):
+        print("improved dslash 64^4 parity", par, flush=True)
+        chi = li.vector(L, 6440 + par)
+        out = lat.unpack_vec(lat.dslash_improved(Up, Up, lat.pack_vec(torch.from_numpy(chi).to(dev)), par)).cpu().numpy()
+        ref = oracle.dslash_imp(L, U, U, chi, par)
+        assert _rel(out, ref) <= 1e-12
+        assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_force_64(big):

@@ -340,6 +340,47 @@ def test_dslash_graph_capture_replay(dev):
             assert _rel(got64.cpu().numpy(), want) <= 1e-12
 
 
+def test_force_and_mrhs_graph_capture_replay(dev):
+    """lgt_force (pack X, Y = D_oe X, outer products; its workspace exists after
+    a first call) and lgt_dslash_mrhs are kernel launches only: captured in one
+    HIP graph and replayed three times with new inputs written eagerly in
+    between, every replay equals the eager calls bit for bit."""
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 151)
+    side = torch.cuda.Stream(dev)
+    with P.Lattice(L, stream=side) as lat:
+        with torch.cuda.stream(side):
+            Ut = _t(U, dev)
+            Up = lat.pack_links(Ut)
+            U32 = lat.pack_links(Ut, P.LGT_F32, P.LGT_R12)
+            X = _t(li.vector(L, 152), dev)
+            vm = lat.pack_vec_mrhs(_t(li.vectors(L, 153, 4), dev), P.LGT_F32)
+            om = torch.empty_like(vm)
+            G = lat.force(Up, X)  # first call: allocates the force workspace
+            lat.dslash_mrhs(U32, vm, 1, om)
+        side.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            Gc = lat.force(Up, X)
+            lat.dslash_mrhs(U32, vm, 1, om)
+        for k in range(3):
+            with torch.cuda.stream(side):
+                X.copy_(_t(li.vector(L, 160 + k), dev))
+                vm.copy_(lat.pack_vec_mrhs(_t(li.vectors(L, 170 + k, 4), dev), P.LGT_F32))
+            side.synchronize()
+            g.replay()
+            side.synchronize()
+            with torch.cuda.stream(side):
+                got_G, got_m = Gc.clone(), om.clone()
+                ref_G = lat.force(Up, X)
+                ref_m = lat.dslash_mrhs(U32, vm, 1)
+            side.synchronize()
+            assert torch.equal(got_G, ref_G), k
+            assert torch.equal(got_m, ref_m), k
+        Gr = oracle.force(L, U, li.vector(L, 162))
+        assert _rel(got_G.cpu().numpy(), Gr) <= 1e-12
+
+
 def test_pack_unpack_roundtrip(dev):
     L = (4, 6, 4, 8)
     v = li.vector(L, 5)

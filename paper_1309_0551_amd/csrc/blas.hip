@@ -9,7 +9,9 @@
 
 namespace lgt {
 
-// p = r + beta p
+// x += alpha p (the previous update's, while pending) ; p = r + beta p.
+// Adding alpha p here rather than in the update saves one vector pass per
+// iteration: this kernel reads p anyway, and the update then touches only r.
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_xpay(VecArgs a)
 {
@@ -17,9 +19,21 @@ __global__ __launch_bounds__(kBS) void k_xpay(VecArgs a)
     const int cb = blockIdx.x * kBS + threadIdx.x;
     if (cb >= a.Vh) return;
     const T beta = (T)a.st->beta;
+    const bool pend = a.st->pend != 0;
     cx<T> r[3], p[3];
     VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
     VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
+    if (pend) {
+        const T alpha = (T)a.st->alpha;
+        cx<T> x[3];
+        VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            x[i].re = fma(alpha, p[i].re, x[i].re);
+            x[i].im = fma(alpha, p[i].im, x[i].im);
+        }
+        VecFmt<T>::template store<false>(a.x, (size_t)a.Vh, cb, x);
+    }
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         p[i].re = fma(beta, p[i].re, r[i].re);
@@ -35,14 +49,43 @@ hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// alpha = rho / <p, Ap>, then x += alpha p ; r -= alpha Ap ; partial |r|^2
-// (FP64). With nparts_in > 0 every workgroup sums the partials of the
-// preceding D_eo itself, in k_finalize's order, so all of them get the same
-// alpha bit for bit without a launch of their own; workgroup 0 records the
-// step in the solver state (fields no other workgroup reads in this kernel).
-// A breakdown (<p, Ap> not positive or not finite) marks the state failed and
-// skips the update. With nparts_in == 0 a FIN_ALPHA finalize has already done
-// all of that, and a breakdown has closed this kernel's gate.
+// x += alpha p if an update is pending (before a reliable update or the final
+// residual, which use x); the finalize step that follows clears the flag
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_x_pending(VecArgs a)
+{
+    if (!gate_open(a.gate, a.st)) return;
+    if (a.st->pend == 0) return;
+    const int cb = blockIdx.x * kBS + threadIdx.x;
+    if (cb >= a.Vh) return;
+    const T alpha = (T)a.st->alpha;
+    cx<T> x[3], p[3];
+    VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
+    VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        x[i].re = fma(alpha, p[i].re, x[i].re);
+        x[i].im = fma(alpha, p[i].im, x[i].im);
+    }
+    VecFmt<T>::template store<false>(a.x, (size_t)a.Vh, cb, x);
+}
+
+hipError_t launch_x_pending(bool f64, const VecArgs &a, hipStream_t s)
+{
+    if (f64) hipLaunchKernelGGL(k_x_pending<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    else hipLaunchKernelGGL(k_x_pending<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    return hipGetLastError();
+}
+
+// alpha = rho / <p, Ap>, then r -= alpha Ap ; partial |r|^2 (FP64); x += alpha p
+// is left pending for the next k_xpay (or k_x_pending). With nparts_in > 0
+// every workgroup sums the partials of the preceding D_eo itself, in
+// k_finalize's order, so all of them get the same alpha bit for bit without a
+// launch of their own; workgroup 0 records the step in the solver state
+// (fields no other workgroup reads in this kernel). A breakdown (<p, Ap> not
+// positive or not finite) marks the state failed and skips the update. With
+// nparts_in == 0 a FIN_ALPHA finalize has already done all of that, and a
+// breakdown has closed this kernel's gate.
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
 {
@@ -50,11 +93,9 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
     const int blk = blockIdx.x;
     const int cb = blk * kBS + threadIdx.x;
     // the vector loads do not depend on alpha: issue them before the sum
-    cx<T> x[3], r[3], p[3], q[3];
+    cx<T> r[3], q[3];
     if (cb < a.Vh) {
-        VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
         VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
-        VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
         VecFmt<T>::template load<false>(a.Ap, (size_t)a.Vh, cb, q);
     }
     double alpha64;
@@ -67,6 +108,7 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
         alpha64 = a.st->rho / pAp;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.st->pAp = pAp;
+            a.st->pend = 0; // the previous alpha p went into x in k_xpay
             if (bad) a.st->state = ST_FAIL;
             else a.st->alpha = alpha64;
         }
@@ -79,13 +121,10 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
         const T alpha = (T)alpha64;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            x[i].re = fma(alpha, p[i].re, x[i].re);
-            x[i].im = fma(alpha, p[i].im, x[i].im);
             r[i].re = fma(-alpha, q[i].re, r[i].re);
             r[i].im = fma(-alpha, q[i].im, r[i].im);
             part += (double)r[i].re * (double)r[i].re + (double)r[i].im * (double)r[i].im;
         }
-        VecFmt<T>::template store<false>(a.x, (size_t)a.Vh, cb, x);
         VecFmt<T>::template store<false>(a.r, (size_t)a.Vh, cb, r);
     }
     write_partial(part, a.partials, blk);
@@ -176,7 +215,7 @@ __global__ void k_state_init(CgState *st, int scheme, int ru_fixed, int max_iter
     st->max_iter = max_iter;
     st->scheme = scheme;
     st->ru_fixed = ru_fixed;
-    st->pad0 = st->pad1 = 0;
+    st->pend = st->pad1 = 0;
 }
 
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol, double inner,

@@ -43,7 +43,11 @@ struct CgState {
     double inner2;     // REFINE: inner_tol^2 (relative); else absolute threshold
     double last_true;  // last FP64 true |r|^2
     int iter, updates, state, max_iter;
-    int scheme, ru_fixed, pad0, pad1;
+    int scheme, ru_fixed;
+    int pend; // 1 while x still lacks alpha p of the last update: the next
+              // p = r + beta p adds it (it reads p anyway), else the reliable
+              // update or the final residual does, before using x
+    int pad1;
 };
 
 // Early-exit rule of a solver kernel, read from CgState at kernel start
@@ -109,6 +113,8 @@ struct VecArgs {
     int gate;
 };
 hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s);
+// x += alpha p when the state holds a pending update (gate: a.gate)
+hipError_t launch_x_pending(bool f64, const VecArgs &a, hipStream_t s);
 hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s);
 hipError_t launch_ru_accum(double *x64, void *xlo, int Vh, CgState *st, int gate, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -55,11 +55,13 @@ __device__ inline void finalize(int fin, CgState *st, double sum)
     switch (fin) {
     case FIN_ALPHA: // alpha = rho / <p, A p>
         st->pAp = sum;
+        st->pend = 0; // the previous alpha p went into x in k_xpay
         if (!(sum > 0.0) || !isfinite(sum)) st->state = ST_FAIL;
         else st->alpha = st->rho / sum;
         break;
     case FIN_UPDATE: { // rho' = |r|^2, beta = rho'/rho
         st->iter += 1;
+        st->pend = 1; // x += alpha p still to do
         if (!isfinite(sum)) {
             st->state = ST_FAIL;
             break;
@@ -72,6 +74,7 @@ __device__ inline void finalize(int fin, CgState *st, double sum)
         break;
     }
     case FIN_RU: { // sum = |b - A x|^2 in FP64
+        st->pend = 0; // applied by k_x_pending before the residual
         const bool init = st->state == ST_INIT;
         if (!init) st->updates += 1;
         st->last_true = sum;
@@ -97,6 +100,7 @@ __device__ inline void finalize(int fin, CgState *st, double sum)
         if (st->scheme != SCH_REFINE) st->stop_inner = st->inner2 * sum;
         break;
     case FIN_FINAL:
+        st->pend = 0;
         st->last_true = sum;
         break;
     default:

@@ -4,10 +4,10 @@
 // beta = rho'/rho, p = r + beta p) with every scalar kept in device memory:
 // the kernels compute alpha and beta themselves from FP64 reductions, and a
 // solver state word makes every later kernel of a finished solve exit at
-// once. An iteration is five launches: p = r + beta p; D_oe; D_eo with 4m^2 p
-// and the partials of <p, Ap>; the update (which sums those partials itself
-// for alpha) with the partials of |r|^2; and the one-workgroup step for beta
-// and the stop tests. On lattices with more than kFuseAlphaMaxParts Dslash
+// once. An iteration is five launches: x += alpha p (the previous update's) and
+// p = r + beta p; D_oe; D_eo with 4m^2 p and the partials of <p, Ap>; the
+// update r -= alpha Ap (which sums those partials itself for alpha) with the
+// partials of |r|^2; and the one-workgroup step for beta and the stop tests. On lattices with more than kFuseAlphaMaxParts Dslash
 // workgroups a one-workgroup alpha step runs before the update instead (six
 // launches), since the redundant sums grow with the square of the lattice
 // size. (Forming r + beta p inside D_oe instead saves the xpay
@@ -168,9 +168,14 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     va.st = dst;
     va.gate = GATE_ITER;
 
+    const int lo_is_f64 = !mixed;
     // FP64 update step: x64 += x_lo ; r = b - A64 x64 (rounded into r_lo when mixed)
     auto reliable = [&](int gate, int slot, int fin) -> hipError_t {
         hipError_t e = hipSuccess;
+        // the last update's x += alpha p, if no p = r + beta p has added it yet
+        VecArgs vp = va;
+        vp.gate = gate;
+        if ((e = launch_x_pending(lo_is_f64, vp, s)) != hipSuccess) return e;
         if (mixed && (e = launch_ru_accum(x64, xlo, Vh, dst, gate, s)) != hipSuccess) return e;
         if ((e = D(fhi, EPI_PLAIN, LGT_ODD, Uhi->ptr, x64, t64, gate, nullptr, nullptr, nullptr,
                    ev(slot, 2 * chunk, true), ev(slot, 2 * chunk, false))) != hipSuccess)
@@ -198,7 +203,6 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     LGT_HIP(reliable(GATE_RU, -1, FIN_RU)); // r = b - A x0, rho, beta = 0
 
     // ---- iterations, `chunk` at a time
-    const int lo_is_f64 = !mixed;
     int k = 0;
     int prev_iter = 0, prev_upd = 0;
     double ms_hi = 0.0, ms_lo = 0.0;

@@ -18,8 +18,12 @@
 // fields W_rho (4 products per site each) and a second evaluates the outer
 // levels per link from them (72 products, plus 2 for N) instead of
 // recomputing W at every (a, b) of every link (168 products). Link and W
-// reads come from the caches; the kernels are bound by FP64 arithmetic and
-// those gathers, not by HBM.
+// reads come from the caches; the kernels are bound by the latency of those
+// gathers (one wave per SIMD) and FP64 arithmetic, not by HBM. Workgroups are
+// dispatched round-robin over the 8 XCDs, so both kernels remap the block
+// index: each XCD walks one contiguous range of checkerboard indices, the two
+// parities of a block of sites back to back (and in the first kernel its
+// three fields W_r), which keeps the y and z neighbours in that XCD's L2.
 #include "fields.hpp"
 #include "kernels.hpp"
 #include "su3.hpp"
@@ -50,6 +54,15 @@ __device__ __forceinline__ M3 adj(const M3 &A)
 #pragma unroll
         for (int j = 0; j < 3; j++) B.e[3 * i + j] = cx<double>{A.e[3 * j + i].re, -A.e[3 * j + i].im};
     return B;
+}
+
+// eo index of thread t of the k-th block taken by XCD xcd: checkerboard block
+// xcd * nbh_pad / 8 + k / 2 of parity k % 2, or -1 past the Vh sites of a
+// parity (nbh_pad: blocks per parity, rounded up to a multiple of 8)
+__device__ __forceinline__ int64_t xcd_site(const Geom &g, int xcd, int k, int nbh_pad, int t)
+{
+    const int64_t cb = (int64_t)(xcd * (nbh_pad >> 3) + (k >> 1)) * kBS + t;
+    return cb < g.Vh ? (k & 1) * (int64_t)g.Vh + cb : -1;
 }
 
 // L_a(y): the link of one step from y along axis a in direction s
@@ -88,15 +101,15 @@ __device__ __forceinline__ M3 staple(const double *U, int64_t V, const Geom &g, 
 }
 
 // W_r(y) = c5 U_mu(y) + c7 (S_{+rho}[U_mu](y) + S_{-rho}[U_mu](y)), rho = the r-th
-// axis other than mu; W is [3][V][3][3][2]
+// axis other than mu; W is [3][V][3][3][2]; 6 * nbh_pad blocks
 __global__ __launch_bounds__(kBS) void k_fat_inner(const double *__restrict__ U, double *__restrict__ W, Geom g,
-                                                   int mu, double c5, double c7)
+                                                   int mu, double c5, double c7, int nbh_pad)
 {
     const int64_t V = 2 * (int64_t)g.Vh;
-    const int64_t l = (int64_t)blockIdx.x * kBS + threadIdx.x; // r * V + y
-    if (l >= 3 * V) return;
-    const int r = (int)(l / V);
-    const int64_t ey = l - r * V;
+    const int k = (int)(blockIdx.x >> 3);
+    const int r = k % 3; // the three fields of one block of sites on one XCD in a row
+    const int64_t ey = xcd_site(g, (int)(blockIdx.x & 7), k / 3, nbh_pad, (int)threadIdx.x);
+    if (ey < 0) return;
     const int rho = other_axis(mu, r);
     int y[4], yp[4], ym[4];
     site_coords(g, ey, y);
@@ -108,14 +121,15 @@ __global__ __launch_bounds__(kBS) void k_fat_inner(const double *__restrict__ U,
     stm3(W, V, r, ey, w);
 }
 
-// F_mu(x) and N_mu(x) for every site x of direction mu, the innermost level from W
+// F_mu(x) and N_mu(x) for every site x of direction mu, the innermost level from
+// W; 2 * nbh_pad blocks
 __global__ __launch_bounds__(kBS) void k_fat_outer(const double *__restrict__ U, const double *__restrict__ W,
                                                    double *__restrict__ F, double *__restrict__ N, Geom g, int mu,
-                                                   FatCoeffs w)
+                                                   FatCoeffs w, int nbh_pad)
 {
     const int64_t V = 2 * (int64_t)g.Vh;
-    const int64_t ex = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (ex >= V) return;
+    const int64_t ex = xcd_site(g, (int)(blockIdx.x & 7), (int)(blockIdx.x >> 3), nbh_pad, (int)threadIdx.x);
+    if (ex < 0) return;
     int x[4];
     site_coords(g, ex, x);
 
@@ -156,13 +170,14 @@ __global__ __launch_bounds__(kBS) void k_fat_outer(const double *__restrict__ U,
 hipError_t launch_fatten(const double *U, double *F, double *N, double *W, const Geom &g, const FatCoeffs &w,
                          hipStream_t s)
 {
-    const int64_t V = 2 * (int64_t)g.Vh;
+    const int nbh = (int)(((int64_t)g.Vh + kBS - 1) / kBS), nbh_pad = (nbh + 7) / 8 * 8;
     for (int mu = 0; mu < 4; mu++) {
-        hipLaunchKernelGGL(k_fat_inner, dim3((unsigned)((3 * V + kBS - 1) / kBS)), dim3(kBS), 0, s, U, W, g, mu, w.c5,
-                           w.c7);
+        hipLaunchKernelGGL(k_fat_inner, dim3(6u * (unsigned)nbh_pad), dim3(kBS), 0, s, U, W, g, mu, w.c5, w.c7,
+                           nbh_pad);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_fat_outer, dim3((unsigned)((V + kBS - 1) / kBS)), dim3(kBS), 0, s, U, W, F, N, g, mu, w);
+        hipLaunchKernelGGL(k_fat_outer, dim3(2u * (unsigned)nbh_pad), dim3(kBS), 0, s, U, W, F, N, g, mu, w,
+                           nbh_pad);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

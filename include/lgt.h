@@ -155,10 +155,24 @@ lgt_status lgt_index_maps(lgt_ctx *ctx, int32_t *lex_of_eo, int32_t *nbr);
 /* ---- packing ---------------------------------------------------------------- */
 
 /* Canonical float64 links (device) -> native packed field of (prec, recon).
- * Rounding to F32 / BF16 is round-to-nearest-even from the float64 value.
+ * The paper's complex numbers have FP32 or FP64 real and imaginary parts
+ * (Sec. 4) and the links are SU(3) (Sec. 1); BF16 storage and the 12-real
+ * form (rows 0 and 1 kept, row 2 = conj(row0 x row1) rebuilt, exact for SU(3))
+ * are this library's reading, not the paper's. Rounding to F32 / BF16 is
+ * round-to-nearest-even from the float64 value (one rounding step).
  * U_packed must hold lgt_links_bytes bytes. */
 lgt_status lgt_pack_links(lgt_ctx *ctx, const double *U_canon, int32_t prec, int32_t recon,
                           void *U_packed);
+/* The inverse view: a packed field of (prec, recon) -> canonical float64 links
+ * [4][V][3][3][2] (device, caller-owned, U_canon must not overlap U_packed).
+ * Every stored real is widened exactly (FP32 and BF16 values are exact in
+ * float64), so unpacking a packed field shows the rounding of lgt_pack_links
+ * element by element; for 12-real formats row 2 is rebuilt as
+ * conj(row0 x row1) in the field's arithmetic precision (FP64 for F64 fields,
+ * FP32 for F32 and BF16 fields), the matrix the Dslash applies. Unsupported
+ * pair: LGT_ERR_UNSUPPORTED. Asynchronous. */
+lgt_status lgt_unpack_links(lgt_ctx *ctx, const void *U_packed, int32_t prec, int32_t recon,
+                            double *U_canon);
 /* Canonical float64 parity vector [V/2][3][2] <-> native vector of `prec`
  * (LGT_F64 or LGT_F32; BF16 fields use F32 vectors). */
 lgt_status lgt_pack_vec(lgt_ctx *ctx, int32_t prec, const double *src, void *dst);
@@ -217,7 +231,14 @@ typedef struct {
     int32_t dslash_timed_lo;
 } lgt_cg_result;
 
-/* Solve A x = b on even sites. U_hi: F64 links (recon 18 or 12). U_lo: the
+/* Solve A x = b on even sites. The paper names the solver only through the
+ * routines it spends its time in (Table 1: the vector updates
+ * scalar_mult_add_su3_vector / add_su3_vector around the Dslash) and prints no
+ * algorithm; the library runs the textbook conjugate-gradient iteration on the
+ * Hermitian positive definite A (the even-odd reduction of M^dag M, M = 2m + D)
+ * with the stop test on the FP64 true residual, and the mixed-precision
+ * schemes of its own reading (reliable updates, iterative refinement), none of
+ * them from the paper. U_hi: F64 links (recon 18 or 12). U_lo: the
  * low-precision links for RELIABLE / REFINE (F32 or BF16), ignored (may be
  * NULL) for FP64. b, x: canonical float64 even-parity vectors (device).
  * NOT_CONVERGED and NONFINITE still write the best x and fill *res.
@@ -277,6 +298,15 @@ lgt_status lgt_force_improved(lgt_ctx *ctx, const lgt_links *fat, const lgt_link
 typedef struct {
     double one_link, staple3, staple5, staple7, lepage, naik;
 } lgt_fat_coeffs;
+
+/* The asqtad weights above with tadpole improvement: each tree-level weight
+ * divided by u0^(path length - 1), i.e. one_link 5/8, staple3 1/16 / u0^2,
+ * staple5 1/64 / u0^4, staple7 1/384 / u0^6, lepage -1/16 / u0^4, naik
+ * -1/24 / u0^2 (u0 = 1: the tree-level weights). The paper's application uses
+ * an improved action without printing its weights (Table 4); this is the
+ * reading the library takes. u0 must be positive and finite (LGT_ERR_ARG).
+ * Host only: no context or device needed. */
+lgt_status lgt_asqtad_coeffs(double u0, lgt_fat_coeffs *out);
 
 /* F, N from U: canonical [4][V][3][3][2] float64 device fields (periodic gauge
  * field; fermion boundary signs stay in the Dslash). U, F and N must not
@@ -436,11 +466,15 @@ typedef struct {
 /* Independent even-odd CGs (own alpha, beta and stop test per right-hand
  * side; not block CG) for every right-hand side of every problem, lattices of
  * different sizes included, in ONE cooperative persistent launch (one
- * workgroup per CU) on the stream of probs[0].ctx. An iteration has three
+ * workgroup per CU) on the stream of probs[0].ctx. Not from the paper, which
+ * solves one system at a time: each right-hand side runs the iteration of
+ * lgt_cg_solve, and batching only shares each link load among the
+ * right-hand sides of a lattice. An iteration has three
  * grid barriers; every workgroup sums the per-workgroup partial sums itself,
  * in a fixed order, so results are bit-reproducible for a given device. FP64
  * reliable updates / refinement steps run inside the same launch. The inner
- * Dslash uses the multi-RHS engine of probs[0].ctx (lgt_set_mrhs_engine).
+ * Dslash of each problem uses the multi-RHS variant of that problem's own
+ * context (lgt_set_mrhs_engine / lgt_set_mrhs_variant / lgt_tune_dslash_mrhs).
  * Schemes and parameters as lgt_cg_solve (shared by all problems); res[j].seconds
  * is the time of the whole batch. Returns LGT_OK when every right-hand side
  * converged, else the first failing status (every res is filled either way).
@@ -465,6 +499,13 @@ lgt_status lgt_cdot(lgt_ctx *ctx, int64_t n_complex, const double *a, const doub
  *   x even: G_mu(x) = +2 eta_mu(x) s+_mu(x) X(x) Y(x+mu)^dag
  *   x odd : G_mu(x) = -2 eta_mu(x) s+_mu(x) Y(x) X(x+mu)^dag,  Y = D_oe X. */
 lgt_status lgt_force(lgt_ctx *ctx, const lgt_links *U, const double *X, double scale, double *G);
+
+/* The derivative of the same action in the source: A^-1 is Hermitian, so
+ * dS = 2 Re <X, dphi> and dS/d(Re phi, Im phi) = 2 (Re X, Im X). gphi
+ * (canonical even vector, device) receives 2 scale X; X and gphi may be the
+ * same buffer. The improved operator's action has the same derivative with its
+ * own X. Asynchronous. */
+lgt_status lgt_action_phi_grad(lgt_ctx *ctx, const double *X, double scale, double *gphi);
 
 /* ---- measurement aid ---------------------------------------------------------- */
 

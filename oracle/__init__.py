@@ -208,6 +208,15 @@ def force_imp(L, F, N, X, bc=None):
     return GF, GN
 
 
+def action_phi_grad(X):
+    """dS/d(Re phi, Im phi) for S = phi^dag A^-1 phi, given X = A^-1 phi.
+
+    A^-1 is Hermitian, so S(phi + d) - S(phi) = 2 Re <X, d> + O(d^2): the
+    derivative along the real and imaginary parts of each component is twice
+    the real and imaginary part of X there. [V/2][3][2]."""
+    return 2.0 * np.asarray(X, dtype=np.float64)
+
+
 def action_variational(L, U, mass, phi, x, bc=None):
     L = _i4(L)
     return float(lib().or_action_variational(_iptr(L), _iptr(_bc(bc)), _dptr(_f64(U)),

@@ -133,6 +133,26 @@ static Geom make_geom(const lgt_geom *lg)
     return g;
 }
 
+lgt_status force_run(lgt_ctx *c, const lgt_links *U, Fmt f, const double *X, double scale, double *G, double *Xn,
+                     double *Yn)
+{
+    LGT_HIP(launch_pack_vec(true, X, Xn, c->g, c->stream));
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.U = U->ptr;
+    a.in = Xn;
+    a.out = Yn;
+    a.g = c->g;
+    a.par = LGT_ODD;
+    a.gate = GATE_NONE;
+    a.l = site_launch(c->g.Vh);
+    a.hpi = c->hpi[f];
+    a.ntl = c->ntl[f];
+    LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
+    LGT_HIP(launch_force(Xn, Yn, scale, G, c->g, c->stream));
+    return LGT_OK;
+}
+
 } // namespace lgt
 
 using namespace lgt;
@@ -271,6 +291,19 @@ lgt_status lgt_pack_links(lgt_ctx *c, const double *Uc, int32_t prec, int32_t re
     if ((s = check_ptr(Up, "U_packed")) != LGT_OK) return s;
     DeviceScope ds(c->device);
     LGT_HIP(launch_pack_links(f, Uc, Up, c->g, c->stream));
+    return LGT_OK;
+}
+
+lgt_status lgt_unpack_links(lgt_ctx *c, const void *Up, int32_t prec, int32_t recon, double *Uc)
+{
+    CHECK_CTX(c);
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    lgt_status s;
+    if ((s = check_ptr(Up, "U_packed")) != LGT_OK) return s;
+    if ((s = check_ptr(Uc, "U_canon")) != LGT_OK) return s;
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_unpack_links(f, Up, Uc, c->g, c->stream));
     return LGT_OK;
 }
 
@@ -534,20 +567,18 @@ lgt_status lgt_force(lgt_ctx *c, const lgt_links *U, const double *X, double sca
     double *Xn = (double *)workspace(c, "force.X", v64);
     double *Yn = (double *)workspace(c, "force.Y", v64);
     if (!Xn || !Yn) return fail(LGT_ERR_OOM, "cannot allocate the force workspace");
-    LGT_HIP(launch_pack_vec(true, X, Xn, c->g, c->stream));
-    DslashArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.U = U->ptr;
-    a.in = Xn;
-    a.out = Yn;
-    a.g = c->g;
-    a.par = LGT_ODD;
-    a.gate = GATE_NONE;
-    a.l = site_launch(c->g.Vh);
-    a.hpi = c->hpi[f];
-    a.ntl = c->ntl[f];
-    LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
-    LGT_HIP(launch_force(Xn, Yn, scale, G, c->g, c->stream));
+    return lgt::force_run(c, U, f, X, scale, G, Xn, Yn);
+}
+
+lgt_status lgt_action_phi_grad(lgt_ctx *c, const double *X, double scale, double *gphi)
+{
+    CHECK_CTX(c);
+    lgt_status s;
+    if ((s = check_ptr(X, "X")) != LGT_OK) return s;
+    if ((s = check_ptr(gphi, "gphi")) != LGT_OK) return s;
+    if (!std::isfinite(scale)) return fail(LGT_ERR_ARG, "scale must be finite");
+    DeviceScope ds(c->device);
+    LGT_HIP(launch_phi_grad(X, scale, gphi, c->g, c->stream));
     return LGT_OK;
 }
 

@@ -81,6 +81,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                     const double *b, double *x, lgt_cg_result *res, const lgt_links *U3hi = nullptr,
                     const lgt_links *U3lo = nullptr);
 
+// the fermion force given its two native scratch vectors (X and Y = D_oe X)
+lgt_status force_run(lgt_ctx *c, const lgt_links *U, Fmt f, const double *X, double scale, double *G, double *Xn,
+                     double *Yn);
+
 } // namespace lgt
 
 #define LGT_HIP(expr)                                                                            \

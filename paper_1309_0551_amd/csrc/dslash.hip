@@ -325,6 +325,40 @@ hipError_t launch_pack_links(Fmt f, const double *Uc, void *Up, const Geom &g, h
     return hipGetLastError();
 }
 
+// planes of format LF -> canonical [4][V][3][3][2] float64: stored reals are
+// widened exactly; 12-real formats rebuild row 2 as the Dslash does
+template <class LF>
+__global__ __launch_bounds__(kBS) void k_unpack_links(const void *__restrict__ Up, double *__restrict__ Uc, Geom g)
+{
+    const int64_t V = 2 * (int64_t)g.Vh;
+    const int64_t idx = (int64_t)blockIdx.x * kBS + threadIdx.x; // mu*V + eo
+    if (idx >= 4 * V) return;
+    const int mu = (int)(idx / V);
+    const int64_t eo = idx - mu * V;
+    const int par = eo >= g.Vh;
+    const unsigned cb = (unsigned)(eo - par * (int64_t)g.Vh);
+    cx<typename LF::real> u[9];
+    LF::template load<false>(Up, (size_t)g.Vh, par * 4 + mu, cb, u);
+    dv2 *dst = (dv2 *)(Uc + idx * 18);
+#pragma unroll
+    for (int k = 0; k < 9; k++) dst[k] = dv2{(double)u[k].re, (double)u[k].im};
+}
+
+hipError_t launch_unpack_links(Fmt f, const void *Up, double *Uc, const Geom &g, hipStream_t s)
+{
+    const int64_t n = 4 * 2 * (int64_t)g.Vh;
+    const dim3 grid((unsigned)((n + kBS - 1) / kBS)), block(kBS);
+    switch (f) {
+    case F64R18: hipLaunchKernelGGL(k_unpack_links<LinkF64R18>, grid, block, 0, s, Up, Uc, g); break;
+    case F64R12: hipLaunchKernelGGL(k_unpack_links<LinkF64R12>, grid, block, 0, s, Up, Uc, g); break;
+    case F32R18: hipLaunchKernelGGL(k_unpack_links<LinkF32R18>, grid, block, 0, s, Up, Uc, g); break;
+    case F32R12: hipLaunchKernelGGL(k_unpack_links<LinkF32R12>, grid, block, 0, s, Up, Uc, g); break;
+    case BF16R12: hipLaunchKernelGGL(k_unpack_links<LinkBF16R12>, grid, block, 0, s, Up, Uc, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_pack_vec(const double *__restrict__ src, void *__restrict__ dst, int Vh)
 {

@@ -81,4 +81,24 @@ hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, do
     return hipGetLastError();
 }
 
+// dS/dphi of S = phi^dag A^-1 phi: A^-1 is Hermitian, so dS = 2 Re <X, dphi>
+// with X = A^-1 phi, i.e. dS/dRe phi = 2 Re X, dS/dIm phi = 2 Im X. One thread
+// per pair of reals of the canonical even vector (bound by its read and write).
+__global__ __launch_bounds__(kBS) void k_phi_grad(const dv2 *__restrict__ X, double s2, dv2 *__restrict__ g,
+                                                  int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    if (i >= n) return;
+    const dv2 v = X[i];
+    g[i] = dv2{s2 * v.x, s2 * v.y};
+}
+
+hipError_t launch_phi_grad(const double *X, double scale, double *gphi, const Geom &g, hipStream_t s)
+{
+    const int64_t n = 3 * (int64_t)g.Vh; // complex numbers of one parity vector
+    const dim3 grid((unsigned)((n + kBS - 1) / kBS)), block(kBS);
+    hipLaunchKernelGGL(k_phi_grad, grid, block, 0, s, (const dv2 *)X, 2.0 * scale, (dv2 *)gphi, n);
+    return hipGetLastError();
+}
+
 } // namespace lgt

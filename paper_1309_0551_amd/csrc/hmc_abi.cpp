@@ -106,6 +106,22 @@ lgt_status lgt_link_update(lgt_ctx *c, const double *P, double eps, double *U)
     return LGT_OK;
 }
 
+lgt_status lgt_asqtad_coeffs(double u0, lgt_fat_coeffs *w)
+{
+    clear_error();
+    if (!w) return fail(LGT_ERR_ARG, "coefficients are NULL");
+    if (!(u0 > 0.0) || !std::isfinite(u0)) return fail(LGT_ERR_ARG, "u0 must be positive and finite");
+    // tree-level weights, each divided by u0^(path length - 1)
+    const double u2 = u0 * u0, u4 = u2 * u2, u6 = u4 * u2;
+    w->one_link = 5.0 / 8.0;
+    w->staple3 = 1.0 / 16.0 / u2;
+    w->staple5 = 1.0 / 64.0 / u4;
+    w->staple7 = 1.0 / 384.0 / u6;
+    w->lepage = -1.0 / 16.0 / u4;
+    w->naik = -1.0 / 24.0 / u2;
+    return LGT_OK;
+}
+
 lgt_status lgt_fatten_links(lgt_ctx *c, const double *U, const lgt_fat_coeffs *w, double *F, double *N)
 {
     CHECK(c);

@@ -96,6 +96,7 @@ struct DslashArgs {
 hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
 hipError_t launch_pack_links(Fmt f, const double *Ucanon, void *Upacked, const Geom &g, hipStream_t s);
+hipError_t launch_unpack_links(Fmt f, const void *Upacked, double *Ucanon, const Geom &g, hipStream_t s);
 hipError_t launch_pack_vec(bool f64, const double *src, void *dst, const Geom &g, hipStream_t s);
 hipError_t launch_unpack_vec(bool f64, const void *src, double *dst, const Geom &g, hipStream_t s);
 hipError_t launch_index_maps(int32_t *lex_of_eo, int32_t *nbr, const Geom &g, hipStream_t s);
@@ -143,5 +144,7 @@ hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, v
 // fermion force of one link field (naik: the three-link field of the improved operator)
 hipError_t launch_force(const double *Xnat, const double *Ynat, double scale, double *G, const Geom &g,
                         hipStream_t s, bool naik = false);
+// gphi = 2 scale X over one canonical parity vector (dS/dphi of phi^dag A^-1 phi)
+hipError_t launch_phi_grad(const double *X, double scale, double *gphi, const Geom &g, hipStream_t s);
 
 } // namespace lgt

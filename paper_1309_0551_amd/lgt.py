@@ -112,10 +112,11 @@ class _FatCoeffs(C.Structure):
 
 
 def asqtad_coeffs(u0: float = 1.0) -> tuple:
-    """Tree-level asqtad weights (one link, 3-, 5-, 7-link staples, Lepage, Naik),
-    each divided by u0^(path length - 1): for unit links F = 9/8, N = -1/24."""
-    return (5.0 / 8.0, 1.0 / 16.0 / u0 ** 2, 1.0 / 64.0 / u0 ** 4, 1.0 / 384.0 / u0 ** 6,
-            -1.0 / 16.0 / u0 ** 4, -1.0 / 24.0 / u0 ** 2)
+    """Tree-level asqtad weights (one link, 3-, 5-, 7-link staples, Lepage, Naik)
+    with tadpole improvement by u0, from the library (lgt_asqtad_coeffs)."""
+    w = _FatCoeffs()
+    _check(lib().lgt_asqtad_coeffs(float(u0), C.byref(w)))
+    return (w.one_link, w.staple3, w.staple5, w.staple7, w.lepage, w.naik)
 
 
 def _setup(l):
@@ -131,6 +132,7 @@ def _setup(l):
         "lgt_set_timing": (st, [vp, i32]),
         "lgt_index_maps": (st, [vp, vp, vp]),
         "lgt_pack_links": (st, [vp, vp, i32, i32, vp]),
+        "lgt_unpack_links": (st, [vp, vp, i32, i32, vp]),
         "lgt_pack_vec": (st, [vp, i32, vp, vp]),
         "lgt_unpack_vec": (st, [vp, i32, vp, vp]),
         "lgt_dslash": (st, [vp, C.POINTER(_Links), i32, vp, vp]),
@@ -158,6 +160,8 @@ def _setup(l):
         "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
         "lgt_gauge_force": (st, [vp, vp, C.c_double, C.c_double, i32, vp]),
         "lgt_fatten_links": (st, [vp, vp, C.POINTER(_FatCoeffs), vp, vp]),
+        "lgt_asqtad_coeffs": (st, [C.c_double, C.POINTER(_FatCoeffs)]),
+        "lgt_action_phi_grad": (st, [vp, vp, C.c_double, vp]),
         "lgt_momentum_update": (st, [vp, vp, vp, C.c_double, vp]),
         "lgt_link_update": (st, [vp, vp, C.c_double, vp]),
         "lgt_plaquette": (st, [vp, vp, C.POINTER(C.c_double)]),
@@ -362,6 +366,15 @@ class Lattice:
         out = torch.empty(links_bytes(self.L, prec, recon, self.bc), dtype=torch.uint8, device=self.device)
         _check(lib().lgt_pack_links(self._ctx, p, prec, recon, out.data_ptr()))
         return PackedLinks(out, prec, recon)
+
+    def unpack_links(self, Up: PackedLinks) -> torch.Tensor:
+        """The links a packed field holds, canonical float64 [4][V][3][3][2]
+        (12-real formats: row 2 rebuilt as the Dslash rebuilds it)."""
+        if Up.data.device != self.device:
+            raise ValueError(f"packed links must be on {self.device}")
+        out = torch.empty((4, self.V, 3, 3, 2), dtype=torch.float64, device=self.device)
+        _check(lib().lgt_unpack_links(self._ctx, _ptr(Up.data), Up.prec, Up.recon, out.data_ptr()))
+        return out
 
     def pack_vec(self, v: torch.Tensor, prec: int = LGT_F64) -> torch.Tensor:
         p = self._dev(v, torch.float64, self.vec_shape(), "v")
@@ -571,6 +584,13 @@ class Lattice:
         _check(lib().lgt_force(self._ctx, C.byref(d), px, float(scale), G.data_ptr()))
         return G
 
+    def action_phi_grad(self, X: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+        """scale * dS/d(Re phi, Im phi) = 2 scale X for S = phi^dag A^-1 phi, X = A^-1 phi."""
+        px = self._dev(X, torch.float64, self.vec_shape(), "X")
+        g = torch.empty_like(X)
+        _check(lib().lgt_action_phi_grad(self._ctx, px, float(scale), g.data_ptr()))
+        return g
+
     def force_improved(self, F: PackedLinks, N: PackedLinks, X: torch.Tensor, scale: float = 1.0):
         """(G_fat, G_naik) = scale * dS/d(Re, Im) of the improved operator's two link fields."""
         px = self._dev(X, torch.float64, self.vec_shape(), "X")
@@ -691,8 +711,7 @@ class PseudofermionAction(torch.autograd.Function):
         (X,) = ctx.saved_tensors
         g = float(gS.item())
         gU = ctx.lat.force(ctx.Up, X, scale=g) if ctx.needs_input_grad[0] else None
-        # dS/d(Re phi, Im phi) = 2 (Re X, Im X)
-        gphi = (2.0 * g) * X if ctx.needs_input_grad[1] else None
+        gphi = ctx.lat.action_phi_grad(X, scale=g) if ctx.needs_input_grad[1] else None
         return gU, gphi, None, None, None, None, None
 
 
@@ -721,5 +740,5 @@ class ImprovedPseudofermionAction(torch.autograd.Function):
             gF, gN = ctx.lat.force_improved(ctx.Fp, ctx.Np, X, scale=g)
             gF = gF if ctx.needs_input_grad[0] else None
             gN = gN if ctx.needs_input_grad[1] else None
-        gphi = (2.0 * g) * X if ctx.needs_input_grad[2] else None
+        gphi = ctx.lat.action_phi_grad(X, scale=g) if ctx.needs_input_grad[2] else None
         return gF, gN, gphi, None, None, None, None

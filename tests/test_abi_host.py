@@ -152,8 +152,26 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_kinetic_energy": (None, None, C.byref(d)),
         "lgt_hmc_trajectory": (None, None, None, None, None, None, None),
         "lgt_fatten_links": (None, None, None, None, None),
+        "lgt_unpack_links": (None, None, 0, 18, None),
+        "lgt_action_phi_grad": (None, None, 1.0, None),
     }
     for name, args in calls.items():
         assert getattr(l, name)(*args) == -1, name
     # no problems / a NULL problem list
     assert l.lgt_cg_solve_batch(None, 0, None) == -1
+
+
+def test_asqtad_coeffs_from_the_library():
+    """lgt_asqtad_coeffs: the tree-level weights at u0 = 1 exactly, a path of n
+    links divided by u0^(n-1) otherwise (against the oracle's table), and bad
+    u0 rejected on the host."""
+    from oracle import fatten as ofat
+
+    assert P.asqtad_coeffs(1.0) == (5.0 / 8.0, 1.0 / 16.0, 1.0 / 64.0, 1.0 / 384.0, -1.0 / 16.0, -1.0 / 24.0)
+    for u0 in (0.9, 0.8751, 1.3):
+        got, want = P.asqtad_coeffs(u0), ofat.asqtad_coeffs(u0)
+        for a, b in zip(got, want):
+            assert abs(a - b) <= 4e-16 * abs(b), (u0, got, want)
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(P.LgtError):
+            P.asqtad_coeffs(bad)

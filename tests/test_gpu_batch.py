@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import lgt_inputs as li
+import lowprec
 import oracle
 
 torch = pytest.importorskip("torch")
@@ -38,6 +39,16 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _per_element(got, L, U, chi, par, prec, recon, bc, ref, what):
+    """FP64: every component within 1e-12 max|ref|; FP32 / BF16 links: every
+    output real within the FP32-arithmetic bound against the oracle on the
+    stored (rounded) links and input (tests/lowprec.py)."""
+    if prec == P.LGT_F64:
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), what
+    else:
+        lowprec.check_dslash(got, L, U, chi, par, prec, recon, bc, None, what)
+
+
 @pytest.mark.parametrize("fmt", sorted(FMTS))
 @pytest.mark.parametrize("nrhs", [1, 2, 4, 16])
 def test_dslash_mrhs_parity(dev, fmt, nrhs):
@@ -54,6 +65,7 @@ def test_dslash_mrhs_parity(dev, fmt, nrhs):
             for r in range(nrhs):
                 ref = oracle.dslash(L, U, chis[r], par, bc)
                 assert _rel(got[r], ref) <= tol, (fmt, nrhs, par, r)
+                _per_element(got[r], L, U, chis[r], par, prec, recon, bc, ref, (fmt, nrhs, par, r))
 
 
 ENGINES = {"lane": 0, "valu4": 1, "mfma": 2}
@@ -82,6 +94,7 @@ def test_dslash_mrhs_engines(dev, engine, fmt, nrhs, L):
             for r in range(nrhs):
                 ref = oracle.dslash(L, U, chis[r], par, bc)
                 assert _rel(got[r], ref) <= tol, (engine, fmt, nrhs, L, par, r)
+                _per_element(got[r], L, U, chis[r], par, prec, recon, bc, ref, (engine, fmt, nrhs, L, par, r))
 
 
 # every (engine, groups, nrhs) with at least one right-hand side per lane
@@ -107,6 +120,7 @@ def test_dslash_mrhs_groups(dev, engine, groups, fmt, nrhs):
             for r in range(nrhs):
                 ref = oracle.dslash(L, U, chis[r], par, bc)
                 assert _rel(got[r], ref) <= tol, (engine, groups, fmt, nrhs, par, r)
+                _per_element(got[r], L, U, chis[r], par, prec, recon, bc, ref, (engine, groups, fmt, nrhs, par, r))
 
 
 def test_mrhs_variant_arguments(dev):

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import lgt_inputs as li
+import lowprec
 import oracle
 
 torch = pytest.importorskip("torch")
@@ -52,6 +53,8 @@ def test_improved_dslash_parity(dev, fmt, L, bc):
             assert _rel(got, ref) <= tol, (fmt, L, par)
             if prec == P.LGT_F64:
                 assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+            else:
+                lowprec.check_dslash_improved(got, L, F, N, chi, par, bc, None, (fmt, L, par))
 
 
 def test_improved_dslash_full_size_32(dev):

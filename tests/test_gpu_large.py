@@ -65,8 +65,7 @@ def test_dslash_64(big, fmt, tol):
                              vec_prec).cpu().numpy()
         ref = oracle.dslash(L, U, chi, par)
         assert _rel(out, ref) <= tol
-        if fmt == "f64r18":
-            assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
 
 
 def test_improved_dslash_64(big):

@@ -7,6 +7,10 @@ Tolerances (norm-wise relative error of the output):
   links and input; the kernel sums 8 hops of 3x3 products in FP32.
 * BF16 links + FP32 vectors: 8 u16 = 1.6e-2, u16 = 2^-9; rows 0-1 are rounded
   and row 2 is rebuilt from the rounded rows.
+* FP32 / BF16 also element by element: every component within tol max|ref|,
+  and every output real within the FP32-arithmetic bound of tests/lowprec.py
+  against the oracle on the stored (rounded) links and input, which a
+  mis-rounded BF16 link fails by orders of magnitude.
 * CG: the oracle recomputes the true residual of the GPU's x in FP64, which must
   meet the tolerance; and |x - x_oracle| <= (tol_gpu + tol_oracle) |b| / (4 m^2),
   since lambda_min(A) >= 4 m^2.
@@ -18,6 +22,7 @@ import pytest
 
 import brute
 import lgt_inputs as li
+import lowprec
 import oracle
 
 torch = pytest.importorskip("torch")
@@ -88,8 +93,9 @@ def test_dslash_parity(dev, fmt, L, bc, kind):
             got = out.cpu().numpy()
             ref = oracle.dslash(L, U, chi, out_par, bc)
             assert _rel(got, ref) <= tol, (fmt, out_par, _rel(got, ref))
-            if prec == P.LGT_F64:
-                assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+            assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+            if prec != P.LGT_F64:
+                lowprec.check_dslash(got, L, U, chi, out_par, prec, recon, bc, None, (fmt, L, out_par))
 
 
 @pytest.mark.parametrize("fmt", sorted(FMTS))
@@ -586,6 +592,17 @@ def test_force_parity(dev, L, bc):
     Gr = oracle.force(L, U, X, bc)
     assert _rel(G, Gr) <= 1e-12
     assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+
+
+def test_action_phi_grad(dev):
+    """lgt_action_phi_grad: scale * dS/dphi = 2 scale X, against the oracle's derivative."""
+    L = (6, 4, 6, 8)
+    X = li.vector(L, 591)
+    with P.Lattice(L) as lat:
+        for scale in (1.0, -0.75, 3.1):
+            got = lat.action_phi_grad(_t(X, dev), scale).cpu().numpy()
+            want = scale * oracle.action_phi_grad(X)
+            assert np.abs(got - want).max() <= 2.0 ** -52 * np.abs(want).max()
 
 
 def test_autograd_action_vs_oracle(dev):

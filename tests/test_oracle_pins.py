@@ -311,6 +311,29 @@ def test_force_vs_dense_central_differences(L, bc):
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (mu, s, fd, an)
 
 
+@pytest.mark.parametrize("L,bc", [((2, 4, 2, 4), (1, 1, 1, 1)), ((4, 2, 2, 4), (1, 1, 1, -1))])
+def test_phi_grad_vs_dense_central_differences(L, bc):
+    """dS/dphi from the oracle's X against central differences of the dense S
+    along random directions in the source."""
+    mass = 0.3
+    U = li.links(L, "expih", 65, c=0.5)
+    phi = li.vector(L, 66)
+    st, X, it, rr = oracle.cg(L, U, mass, phi, tol=1e-14, bc=bc)
+    gphi = oracle.action_phi_grad(X)
+    g = li.rng(67)
+    eps = 1e-5
+    for _ in range(6):
+        E = g.standard_normal(phi.shape)
+        E /= np.linalg.norm(E)
+        fd = (_S_dense(L, U, mass, phi + eps * E, bc) - _S_dense(L, U, mass, phi - eps * E, bc)) / (2 * eps)
+        an = float(np.sum(gphi * E))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
+    # a planted factor: X alone (without the 2) misses the central difference
+    E = g.standard_normal(phi.shape)
+    fd = (_S_dense(L, U, mass, phi + eps * E, bc) - _S_dense(L, U, mass, phi - eps * E, bc)) / (2 * eps)
+    assert abs(fd - float(np.sum(X * E))) > 1e-3 * abs(fd)
+
+
 def test_force_vs_oracle_cg_differences():
     """Same check through the oracle's own CG and the variational S estimate."""
     L = (4, 4, 4, 4)

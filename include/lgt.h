@@ -500,6 +500,19 @@ lgt_status lgt_cdot(lgt_ctx *ctx, int64_t n_complex, const double *a, const doub
  *   x odd : G_mu(x) = -2 eta_mu(x) s+_mu(x) Y(x) X(x+mu)^dag,  Y = D_oe X. */
 lgt_status lgt_force(lgt_ctx *ctx, const lgt_links *U, const double *X, double scale, double *G);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lgt_force
+ * with its two scratch vectors (X and Y = D_oe X in native layout, 96 bytes per
+ * even site) in a fixed 64 MiB device array of the library instead of context
+ * workspace. Same arguments and results as lgt_force, bit for bit; the call
+ * allocates nothing (the array's address on each device is looked up once, by
+ * lgt_create). Limit: V/2 <= 699050 sites (a 32^4 lattice fits), else
+ * LGT_ERR_UNSUPPORTED before anything runs. Every call on one GPU shares that
+ * GPU's single array: calls that overlap on one device (other streams, other
+ * contexts, other threads) race and must be ordered by the caller. Nothing in
+ * the array needs to start at zero. Asynchronous. */
+lgt_status lgt_force_noalloc(lgt_ctx *ctx, const lgt_links *U, const double *X, double scale, double *G);
+
 /* The derivative of the same action in the source: A^-1 is Hermitian, so
  * dS = 2 Re <X, dphi> and dS/d(Re phi, Im phi) = 2 (Re X, Im X). gphi
  * (canonical even vector, device) receives 2 scale X; X and gphi may be the

@@ -229,6 +229,12 @@ lgt_status lgt_create(const lgt_geom *g, int32_t device, void *hip_stream, lgt_c
         return fail(LGT_ERR_DEVICE, "cannot query device %d", device);
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(LGT_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    {
+        // the device address of the library's fixed scratch array on this
+        // device, looked up once (lgt_force_noalloc uses it)
+        DeviceScope ds(device);
+        if ((s = lgt::scratch_init(device)) != LGT_OK) return s;
+    }
     lgt_ctx *c = new (std::nothrow) lgt_ctx();
     if (!c) return fail(LGT_ERR_OOM, "cannot allocate the context");
     c->geom = *g;

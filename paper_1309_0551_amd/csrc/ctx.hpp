@@ -85,6 +85,15 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
 lgt_status force_run(lgt_ctx *c, const lgt_links *U, Fmt f, const double *X, double scale, double *G, double *Xn,
                      double *Yn);
 
+// Fixed scratch array of the library (noalloc.hip), kScratchBytes per device:
+// scratch_init looks up its address on `device` (which must be current) once
+// per device; scratch_ptr returns it (null before scratch_init succeeded).
+// 64 MiB: the two FP64 parity vectors of the force up to V/2 = 699050 sites
+// (a 32^4 lattice needs 50 MB).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+lgt_status scratch_init(int device);
+void *scratch_ptr(int device);
+
 } // namespace lgt
 
 #define LGT_HIP(expr)                                                                            \

@@ -140,6 +140,7 @@ def _setup(l):
                               C.POINTER(_CgResult)]),
         "lgt_cdot": (st, [vp, C.c_int64, vp, vp, C.POINTER(C.c_double)]),
         "lgt_force": (st, [vp, C.POINTER(_Links), vp, C.c_double, vp]),
+        "lgt_force_noalloc": (st, [vp, C.POINTER(_Links), vp, C.c_double, vp]),
         "lgt_set_dslash_variant": (st, [vp, i32, i32, i32, i32]),
         "lgt_get_dslash_variant": (st, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),

@@ -154,6 +154,7 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_fatten_links": (None, None, None, None, None),
         "lgt_unpack_links": (None, None, 0, 18, None),
         "lgt_action_phi_grad": (None, None, 1.0, None),
+        "lgt_force_noalloc": (None, None, None, 1.0, None),
     }
     for name, args in calls.items():
         assert getattr(l, name)(*args) == -1, name

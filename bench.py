@@ -179,7 +179,7 @@ def small_configs(args):
     import lgt_inputs as li
     import paper_1309_0551_amd as P
     import torch
-    out = {}
+    out, sols = {}, {}
     for key in ("c1_4x4x4x4", "c2_16x16x16x16"):
         cfg = li.CONFIGS[key]
         L = cfg["L"]
@@ -187,6 +187,8 @@ def small_configs(args):
             dev = lat.device
             U = torch.from_numpy(li.links(L, cfg["kind"], cfg["link_seed"], cfg["c"] or 0.3)).to(dev)
             Up = lat.pack_links(U, P.LGT_F64, P.LGT_R18)
+            if not args.no_tune:
+                lat.tune_dslash(Up, report=False)
             b = torch.from_numpy(li.vector(L, cfg["src_seed"])).to(dev)
             xin = lat.pack_vec(b)
             y = torch.empty_like(xin)
@@ -209,21 +211,140 @@ def small_configs(args):
             d.update({"lattice": list(L), "mass": cfg["mass"], "cg_fp64_s": round(r.seconds, 5), "iters": r.iters,
                       "true_rel_resid": r.true_rel_resid,
                       "dslash_in_cg_us": round(1e3 * rt.dslash_ms_hi / max(rt.dslash_timed_hi, 1), 2),
-                      "variant": "hops=%d streaming=%d" % lat.dslash_variant(P.LGT_F64, P.LGT_R18)})
+                      "variant": "hops=%d streaming=%d workgroup=%d" % (
+                          lat.dslash_variant(P.LGT_F64, P.LGT_R18) + (lat.dslash_workgroup(P.LGT_F64, P.LGT_R18),))})
             out[key[3:]] = d
-    return out
+            sols[key[3:]] = (L, U.cpu().numpy(), cfg["mass"], b.cpu().numpy(), x.cpu().numpy())
+    return out, sols
 
 
-def cpu_baseline(L, U, chi, budget_s):
-    import oracle
-    oracle.dslash(L, U, chi, 1)  # warm: page in, start the thread pool
+def _timed(fn, budget_s):
+    """Repeat fn until budget_s seconds have passed (at least once); (runs, seconds)."""
     n, t0 = 0, time.perf_counter()
     while True:
-        oracle.dslash(L, U, chi, 1)
+        fn()
         n += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
             return n, el
+
+
+def cpu_leg(L, U, chi, mass, budget_s, gpu):
+    """The oracle's side of the measurement, on the host cores after the GPU
+    work: its FP64 Dslash and CG timed on bounded samples of the workloads
+    (all threads and one thread), and the oracle's errors of the GPU results
+    of this run (`gpu`: host copies of the 32^4 solutions, the Dslash output
+    and the small-lattice solutions)."""
+    import lgt_inputs as li
+    import numpy as np
+    import oracle
+    nthreads = oracle.threads()
+    Vh = int(np.prod(L)) // 2
+    site_bytes = 1248
+    oracle.dslash(L, U, chi, 1)  # warm: page in, start the thread pool
+    n, el = _timed(lambda: oracle.dslash(L, U, chi, 1), budget_s)
+    out = {"value": round(site_bytes * Vh * n / el / 1e9, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"{n} FP64 D_oe applications of the C oracle (OpenMP, {nthreads} threads) at "
+                     f"{'x'.join(map(str, L))} in {el:.1f} s; algorithmic bytes of a plain Dslash (1248 B/site)"}
+    extra = {}
+    oracle.set_threads(1)
+    try:
+        n1, el1 = _timed(lambda: oracle.dslash(L, U, chi, 1), budget_s / 4)
+        extra["dslash_1thread_GBps"] = round(site_bytes * Vh * n1 / el1 / 1e9, 3)
+        for key in ("c1_4x4x4x4", "c2_16x16x16x16"):
+            cfg = li.CONFIGS[key]
+            Lc = cfg["L"]
+            Uc = li.links(Lc, cfg["kind"], cfg["link_seed"], cfg["c"] or 0.3)
+            bc_ = li.vector(Lc, cfg["src_seed"])
+            row = {}
+            for label, th in (("all_threads", nthreads), ("1_thread", 1)):
+                oracle.set_threads(th)
+                t0 = time.perf_counter()
+                st, _, it, rr = oracle.cg(Lc, Uc, cfg["mass"], bc_, tol=cfg["tol"])
+                row[label + "_s"] = round(time.perf_counter() - t0, 4)
+            row.update({"iters": it, "true_rel_resid": rr, "status": st})
+            extra["cg_fp64_" + key[3:]] = row
+        # 32^4: a bounded sample of the FP64 CG (the first 200 iterations), per iteration
+        oracle.set_threads(nthreads)
+        t0 = time.perf_counter()
+        st, _, it, _ = oracle.cg(L, U, mass, chi, tol=1e-10, max_iter=200)
+        per_it = (time.perf_counter() - t0) / max(it, 1)
+        extra["cg_fp64_32x32x32x32_sample"] = {"iters_run": it, "s_per_iter": round(per_it, 5),
+                                               "s_at_gpu_iters": round(per_it * gpu["fp64_iters"], 2),
+                                               "threads": nthreads}
+    finally:
+        oracle.set_threads(nthreads)
+    out["extra"] = extra
+    # errors of this run's GPU results against the oracle (north star: per result)
+    bn = float(np.linalg.norm(chi))
+    errs = {}
+    for key, x in gpu["x32"].items():
+        r = chi - oracle.apply_A(L, U, mass, x)
+        errs["cg_" + key] = {"oracle_true_rel_resid": float(np.linalg.norm(r) / bn),
+                             "x_err_bound_rel": float(np.linalg.norm(r) / (4 * mass * mass) / np.linalg.norm(x))}
+    for key in ("f32r12_reliable", "bf16r12_refine"):
+        if key in gpu["x32"] and "fp64" in gpu["x32"]:
+            d = gpu["x32"][key] - gpu["x32"]["fp64"]
+            errs["cg_" + key]["rel_diff_vs_fp64_gpu"] = float(np.linalg.norm(d) / np.linalg.norm(gpu["x32"]["fp64"]))
+    ref = oracle.dslash(L, U, gpu["dslash_in"], 1)
+    d = gpu["dslash_out"] - ref
+    errs["dslash_f64r18"] = {"rel": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                             "max_abs_over_max_ref": float(np.abs(d).max() / np.abs(ref).max())}
+    for key, (Lc, Uc, m, bc_, xg) in gpu["small"].items():
+        st, xo, it, rr = oracle.cg(Lc, Uc, m, bc_, tol=1e-10)
+        r = bc_ - oracle.apply_A(Lc, Uc, m, xg)
+        errs["cg_fp64_" + key] = {"oracle_true_rel_resid": float(np.linalg.norm(r) / np.linalg.norm(bc_)),
+                                  "x_rel_err_vs_oracle_solve": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                                  "oracle_iters": it}
+    return out, errs
+
+
+PROBE_FMTS = {"f64r18": (0, 18), "f64r12": (0, 12), "f32r18": (1, 18), "f32r12": (1, 12), "bf16r12": (2, 12)}
+
+
+def probe_dslash(L, fmt, launches, hops, streaming):
+    """--probe: the one-link Dslash alone on a lattice of any size. Links are
+    independent draws from a pool of 2^16 Haar matrices, gathered on the device
+    (lattices of many GB take seconds); `launches` plain Dslash applications
+    (output parity odd) after one warm-up, timed with events on their stream;
+    prints the mean kernel time and the algorithmic bandwidth (8 links, the
+    input once and the output once per output site). Run it under rocprofv3 to
+    read the same launches' counters."""
+    import math
+
+    import torch
+
+    import lgt_inputs as li
+    import paper_1309_0551_amd as P
+    dev = torch.device("cuda", 0)
+    V = math.prod(L)
+    prec, recon = PROBE_FMTS[fmt]
+    vp = P.LGT_F64 if prec == P.LGT_F64 else P.LGT_F32
+    pool = torch.from_numpy(li.to_real(li.haar_su3(1 << 16, li.rng(7)))).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    with P.Lattice(L) as lat:
+        U = pool[torch.randint(0, pool.shape[0], (4 * V,), device=dev, generator=g)].reshape(4, V, 3, 3, 2)
+        Up = lat.pack_links(U.contiguous(), prec, recon)
+        del U, pool
+        torch.cuda.empty_cache()
+        if hops:
+            lat.set_dslash_variant(prec, recon, hops, streaming)
+        x = lat.pack_vec(torch.randn(lat.Vh, 3, 2, dtype=torch.float64, device=dev, generator=g), vp)
+        y = torch.empty_like(x)
+        lat.dslash(Up, x, 1, y)  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(lat.stream)
+        for _ in range(launches):
+            lat.dslash(Up, x, 1, y)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / launches
+        h, st = lat.dslash_variant(prec, recon)
+    alg = lat.Vh * alg_bytes_per_site(prec, recon)
+    return {"probe": "dslash", "L": list(L), "fmt": fmt, "hops": h, "streaming": st, "launches": launches,
+            "us_per_launch": round(us, 2), "alg_bytes_per_launch": alg, "alg_GBps": round(alg / us / 1e3, 1)}
 
 
 def main():
@@ -247,11 +368,22 @@ def main():
                     help="skip the improved (fat + Naik) operator measurement after the timed steps")
     ap.add_argument("--no-batch", action="store_true",
                     help="leave the batched solves out of the step (short runs under hardware counters)")
+    ap.add_argument("--probe", type=int, nargs=4, metavar="L",
+                    help="instead of the benchmark: time the plain Dslash alone on this lattice and print one "
+                         "JSON line (options --fmt, --launches, --hops, --streaming)")
+    ap.add_argument("--fmt", default="f64r18", choices=sorted(PROBE_FMTS))
+    ap.add_argument("--launches", type=int, default=12)
+    ap.add_argument("--hops", type=int, default=0, choices=(0, 1, 2, 4, 8), help="0: the library's default")
+    ap.add_argument("--streaming", type=int, default=1, choices=(0, 1))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (its domain decomposition "
               "over several GPUs is a design only); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.probe:
+        print(json.dumps(probe_dslash(tuple(args.probe), args.fmt, args.launches, args.hops, args.streaming)),
+              flush=True)
+        return
 
     import numpy as np
     import torch
@@ -292,8 +424,18 @@ def main():
         dslash[name] = {"us": round(ms * 1e3, 2), "GBps": round(by / (ms * 1e-3) / 1e9, 1),
                         "GFLOPs": round(P.DSLASH_FLOP_PER_SITE * Vh / (ms * 1e-3) / 1e9, 1),
                         "alg_bytes": by, "variant": "hops=%d streaming=%d" % lat.dslash_variant(Up.prec, Up.recon),
-                        "tune_us": {"%d/%d" % k: round(v, 2) for k, v in tune.items()} if tune else None}
+                        "workgroup": lat.dslash_workgroup(Up.prec, Up.recon),
+                        "tune_us": {"%d/%d/%d" % k: round(v, 2) for k, v in tune.items()} if tune else None}
         log(f"dslash {name}: {dslash[name]}")
+        if name == "f64r18":
+            dslash_f64_out = lat.unpack_vec(out).cpu().numpy()
+    # the Dslash's own link-read pattern without vectors or arithmetic (streaming
+    # FP64 x 18 links, parity 1): the achievable read rate of that pattern
+    sink = torch.zeros(2, dtype=torch.float64, device=dev)
+    lr_ms = statistics.median(event_times(lat, lambda: lat.stream_read_links(packed["f64r18"], 1, 1, sink), 20, 5))
+    link_read = {"us": round(lr_ms * 1e3, 2), "bytes": 8 * 144 * Vh,
+                 "GBps": round(8 * 144 * Vh / (lr_ms * 1e-3) / 1e9, 1)}
+    log(f"link-read pattern: {link_read}")
 
     # ---- batching workload (row a8)
     c4, c4m = li.CONFIGS["c4_24x24x24x48"], li.CONFIGS["c4_mixed"]
@@ -339,6 +481,9 @@ def main():
     flat = P.Lattice(c5["L"], device=0)
     Uf = torch.from_numpy(li.links(c5["L"], c5["kind"], c5["link_seed"], c5["c"])).to(dev)
     phi = torch.from_numpy(li.vector(c5["L"], c5["src_seed"])).to(dev)
+    if not args.no_tune:  # the Dslash variants of this lattice (the action packs its own links)
+        flat.tune_dslash(flat.pack_links(Uf, P.LGT_F64, P.LGT_R18), report=False)
+        flat.tune_dslash(flat.pack_links(Uf, P.LGT_F32, P.LGT_R12), report=False)
 
     def action_and_force():
         U = Uf.clone().requires_grad_(True)
@@ -350,13 +495,17 @@ def main():
         t2 = time.perf_counter()
         return {"S": float(S.detach()), "forward_s": t1 - t0, "backward_s": t2 - t1, "grad_norm": float(U.grad.norm())}
 
+    last_x = {}
+
     def solves():
         out = {}
-        _, out["fp64"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
-        _, out["f32r12_reliable"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10,
-                                                 scheme=P.LGT_CG_RELIABLE, U_lo=packed["f32r12"], ru_interval=50)
-        _, out["bf16r12_refine"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10,
-                                                scheme=P.LGT_CG_REFINE, U_lo=packed["bf16r12"], inner_tol=0.1)
+        last_x["fp64"], out["fp64"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
+        last_x["f32r12_reliable"], out["f32r12_reliable"] = lat.cg_solve(
+            packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE, U_lo=packed["f32r12"],
+            ru_interval=50)
+        last_x["bf16r12_refine"], out["bf16r12_refine"] = lat.cg_solve(
+            packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_REFINE, U_lo=packed["bf16r12"],
+            inner_tol=0.1)
         if not args.no_batch:
             out["batch"] = batched()
         out["force"] = action_and_force()
@@ -385,7 +534,10 @@ def main():
     n_ru = sum(s["fp64"].updates for s in steps)
     n_it = n_hi // 2 - n_ru
     by64 = (n_it * it_pair + n_ru * ru_pair) * Vh / max(n_hi, 1)
-    gbs = by64 / (avg_ms * 1e-3) / 1e9
+    gbs_fused = by64 / (avg_ms * 1e-3) / 1e9
+    # headline: the Dslash's own algorithmic bytes, 8 links + input once + output
+    # once = 1248 B per output site, whatever epilogue the CG fuses into it
+    gbs = base * Vh / (avg_ms * 1e-3) / 1e9
     gflops = P.DSLASH_FLOP_PER_SITE * Vh / (avg_ms * 1e-3) / 1e9
 
     def summ(key):
@@ -478,7 +630,7 @@ def main():
     fd_s, fd_err = fd_check(flat, Uf, phi, c5["mass"], grads[False][2], c5["L"], c5["fd_seed"], 64)
     force["fd_64_directions"] = {"seconds": round(fd_s, 3), "max_rel_dev_from_grad": fd_err, "eps": 1e-6}
     del grads
-    small = small_configs(args)
+    small, small_sols = small_configs(args)
 
     # improved (fat + Naik) operator at 32^4, measured after the timed steps:
     # standalone Dslash per format and link-load kind, FP64 vs FP32 reliable-update CG
@@ -562,6 +714,9 @@ def main():
         Ro = torch.from_numpy(li.vector(ch["L"], ch["ro_seed"])).to(dev)
         u = li.uniform(ch["u_seed"])
         kw = dict(beta=ch["beta"], mass=ch["mass"], eps=ch["eps"], nsteps=ch["nsteps"], u=u, tol=ch["tol"])
+        if not args.no_tune:  # the trajectory packs F64 x 18 and F32 x 12 links of this lattice
+            hl.tune_dslash(hl.pack_links(U0, P.LGT_F64, P.LGT_R18), report=False)
+            hl.tune_dslash(hl.pack_links(U0, P.LGT_F32, P.LGT_R12), report=False)
         hl.hmc_trajectory(U0.clone(), P0.clone(), Re, Ro, **dict(kw, nsteps=1))  # allocate workspace
         hmc_res = {"lattice": list(ch["L"]), "beta": ch["beta"], "mass": ch["mass"], "eps": ch["eps"],
                    "nsteps": ch["nsteps"], "tol": ch["tol"]}
@@ -608,14 +763,12 @@ def main():
             log(f"routine {name}: {routines[name]}")
         torch.cuda.empty_cache()
 
-    cpu = None
+    cpu, oracle_errors = None, None
     if not args.no_cpu_baseline:
-        import oracle
-        n, el = cpu_baseline(L, U, b, args.cpu_budget)
-        cpu = {"value": round(base * Vh * n / el / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(),
-               "kind": "oracle",
-               "sample": f"{n} FP64 D_oe applications of the C oracle (OpenMP) at {'x'.join(map(str, L))} "
-                         f"in {el:.1f} s; algorithmic bytes of a plain Dslash (1248 B/site)"}
+        gpu_results = {"x32": {k: v.cpu().numpy() for k, v in last_x.items()}, "dslash_in": b,
+                       "dslash_out": dslash_f64_out, "small": small_sols, "fp64_iters": cg["fp64"]["iters"]}
+        cpu, oracle_errors = cpu_leg(L, U, b, args.mass, args.cpu_budget, gpu_results)
+        log(f"cpu leg: {cpu}; oracle errors: {oracle_errors}")
 
     traffic = measured_traffic()
     line = {
@@ -631,12 +784,17 @@ def main():
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic,
-                     "kernel": "k_dslash<LinkF64R18,*> inside the FP64 CG: plain D_oe (1248 B/site) and "
-                               "D_eo with 4m^2 p and <p,Ap> (1296 B/site)",
-                     "alg_bytes_per_launch": round(by64), "alg_bytes_per_site": round(by64 / Vh, 1),
-                     "avg_launch_us": round(avg_ms * 1e3, 2),
-                     "launches_timed": n_hi, "measured_ceiling_GBps": ceil,
-                     "frac_of_measured_read_ceiling": round(gbs / ceil["read_GBps"], 4)},
+                     "kernel": "k_dslash<LinkF64R18,*> inside the FP64 CG: plain D_oe and D_eo with the "
+                               "4m^2 p epilogue and <p,Ap> partials",
+                     "alg_bytes_per_site": base, "alg_bytes_per_launch": base * Vh,
+                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": n_hi,
+                     "with_epilogue_reads": {"bytes_per_site": round(by64 / Vh, 1), "GBps": round(gbs_fused, 1),
+                                             "frac": round(gbs_fused / HBM_PEAK_GBS, 4)},
+                     "measured_ceiling_GBps": {"read_1GiB_single_stream": ceil["read_GBps"],
+                                               "copy_1GiB": ceil["copy_GBps"],
+                                               "dslash_link_read_pattern": link_read["GBps"]},
+                     "frac_of_link_read_pattern": round(gbs / link_read["GBps"], 4),
+                     "link_read_pattern": link_read},
         "cg": cg,
         "batch": batch,
         "mrhs_tune": mrhs_tune,
@@ -647,6 +805,7 @@ def main():
         "dslash_standalone": dslash,
         "small_configs": small,
         "cpu_baseline": cpu,
+        "oracle_errors": oracle_errors,
         "paper_context": paper_context(),
     }
     print(json.dumps(line), flush=True)

@@ -134,16 +134,27 @@ lgt_status lgt_set_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int
                                   int32_t streaming);
 lgt_status lgt_get_dslash_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *hops_per_group,
                                   int32_t *streaming);
+/* Workgroup size of the Dslash for one link format: 64, 128 or 256 sites
+ * (default 256; LGT_ERR_ARG otherwise). A lattice with fewer 256-site
+ * workgroups than the chip has CUs (16^4: 128 for 256 CUs) reaches more CUs
+ * with smaller ones. Speed only: the operator is the same; the per-workgroup
+ * partial sums of the CG's dot products then group differently, so solves
+ * agree to rounding rather than bit for bit across sizes. */
+lgt_status lgt_set_dslash_workgroup(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t threads);
+lgt_status lgt_get_dslash_workgroup(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *threads);
 /* Time every variant on U as the CG runs it (1 warm-up and 5 timed pairs of a
  * plain D_oe and a D_eo with the 4m^2 p epilogue and its partial sums, on the
  * context's stream; synchronises) and keep, for U's format, the first variant
  * in the order below whose time is within 1 % of the fastest. times_us (host,
- * may be NULL) receives the mean launch time of the variants (hops,
- * streaming) = (8,1) (2,1) (1,1) (4,1) (8,0) (2,0) (1,0) (4,0). When the environment variable LGT_TUNE_CACHE names a file and
- * times_us is NULL, a cached choice for (device architecture, lattice,
- * format) is used without timing unless LGT_TUNE=force; new results are
- * appended to that file. */
-lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[8]);
+ * may be NULL; 24 entries) receives the mean launch time of the variants
+ * (hops, streaming) = (8,1) (2,1) (1,1) (4,1) (8,0) (2,0) (1,0) (4,0), first
+ * with 256-site workgroups, then 128, then 64; the smaller workgroups are
+ * timed only on lattices with fewer than 1024 workgroups of 256 sites (-1
+ * elsewhere: there they only add partial sums to the CG). When the environment variable
+ * LGT_TUNE_CACHE names a file and times_us is NULL, a cached choice for
+ * (device architecture, lattice, format) is used without timing unless
+ * LGT_TUNE=force; new results are appended to that file. */
+lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[24]);
 
 /* ---- geometry export (Sec. 1: unique 4-tuple per site, 8 neighbours) ------- */
 
@@ -533,6 +544,17 @@ lgt_status lgt_stream_copy(lgt_ctx *ctx, const void *src, void *dst, size_t byte
  * improbable data pattern). The read-only ceiling for read-dominated kernels
  * such as the Dslash. Asynchronous. */
 lgt_status lgt_stream_read(lgt_ctx *ctx, const void *src, size_t bytes, void *sink);
+
+/* The Dslash's link reads alone: for every site of out_parity, its four
+ * forward links and the four backward links U_mu(x - mu), with the Dslash's
+ * workgroup order and load grouping (all of a site's loads issued together),
+ * streaming (1) or cached (0) loads, and no vector reads, arithmetic or output
+ * (sink: 8 bytes of device memory written only for one improbable sum). Its
+ * rate, 8 links per site over the time, is the read ceiling of the Dslash's
+ * own link-access pattern, which the Dslash's bandwidth is compared with
+ * (Sec. 5: the routines are bound by memory traffic). Asynchronous. */
+lgt_status lgt_stream_read_links(lgt_ctx *ctx, const lgt_links *U, int32_t out_parity, int32_t streaming,
+                                 void *sink);
 
 #ifdef __cplusplus
 }

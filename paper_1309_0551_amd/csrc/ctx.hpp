@@ -25,6 +25,9 @@ struct lgt_ctx {
     // and stream beyond 384 MB (lgt_create sets ntl from the field size).
     int hpi[lgt::FMT_COUNT] = {2, 2, 8, 8, 8};
     int ntl[lgt::FMT_COUNT] = {1, 1, 0, 0, 0};
+    // Dslash workgroup size per link format (64, 128 or 256 sites): small
+    // lattices have too few 256-site workgroups to reach every CU
+    int dbs[lgt::FMT_COUNT] = {256, 256, 256, 256, 256};
     // multi-RHS Dslash: engine (0 lane per RHS, 1 four-lane VALU, 2 four-lane
     // MFMA) last set for all cases, and the variant per (link format, log2 N):
     // engine and groups of four lanes per site. Set by lgt_set_mrhs_engine,
@@ -80,6 +83,9 @@ struct DeviceScope {
 lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
                     const double *b, double *x, lgt_cg_result *res, const lgt_links *U3hi = nullptr,
                     const lgt_links *U3lo = nullptr);
+
+// launch geometry of the one-link / improved Dslash for link format f
+inline Launch dslash_launch(const lgt_ctx *c, Fmt f) { return site_launch(c->g.Vh, c->dbs[f]); }
 
 // the fermion force given its two native scratch vectors (X and Y = D_oe X)
 lgt_status force_run(lgt_ctx *c, const lgt_links *U, Fmt f, const double *X, double scale, double *G, double *Xn,

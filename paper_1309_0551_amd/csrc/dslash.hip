@@ -29,16 +29,16 @@ namespace lgt {
 // per site from two link fields of the same format.
 //
 // HPI = 4 is the direction loop of HPI = 2 with the input vector staged in LDS:
-// a workgroup's 256 output sites are consecutive cb indices, whole x rows
-// (Lx/2 sites each) of a few y values, so their x and y neighbours of the
-// other parity lie in the cb range [first - Lx/2, last + Lx/2]. The workgroup
-// copies that range (256 + Lx sites) into LDS once with coalesced loads; every
-// hop whose neighbour falls in it reads LDS, the others (z and t, and wrapped
-// x/y hops) read global memory.
+// a workgroup's bs output sites (64, 128 or 256) are consecutive cb indices,
+// x rows (Lx/2 sites each) of a few y values, so their x and y neighbours of
+// the other parity lie in the cb range [first - Lx/2, last + Lx/2]. The
+// workgroup copies that range (bs + Lx sites) into LDS once with coalesced
+// loads; every hop whose neighbour falls in it reads LDS, the others (z and t,
+// and wrapped x/y hops) read global memory.
 extern __shared__ __align__(16) unsigned char lds_dyn[];
 
-// sites of the staged cb range of one workgroup
-__host__ __device__ __forceinline__ int staged_sites(const Geom &g) { return kBS + 2 * g.hx; }
+// sites of the staged cb range of a workgroup of bs sites
+__host__ __device__ __forceinline__ int staged_sites(const Geom &g, int bs) { return bs + 2 * g.hx; }
 
 template <class LF, int EPI, int HPI, bool NTL>
 __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
@@ -47,13 +47,14 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
     using VF = VecFmt<T>;
     using S2 = typename VF::store_t;
     if (!gate_open(a.gate, a.st)) return;
+    const int bs = (int)blockDim.x; // 64, 128 or 256 sites per workgroup
     const int blk = xcd_block(blockIdx.x, a.l.nblk_pad);
-    const int cb = blk * kBS + threadIdx.x;
+    const int cb = blk * bs + threadIdx.x;
     const size_t Vh = (size_t)a.g.Vh;
-    [[maybe_unused]] const int s0 = blk * kBS - a.g.hx, ns = staged_sites(a.g);
+    [[maybe_unused]] const int s0 = blk * bs - a.g.hx, ns = staged_sites(a.g, bs);
     [[maybe_unused]] S2 *lds = (S2 *)lds_dyn; // [3][ns]
     if constexpr (HPI == 4) {
-        for (int i = threadIdx.x; i < ns; i += kBS) {
+        for (int i = threadIdx.x; i < ns; i += bs) {
             const int n = s0 + i;
             if (n >= 0 && n < a.g.Vh) {
 #pragma unroll
@@ -222,8 +223,9 @@ static void launch_k(K kernel, dim3 grid, dim3 block, size_t shm, hipStream_t s,
 template <class LF, int HPI, bool NTL>
 static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    const dim3 grid(a.l.nblk_pad), block(kBS);
-    const size_t shm = HPI == 4 ? (size_t)3 * staged_sites(a.g) * sizeof(typename VecFmt<typename LF::real>::store_t) : 0;
+    const dim3 grid(a.l.nblk_pad), block(a.l.bs);
+    const size_t shm =
+        HPI == 4 ? (size_t)3 * staged_sites(a.g, a.l.bs) * sizeof(typename VecFmt<typename LF::real>::store_t) : 0;
     switch (epi) {
     case EPI_PLAIN: launch_k(k_dslash<LF, EPI_PLAIN, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_A: launch_k(k_dslash<LF, EPI_A, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
@@ -256,7 +258,7 @@ static hipError_t launch_hpi_ntl(int epi, const DslashArgs &a, hipStream_t s, hi
     case 2: return launch_fmt<LF, 2, NTL>(epi, a, s, e0, e1);
     case 4:
         // the staged range must fit the LDS budget of a workgroup
-        if (staged_sites(a.g) > kMaxStagedSites) return launch_fmt<LF, 2, NTL>(epi, a, s, e0, e1);
+        if (staged_sites(a.g, a.l.bs) > kMaxStagedSites) return launch_fmt<LF, 2, NTL>(epi, a, s, e0, e1);
         return launch_fmt<LF, 4, NTL>(epi, a, s, e0, e1);
     case 8: return launch_fmt<LF, 8, NTL>(epi, a, s, e0, e1);
     default: return hipErrorInvalidValue;
@@ -276,6 +278,7 @@ static hipError_t launch_hpi(int epi, const DslashArgs &a, hipStream_t s, hipEve
 
 hipError_t launch_dslash(Fmt f, int epi, const DslashArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
+    if (!dslash_bs_ok(a.l.bs) || a.l.nblk_pad % 8 || a.l.nblk_pad * a.l.bs < a.g.Vh) return hipErrorInvalidValue;
     switch (f) {
     case F64R18: return launch_hpi<LinkF64R18>(epi, a, s, e0, e1);
     case F64R12: return launch_hpi<LinkF64R12>(epi, a, s, e0, e1);

@@ -58,15 +58,20 @@ enum Fin { FIN_NONE = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_RU = 3, FIN_INIT = 4
 struct Launch {
     int nblk;     // workgroups doing work
     int nblk_pad; // launched (multiple of 8 for the XCD remap)
+    int bs;       // threads (sites) per workgroup: 64, 128 or 256
 };
 
-inline Launch site_launch(int Vh)
+// one thread per site, bs sites per workgroup (the Dslash's workgroup size is a
+// tuned choice per link format; the vector kernels use kBS)
+inline Launch site_launch(int Vh, int bs = kBS)
 {
     Launch l;
-    l.nblk = (Vh + kBS - 1) / kBS;
+    l.bs = bs;
+    l.nblk = (Vh + bs - 1) / bs;
     l.nblk_pad = (l.nblk + 7) / 8 * 8;
     return l;
 }
+inline bool dslash_bs_ok(int bs) { return bs == 64 || bs == 128 || bs == 256; }
 
 // ---- Dslash family ------------------------------------------------------
 enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3 };

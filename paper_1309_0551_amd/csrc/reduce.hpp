@@ -1,10 +1,10 @@
 // reduce.hpp -- deterministic FP64 reductions and the solver's scalar steps.
 //
 // Each workgroup reduces its values (wavefront butterfly over 64 lanes, then
-// the 4 wave sums in LDS) into one partial per workgroup; the last workgroup
-// to finish (device-scope counter) sums the partials in index order. The
-// result does not depend on which workgroup finishes last, so repeated runs
-// give bit-identical scalars.
+// the 4 wave sums in LDS) into one partial per workgroup, written with a plain
+// store; a later kernel (the one-workgroup finalize, or every workgroup of the
+// CG update for alpha) sums the partials in index order. The order is fixed,
+// so repeated runs give bit-identical scalars.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -22,8 +22,8 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kBS / 64; i++) s += lds[i];
+        const int nw = (int)(blockDim.x >> 6); // waves of this workgroup (<= kBS / 64)
+        for (int i = 0; i < nw; i++) s += lds[i];
     }
     __syncthreads();
     return s;

@@ -77,7 +77,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     const Geom g = c->g;
     const int Vh = g.Vh;
     const hipStream_t s = c->stream;
-    const Launch l = site_launch(Vh);
+    const Launch l = site_launch(Vh); // vector kernels
     const int scheme = p->scheme;
     const bool mixed = scheme != SCH_FP64;
 
@@ -106,9 +106,13 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     void *Ap = workspace(c, "cg.Ap", vlo);
     void *t = workspace(c, "cg.t", vlo);
     void *xlo = mixed ? workspace(c, "cg.xlo", vlo) : x64;
+    // Dslash launches of the two link formats (their workgroup sizes are
+    // per-format choices, so their partial-sum counts may differ)
+    const Launch lhi = dslash_launch(c, fhi), llo = dslash_launch(c, flo);
     // two partial-sum buffers: the update reads D_eo's while writing its own
-    double *partials = (double *)workspace(c, "cg.partials", 2 * sizeof(double) * (size_t)l.nblk_pad);
-    double *partials2 = partials ? partials + l.nblk_pad : nullptr;
+    const size_t np1 = (size_t)std::max(std::max(lhi.nblk_pad, llo.nblk_pad), l.nblk_pad);
+    double *partials = (double *)workspace(c, "cg.partials", sizeof(double) * (np1 + (size_t)l.nblk_pad));
+    double *partials2 = partials ? partials + np1 : nullptr;
     CgState *dst = (CgState *)workspace(c, "cg.state", sizeof(CgState));
     CgState *host = (CgState *)pinned(c, 3 * sizeof(CgState));
     if (!b64 || !x64 || !t64 || !q64 || !r || !pp || !Ap || !t || !xlo || !partials || !dst || !host)
@@ -134,7 +138,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.g = g;
         a.par = par;
         a.gate = gate;
-        a.l = l;
+        a.l = f == fhi ? lhi : llo;
         a.aux0 = aux0;
         a.aux1 = aux1;
         a.out_lo = out_lo;
@@ -161,9 +165,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     va.Vh = Vh;
     va.l = l;
     // partial slots from nblk on belong to idle workgroups (zeros): sum nblk
-    const bool fuse_alpha = l.nblk <= fuse_alpha_max();
+    // (the iteration's D_eo runs in the inner format's launch geometry)
+    const bool fuse_alpha = llo.nblk <= fuse_alpha_max();
     va.parts_in = fuse_alpha ? partials : nullptr;
-    va.nparts_in = fuse_alpha ? l.nblk : 0;
+    va.nparts_in = fuse_alpha ? llo.nblk : 0;
     va.partials = partials2;
     va.st = dst;
     va.gate = GATE_ITER;
@@ -188,7 +193,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         else
             e = D(fhi, EPI_RES, LGT_EVEN, Uhi->ptr, t64, r, gate, x64, b64, nullptr, r0, r1);
         if (e != hipSuccess) return e;
-        return F(partials, fin, gate, l.nblk);
+        return F(partials, fin, gate, lhi.nblk);
     };
 
     LGT_HIP(hipEventRecord(evs.ev[0], s));
@@ -250,7 +255,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                       ev(ts, 2 * i, false)));
             LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
                       ev(ts, 2 * i + 1, false)));
-            if (!fuse_alpha) LGT_HIP(F(partials, FIN_ALPHA, GATE_ITER, l.nblk));
+            if (!fuse_alpha) LGT_HIP(F(partials, FIN_ALPHA, GATE_ITER, llo.nblk));
             LGT_HIP(launch_update(lo_is_f64, va, s));
             LGT_HIP(F(partials2, FIN_UPDATE, GATE_ITER, l.nblk));
         }

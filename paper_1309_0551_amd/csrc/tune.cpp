@@ -2,9 +2,10 @@
 //
 // The variants differ in how many hops' loads are issued together (8, 2 or
 // 1: more loads in flight per thread against fewer registers and more waves
-// per SIMD) and in whether link loads stream past the caches or are cached
+// per SIMD), in whether link loads stream past the caches or are cached
 // (a link field that fits in the Infinity Cache can then be served from it on
-// the next Dslash). Which wins depends on the format and the lattice, so it is
+// the next Dslash), and in the workgroup size (256, 128 or 64 sites: a small
+// lattice has fewer 256-site workgroups than the chip has CUs). Which wins depends on the format and the lattice, so it is
 // timed on the caller's own link field and kept in the context; with the
 // environment variable LGT_TUNE_CACHE naming a file, results persist per
 // (device architecture, lattice, format) and later contexts reuse them
@@ -34,6 +35,8 @@ namespace {
 constexpr int kNumVariants = 8;
 const int kHops[kNumVariants] = {8, 2, 1, 4, 8, 2, 1, 4};
 const int kStream[kNumVariants] = {1, 1, 1, 1, 0, 0, 0, 0};
+constexpr int kNumBs = 3;
+const int kBsList[kNumBs] = {256, 128, 64};
 
 const char *fmt_name(Fmt f)
 {
@@ -92,16 +95,40 @@ void cache_store_pair(const std::string &key, int a, int b, const double *t, int
     out << "\n";
 }
 
-// "<key> <hops> <stream> ..." ; the last matching line wins
-bool cache_lookup(const std::string &key, int *hops, int *stream)
+// "<key> <hops> <stream> wg<threads> us:..." ; the last matching line wins (a
+// line without the workgroup field is a 256-thread choice)
+bool cache_lookup(const std::string &key, int *hops, int *stream, int *bs)
 {
-    return cache_lookup_pair(key, hops, stream,
-                             [](int h, int st) { return (h == 1 || h == 2 || h == 4 || h == 8) && (st == 0 || st == 1); });
+    const char *path = std::getenv("LGT_TUNE_CACHE");
+    if (!path) return false;
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != ' ') continue;
+        std::istringstream rest(line.substr(key.size() + 1));
+        int h = -1, st = -1, w = 256;
+        std::string tok;
+        rest >> h >> st >> tok;
+        if (tok.compare(0, 2, "wg") == 0) w = std::atoi(tok.c_str() + 2);
+        if ((h == 1 || h == 2 || h == 4 || h == 8) && (st == 0 || st == 1) && dslash_bs_ok(w)) {
+            *hops = h;
+            *stream = st;
+            *bs = w;
+            found = true;
+        }
+    }
+    return found;
 }
 
-void cache_store(const std::string &key, int hops, int stream, const double *t)
+void cache_store(const std::string &key, int hops, int stream, int bs, const double *t, int n)
 {
-    cache_store_pair(key, hops, stream, t, kNumVariants);
+    const char *path = std::getenv("LGT_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream out(path, std::ios::app);
+    out << key << " " << hops << " " << stream << " wg" << bs << " us:";
+    for (int i = 0; i < n; i++) out << (i ? "," : "") << t[i];
+    out << "\n";
 }
 
 } // namespace
@@ -122,6 +149,28 @@ lgt_status lgt_set_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32
     return LGT_OK;
 }
 
+lgt_status lgt_set_dslash_workgroup(lgt_ctx *c, int32_t prec, int32_t recon, int32_t threads)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    if (!dslash_bs_ok(threads)) return fail(LGT_ERR_ARG, "workgroup size must be 64, 128 or 256");
+    c->dbs[f] = threads;
+    return LGT_OK;
+}
+
+lgt_status lgt_get_dslash_workgroup(lgt_ctx *c, int32_t prec, int32_t recon, int32_t *threads)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (!threads) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    *threads = c->dbs[f];
+    return LGT_OK;
+}
+
 lgt_status lgt_get_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32_t *hops, int32_t *streaming)
 {
     clear_error();
@@ -134,7 +183,7 @@ lgt_status lgt_get_dslash_variant(lgt_ctx *c, int32_t prec, int32_t recon, int32
     return LGT_OK;
 }
 
-lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[8])
+lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[24])
 {
     clear_error();
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
@@ -146,15 +195,16 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[8])
     const char *force = std::getenv("LGT_TUNE");
     const bool forced = force && std::strcmp(force, "force") == 0;
     if (!forced && !times_us) {
-        int h, s;
-        if (cache_lookup(key, &h, &s)) {
+        int h, s, w;
+        if (cache_lookup(key, &h, &s, &w)) {
             c->hpi[f] = h;
             c->ntl[f] = s;
+            c->dbs[f] = w;
             return LGT_OK;
         }
     }
     const size_t vb = (size_t)c->g.Vh * (fmt_is_f64(f) ? 48 : 24);
-    const Launch l = site_launch(c->g.Vh);
+    const Launch l = site_launch(c->g.Vh, 64); // the most partial sums of any workgroup size
     void *in = workspace(c, "tune.in", vb);
     void *out = workspace(c, "tune.out", vb);
     void *ap = workspace(c, "tune.ap", vb);
@@ -177,7 +227,8 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[8])
     a.l = l;
     a.m4 = 0.04;
     a.partials = parts;
-    double t[kNumVariants] = {};
+    constexpr int kN = kNumVariants * kNumBs;
+    double t[kN] = {};
     double best_t = 1e300;
     const int reps = 5;
     hipError_t e = hipSuccess;
@@ -196,9 +247,17 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[8])
         a.aux0 = in;
         return launch_dslash(f, EPI_A, a, c->stream);
     };
-    for (int i = 0; i < kNumVariants && e == hipSuccess; i++) {
-        a.hpi = kHops[i];
-        a.ntl = kStream[i];
+    // Smaller workgroups only pay where 256-site ones are too few to keep every
+    // CU busy; elsewhere they only multiply the CG's per-workgroup partial
+    // sums (which the update kernel re-sums in every workgroup), so they are
+    // timed only below 1024 workgroups of 256 sites (4 per CU).
+    const bool small = site_launch(c->g.Vh).nblk < 1024;
+    for (int i = 0; i < kN; i++) t[i] = -1.0;
+    for (int i = 0; i < kN && e == hipSuccess; i++) {
+        if (kBsList[i / kNumVariants] != 256 && !small) continue;
+        a.hpi = kHops[i % kNumVariants];
+        a.ntl = kStream[i % kNumVariants];
+        a.l = site_launch(c->g.Vh, kBsList[i / kNumVariants]);
         e = pair();
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
         for (int r = 0; r < reps && e == hipSuccess; r++) e = pair();
@@ -215,12 +274,13 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[8])
     // the first variant in list order within 1 % of the fastest: timing noise
     // alone does not flip the choice between near-equal variants
     int best = 0;
-    while (best < kNumVariants - 1 && t[best] > 1.01 * best_t) best++;
-    c->hpi[f] = kHops[best];
-    c->ntl[f] = kStream[best];
-    cache_store(key, kHops[best], kStream[best], t);
+    while (best < kN - 1 && (t[best] < 0.0 || t[best] > 1.01 * best_t)) best++;
+    c->hpi[f] = kHops[best % kNumVariants];
+    c->ntl[f] = kStream[best % kNumVariants];
+    c->dbs[f] = kBsList[best / kNumVariants];
+    cache_store(key, c->hpi[f], c->ntl[f], c->dbs[f], t, kN);
     if (times_us)
-        for (int i = 0; i < kNumVariants; i++) times_us[i] = t[i];
+        for (int i = 0; i < kN; i++) times_us[i] = t[i];
     return LGT_OK;
 }
 

@@ -143,10 +143,13 @@ def _setup(l):
         "lgt_force_noalloc": (st, [vp, C.POINTER(_Links), vp, C.c_double, vp]),
         "lgt_set_dslash_variant": (st, [vp, i32, i32, i32, i32]),
         "lgt_get_dslash_variant": (st, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "lgt_set_dslash_workgroup": (st, [vp, i32, i32, i32]),
+        "lgt_get_dslash_workgroup": (st, [vp, i32, i32, C.POINTER(C.c_int32)]),
         "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),
         "lgt_apply_normal": (st, [vp, C.POINTER(_Links), C.c_double, vp, vp, C.POINTER(C.c_double)]),
         "lgt_stream_copy": (st, [vp, vp, vp, C.c_size_t]),
         "lgt_stream_read": (st, [vp, vp, C.c_size_t, vp]),
+        "lgt_stream_read_links": (st, [vp, C.POINTER(_Links), i32, i32, vp]),
         "lgt_pack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
         "lgt_unpack_vec_mrhs": (st, [vp, i32, i32, vp, vp]),
         "lgt_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, i32, vp, vp]),
@@ -294,6 +297,15 @@ class Lattice:
         _check(lib().lgt_get_dslash_variant(self._ctx, prec, recon, C.byref(h), C.byref(s)))
         return int(h.value), int(s.value)
 
+    def set_dslash_workgroup(self, prec: int, recon: int, threads: int):
+        """Dslash workgroup size for this link format: 64, 128 or 256 sites."""
+        _check(lib().lgt_set_dslash_workgroup(self._ctx, prec, recon, int(threads)))
+
+    def dslash_workgroup(self, prec: int, recon: int) -> int:
+        w = C.c_int32()
+        _check(lib().lgt_get_dslash_workgroup(self._ctx, prec, recon, C.byref(w)))
+        return int(w.value)
+
     def set_mrhs_engine(self, engine: int):
         """Multi-RHS Dslash engine: LGT_MRHS_LANE, LGT_MRHS_VALU4 or LGT_MRHS_MFMA."""
         _check(lib().lgt_set_mrhs_engine(self._ctx, int(engine)))
@@ -326,17 +338,19 @@ class Lattice:
         _check(lib().lgt_tune_dslash_mrhs(self._ctx, C.byref(d), int(nrhs), t))
         return {v: t[i] for i, v in enumerate(self.MRHS_VARIANTS) if t[i] >= 0}
 
-    TUNE_VARIANTS = ((8, 1), (2, 1), (1, 1), (4, 1), (8, 0), (2, 0), (1, 0), (4, 0))
+    TUNE_VARIANTS = tuple((h, st, w) for w in (256, 128, 64)
+                          for h, st in ((8, 1), (2, 1), (1, 1), (4, 1), (8, 0), (2, 0), (1, 0), (4, 0)))
 
     def tune_dslash(self, U: "PackedLinks", report: bool = True):
-        """Time every variant on U and keep the fastest; returns {(hops, streaming): us} or None."""
+        """Time every variant on U and keep the fastest; returns
+        {(hops, streaming, workgroup size): us} or None."""
         d = U.desc()
         if not report:
             _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), None))
             return None
         t = (C.c_double * len(self.TUNE_VARIANTS))()
         _check(lib().lgt_tune_dslash(self._ctx, C.byref(d), t))
-        return {v: t[i] for i, v in enumerate(self.TUNE_VARIANTS)}
+        return {v: t[i] for i, v in enumerate(self.TUNE_VARIANTS) if t[i] >= 0}
 
     # -- helpers
     def _dev(self, t: torch.Tensor, dtype=None, shape=None, what="tensor"):
@@ -568,6 +582,14 @@ class Lattice:
             raise ValueError("sink must hold 16 bytes")
         _check(lib().lgt_stream_read(self._ctx, self._dev(src, None, None, "src"),
                                      src.numel() * src.element_size(), self._dev(sink, None, None, "sink")))
+
+    def stream_read_links(self, U: PackedLinks, out_parity: int, streaming: int, sink: torch.Tensor):
+        """Read the 8 links of every site of out_parity as the Dslash does, nothing else (probe)."""
+        if sink.numel() * sink.element_size() < 8:
+            raise ValueError("sink must hold 8 bytes")
+        d = U.desc()
+        _check(lib().lgt_stream_read_links(self._ctx, C.byref(d), int(out_parity), int(streaming),
+                                           self._dev(sink, None, None, "sink")))
 
     def cdot(self, a: torch.Tensor, b: torch.Tensor) -> complex:
         if a.numel() != b.numel() or a.numel() % 2:

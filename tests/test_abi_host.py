@@ -155,6 +155,9 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_unpack_links": (None, None, 0, 18, None),
         "lgt_action_phi_grad": (None, None, 1.0, None),
         "lgt_force_noalloc": (None, None, None, 1.0, None),
+        "lgt_stream_read_links": (None, None, 1, 1, None),
+        "lgt_set_dslash_workgroup": (None, 0, 18, 64),
+        "lgt_get_dslash_workgroup": (None, 0, 18, C.byref(i)),
     }
     for name, args in calls.items():
         assert getattr(l, name)(*args) == -1, name

@@ -235,30 +235,51 @@ def test_tune_dslash_picks_a_variant(dev, tmp_path, monkeypatch):
     with P.Lattice(L) as lat:
         Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
         t = lat.tune_dslash(Up)
+        # 8^4: 8 workgroups of 256 sites, so the 128- and 64-site ones are timed too
         assert set(t) == set(P.Lattice.TUNE_VARIANTS) and all(v > 0 for v in t.values())
         # the first variant in list order within 1 % of the fastest
         fastest = min(t.values())
         best = next(v for v in P.Lattice.TUNE_VARIANTS if t[v] <= 1.01 * fastest)
-        assert lat.dslash_variant(P.LGT_F32, P.LGT_R12) == best
+        assert lat.dslash_variant(P.LGT_F32, P.LGT_R12) + (lat.dslash_workgroup(P.LGT_F32, P.LGT_R12),) == best
     assert "f32r12" in cache.read_text()
     with P.Lattice(L) as lat2:
-        other = (8, 1) if best != (8, 1) else (1, 0)
+        other = (8, 1) if best[:2] != (8, 1) else (1, 0)
         lat2.set_dslash_variant(P.LGT_F32, P.LGT_R12, *other)
+        lat2.set_dslash_workgroup(P.LGT_F32, P.LGT_R12, 128 if best[2] != 128 else 64)
         lat2.tune_dslash(Up, report=False)  # cached: no timing
-        assert lat2.dslash_variant(P.LGT_F32, P.LGT_R12) == best
+        assert lat2.dslash_variant(P.LGT_F32, P.LGT_R12) + (lat2.dslash_workgroup(P.LGT_F32, P.LGT_R12),) == best
 
 
-@pytest.mark.parametrize("L,f32r18,f32r12,bf16r12", [((32, 32, 32, 32), 0, 0, 0), ((40, 40, 40, 40), 1, 1, 0),
-                                                       ((48, 48, 48, 48), 1, 1, 1), ((24, 24, 24, 48), 0, 0, 0)])
-def test_default_link_loads_follow_field_size(dev, L, f32r18, f32r12, bf16r12):
+def test_tune_dslash_large_lattice_keeps_256(dev):
+    """At 32^4 (2048 workgroups of 256 sites) only 256-site workgroups are timed."""
+    L = (32, 32, 32, 32)
+    with P.Lattice(L) as lat:
+        U = torch.zeros((4, lat.V, 3, 3, 2), dtype=torch.float64, device=dev)
+        U[..., 0, 0, 0] = U[..., 1, 1, 0] = U[..., 2, 2, 0] = 1.0
+        Up = lat.pack_links(U, P.LGT_BF16, P.LGT_R12)
+        del U
+        t = lat.tune_dslash(Up)
+        assert set(t) == {v for v in P.Lattice.TUNE_VARIANTS if v[2] == 256}
+        assert lat.dslash_workgroup(P.LGT_BF16, P.LGT_R12) == 256
+
+
+@pytest.mark.parametrize("L,f32r18,f32r12,bf16r12,f64", [((32, 32, 32, 32), 0, 0, 0, (2, 1)),
+                                                           ((40, 40, 40, 40), 1, 1, 0, (2, 1)),
+                                                           ((48, 48, 48, 48), 1, 1, 1, (2, 1)),
+                                                           ((24, 24, 24, 48), 0, 0, 0, (2, 1)),
+                                                           ((16, 16, 16, 16), 0, 0, 0, (8, 0)),
+                                                           ((16, 16, 16, 32), 0, 0, 0, (8, 0))])
+def test_default_link_loads_follow_field_size(dev, L, f32r18, f32r12, bf16r12, f64):
     """FP32/BF16 link loads default to cached while the field (mostly) fits
     in the 256 MB Infinity Cache -- up to 384 MB -- and to streaming beyond;
-    FP64 fields stream."""
+    FP64 x 18 fields up to 128 MB take 8 hops with cached loads, larger ones
+    2 hops streaming; every format starts with 256-site workgroups."""
     with P.Lattice(L) as lat:
         assert lat.dslash_variant(P.LGT_F32, P.LGT_R18)[1] == f32r18
         assert lat.dslash_variant(P.LGT_F32, P.LGT_R12)[1] == f32r12
         assert lat.dslash_variant(P.LGT_BF16, P.LGT_R12)[1] == bf16r12
-        assert lat.dslash_variant(P.LGT_F64, P.LGT_R18)[1] == 1
+        assert lat.dslash_variant(P.LGT_F64, P.LGT_R18) == f64
+        assert lat.dslash_workgroup(P.LGT_F64, P.LGT_R18) == 256
 
 
 def test_dslash_full_size_32(dev):

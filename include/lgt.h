@@ -492,7 +492,10 @@ typedef struct {
  * nprob <= 64; the sum over problems of nrhs rounded up to a power of two
  * is <= 256 (a padding right-hand side costs the work of a real one but
  * converges at once and is never reported); a context may appear in several
- * problems. Synchronous. */
+ * problems. Every grid-barrier wait inside the launch is bounded (about 2^21
+ * polls, seconds; the environment variable LGT_BATCH_SPIN_LIMIT sets another
+ * bound in [1, 2^30]): a wait that runs out ends the launch in every
+ * workgroup and the call returns LGT_ERR_DEVICE. Synchronous. */
 lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p);
 
 /* ---- reductions ------------------------------------------------------------ */

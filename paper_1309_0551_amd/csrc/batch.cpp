@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -270,7 +271,17 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     ha->max_iter = p->max_iter;
     ha->tol = p->tol;
     ha->inner = p->scheme == LGT_CG_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
-    ha->spin_limit = 1u << 21; // seconds of polling: far beyond any phase of a valid launch
+    // Bound on the polls of one grid-barrier wait: seconds of polling, far
+    // beyond any phase of a valid launch. LGT_BATCH_SPIN_LIMIT overrides it (a
+    // tiny limit makes the barriers time out: every workgroup then leaves the
+    // kernel and the call reports LGT_ERR_DEVICE, which tests of that path use).
+    ha->spin_limit = 1u << 21;
+    if (const char *e = std::getenv("LGT_BATCH_SPIN_LIMIT")) {
+        char *end = nullptr;
+        const long v = std::strtol(e, &end, 10);
+        if (!end || *end || v < 1 || v > (1L << 30)) return fail(LGT_ERR_ARG, "LGT_BATCH_SPIN_LIMIT must be in [1, 2^30]");
+        ha->spin_limit = (unsigned int)v;
+    }
     CgState *states = (CgState *)workspace(c0, "batch.states", sizeof(CgState) * (size_t)total_rhs);
     double *rows = (double *)workspace(c0, "batch.rows", 2 * sizeof(double) * (size_t)grid * total_rhs);
     BatchCtl *ctl = (BatchCtl *)workspace(c0, "batch.ctl", sizeof(BatchCtl));

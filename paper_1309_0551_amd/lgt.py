@@ -8,10 +8,12 @@ fields, float32 otherwise); packed links as uint8 tensors.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import dataclasses
 import os
 import re
+import weakref
 
 import torch
 
@@ -253,6 +255,23 @@ class CgResult:
     dslash_timed_lo: int
 
 
+# Contexts still open when the interpreter exits are destroyed from an atexit
+# hook, in order, while the HIP runtime is fully alive: left to garbage
+# collection at shutdown, lgt_destroy (a stream synchronise and hipFree of the
+# workspace) could run after the runtime or a profiler attached to it has
+# begun tearing down.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for lat in list(_live):
+        try:
+            lat.close()
+        except Exception:
+            pass
+
+
 class Lattice:
     """One lattice geometry on one GPU: an lgt_ctx bound to torch's current stream."""
 
@@ -266,11 +285,13 @@ class Lattice:
         self._ctx = C.c_void_p()
         _check(lib().lgt_create(C.byref(_geom(self.L, self.bc)), device, C.c_void_p(self.stream.cuda_stream),
                                 C.byref(self._ctx)))
+        _live.add(self)
 
     def close(self):
         if self._ctx:
             lib().lgt_destroy(self._ctx)
             self._ctx = C.c_void_p()
+        _live.discard(self)
 
     def __del__(self):
         try:

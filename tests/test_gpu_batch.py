@@ -333,3 +333,33 @@ def test_batch_inner_shapes(dev, nrhs, engine, groups):
     xg = xs[0].cpu().numpy()
     for j in range(nrhs):
         _check_solution(L, U, mass, bs[j], xg[j], res[0][j], tol)
+
+
+def test_batch_barrier_timeout_is_reported(dev, monkeypatch):
+    """A grid-barrier wait bounded at one poll (LGT_BATCH_SPIN_LIMIT, set on
+    the host) times out: every workgroup leaves the persistent kernel, the call
+    returns LGT_ERR_DEVICE naming the barrier, and the next call with the
+    normal bound solves the same batch."""
+    L, mass = (8, 8, 8, 8), 0.1
+    U = li.links(L, "haar", 181)
+    bs = li.vectors(L, 182, 4)
+    with P.Lattice(L) as lat:
+        Ut = torch.from_numpy(U).to(dev)
+        uh, ul = lat.pack_links(Ut, P.LGT_F64, P.LGT_R18), lat.pack_links(Ut, P.LGT_F32, P.LGT_R12)
+        probs = [(lat, uh, ul, torch.from_numpy(bs).to(dev))]
+        monkeypatch.setenv("LGT_BATCH_SPIN_LIMIT", "1")
+        with pytest.raises(P.LgtError) as ei:
+            P.cg_solve_batch(probs, mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE)
+        assert ei.value.status == -4 and "barrier" in str(ei.value)
+        torch.cuda.synchronize()
+        monkeypatch.setenv("LGT_BATCH_SPIN_LIMIT", "0")
+        with pytest.raises(P.LgtError) as ei:                  # out of range: rejected before any launch
+            P.cg_solve_batch(probs, mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE)
+        assert ei.value.status == -1
+        monkeypatch.delenv("LGT_BATCH_SPIN_LIMIT")
+        xs, res = P.cg_solve_batch(probs, mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE)
+    assert all(r.status == 0 for r in res[0])
+    x = xs[0].cpu().numpy()
+    for j in range(4):
+        r = bs[j] - oracle.apply_A(L, U, mass, x[j])
+        assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(bs[j])

@@ -596,6 +596,62 @@ def main():
                       "iters_max": max(r.iters for r in last), "updates_max": max(r.updates for r in last),
                       "true_rel_resid_max": max(r.true_rel_resid for r in last),
                       "status_all_ok": all(r.status == 0 for r in last)}
+    # batched solver: phase profile of one more solve of each batch (workgroup
+    # 0's clock inside the persistent launch), and the roofline of an iteration:
+    # per even site and right-hand side (FP32 x 12 inner links shared by the N
+    # right-hand sides), step 1 reads r and p at the neighbours once (48 B) and
+    # writes t and p' (48 B) plus 384/N B of links, step 2 reads t and p' (48 B),
+    # writes Ap (24 B) plus 384/N B of links, step 3 reads x, r, p', Ap (96 B)
+    # and writes x and r (48 B)
+    for key, probs in (("24x24x24x48_x16", big), ("mixed_8x8x8x8_12x12x12x12_16x16x16x32_x4", mixed)):
+        if args.no_batch:
+            break
+        lb0 = probs[0][0]
+        lb0.set_timing(1)
+        _, res = P.cg_solve_batch(probs, c4["mass"], tol=c4["tol"], scheme=P.LGT_CG_RELIABLE, ru_interval=50)
+        lb0.set_timing(0)
+        prof = lb0.batch_profile()
+        its = max(prof.pop("iters"), 1)
+        sec = res[0][0].seconds
+        alg = sum(lb.Vh * (int(bb.shape[0]) * (96 + 72 + 144) + 2 * 384) for lb, _, _, bb in probs)
+        per_it_us = 1e6 * sec / its
+        # the FP64 updates are amortised over the iterations; the roofline is
+        # that of the inner iteration (steps 1-3, their waits and scalar steps)
+        inner_us = 1e3 * sum(v for k, v in prof.items() if k not in ("setup_and_final", "fp64_updates")) / its
+        batch[key]["phases_us_per_iter"] = {k: round(1e3 * v / its, 2) for k, v in prof.items()}
+        batch[key]["roofline_inner_iteration"] = {
+            "bound": "hbm", "alg_bytes": alg, "us": round(inner_us, 2),
+            "achieved_GBps": round(alg / (inner_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "frac": round(alg / (inner_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "whole_iteration_us": round(per_it_us, 2)}
+        log(f"batch profile {key}: {batch[key]['phases_us_per_iter']} {batch[key]['roofline_inner_iteration']}")
+
+    # the single-RHS CG per iteration at 32^4: Dslash pair, the vector kernels
+    # and the rest (launch gaps, the reliable updates' other kernels), from one
+    # more solve per scheme with every 16th iteration timed
+    lat.set_timing(TIMING_EVERY)
+    breakdown = {}
+    for key, kw in (("fp64", dict(scheme=P.LGT_CG_FP64)),
+                    ("f32r12_reliable", dict(scheme=P.LGT_CG_RELIABLE, U_lo=packed["f32r12"], ru_interval=50))):
+        _, r = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, **kw)
+        vk = lat.cg_profile()
+        it = max(r.iters, 1)
+        if key == "fp64":
+            pair = 2e3 * r.dslash_ms_hi / max(r.dslash_timed_hi, 1)
+            ru = (r.updates * pair) / it
+        else:
+            pair = 2e3 * r.dslash_ms_lo / max(r.dslash_timed_lo, 1)
+            ru = (r.updates * 2e3 * r.dslash_ms_hi / max(r.dslash_timed_hi, 1)) / it
+        vec = {k: round(1e3 * vk[k], 2) for k in ("xpay", "update", "beta_step", "alpha_step")}
+        total = 1e6 * r.seconds / it
+        breakdown[key] = {"total_us": round(total, 2), "dslash_pair_us": round(pair, 2), **{k + "_us": v for k, v in vec.items()},
+                          "fp64_update_dslash_us_amortised": round(ru, 2),
+                          "rest_us": round(total - pair - sum(vec.values()) - ru, 2), "iters": r.iters,
+                          "host_waits": "none: the host enqueues 50 iterations ahead and polls the state one chunk behind"}
+        log(f"cg breakdown {key}: {breakdown[key]}")
+    lat.set_timing(0)
+    cg["per_iteration_breakdown"] = breakdown
+
     # differentiation: whole S and dS/dU per step, and the force kernel alone
     fs = [s["force"] for s in steps]
     Upf = flat.pack_links(Uf, P.LGT_F64, P.LGT_R18)

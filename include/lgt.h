@@ -116,6 +116,15 @@ lgt_status lgt_destroy(lgt_ctx *ctx);
  * (every = 16, say) keeps the host's event bookkeeping small. 0 = off (the
  * default); negative is LGT_ERR_ARG. */
 lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t every);
+/* The rest of a timed CG iteration: for the last lgt_cg_solve* on this context
+ * with timing on, ms[4] receives the mean kernel time (ms) per timed iteration
+ * of the vector kernels around the Dslash pair -- (0) x += alpha p with
+ * p = r + beta p, (1) the update r -= alpha Ap with the |r|^2 partials, (2)
+ * the one-workgroup step for beta and the stop tests, (3) the one-workgroup
+ * alpha step (0 where the update sums the <p, Ap> partials itself) -- and n
+ * the number of iterations timed (their Dslash pairs are in lgt_cg_result).
+ * Host only. */
+lgt_status lgt_cg_profile(lgt_ctx *ctx, double ms[4], int32_t *n);
 
 /* ---- kernel variants and autotuning ---------------------------------------- */
 
@@ -497,6 +506,17 @@ typedef struct {
  * bound in [1, 2^30]): a wait that runs out ends the launch in every
  * workgroup and the call returns LGT_ERR_DEVICE. Synchronous. */
 lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p);
+
+/* Phase profile of the last lgt_cg_solve_batch whose first problem's context
+ * had timing on (lgt_set_timing > 0): ms[9] receives the milliseconds that
+ * workgroup 0 of the persistent launch spent in (0) set-up and the final FP64
+ * step, (1) the inner D_oe step with p = r + beta p, (2) the wait at the
+ * barrier after it, (3) the inner D_eo step with <p, Ap>, (4) its barrier
+ * wait, (5) the vector update with |r|^2, (6) its barrier wait, (7) the scalar
+ * steps, (8) the FP64 reliable updates / refinement steps; iters the
+ * iterations run. A wait is the slowest workgroup's extra time plus the
+ * barrier itself. Zeros before any such solve. Host only. */
+lgt_status lgt_batch_profile(lgt_ctx *ctx, double ms[9], int32_t *iters);
 
 /* ---- reductions ------------------------------------------------------------ */
 

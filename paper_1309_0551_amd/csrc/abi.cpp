@@ -277,6 +277,15 @@ lgt_status lgt_destroy(lgt_ctx *c)
     return LGT_OK;
 }
 
+lgt_status lgt_cg_profile(lgt_ctx *c, double ms[4], int32_t *n)
+{
+    CHECK_CTX(c);
+    if (!ms || !n) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    for (int k = 0; k < 4; k++) ms[k] = c->cg_prof_ms[k];
+    *n = c->cg_prof_n;
+    return LGT_OK;
+}
+
 lgt_status lgt_set_timing(lgt_ctx *c, int32_t every)
 {
     CHECK_CTX(c);

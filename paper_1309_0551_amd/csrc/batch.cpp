@@ -287,6 +287,13 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     BatchCtl *ctl = (BatchCtl *)workspace(c0, "batch.ctl", sizeof(BatchCtl));
     BatchArgs *da = (BatchArgs *)workspace(c0, "batch.args", sizeof(BatchArgs));
     if (!states || !rows || !ctl || !da) return fail(LGT_ERR_OOM, "cannot allocate the batch control buffers");
+    // phase profile of the launch while timing is on for the first problem's context
+    unsigned long long *prof = nullptr;
+    if (c0->timing > 0) {
+        prof = (unsigned long long *)workspace(c0, "batch.prof", sizeof(unsigned long long) * kBatchPhases);
+        if (!prof) return fail(LGT_ERR_OOM, "cannot allocate the batch profile");
+    }
+    ha->prof = prof;
     ha->states = states;
     ha->rows[0] = rows;
     ha->rows[1] = rows + (size_t)grid * total_rhs;
@@ -333,7 +340,14 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     LGT_HIP(hipMemcpyAsync(st.data(), states, sizeof(CgState) * (size_t)total_rhs, hipMemcpyDeviceToHost, s));
     BatchCtl hc;
     LGT_HIP(hipMemcpyAsync(&hc, ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    unsigned long long hp[kBatchPhases] = {};
+    if (prof) LGT_HIP(hipMemcpyAsync(hp, prof, sizeof(hp), hipMemcpyDeviceToHost, s));
     LGT_HIP(hipStreamSynchronize(s));
+    if (prof) {
+        // ticks of the constant 100 MHz clock -> milliseconds
+        for (int k = 0; k < kBatchPhases; k++) c0->batch_prof_ms[k] = 1e-5 * (double)hp[k];
+        c0->batch_prof_iters = (int)hc.iters_done;
+    }
     float ms = 0.f;
     LGT_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (hc.err) return fail(LGT_ERR_DEVICE, "batched CG: a grid barrier timed out");
@@ -357,6 +371,16 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         }
     }
     if (ret != LGT_OK) return fail(ret, "batched CG: at least one right-hand side did not converge");
+    return LGT_OK;
+}
+
+lgt_status lgt_batch_profile(lgt_ctx *c, double ms[9], int32_t *iters)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (!ms || !iters) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    for (int k = 0; k < kBatchPhases; k++) ms[k] = c->batch_prof_ms[k];
+    *iters = c->batch_prof_iters;
     return LGT_OK;
 }
 

@@ -60,6 +60,15 @@ struct BatchCtl {
     unsigned int grp[8][16]; // per-XCD arrival counters, one 64-byte line each
 };
 
+// Phases of the batched solver's profile (BatchArgs::prof, clock ticks of
+// workgroup 0 at the constant 100 MHz rate): set-up and final step, the inner
+// Dslash steps 1 and 2 and the vector update 3 (this workgroup's own work),
+// the waits at the barriers after them (imbalance + barrier), the scalar steps
+// after barriers 2 and 3, and the FP64 reliable updates / refinement steps.
+enum BatchPhase {
+    PH_SETUP = 0, PH_STEP1, PH_WAIT1, PH_STEP2, PH_WAIT2, PH_STEP3, PH_WAIT3, PH_SCALAR, PH_FP64, kBatchPhases
+};
+
 struct BatchArgs {
     BatchProb prob[kMaxProblems];
     int nprob;
@@ -74,6 +83,7 @@ struct BatchArgs {
     double *rows[2];    // partial-sum rows [grid][total_rhs], two buffers
     BatchCtl *ctl;
     unsigned int spin_limit;
+    unsigned long long *prof; // [kBatchPhases] phase profile, or null (off)
 };
 
 // Multi-RHS Dslash engines: one lane per (site, rhs); four lanes per site

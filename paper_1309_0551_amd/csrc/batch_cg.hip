@@ -41,7 +41,23 @@ struct Shared {
     unsigned char sel[kMaxTotalRhs];   // selected for the current FP64 step
     int prun[kMaxProblems], psel[kMaxProblems];
     int any_run, any_sel, ok, pad;
+    unsigned long long prof[kBatchPhases]; // phase profile of workgroup 0 (thread 0 only)
+    unsigned long long prof_last;
 };
+
+// Phase profile (when BatchArgs::prof is set): workgroup 0's thread 0 adds the
+// constant-rate clock ticks since its previous mark to phase k. Its marks
+// after each barrier make a phase's time the slowest workgroup's work on it
+// plus the barrier; the marks before a barrier separate its own work from the
+// wait, which is then imbalance plus barrier latency.
+__device__ __forceinline__ void mark(const BatchArgs *A, Shared &S, int k)
+{
+    if (A->prof && blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+        if (k >= 0) S.prof[k] += now - S.prof_last;
+        S.prof_last = now;
+    }
+}
 
 __device__ __forceinline__ double ld_f64(const double *p)
 {
@@ -419,7 +435,9 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
         S.prun[p] = 0;
         S.psel[p] = 1;
     }
+    if (threadIdx.x < kBatchPhases) S.prof[threadIdx.x] = 0ull;
     __syncthreads();
+    mark(A, S, -1);
 
     auto flush_lane = [&](int p) { flush_prob(S, v, A->prob[p], false); };
     auto no_flush = [](int) {};
@@ -525,6 +543,7 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
         __syncthreads();
         ok = fp64_step(FIN_RU);
     }
+    mark(A, S, PH_SETUP);
 
     // ---- iterations, all right-hand sides of all problems in lock-step
     const int cap = A->max_iter + 2;
@@ -538,20 +557,25 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
                 step1<LF>(P, S, dt, po, pn);
             },
             no_flush);
+        mark(A, S, PH_STEP1);
         if (!(ok = grid_sync(ctl, lim, S))) break;
+        mark(A, S, PH_WAIT1);
         // 2. Ap = 4m^2 p' - D_eo t, <p', Ap>  -> alpha
         tiles<true>(
             A, S.prun,
             [&](const BatchProb &P, int dt) { step2<LF>(P, S, dt, (it & 1) ? P.pa : P.pb, v); },
             [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
         write_row(A, A->rows[0], S);
+        mark(A, S, PH_STEP2);
         if (!(ok = grid_sync(ctl, lim, S))) break;
+        mark(A, S, PH_WAIT2);
         {
             const double tot = sum_rows(A, A->rows[0], S);
             if ((int)threadIdx.x < Q && S.run[threadIdx.x]) finalize(FIN_ALPHA, &S.st[threadIdx.x], tot);
             __syncthreads();
             refresh(A, S, true, 0, false);
         }
+        mark(A, S, PH_SCALAR);
         // 3. x += alpha p', r -= alpha Ap, |r|^2  -> beta, stop tests
         tiles<false>(
             A, S.prun,
@@ -581,7 +605,9 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
             },
             flush_lane);
         write_row(A, A->rows[1], S);
+        mark(A, S, PH_STEP3);
         if (!(ok = grid_sync(ctl, lim, S))) break;
+        mark(A, S, PH_WAIT3);
         {
             const double tot = sum_rows(A, A->rows[1], S);
             if ((int)threadIdx.x < Q && S.run[threadIdx.x]) finalize(FIN_UPDATE, &S.st[threadIdx.x], tot);
@@ -589,7 +615,9 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
             const bool fixed = A->scheme == SCH_RELIABLE && (it + 1) % A->ru_interval == 0;
             refresh(A, S, false, 1, fixed);
         }
+        mark(A, S, PH_SCALAR);
         if (S.any_sel) ok = fp64_step(FIN_RU);
+        mark(A, S, PH_FP64);
         if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iters_done = it + 1;
     }
 
@@ -600,8 +628,11 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
         __syncthreads();
         ok = fp64_step(FIN_FINAL);
     }
-    if (blockIdx.x == 0)
+    mark(A, S, PH_SETUP);
+    if (blockIdx.x == 0) {
         for (int q = threadIdx.x; q < Q; q += kBB) A->states[q] = S.st[q];
+        if (A->prof && threadIdx.x < kBatchPhases) A->prof[threadIdx.x] = S.prof[threadIdx.x];
+    }
 }
 
 template <class LF> static int max_blocks_per_cu()

@@ -7,7 +7,18 @@
 #include "kernels.hpp"
 #include "reduce.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace lgt {
+
+// Launch with optional start / stop events carried on the kernel's own
+// dispatch packet (they time the kernel alone, as a kernel trace does).
+template <class K, class... Args>
+static void launch_ev(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args)
+{
+    if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, 0u, s, e0, e1, 0u, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 // x += alpha p (the previous update's, while pending) ; p = r + beta p.
 // Adding alpha p here rather than in the update saves one vector pass per
@@ -42,10 +53,10 @@ __global__ __launch_bounds__(kBS) void k_xpay(VecArgs a)
     VecFmt<T>::template store<false>(a.p, (size_t)a.Vh, cb, p);
 }
 
-hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s)
+hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (f64) hipLaunchKernelGGL(k_xpay<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
-    else hipLaunchKernelGGL(k_xpay<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    if (f64) launch_ev(k_xpay<double>, dim3(a.l.nblk), dim3(kBS), s, e0, e1, a);
+    else launch_ev(k_xpay<float>, dim3(a.l.nblk), dim3(kBS), s, e0, e1, a);
     return hipGetLastError();
 }
 
@@ -130,10 +141,10 @@ __global__ __launch_bounds__(kBS) void k_update(VecArgs a)
     write_partial(part, a.partials, blk);
 }
 
-hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s)
+hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (f64) hipLaunchKernelGGL(k_update<double>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
-    else hipLaunchKernelGGL(k_update<float>, dim3(a.l.nblk), dim3(kBS), 0, s, a);
+    if (f64) launch_ev(k_update<double>, dim3(a.l.nblk), dim3(kBS), s, e0, e1, a);
+    else launch_ev(k_update<float>, dim3(a.l.nblk), dim3(kBS), s, e0, e1, a);
     return hipGetLastError();
 }
 
@@ -151,9 +162,10 @@ __global__ __launch_bounds__(kBS) void k_finalize(const double *__restrict__ par
     if (threadIdx.x == 0) finalize(fin, st, tot);
 }
 
-hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s)
+hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBS), 0, s, partials, n, st, fin, gate);
+    launch_ev(k_finalize, dim3(1), dim3(kBS), s, e0, e1, partials, n, st, fin, gate);
     return hipGetLastError();
 }
 

@@ -44,6 +44,15 @@ struct lgt_ctx {
     std::map<std::string, Buf> ws; // named device workspace, grown on demand
     void *pinned = nullptr;        // host pinned staging for state read-back
     size_t pinned_bytes = 0;
+    // phase profile of the last batched solve launched from this context with
+    // timing on (lgt_batch_profile), ms per phase and iterations
+    double batch_prof_ms[9] = {};
+    int batch_prof_iters = 0;
+    // mean kernel times (ms) of the vector kernels of the timed iterations of
+    // the last lgt_cg_solve* with timing on: xpay, update, beta step, alpha
+    // step (0 when fused into the update), and the number of those iterations
+    double cg_prof_ms[4] = {};
+    int cg_prof_n = 0;
 };
 
 namespace lgt {

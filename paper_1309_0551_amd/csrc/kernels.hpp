@@ -118,10 +118,12 @@ struct VecArgs {
     CgState *st;
     int gate;
 };
-hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s);
+// e0 / e1 (may be null): events on the kernel's own dispatch packet
+hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // x += alpha p when the state holds a pending update (gate: a.gate)
 hipError_t launch_x_pending(bool f64, const VecArgs &a, hipStream_t s);
-hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s);
+hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 hipError_t launch_ru_accum(double *x64, void *xlo, int Vh, CgState *st, int gate, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol,
@@ -130,7 +132,8 @@ hipError_t launch_norm_init(const double *b64, int Vh, double *partials, CgState
 hipError_t launch_cdot(int64_t n, const double *a, const double *b, double *partials, double *result,
                        hipStream_t s);
 // sum n partials in order and run the scalar step `fin` (one workgroup)
-hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s);
+hipError_t launch_finalize(const double *partials, int n, CgState *st, int fin, int gate, hipStream_t s,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // ---- link fattening (fatten.hip) --------------------------------------------
 struct FatCoeffs {

@@ -121,9 +121,12 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     const bool timing = c->timing > 0;
     const int every = timing ? c->timing : 1; // iterations of a chunk whose Dslash pair is timed: i % every == 0
     const int pairs = 2 * chunk + 2; // event pairs per chunk: 2 Dslash per iteration + 2 in the update
-    Events evs, tev;
+    Events evs, tev, vev;
     LGT_HIP(evs.make(4)); // 0 start, 1 end, 2/3 chunk slots
     if (timing) LGT_HIP(tev.make((size_t)2 * 2 * pairs));
+    // the vector kernels of the timed iterations: xpay, update, beta step, alpha step
+    constexpr int kVec = 4;
+    if (timing) LGT_HIP(vev.make((size_t)2 * chunk * kVec * 2));
 
     // Dslash launch; the reducing epilogues (EPI_A, EPI_RES*) leave one
     // partial sum per workgroup for the finalize kernel that follows.
@@ -157,6 +160,13 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         if (!timing || slot < 0) return nullptr;
         return tev.ev[((size_t)slot * pairs + idx) * 2 + (begin ? 0 : 1)];
     };
+    // events of vector kernel k of iteration i of a chunk slot (null: untimed)
+    auto vv = [&](int slot, int i, int k, bool begin) -> hipEvent_t {
+        if (!timing || slot < 0) return nullptr;
+        return vev.ev[(((size_t)slot * chunk + i) * kVec + k) * 2 + (begin ? 0 : 1)];
+    };
+    double vms[kVec] = {0.0, 0.0, 0.0, 0.0};
+    int vn = 0;
     VecArgs va;
     va.x = xlo;
     va.r = r;
@@ -218,6 +228,16 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     auto harvest = [&](int slot, const CgState &end) -> hipError_t {
         if (!timing) return hipSuccess;
         const int nreal = std::min(end.iter - prev_iter, chunk);
+        for (int i = 0; i < nreal; i += every) {
+            for (int k = 0; k < kVec; k++) {
+                if (k == 3 && fuse_alpha) continue;
+                float ms = 0.f;
+                hipError_t e = hipEventElapsedTime(&ms, vv(slot, i, k, true), vv(slot, i, k, false));
+                if (e != hipSuccess) return e;
+                vms[k] += ms;
+            }
+            vn++;
+        }
         for (int i = 0; i < 2 * nreal; i++) {
             if ((i / 2) % every != 0) continue;
             float ms = 0.f;
@@ -250,14 +270,17 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         for (int i = 0; i < chunk; i++) {
             const int ts = i % every == 0 ? slot : -1;
             const void *Ui = mixed ? Ulo->ptr : Uhi->ptr;
-            LGT_HIP(launch_xpay(lo_is_f64, va, s));
+            LGT_HIP(launch_xpay(lo_is_f64, va, s, vv(ts, i, 0, true), vv(ts, i, 0, false)));
             LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, Ui, pp, t, GATE_ITER, nullptr, nullptr, nullptr, ev(ts, 2 * i, true),
                       ev(ts, 2 * i, false)));
             LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
                       ev(ts, 2 * i + 1, false)));
-            if (!fuse_alpha) LGT_HIP(F(partials, FIN_ALPHA, GATE_ITER, llo.nblk));
-            LGT_HIP(launch_update(lo_is_f64, va, s));
-            LGT_HIP(F(partials2, FIN_UPDATE, GATE_ITER, l.nblk));
+            if (!fuse_alpha)
+                LGT_HIP(launch_finalize(partials, llo.nblk, dst, FIN_ALPHA, GATE_ITER, s, vv(ts, i, 3, true),
+                                        vv(ts, i, 3, false)));
+            LGT_HIP(launch_update(lo_is_f64, va, s, vv(ts, i, 1, true), vv(ts, i, 1, false)));
+            LGT_HIP(launch_finalize(partials2, l.nblk, dst, FIN_UPDATE, GATE_ITER, s, vv(ts, i, 2, true),
+                                    vv(ts, i, 2, false)));
         }
         LGT_HIP(reliable(GATE_RU, timing ? slot : -1, FIN_RU));
         LGT_HIP(hipMemcpyAsync(host + slot, dst, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -300,6 +323,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     out.dslash_ms_lo = ms_lo;
     out.dslash_timed_hi = n_hi;
     out.dslash_timed_lo = n_lo;
+    if (timing) {
+        for (int k = 0; k < kVec; k++) c->cg_prof_ms[k] = vn ? vms[k] / vn : 0.0;
+        c->cg_prof_n = vn;
+    }
     lgt_status ret;
     if (e.state == ST_DONE) ret = LGT_OK;
     else if (e.state == ST_FAIL || !std::isfinite(e.last_true)) ret = LGT_ERR_NONFINITE;

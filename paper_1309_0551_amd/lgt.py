@@ -161,6 +161,8 @@ def _setup(l):
         "lgt_get_mrhs_variant": (st, [vp, i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "lgt_tune_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, C.POINTER(C.c_double)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
+        "lgt_batch_profile": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "lgt_cg_profile": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "lgt_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), i32, vp, vp]),
         "lgt_force_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), vp, C.c_double, vp, vp]),
         "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
@@ -326,6 +328,25 @@ class Lattice:
         w = C.c_int32()
         _check(lib().lgt_get_dslash_workgroup(self._ctx, prec, recon, C.byref(w)))
         return int(w.value)
+
+    def cg_profile(self) -> dict:
+        """Mean times (ms) of the vector kernels of the timed iterations of the last CG with timing on."""
+        ms = (C.c_double * 4)()
+        n = C.c_int32()
+        _check(lib().lgt_cg_profile(self._ctx, ms, C.byref(n)))
+        return {"xpay": ms[0], "update": ms[1], "beta_step": ms[2], "alpha_step": ms[3], "iters_timed": int(n.value)}
+
+    BATCH_PHASES = ("setup_and_final", "step1_doe", "wait1", "step2_deo", "wait2", "step3_update", "wait3",
+                    "scalar", "fp64_updates")
+
+    def batch_profile(self) -> dict:
+        """Phase times (ms) of the last batched solve launched with timing on from this context."""
+        ms = (C.c_double * len(self.BATCH_PHASES))()
+        it = C.c_int32()
+        _check(lib().lgt_batch_profile(self._ctx, ms, C.byref(it)))
+        out = {k: ms[i] for i, k in enumerate(self.BATCH_PHASES)}
+        out["iters"] = int(it.value)
+        return out
 
     def set_mrhs_engine(self, engine: int):
         """Multi-RHS Dslash engine: LGT_MRHS_LANE, LGT_MRHS_VALU4 or LGT_MRHS_MFMA."""

@@ -158,6 +158,8 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_stream_read_links": (None, None, 1, 1, None),
         "lgt_set_dslash_workgroup": (None, 0, 18, 64),
         "lgt_get_dslash_workgroup": (None, 0, 18, C.byref(i)),
+        "lgt_batch_profile": (None, (C.c_double * 9)(), C.byref(i)),
+        "lgt_cg_profile": (None, (C.c_double * 4)(), C.byref(i)),
     }
     for name, args in calls.items():
         assert getattr(l, name)(*args) == -1, name

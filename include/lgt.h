@@ -487,10 +487,11 @@ typedef struct {
  * side; not block CG) for every right-hand side of every problem, lattices of
  * different sizes included, in ONE cooperative persistent launch (one
  * workgroup per CU) on the stream of probs[0].ctx. Not from the paper, which
- * solves one system at a time: each right-hand side runs the iteration of
- * lgt_cg_solve, and batching only shares each link load among the
- * right-hand sides of a lattice. An iteration has three
- * grid barriers; every workgroup sums the per-workgroup partial sums itself,
+ * solves one system at a time: each right-hand side runs the CG iteration of
+ * lgt_cg_solve, with <p, A p> taken as 4m^2 |p|^2 + |D_oe p|^2 (the same number,
+ * since D_eo = -D_oe^dag) so that alpha is known before D_eo, and batching
+ * shares each link load among the right-hand sides of a lattice. An iteration
+ * has two grid barriers; every workgroup sums the per-workgroup partial sums itself,
  * in a fixed order, so results are bit-reproducible for a given device. FP64
  * reliable updates / refinement steps run inside the same launch. The inner
  * Dslash of each problem uses the multi-RHS variant of that problem's own
@@ -510,10 +511,11 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
 /* Phase profile of the last lgt_cg_solve_batch whose first problem's context
  * had timing on (lgt_set_timing > 0): ms[9] receives the milliseconds that
  * workgroup 0 of the persistent launch spent in (0) set-up and the final FP64
- * step, (1) the inner D_oe step with p = r + beta p, (2) the wait at the
- * barrier after it, (3) the inner D_eo step with <p, Ap>, (4) its barrier
- * wait, (5) the vector update with |r|^2, (6) its barrier wait, (7) the scalar
- * steps, (8) the FP64 reliable updates / refinement steps; iters the
+ * step, (1) the inner D_oe step with p = r + beta p and <p, A p>, (2) the
+ * wait at the barrier after it, (3) the inner D_eo step with the update of x
+ * and r and |r|^2, (4) its barrier wait, (5, 6) zero (kept for a separate
+ * update step), (7) the scalar steps, (8) the FP64 reliable updates /
+ * refinement steps; iters the
  * iterations run. A wait is the slowest workgroup's extra time plus the
  * barrier itself. Zeros before any such solve. Host only. */
 lgt_status lgt_batch_profile(lgt_ctx *ctx, double ms[9], int32_t *iters);

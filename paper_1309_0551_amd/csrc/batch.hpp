@@ -62,9 +62,11 @@ struct BatchCtl {
 
 // Phases of the batched solver's profile (BatchArgs::prof, clock ticks of
 // workgroup 0 at the constant 100 MHz rate): set-up and final step, the inner
-// Dslash steps 1 and 2 and the vector update 3 (this workgroup's own work),
-// the waits at the barriers after them (imbalance + barrier), the scalar steps
-// after barriers 2 and 3, and the FP64 reliable updates / refinement steps.
+// steps 1 (D_oe with p' and <p', A p'>) and 2 (D_eo with the update of x and r
+// and |r|^2) as this workgroup's own work, the waits at the barriers after
+// them (imbalance + barrier), the scalar steps after the barriers, and the
+// FP64 reliable updates / refinement steps. (PH_STEP3 / PH_WAIT3 stay zero:
+// the update is part of step 2.)
 enum BatchPhase {
     PH_SETUP = 0, PH_STEP1, PH_WAIT1, PH_STEP2, PH_WAIT2, PH_STEP3, PH_WAIT3, PH_SCALAR, PH_FP64, kBatchPhases
 };

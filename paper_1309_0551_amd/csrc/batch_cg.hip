@@ -5,14 +5,16 @@
 // different sizes included -- run in lock-step in one cooperative launch of
 // one kBB-thread workgroup per CU.
 //
-// An iteration takes three grid barriers, the fewest that CG on
-// A = 4m^2 - D_eo D_oe allows (D_eo needs all of D_oe's output, and alpha
-// and beta are global sums):
+// An iteration takes two grid barriers (D_eo needs all of D_oe's output, and
+// beta is a global sum):
 //   1. t = D_oe p', where p' = r + beta p is formed at the neighbours from r
 //      and the previous p, and written by the owner of each even index into
-//      the other of two p buffers;
-//   2. Ap = 4m^2 p' - D_eo t and partial <p', Ap>        -> alpha;
-//   3. x += alpha p', r -= alpha Ap and partial |r|^2     -> beta, stop tests.
+//      the other of two p buffers; partial <p', A p'> = 4m^2 |p'|^2 + |t|^2
+//      (D_eo = -D_oe^dag, so -<p', D_eo D_oe p'> = |D_oe p'|^2)  -> alpha;
+//   2. Ap = 4m^2 p' - D_eo t, used at once: x += alpha p', r -= alpha Ap,
+//      partial |r|^2                                           -> beta, stop tests.
+// Knowing alpha before D_eo saves the third barrier and a pass over x, r, p'
+// and Ap that a separate update step would take.
 // Each workgroup adds its partial sums per right-hand side into one row.
 // After the barrier EVERY workgroup sums all rows in the same fixed order and
 // runs the scalar step on its own copy of the states, kept in LDS: the copies
@@ -240,10 +242,18 @@ __device__ void refresh(const BatchArgs *A, Shared &S, bool alpha, int sel_mode,
     __syncthreads();
 }
 
-// ---- inner-precision Dslash steps, four lanes per site
+// ---- inner-precision steps, four lanes per site
+//
+// Step 1 (odd sites): t = D_oe p', with p' = r + beta p formed at every
+// neighbour from r and the previous p; the owner of each even index writes
+// p' into the other p buffer. Partial m4 |p'|^2 + |t|^2 = <p', A p'> (A =
+// 4m^2 - D_eo D_oe and D_eo = -D_oe^dag), from which alpha follows before
+// step 2. Step 2 (even sites): Ap = m4 p' - D_eo t, then at once x += alpha
+// p', r -= alpha Ap and the partial |r|^2 for beta; Ap is never stored.
 
 template <class LF, int R, int GPS, bool MFMA>
-__device__ __forceinline__ void step1_four(const BatchProb &P, const Shared &S, int dt, const void *pold, void *pnew)
+__device__ __forceinline__ void step1_four(const BatchProb &P, const Shared &S, int dt, const void *pold, void *pnew,
+                                           double v[4])
 {
     constexpr int LPS = 4 * GPS; // lanes per site
     const unsigned s = (unsigned)dt * (kBB / LPS) + threadIdx.x / LPS, lane4 = threadIdx.x & 3u;
@@ -269,11 +279,22 @@ __device__ __forceinline__ void step1_four(const BatchProb &P, const Shared &S, 
             }
         }
     };
-    cx<float> acc[R][3];
+    cx<float> acc[R][3], pp[R][3];
     dslash_site4<LF, R, MFMA>(P.g, kOdd, P.Ulo, s, lane4, IN, acc);
     stm_r<float, R>(P.t, Vh, logN, s, r0, acc);
-    IN(s, acc);
-    stm_r<float, R>(pnew, Vh, logN, s, r0, acc);
+    IN(s, pp);
+    stm_r<float, R>(pnew, Vh, logN, s, r0, pp);
+    const double m4 = P.m4;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        double tt = 0.0, qq = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            tt += (double)acc[r][c].re * (double)acc[r][c].re + (double)acc[r][c].im * (double)acc[r][c].im;
+            qq += (double)pp[r][c].re * (double)pp[r][c].re + (double)pp[r][c].im * (double)pp[r][c].im;
+        }
+        if (S.run[P.rhs0 + r0 + r]) v[r] += m4 * qq + tt;
+    }
 }
 
 template <class LF, int R, int GPS, bool MFMA>
@@ -287,28 +308,38 @@ __device__ __forceinline__ void step2_four(const BatchProb &P, const Shared &S, 
     const unsigned r0 = (threadIdx.x % LPS) * R; // group g, lane l: rhs (4 g + l) R + r
     const void *tv = P.t;
     auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(tv, Vh, logN, n, r0, u); };
-    cx<float> acc[R][3], pp[R][3];
+    cx<float> acc[R][3], pp[R][3], x[R][3], rr[R][3];
     dslash_site4<LF, R, MFMA>(P.g, kEven, P.Ulo, s, lane4, IN, acc);
     ldm_r<float, R>(pnew, Vh, logN, s, r0, pp);
+    ldm_r<float, R>(P.xlo, Vh, logN, s, r0, x);
+    ldm_r<float, R>(P.r, Vh, logN, s, r0, rr);
     const float m4 = (float)P.m4;
 #pragma unroll
     for (int r = 0; r < R; r++) {
+        // alpha is 0 for right-hand sides that are not iterating: x and r stay
+        const float alpha = (float)S.coef[P.rhs0 + r0 + r];
         double d = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            acc[r][c].re = m4 * pp[r][c].re - acc[r][c].re;
-            acc[r][c].im = m4 * pp[r][c].im - acc[r][c].im;
-            d += (double)pp[r][c].re * (double)acc[r][c].re + (double)pp[r][c].im * (double)acc[r][c].im;
+            const float apr = m4 * pp[r][c].re - acc[r][c].re;
+            const float api = m4 * pp[r][c].im - acc[r][c].im;
+            x[r][c].re = fmaf(alpha, pp[r][c].re, x[r][c].re);
+            x[r][c].im = fmaf(alpha, pp[r][c].im, x[r][c].im);
+            rr[r][c].re = fmaf(-alpha, apr, rr[r][c].re);
+            rr[r][c].im = fmaf(-alpha, api, rr[r][c].im);
+            d += (double)rr[r][c].re * (double)rr[r][c].re + (double)rr[r][c].im * (double)rr[r][c].im;
         }
         if (S.run[P.rhs0 + r0 + r]) v[r] += d;
     }
-    stm_r<float, R>(P.Ap, Vh, logN, s, r0, acc);
+    stm_r<float, R>(P.xlo, Vh, logN, s, r0, x);
+    stm_r<float, R>(P.r, Vh, logN, s, r0, rr);
 }
 
-// ---- inner-precision Dslash steps, one lane per (site, rhs)
+// ---- inner-precision steps, one lane per (site, rhs)
 
 template <class LF>
-__device__ __forceinline__ void step1_lane(const BatchProb &P, const Shared &S, int lt, const void *pold, void *pnew)
+__device__ __forceinline__ void step1_lane(const BatchProb &P, const Shared &S, int lt, const void *pold, void *pnew,
+                                           double v[4])
 {
     using T = typename LF::real;
     const unsigned idx = (unsigned)lt * kBB + threadIdx.x;
@@ -328,11 +359,18 @@ __device__ __forceinline__ void step1_lane(const BatchProb &P, const Shared &S, 
             v[c].im = fma(beta, pp[c].im, v[c].im);
         }
     };
-    cx<T> acc[3];
+    cx<T> acc[3], pp[3];
     dslash_mrhs<LF>(P.g, kOdd, P.Ulo, site, IN, acc);
     stm<T>(P.t, Vh, logN, site, rhs, acc);
-    IN(site, acc);
-    stm<T>(pnew, Vh, logN, site, rhs, acc);
+    IN(site, pp);
+    stm<T>(pnew, Vh, logN, site, rhs, pp);
+    double tt = 0.0, qq = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        tt += (double)acc[c].re * (double)acc[c].re + (double)acc[c].im * (double)acc[c].im;
+        qq += (double)pp[c].re * (double)pp[c].re + (double)pp[c].im * (double)pp[c].im;
+    }
+    if (S.run[P.rhs0 + rhs]) v[0] += P.m4 * qq + tt;
 }
 
 template <class LF>
@@ -346,29 +384,38 @@ __device__ __forceinline__ void step2_lane(const BatchProb &P, const Shared &S, 
     const int logN = P.logN;
     const void *tv = P.t;
     auto IN = [=](int n, cx<T> u[3]) __attribute__((always_inline)) { ldm<T>(tv, Vh, logN, n, rhs, u); };
-    cx<T> acc[3], pp[3];
+    cx<T> acc[3], pp[3], x[3], rr[3];
     dslash_mrhs<LF>(P.g, kEven, P.Ulo, site, IN, acc);
     ldm<T>(pnew, Vh, logN, site, rhs, pp);
+    ldm<T>(P.xlo, Vh, logN, site, rhs, x);
+    ldm<T>(P.r, Vh, logN, site, rhs, rr);
     const T m4 = (T)P.m4;
+    const T alpha = (T)S.coef[P.rhs0 + rhs]; // 0 unless iterating: x and r stay
     double d = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        acc[c].re = m4 * pp[c].re - acc[c].re;
-        acc[c].im = m4 * pp[c].im - acc[c].im;
-        d += (double)pp[c].re * (double)acc[c].re + (double)pp[c].im * (double)acc[c].im;
+        const T apr = m4 * pp[c].re - acc[c].re;
+        const T api = m4 * pp[c].im - acc[c].im;
+        x[c].re = fma(alpha, pp[c].re, x[c].re);
+        x[c].im = fma(alpha, pp[c].im, x[c].im);
+        rr[c].re = fma(-alpha, apr, rr[c].re);
+        rr[c].im = fma(-alpha, api, rr[c].im);
+        d += (double)rr[c].re * (double)rr[c].re + (double)rr[c].im * (double)rr[c].im;
     }
     if (S.run[P.rhs0 + rhs]) v[0] += d;
-    stm<T>(P.Ap, Vh, logN, site, rhs, acc);
+    stm<T>(P.xlo, Vh, logN, site, rhs, x);
+    stm<T>(P.r, Vh, logN, site, rhs, rr);
 }
 
-// engine dispatch for the inner Dslash steps (F32/BF16 links only)
+// engine dispatch for the inner steps (four-lane engines for F32/BF16 links only)
 template <class LF>
-__device__ __forceinline__ void step1(const BatchProb &P, const Shared &S, int dt, const void *pold, void *pnew)
+__device__ __forceinline__ void step1(const BatchProb &P, const Shared &S, int dt, const void *pold, void *pnew,
+                                      double v[4])
 {
     if constexpr (!std::is_same<typename LF::real, double>::value) {
         if (P.eng != MRHS_LANE) {
             const bool mf = P.eng == MRHS_MFMA;
-#define LGT_STEP1(R, G) (mf ? step1_four<LF, R, G, true>(P, S, dt, pold, pnew) : step1_four<LF, R, G, false>(P, S, dt, pold, pnew))
+#define LGT_STEP1(R, G) (mf ? step1_four<LF, R, G, true>(P, S, dt, pold, pnew, v) : step1_four<LF, R, G, false>(P, S, dt, pold, pnew, v))
             if (P.logN == 2) LGT_STEP1(1, 1);
             else if (P.logN == 3) P.gps == 2 ? LGT_STEP1(1, 2) : LGT_STEP1(2, 1);
             else P.gps == 4 ? LGT_STEP1(1, 4) : LGT_STEP1(2, 2);
@@ -376,7 +423,7 @@ __device__ __forceinline__ void step1(const BatchProb &P, const Shared &S, int d
             return;
         }
     }
-    step1_lane<LF>(P, S, dt, pold, pnew);
+    step1_lane<LF>(P, S, dt, pold, pnew, v);
 }
 
 template <class LF>
@@ -548,27 +595,20 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
     // ---- iterations, all right-hand sides of all problems in lock-step
     const int cap = A->max_iter + 2;
     for (int it = 0; ok && S.any_run && it < cap; it++) {
-        // 1. t = D_oe p', p' = r + beta p (written to the other p buffer)
+        // 1. t = D_oe p', p' = r + beta p (written to the other p buffer),
+        //    <p', A p'> = m4 |p'|^2 + |t|^2  -> alpha
         tiles<true>(
             A, S.prun,
             [&](const BatchProb &P, int dt) {
                 const void *po = (it & 1) ? P.pb : P.pa;
                 void *pn = (it & 1) ? P.pa : P.pb;
-                step1<LF>(P, S, dt, po, pn);
+                step1<LF>(P, S, dt, po, pn, v);
             },
-            no_flush);
+            [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
+        write_row(A, A->rows[0], S);
         mark(A, S, PH_STEP1);
         if (!(ok = grid_sync(ctl, lim, S))) break;
         mark(A, S, PH_WAIT1);
-        // 2. Ap = 4m^2 p' - D_eo t, <p', Ap>  -> alpha
-        tiles<true>(
-            A, S.prun,
-            [&](const BatchProb &P, int dt) { step2<LF>(P, S, dt, (it & 1) ? P.pa : P.pb, v); },
-            [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
-        write_row(A, A->rows[0], S);
-        mark(A, S, PH_STEP2);
-        if (!(ok = grid_sync(ctl, lim, S))) break;
-        mark(A, S, PH_WAIT2);
         {
             const double tot = sum_rows(A, A->rows[0], S);
             if ((int)threadIdx.x < Q && S.run[threadIdx.x]) finalize(FIN_ALPHA, &S.st[threadIdx.x], tot);
@@ -576,38 +616,15 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
             refresh(A, S, true, 0, false);
         }
         mark(A, S, PH_SCALAR);
-        // 3. x += alpha p', r -= alpha Ap, |r|^2  -> beta, stop tests
-        tiles<false>(
+        // 2. Ap = m4 p' - D_eo t ; x += alpha p', r -= alpha Ap ; |r|^2  -> beta, stop tests
+        tiles<true>(
             A, S.prun,
-            [&](const BatchProb &P, int lt) {
-                const unsigned idx = (unsigned)lt * kBB + threadIdx.x;
-                const unsigned site = idx >> P.logN, rhs = idx & ((1u << P.logN) - 1u);
-                if (site >= (unsigned)P.g.Vh || !S.run[P.rhs0 + rhs]) return;
-                const size_t Vh = (size_t)P.g.Vh;
-                const int logN = P.logN;
-                const void *pn = (it & 1) ? P.pa : P.pb;
-                const T alpha = (T)S.coef[P.rhs0 + rhs];
-                cx<T> x[3], rr[3], pp[3], q[3];
-                ldm<T>(P.xlo, Vh, logN, site, rhs, x);
-                ldm<T>(P.r, Vh, logN, site, rhs, rr);
-                ldm<T>(pn, Vh, logN, site, rhs, pp);
-                ldm<T>(P.Ap, Vh, logN, site, rhs, q);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    x[c].re = fma(alpha, pp[c].re, x[c].re);
-                    x[c].im = fma(alpha, pp[c].im, x[c].im);
-                    rr[c].re = fma(-alpha, q[c].re, rr[c].re);
-                    rr[c].im = fma(-alpha, q[c].im, rr[c].im);
-                    v[0] += (double)rr[c].re * (double)rr[c].re + (double)rr[c].im * (double)rr[c].im;
-                }
-                stm<T>(P.xlo, Vh, logN, site, rhs, x);
-                stm<T>(P.r, Vh, logN, site, rhs, rr);
-            },
-            flush_lane);
+            [&](const BatchProb &P, int dt) { step2<LF>(P, S, dt, (it & 1) ? P.pa : P.pb, v); },
+            [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
         write_row(A, A->rows[1], S);
-        mark(A, S, PH_STEP3);
+        mark(A, S, PH_STEP2);
         if (!(ok = grid_sync(ctl, lim, S))) break;
-        mark(A, S, PH_WAIT3);
+        mark(A, S, PH_WAIT2);
         {
             const double tot = sum_rows(A, A->rows[1], S);
             if ((int)threadIdx.x < Q && S.run[threadIdx.x]) finalize(FIN_UPDATE, &S.st[threadIdx.x], tot);

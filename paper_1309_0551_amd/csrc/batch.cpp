@@ -225,6 +225,8 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
             P.eng = MRHS_VALU4; // MFMA needs V/2 % 16 == 0
             P.gps = batch_groups(logN, c->mrhs_gps[flo][logN]);
         }
+        // LDS staging of the inner Dslash's x/y neighbourhood (four-lane engines)
+        P.stage = P.eng != MRHS_LANE && batch_stage_fits(kBB / (4 * P.gps), c->g.hx, logN);
         P.lt0 = lt;
         P.nlt = (int)((n + kBB - 1) / kBB);
         P.dt0 = dt;

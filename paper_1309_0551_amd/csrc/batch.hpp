@@ -18,6 +18,14 @@ constexpr int kMaxRhs = 16;        // right-hand sides per problem (power of two
 constexpr int kMaxProblems = 64;   // problems per batched launch
 constexpr int kMaxTotalRhs = 256;  // right-hand sides per batched launch
 constexpr int kBB = 1024;          // threads per workgroup of the batched solver
+// LDS per workgroup of the batched solver for the staged input tiles of its
+// four-lane Dslash steps: 3 colours x (sites of a tile + Lx) x N right-hand
+// sides of FP32 complex (8 B) must fit
+constexpr int kBatchStageBytes = 64 * 1024;
+inline bool batch_stage_fits(int tile_sites, int hx, int logN)
+{
+    return (size_t)3 * (tile_sites + 2 * hx) * ((size_t)8 << logN) <= (size_t)kBatchStageBytes;
+}
 // Groups of four lanes per site the batched solver can run for N = 2^logN
 // right-hand sides (R = N / (4 groups) per lane): N = 4: 1; N = 8: 1 or 2;
 // N = 16: 2 or 4 (R = 4 needs more registers than its 1024-thread
@@ -41,6 +49,7 @@ struct BatchProb {
     int lt0, nlt; // first global lane tile, lane tiles
     int dt0, ndt; // first global inner-Dslash tile, inner-Dslash tiles
     int rhs0;    // first global right-hand-side index
+    int stage;   // four-lane engines: 1 if a tile's x/y neighbourhood is staged in LDS
     double m4;   // 4 m^2
     const void *Ulo, *Uhi;
     const double *b64;          // FP64 multi-RHS vectors

@@ -58,6 +58,16 @@ def _staple(L, Uc, mu, a, M):
     return La @ M[shift(L, a[0], a[1])] @ dag(La[shift(L, mu, 1)])
 
 
+def _levels(L, Uc, mu):
+    """The six signed directions orthogonal to mu, the three-link staples
+    S_a[U_mu] (keyed by a) and the five-link ones S_a[S_b[U_mu]] (keyed by (a, b),
+    a and b on different axes)."""
+    dirs = [(nu, sg) for nu in range(4) if nu != mu for sg in (1, -1)]
+    one = {a: _staple(L, Uc, mu, a, Uc[mu]) for a in dirs}
+    two = {(a, b): _staple(L, Uc, mu, a, one[b]) for a in dirs for b in dirs if a[0] != b[0]}
+    return dirs, one, two
+
+
 def fatten(L, U, coeffs):
     """(F, N) from the gauge field U (canonical real layout in and out)."""
     c1, c3, c5, c7, cL, cN = (float(c) for c in coeffs)
@@ -66,9 +76,7 @@ def fatten(L, U, coeffs):
     N = np.empty_like(Uc)
     for mu in range(4):
         M0 = Uc[mu]
-        dirs = [(nu, sg) for nu in range(4) if nu != mu for sg in (1, -1)]
-        one = {a: _staple(L, Uc, mu, a, M0) for a in dirs}
-        two = {(a, b): _staple(L, Uc, mu, a, one[b]) for a in dirs for b in dirs if a[0] != b[0]}
+        dirs, one, two = _levels(L, Uc, mu)
         three = [_staple(L, Uc, mu, a, two[(b, c)]) for a in dirs for b in dirs for c in dirs
                  if len({a[0], b[0], c[0]}) == 3]
         lepage = [_staple(L, Uc, mu, a, one[a]) for a in dirs]
@@ -76,3 +84,81 @@ def fatten(L, U, coeffs):
                  + cL * sum(lepage))
         N[mu] = cN * (Uc[mu] @ Uc[mu][shift(L, mu, 1)] @ Uc[mu][shift(L, mu, 2)])
     return real(F), real(N)
+
+
+# ---- the chain rule through the fattening -------------------------------------
+#
+# With S depending on U through F(U) and N(U) and the derivative convention of
+# the fermion force, dS = sum Re tr(G_F^dag dF) + Re tr(G_N^dag dN), the field
+# G_U with dS = sum Re tr(G_U^dag dU) follows from the product rule. For a
+# product P = A B C^dag and dS = Re tr(G^dag dP):
+#   A receives G C B^dag,   B receives A^dag G C,   C receives G^dag A B,
+# and a link entering as its adjoint (L_{-nu}(y) = U_nu(y - nu)^dag) passes the
+# adjoint of what it receives to U_nu(y - nu). The nested staple sums of
+# fatten() are taken back level by level in that way.
+
+
+def _add_to_step_link(L, GU, a, y_grad):
+    """Add the gradient of L_a(y), given for every y, to the gradient of U."""
+    nu, sg = a
+    if sg > 0:
+        GU[nu] += y_grad
+    else:
+        # L_{-nu}(y) = U_nu(y - nu)^dag: U_nu(z) receives (grad at z + nu)^dag
+        GU[nu] += dag(y_grad[shift(L, nu, 1)])
+
+
+def _staple_vjp(L, Uc, mu, a, M, G, GU):
+    """For P = S_a[M] with dS = Re tr(G^dag P) summed over x: return the
+    gradient of M (as a field over y = x + a) and add the link gradients to GU."""
+    La = _step_link(L, Uc, a)
+    xa = shift(L, a[0], a[1])
+    xm = shift(L, mu, 1)
+    A, B, C = La, M[xa], La[xm]
+    gM = np.empty_like(M)
+    gM[xa] = dag(A) @ G @ C
+    gA = G @ C @ dag(B)
+    gC = np.empty_like(M)
+    gC[xm] = dag(G) @ A @ B
+    _add_to_step_link(L, GU, a, gA + gC)
+    return gM
+
+
+def fatten_vjp(L, U, coeffs, GF, GN):
+    """G_U (canonical real layout) from G_F and G_N (same layout) for the
+    fattening of fatten(L, U, coeffs): dS = sum Re tr(G_U^dag dU)."""
+    c1, c3, c5, c7, cL, cN = (float(c) for c in coeffs)
+    Uc = cplx(np.asarray(U, dtype=np.float64))
+    gF, gN = cplx(np.asarray(GF, dtype=np.float64)), cplx(np.asarray(GN, dtype=np.float64))
+    GU = np.zeros_like(Uc)
+    for mu in range(4):
+        M0 = Uc[mu]
+        G = gF[mu]
+        dirs, one, two = _levels(L, Uc, mu)
+        g_two = {k: np.zeros_like(M0) for k in two}
+        g_one = {a: np.zeros_like(M0) for a in dirs}
+        # c1 U_mu; then the seven-link and Lepage staples pass their gradient
+        # to the five- and three-link fields under them, those to U_mu
+        GU[mu] += c1 * G
+        for a in dirs:
+            for b in dirs:
+                for c in dirs:
+                    if len({a[0], b[0], c[0]}) == 3:
+                        g_two[(b, c)] += _staple_vjp(L, Uc, mu, a, two[(b, c)], c7 * G, GU)
+            g_one[a] += _staple_vjp(L, Uc, mu, a, one[a], cL * G, GU)
+        for (a, b) in two:
+            g_one[b] += _staple_vjp(L, Uc, mu, a, one[b], c5 * G + g_two[(a, b)], GU)
+        for b in dirs:
+            GU[mu] += _staple_vjp(L, Uc, mu, b, M0, c3 * G + g_one[b], GU)
+        # Naik: N = cN A B C with A = U_mu(x), B = U_mu(x+mu), C = U_mu(x+2mu)
+        x1, x2 = shift(L, mu, 1), shift(L, mu, 2)
+        A, B, C = M0, M0[x1], M0[x2]
+        H = cN * gN[mu]
+        GU[mu] += H @ dag(B @ C)
+        gb = np.empty_like(M0)
+        gb[x1] = dag(A) @ H @ dag(C)
+        GU[mu] += gb
+        gc = np.empty_like(M0)
+        gc[x2] = dag(A @ B) @ H
+        GU[mu] += gc
+    return real(GU)

@@ -24,6 +24,11 @@ the textbook one:
   R on all sites, so phi_e is distributed as exp(-phi^dag A^-1 phi).
 * S_f = Re <phi, X>, X = A^-1 phi by CG; its G from the fermion-force oracle.
 * Metropolis: accept when u < exp(-dH) for a uniform u given as input.
+* Improved operator (the application's action, Table 4): with fattening
+  weights given, the Dslash takes the fat and Naik fields F(U), N(U) of the
+  fattening oracle. phi_e = 2m R_e - D^imp_eo R_o, S_f = Re <phi, X> with
+  X = A_imp^-1 phi, and G_fermion = the fermion-force oracle's derivatives with
+  respect to F and N taken back to U by the chain rule through the fattening.
 """
 from __future__ import annotations
 
@@ -31,8 +36,11 @@ import numpy as np
 import scipy.linalg
 
 from . import cg as _cg
+from . import cg_imp as _cg_imp
 from . import dslash as _dslash
+from . import dslash_imp as _dslash_imp
 from . import force as _force
+from . import force_imp as _force_imp
 
 _SHIFT_CACHE: dict = {}
 
@@ -134,33 +142,49 @@ def expm_su3(A):
     return np.stack([scipy.linalg.expm(m) for m in flat]).reshape(A.shape)
 
 
-def pseudofermion(L, U, mass, R_e, R_o, bc=None):
-    """phi_e = 2m R_e - D_eo R_o."""
-    return 2.0 * mass * R_e - _dslash(L, U, R_o, 0, bc)
+def pseudofermion(L, U, mass, R_e, R_o, bc=None, coeffs=None):
+    """phi_e = 2m R_e - D_eo R_o (the improved D_eo of F(U), N(U) with coeffs)."""
+    if coeffs is None:
+        return 2.0 * mass * R_e - _dslash(L, U, R_o, 0, bc)
+    from .fatten import fatten
+    F, N = fatten(L, U, coeffs)
+    return 2.0 * mass * R_e - _dslash_imp(L, F, N, R_o, 0, bc)
 
 
-def fermion_action_and_G(L, U, mass, phi, tol, bc=None):
-    st, X, it, rr = _cg(L, U, mass, phi, tol=tol, bc=bc)
+def fermion_action_and_G(L, U, mass, phi, tol, bc=None, coeffs=None):
+    """(S_f, G_fermion, CG iterations) at links U; with coeffs the improved
+    operator of the fattened fields, G taken back to U through the fattening."""
+    if coeffs is None:
+        st, X, it, rr = _cg(L, U, mass, phi, tol=tol, bc=bc)
+    else:
+        from .fatten import fatten, fatten_vjp
+        F, N = fatten(L, U, coeffs)
+        st, X, it, rr = _cg_imp(L, F, N, mass, phi, tol=tol, bc=bc)
     if st != 0:
         raise RuntimeError(f"oracle CG failed ({st})")
     S = float(np.sum(phi * X))  # Re <phi, X> over the real layout
-    return S, _force(L, U, X, bc), it
+    if coeffs is None:
+        return S, _force(L, U, X, bc), it
+    GF, GN = _force_imp(L, F, N, X, bc)
+    return S, fatten_vjp(L, U, coeffs, GF, GN), it
 
 
-def trajectory(L, U0, P0, R_e, R_o, beta, mass, eps, nsteps, tol=1e-12, bc=None, phi=None):
+def trajectory(L, U0, P0, R_e, R_o, beta, mass, eps, nsteps, tol=1e-12, bc=None, phi=None, coeffs=None):
     """One leapfrog trajectory. U0 real canonical, P0 complex [4][V][3][3]
     (traceless anti-Hermitian). The pseudofermion comes from R_e, R_o at U0
-    unless phi is given. Returns dict with U, P, phi, H0, H1, dH and parts."""
+    unless phi is given. coeffs: fattening weights (c1, c3, c5, c7, cL, cN) for
+    the improved operator, None for the one-link one. Returns dict with U, P,
+    phi, H0, H1, dH and parts."""
     U = U0.copy()
     P = P0.copy()
     if phi is None:
-        phi = pseudofermion(L, U, mass, R_e, R_o, bc)
+        phi = pseudofermion(L, U, mass, R_e, R_o, bc, coeffs)
 
     def force(U):
-        Sf, Gf, it = fermion_action_and_G(L, U, mass, phi, tol, bc)
+        Sf, Gf, it = fermion_action_and_G(L, U, mass, phi, tol, bc, coeffs)
         return md_force(U, Gf + gauge_force_G(L, U, beta)), Sf, it
 
-    Sf0, _, _ = fermion_action_and_G(L, U, mass, phi, tol, bc)
+    Sf0, _, _ = fermion_action_and_G(L, U, mass, phi, tol, bc, coeffs)
     Sg0, K0 = gauge_action(L, U, beta), kinetic(P)
     F, _, its = force(U)
     P = P + 0.5 * eps * F
@@ -170,7 +194,7 @@ def trajectory(L, U0, P0, R_e, R_o, beta, mass, eps, nsteps, tol=1e-12, bc=None,
         F, _, it = force(U)
         its += it
         P = P + (eps if k < nsteps - 1 else 0.5 * eps) * F
-    Sf1, _, _ = fermion_action_and_G(L, U, mass, phi, tol, bc)
+    Sf1, _, _ = fermion_action_and_G(L, U, mass, phi, tol, bc, coeffs)
     Sg1, K1 = gauge_action(L, U, beta), kinetic(P)
     H0, H1 = K0 + Sg0 + Sf0, K1 + Sg1 + Sf1
     return dict(U=U, P=P, phi=phi, H0=H0, H1=H1, dH=H1 - H0, Sg0=Sg0, Sg1=Sg1, Sf0=Sf0, Sf1=Sf1, K0=K0, K1=K1,

@@ -14,6 +14,13 @@
   with extent 2 (where x + a and x - a coincide) and non-cubic shapes;
 * tree-level asqtad weights give the free improved operator, F = 9/8 and
   N = -1/24.
+
+The chain rule through the fattening (fatten_vjp) is pinned by central
+differences of the (already pinned) forward: of a linear functional
+sum Re tr(R_F^dag F(U)) + Re tr(R_N^dag N(U)) on general complex links, and of
+the composed improved fermion action phi^dag A_imp(F(U), N(U))^-1 phi, whose
+derivative runs through the C oracle's improved CG and force first; planted
+mistakes in the chain rule must fail the first of these.
 """
 import numpy as np
 import pytest
@@ -169,3 +176,111 @@ def test_mutants_fail_a_pin(name):
         except AssertionError:
             caught.append(pin)
     assert caught, name
+
+
+# ------------------------------------------------------ chain rule (fatten_vjp) ---
+
+def _directional_fd(S, U, E, h):
+    return (S(U + h * E) - S(U - h * E)) / (2 * h)
+
+
+def pin_vjp_linear(fatten_vjp, L=(4, 2, 4, 6), ndir=3):
+    """d/dh of sum Re tr(R_F^dag F(U + hE)) + Re tr(R_N^dag N(U + hE)) against
+    sum Re tr(G_U^dag E); in the real layout Re tr(A^dag B) is the plain dot."""
+    U = _gauss_links(L, 7401 + L[1])
+    g = li.rng(7402)
+    RF, RN = g.standard_normal(U.shape), g.standard_normal(U.shape)
+    GU = fatten_vjp(L, U, W, RF, RN)
+
+    def S(Ux):
+        F, N = fat.fatten(L, Ux, W)
+        return float(np.sum(RF * F) + np.sum(RN * N))
+
+    for k in range(ndir):
+        E = g.standard_normal(U.shape)
+        fd = _directional_fd(S, U, E, 1e-5)
+        an = float(np.sum(GU * E))
+        assert abs(fd - an) <= 1e-8 * max(1.0, abs(an)), (L, k, fd, an)
+
+
+@pytest.mark.parametrize("L", [(4, 2, 4, 6), (2, 4, 2, 4), (4, 4, 4, 4)])
+def test_vjp_linear_functional_central_differences(L):
+    pin_vjp_linear(fat.fatten_vjp, L)
+
+
+def test_vjp_one_link_and_naik_alone():
+    """only c1: G_U = c1 G_F; only cN: U_mu(z) gets the three positions of the
+    three-link product (checked entry by entry against a direct loop)"""
+    L = (4, 2, 2, 6)
+    U = _gauss_links(L, 7411)
+    g = li.rng(7412)
+    RF, RN = g.standard_normal(U.shape), g.standard_normal(U.shape)
+    np.testing.assert_allclose(fat.fatten_vjp(L, U, (0.7, 0, 0, 0, 0, 0), RF, RN), 0.7 * RF, atol=1e-15)
+    GU = hmc.cplx(fat.fatten_vjp(L, U, (0, 0, 0, 0, 0, 1.0), RF, RN))
+    Uc, H = hmc.cplx(U), hmc.cplx(RN)
+    V = li.volume(L)
+    for mu in range(4):
+        p1, p2 = hmc.shift(L, mu, 1), hmc.shift(L, mu, 2)
+        want = np.zeros((V, 3, 3), complex)
+        for x in range(V):
+            A, B, C = Uc[mu, x], Uc[mu, p1[x]], Uc[mu, p2[x]]
+            want[x] += H[mu, x] @ (B @ C).conj().T
+            want[p1[x]] += A.conj().T @ H[mu, x] @ C.conj().T
+            want[p2[x]] += (A @ B).conj().T @ H[mu, x]
+        np.testing.assert_allclose(GU[mu], want, atol=1e-12)
+
+
+def test_vjp_composed_improved_action_central_differences():
+    """S(U) = phi^dag A_imp^-1 phi with F, N = fatten(U): the gradient from the
+    C oracle's improved CG and force, taken back through fatten_vjp, against
+    central differences of S (CG to 1e-14)."""
+    L, mass, bc = (4, 2, 2, 4), 0.3, (1, 1, 1, -1)
+    U = li.links(L, "expih", 7421, c=0.3)
+    phi = li.vector(L, 7422)
+    w = fat.asqtad_coeffs(0.9)
+    S0, GU, _ = hmc.fermion_action_and_G(L, U, mass, phi, 1e-14, bc, w)
+
+    def S(Ux):
+        return hmc.fermion_action_and_G(L, Ux, mass, phi, 1e-14, bc, w)[0]
+
+    g = li.rng(7423)
+    for k in range(3):
+        E = g.standard_normal(U.shape)
+        fd = _directional_fd(S, U, E, 1e-5)
+        an = float(np.sum(GU * E))
+        assert abs(fd - an) <= 1e-7 * abs(an), (k, fd, an)
+
+
+VJP_MUTANTS = {
+    # return leg's gradient without the adjoint of G
+    "vjp_return_leg_no_adjoint": ("gC[xm] = dag(G) @ A @ B", "gC[xm] = G @ A @ B"),
+    # first leg's gradient with its factors swapped
+    "vjp_first_leg_order": ("gA = G @ C @ dag(B)", "gA = G @ dag(B) @ C"),
+    # backward link's gradient put at y instead of y - nu
+    "vjp_backward_unshifted": ("GU[nu] += dag(y_grad[shift(L, nu, 1)])", "GU[nu] += dag(y_grad)"),
+    # inner field's gradient left at x instead of x + a
+    "vjp_inner_at_x": ("gM[xa] = dag(A) @ G @ C", "gM[:] = dag(A) @ G @ C"),
+    # seven-link gradient not passed on to the five-link fields
+    "vjp_seven_not_passed": ("c5 * G + g_two[(a, b)]", "c5 * G"),
+    # Lepage term dropped
+    "vjp_lepage_dropped": ("one[a], cL * G, GU)", "one[a], 0.0 * G, GU)"),
+    # Naik middle link's gradient two sites on
+    "vjp_naik_middle_shift": ("gb[x1] = dag(A) @ H @ dag(C)", "gb[x2] = dag(A) @ H @ dag(C)"),
+}
+
+
+def _vjp_mutant(name):
+    import types
+    src = open(fat.__file__).read()
+    old, new = VJP_MUTANTS[name]
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("oracle._fatten_vjp_mutant_" + name)
+    mod.__package__ = "oracle"
+    exec(compile(src.replace(old, new), mod.__name__, "exec"), mod.__dict__)
+    return mod.fatten_vjp
+
+
+@pytest.mark.parametrize("name", sorted(VJP_MUTANTS))
+def test_vjp_mutants_fail_the_central_difference_pin(name):
+    with pytest.raises(AssertionError):
+        pin_vjp_linear(_vjp_mutant(name))

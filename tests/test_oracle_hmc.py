@@ -122,3 +122,44 @@ def test_energy_pin_catches_mutant(name, monkeypatch):
     MUTANTS[name](monkeypatch)
     with pytest.raises(AssertionError):
         test_leapfrog_energy_error_scales_as_eps_squared()
+
+
+# ------------------------------------------------ improved operator (fat + Naik) ---
+
+def _dH_imp(eps, nsteps):
+    import oracle.fatten as fat
+    L, U, P, Re, Ro, beta, mass = _setup()
+    return hmc.trajectory(L, U, P, Re, Ro, beta, mass, eps, nsteps, coeffs=fat.asqtad_coeffs(0.9))["dH"]
+
+
+@pytest.mark.slow
+def test_improved_leapfrog_energy_error_scales_as_eps_squared():
+    """the improved operator's force (through the fattening's chain rule)
+    conserves H to O(eps^2): a wrong force leaves dH of O(eps) or O(1)"""
+    tau = 0.2
+    d8, d16 = _dH_imp(tau / 8, 8), _dH_imp(tau / 16, 16)
+    assert abs(d16) < 0.1
+    ratio = d8 / d16
+    assert 3.5 < ratio < 4.5, (d8, d16, ratio)
+
+
+def test_improved_trajectory_reversible():
+    import oracle.fatten as fat
+    L, beta, mass = (4, 2, 2, 4), 5.5, 0.2
+    U, P = li.links(L, "expih", 571, c=0.3), li.momenta(L, 572)
+    Re, Ro = li.vector(L, 573), li.vector(L, 574)
+    w = fat.asqtad_coeffs(0.9)
+    fwd = hmc.trajectory(L, U, P, Re, Ro, beta, mass, 0.05, 3, coeffs=w)
+    back = hmc.trajectory(L, fwd["U"], -fwd["P"], None, None, beta, mass, 0.05, 3, phi=fwd["phi"], coeffs=w)
+    np.testing.assert_allclose(back["U"], U, atol=1e-10)
+    np.testing.assert_allclose(back["P"], -P, atol=1e-9)
+    assert back["dH"] == pytest.approx(-fwd["dH"], abs=1e-8)
+
+
+@pytest.mark.slow
+def test_improved_energy_pin_catches_a_chain_rule_that_stops_at_the_fat_field(monkeypatch):
+    """G_U = G_F (the fat field taken as the link) must break the eps^2 scaling"""
+    import oracle.fatten as fat
+    monkeypatch.setattr(fat, "fatten_vjp", lambda L, U, c, GF, GN: GF)
+    with pytest.raises(AssertionError):
+        test_improved_leapfrog_energy_error_scales_as_eps_squared()

@@ -336,6 +336,24 @@ lgt_status lgt_asqtad_coeffs(double u0, lgt_fat_coeffs *out);
  * Asynchronous. */
 lgt_status lgt_fatten_links(lgt_ctx *ctx, const double *U, const lgt_fat_coeffs *coeffs, double *F, double *N);
 
+/* The chain rule through lgt_fatten_links, for the molecular-dynamics force of
+ * the improved operator: given G_fat and G_naik with
+ * dS = sum Re tr(G_fat^dag dF) + Re tr(G_naik^dag dN) (what lgt_force_improved
+ * writes), G_U receives scale * the G with dS = sum Re tr(G^dag dU) (added to
+ * it when accumulate != 0, else overwriting it). Every staple
+ * P(x) = L(x) M(x+a) L(x+mu)^dag whose output receives Gp(x) passes
+ * L(x)^dag Gp(x) L(x+mu) to M(x+a), Gp(x) L(x+mu) M(x+a)^dag to L(x) and
+ * Gp(x)^dag L(x) M(x+a) to L(x+mu); a backward link L_{-nu}(y) passes the
+ * adjoint of its share to U_nu(y-nu); the nested sums are taken back level by
+ * level, as gathers at each receiving site (no atomics: the result does not
+ * depend on scheduling). All fields canonical [4][V][3][3][2] float64 device
+ * memory; G_U must not overlap U, G_fat or G_naik (LGT_ERR_ARG); coefficients
+ * and scale finite (LGT_ERR_ARG). Needs a context workspace of 18 V matrices
+ * (2.6 kB per site; allocated on first use, LGT_ERR_OOM if that fails).
+ * Asynchronous. */
+lgt_status lgt_fatten_links_vjp(lgt_ctx *ctx, const double *U, const lgt_fat_coeffs *coeffs, const double *G_fat,
+                                const double *G_naik, double scale, int32_t accumulate, double *G_U);
+
 /* ---- the HMC step around the solve ----------------------------------------- *
  * Fields in the canonical layout [4][V][3][3][2] float64, eo site order, device
  * memory: links U, momenta P (traceless anti-Hermitian), derivatives G with
@@ -363,7 +381,8 @@ typedef struct {
     double tol;       /* CG relative residual for the action and every force */
     double u;         /* uniform in [0, 1) for the Metropolis test */
     int32_t nsteps;   /* leapfrog steps */
-    int32_t scheme;   /* LGT_CG_FP64, or LGT_CG_RELIABLE with F32 x 12 inner links */
+    int32_t scheme;   /* LGT_CG_FP64, or LGT_CG_RELIABLE with F32 x 12 inner links
+                         (F32 x 18 fat and Naik fields for the improved trajectory) */
     int32_t reserved[2];
 } lgt_hmc_params;
 
@@ -384,6 +403,17 @@ typedef struct {
  * the trajectory is rejected. Uses context workspace; synchronous. */
 lgt_status lgt_hmc_trajectory(lgt_ctx *ctx, double *U, double *P, const double *R_e, const double *R_o,
                               const lgt_hmc_params *p, lgt_hmc_result *res);
+
+/* lgt_hmc_trajectory with the improved operator of the application the paper
+ * times (Table 4): at every step the fat and Naik fields F(U), N(U) come from
+ * lgt_fatten_links with coeffs and are packed F64 x 18 (LGT_CG_RELIABLE: also
+ * F32 x 18 for the inner solver); the pseudofermion, action and CG use
+ * lgt_dslash_improved's operator, and the fermion force is lgt_force_improved
+ * taken back to U with lgt_fatten_links_vjp. Same arguments, workspace and
+ * errors as lgt_hmc_trajectory, plus coeffs (non-NULL, finite: LGT_ERR_ARG). */
+lgt_status lgt_hmc_trajectory_improved(lgt_ctx *ctx, double *U, double *P, const double *R_e, const double *R_o,
+                                       const lgt_hmc_params *p, const lgt_fat_coeffs *coeffs,
+                                       lgt_hmc_result *res);
 
 /* ---- Table 1 routines, one at a time --------------------------------------- *
  * lgt_routine applies one SU(3) routine of Table 1 to n independent operand

@@ -143,6 +143,11 @@ struct FatCoeffs {
 // of 3 V matrices (the innermost staple fields of one direction at a time)
 hipError_t launch_fatten(const double *U, double *F, double *N, double *W, const Geom &g, const FatCoeffs &w,
                          hipStream_t s);
+// GU (+)= scale * dS/dU from GF = dS/dF and GN = dS/dN (all canonical); ws:
+// workspace of kFatVjpMatrices * V matrices (18 doubles each)
+constexpr int kFatVjpMatrices = 18;
+hipError_t launch_fatten_vjp(const double *U, const double *GF, const double *GN, double *GU, double *ws,
+                             const Geom &g, const FatCoeffs &w, double scale, bool accumulate, hipStream_t s);
 
 // ---- Table 1 routines (routines.hip) ---------------------------------------
 hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, void *c, int64_t n, double s,

@@ -168,6 +168,7 @@ def _setup(l):
         "lgt_routine": (st, [vp, i32, i32, C.c_int64, vp, vp, vp, C.c_double]),
         "lgt_gauge_force": (st, [vp, vp, C.c_double, C.c_double, i32, vp]),
         "lgt_fatten_links": (st, [vp, vp, C.POINTER(_FatCoeffs), vp, vp]),
+        "lgt_fatten_links_vjp": (st, [vp, vp, C.POINTER(_FatCoeffs), vp, vp, C.c_double, i32, vp]),
         "lgt_asqtad_coeffs": (st, [C.c_double, C.POINTER(_FatCoeffs)]),
         "lgt_action_phi_grad": (st, [vp, vp, C.c_double, vp]),
         "lgt_momentum_update": (st, [vp, vp, vp, C.c_double, vp]),
@@ -175,6 +176,8 @@ def _setup(l):
         "lgt_plaquette": (st, [vp, vp, C.POINTER(C.c_double)]),
         "lgt_kinetic_energy": (st, [vp, vp, C.POINTER(C.c_double)]),
         "lgt_hmc_trajectory": (st, [vp, vp, vp, vp, vp, C.POINTER(_HmcParams), C.POINTER(_HmcResult)]),
+        "lgt_hmc_trajectory_improved": (st, [vp, vp, vp, vp, vp, C.POINTER(_HmcParams), C.POINTER(_FatCoeffs),
+                                             C.POINTER(_HmcResult)]),
         "lgt_cg_solve_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), C.POINTER(_Links),
                                        C.POINTER(_Links), C.POINTER(_CgParams), vp, vp, C.POINTER(_CgResult)]),
     }
@@ -523,6 +526,18 @@ class Lattice:
         _check(lib().lgt_fatten_links(self._ctx, pu, C.byref(w), self._field(F, "F"), self._field(N, "N")))
         return F, N
 
+    def fatten_links_vjp(self, U: torch.Tensor, G_fat: torch.Tensor, G_naik: torch.Tensor, coeffs=None,
+                         scale: float = 1.0, G: torch.Tensor | None = None, accumulate: bool = False):
+        """G (+)= scale * dS/dU from G_fat = dS/dF and G_naik = dS/dN through the
+        fattening with coeffs (asqtad_coeffs() by default); canonical fields."""
+        w = _FatCoeffs(*(float(c) for c in (coeffs if coeffs is not None else asqtad_coeffs())))
+        if G is None:
+            G = torch.zeros_like(U) if accumulate else torch.empty_like(U)
+        _check(lib().lgt_fatten_links_vjp(self._ctx, self._field(U, "U"), C.byref(w), self._field(G_fat, "G_fat"),
+                                          self._field(G_naik, "G_naik"), float(scale), int(bool(accumulate)),
+                                          self._field(G, "G")))
+        return G
+
     def plaquette(self, U: torch.Tensor) -> float:
         out = C.c_double()
         _check(lib().lgt_plaquette(self._ctx, self._field(U, "U"), C.byref(out)))
@@ -543,6 +558,20 @@ class Lattice:
                                         self._dev(R_e, torch.float64, self.vec_shape(), "R_e"),
                                         self._dev(R_o, torch.float64, self.vec_shape(), "R_o"),
                                         C.byref(prm), C.byref(res)))
+        return {f[0]: getattr(res, f[0]) for f in _HmcResult._fields_ if f[0] != "reserved"}
+
+    def hmc_trajectory_improved(self, U: torch.Tensor, P: torch.Tensor, R_e: torch.Tensor, R_o: torch.Tensor,
+                                beta: float, mass: float, eps: float, nsteps: int, u: float, coeffs=None,
+                                tol: float = 1e-10, scheme: int = LGT_CG_FP64) -> dict:
+        """hmc_trajectory with the improved operator of the fattened fields
+        (coeffs: asqtad_coeffs() by default)."""
+        w = _FatCoeffs(*(float(c) for c in (coeffs if coeffs is not None else asqtad_coeffs())))
+        prm = _HmcParams(float(beta), float(mass), float(eps), float(tol), float(u), int(nsteps), int(scheme))
+        res = _HmcResult()
+        _check(lib().lgt_hmc_trajectory_improved(self._ctx, self._field(U, "U"), self._field(P, "P"),
+                                                 self._dev(R_e, torch.float64, self.vec_shape(), "R_e"),
+                                                 self._dev(R_o, torch.float64, self.vec_shape(), "R_o"),
+                                                 C.byref(prm), C.byref(w), C.byref(res)))
         return {f[0]: getattr(res, f[0]) for f in _HmcResult._fields_ if f[0] != "reserved"}
 
     # -- improved (fat + Naik) operator

@@ -83,12 +83,14 @@ int main(void)
     EXPECT(lgt_cg_solve_improved(NULL, &Ul, &Ul, NULL, NULL, &prm, NULL, NULL, &res), LGT_ERR_ARG);
     EXPECT(lgt_force_improved(NULL, &Ul, &Ul, NULL, 1.0, NULL, NULL), LGT_ERR_ARG);
     EXPECT(lgt_fatten_links(NULL, NULL, &w, NULL, NULL), LGT_ERR_ARG);
+    EXPECT(lgt_fatten_links_vjp(NULL, NULL, &w, NULL, NULL, 1.0, 0, NULL), LGT_ERR_ARG);
     EXPECT(lgt_gauge_force(NULL, NULL, 5.6, 1.0, 0, NULL), LGT_ERR_ARG);
     EXPECT(lgt_momentum_update(NULL, NULL, NULL, 0.1, NULL), LGT_ERR_ARG);
     EXPECT(lgt_link_update(NULL, NULL, 0.1, NULL), LGT_ERR_ARG);
     EXPECT(lgt_plaquette(NULL, NULL, d), LGT_ERR_ARG);
     EXPECT(lgt_kinetic_energy(NULL, NULL, d), LGT_ERR_ARG);
     EXPECT(lgt_hmc_trajectory(NULL, NULL, NULL, NULL, NULL, NULL, NULL), LGT_ERR_ARG);
+    EXPECT(lgt_hmc_trajectory_improved(NULL, NULL, NULL, NULL, NULL, NULL, &w, NULL), LGT_ERR_ARG);
     EXPECT(lgt_routine(NULL, 1, 0, 16, NULL, NULL, NULL, 1.0), LGT_ERR_ARG);
     EXPECT(lgt_pack_vec_mrhs(NULL, 1, 4, NULL, NULL), LGT_ERR_ARG);
     EXPECT(lgt_unpack_vec_mrhs(NULL, 1, 4, NULL, NULL), LGT_ERR_ARG);

@@ -152,6 +152,8 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_kinetic_energy": (None, None, C.byref(d)),
         "lgt_hmc_trajectory": (None, None, None, None, None, None, None),
         "lgt_fatten_links": (None, None, None, None, None),
+        "lgt_fatten_links_vjp": (None, None, None, None, None, 1.0, 0, None),
+        "lgt_hmc_trajectory_improved": (None, None, None, None, None, None, None, None),
         "lgt_unpack_links": (None, None, 0, 18, None),
         "lgt_action_phi_grad": (None, None, 1.0, None),
         "lgt_force_noalloc": (None, None, None, 1.0, None),

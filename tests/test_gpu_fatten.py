@@ -161,3 +161,62 @@ def test_fatten_argument_checks(dev):
         with pytest.raises(P.LgtError) as e:
             lat.fatten_links(U, (float("nan"),) + W[1:])
         assert e.value.status == -1
+
+
+# ------------------------------------------------ chain rule (lgt_fatten_links_vjp) ---
+# G_U sums a few hundred products per link in an order that differs from the
+# oracle's level-by-level one: 1e-12 norm-wise and relative to the largest entry.
+
+@pytest.mark.parametrize("L,weights", [((4, 4, 4, 4), "generic"), ((2, 4, 2, 6), "generic"),
+                                       ((6, 4, 4, 8), "asqtad"), ((8, 8, 8, 8), "asqtad")])
+def test_fatten_vjp_vs_oracle(dev, L, weights):
+    print("fatten_vjp", L, weights, flush=True)
+    w = W if weights == "generic" else P.asqtad_coeffs(0.87)
+    U = li.links(L, "haar", 7411)
+    g = li.rng(7412)
+    GF, GN = g.standard_normal(U.shape), g.standard_normal(U.shape)
+    want = ofat.fatten_vjp(L, U, w, GF, GN)
+    with P.Lattice(L) as lat:
+        got = lat.fatten_links_vjp(_t(U, dev), _t(GF, dev), _t(GN, dev), w).cpu().numpy()
+    _check(got, want, 1e-12)
+
+
+def test_fatten_vjp_scale_and_accumulate(dev):
+    L = (4, 2, 4, 6)
+    U = li.links(L, "haar", 7421)
+    g = li.rng(7422)
+    GF, GN, G0 = (g.standard_normal(U.shape) for _ in range(3))
+    want = G0 - 0.75 * ofat.fatten_vjp(L, U, W, GF, GN)
+    with P.Lattice(L) as lat:
+        G = _t(G0, dev)
+        lat.fatten_links_vjp(_t(U, dev), _t(GF, dev), _t(GN, dev), W, scale=-0.75, G=G, accumulate=True)
+        _check(G.cpu().numpy(), want, 1e-12)
+        with pytest.raises(P.LgtError):  # G_U overlapping an input
+            Ut = _t(U, dev)
+            lat.fatten_links_vjp(Ut, _t(GF, dev), _t(GN, dev), W, G=Ut)
+
+
+def test_fatten_vjp_16_directional_derivative(dev):
+    """16^4 (the trajectory benchmark's lattice): <G_U, E> against central
+    differences of sum Re tr(R_F^dag F) + Re tr(R_N^dag N) along E, with F, N
+    from the GPU forward (itself checked against the oracle above)"""
+    L = (16, 16, 16, 16)
+    print("fatten_vjp 16^4", flush=True)
+    w = P.asqtad_coeffs(0.9)
+    g = li.rng(7431)
+    with P.Lattice(L) as lat:
+        U = _t(li.links(L, "haar", 7432), dev)
+        RF = _t(g.standard_normal(U.shape), dev)
+        RN = _t(g.standard_normal(U.shape), dev)
+        G = lat.fatten_links_vjp(U, RF, RN, w)
+
+        def S(Ux):
+            F, N = lat.fatten_links(Ux, w)
+            return float((RF * F).sum() + (RN * N).sum())
+
+        for k in range(3):
+            E = _t(g.standard_normal(U.shape), dev)
+            h = 1e-5
+            fd = (S(U + h * E) - S(U - h * E)) / (2 * h)
+            an = float((G * E).sum())
+            assert abs(fd - an) <= 1e-6 * abs(an), (k, fd, an)

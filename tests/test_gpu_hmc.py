@@ -167,3 +167,48 @@ def test_trajectory_energy_error_is_second_order(dev):
             dH.append(r["dH"])
     print(f"\nhmc dH: {dH}", flush=True)
     assert 3.5 <= abs(dH[0] / dH[1]) <= 4.5
+
+
+# ------------------------------------------------ improved operator (fat + Naik) ---
+
+@pytest.mark.parametrize("scheme", ["fp64", "reliable_f32r18"])
+def test_improved_trajectory_vs_oracle(dev, scheme):
+    """lgt_hmc_trajectory_improved against the oracle's improved trajectory
+    (fattening, improved CG and force, chain rule through the fattening)"""
+    import oracle.fatten as ofat
+    L, beta, mass, eps, nsteps, tol = (4, 4, 4, 4), 5.5, 0.2, 0.025, 8, 1e-12
+    w = ofat.asqtad_coeffs(0.9)
+    U, Pc, Re, Ro = _traj_inputs(L, 671)
+    ref = hmc.trajectory(L, U, Pc, Re, Ro, beta, mass, eps, nsteps, tol=tol, coeffs=w)
+    sch = P_.LGT_CG_FP64 if scheme == "fp64" else P_.LGT_CG_RELIABLE
+    with P_.Lattice(L) as lat:
+        Ut, Pt = _t(U, dev), _t(hmc.real(Pc), dev)
+        r = lat.hmc_trajectory_improved(Ut, Pt, _t(Re, dev), _t(Ro, dev), beta, mass, eps, nsteps, u=0.0,
+                                        coeffs=w, tol=tol, scheme=sch)
+        Ug, Pg = Ut.cpu().numpy(), Pt.cpu().numpy()
+    print(f"\nhmc improved {scheme}: dH gpu {r['dH']:.10f} oracle {ref['dH']:.10f}; "
+          f"cg {r['cg_solves']} solves {r['cg_iters']} iters", flush=True)
+    assert r["accepted"] == 1
+    for k in ("H0", "Sg0", "Sf0", "K0", "H1", "Sg1", "Sf1", "K1"):
+        assert r[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-9), k
+    assert abs(r["dH"] - ref["dH"]) <= 1e-8
+    assert np.abs(Ug - ref["U"]).max() <= 1e-10
+    assert np.abs(Pg - hmc.real(ref["P"])).max() <= 1e-9
+    assert r["cg_solves"] == nsteps + 3
+
+
+def test_improved_trajectory_energy_error_is_second_order(dev):
+    L, beta, mass = (4, 4, 4, 4), 5.5, 0.2
+    U, Pc, Re, Ro = _traj_inputs(L, 681)
+    w = P_.asqtad_coeffs(0.9)
+    dH = []
+    with P_.Lattice(L) as lat:
+        for eps, n in ((0.04, 5), (0.02, 10)):
+            r = lat.hmc_trajectory_improved(_t(U, dev), _t(hmc.real(Pc), dev), _t(Re, dev), _t(Ro, dev), beta,
+                                            mass, eps, n, u=0.0, coeffs=w, tol=1e-12)
+            dH.append(r["dH"])
+        with pytest.raises(P_.LgtError):  # non-finite weights
+            lat.hmc_trajectory_improved(_t(U, dev), _t(hmc.real(Pc), dev), _t(Re, dev), _t(Ro, dev), beta,
+                                        mass, 0.02, 1, u=0.0, coeffs=(1.0, 0, 0, 0, 0, float("nan")))
+    print(f"\nhmc improved dH: {dH}", flush=True)
+    assert 3.5 <= abs(dH[0] / dH[1]) <= 4.5

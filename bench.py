@@ -704,17 +704,16 @@ def main():
         improved = {"lattice": list(L), "flop_per_site": P.IMPROVED_FLOP_PER_SITE, "dslash": {}}
         for name, (Fp, Np) in imp_packed.items():
             prec = Fp.prec
-            hops0, st0 = lat.dslash_variant(prec, P.LGT_R18)
             vb = P.vec_bytes_per_site(prec)
             by = (16 * P.link_bytes_per_dir(prec, P.LGT_R18) + 2 * vb) * Vh
             xi = lat.pack_vec(bi, prec)
             oi = lat.native_vec(prec)
             t = {}
             for streaming in (1, 0):
-                lat.set_dslash_variant(prec, P.LGT_R18, hops0, streaming)
+                lat.set_dslash_improved_variant(prec, streaming, 256)
                 t[streaming] = statistics.median(event_times(lat, lambda: lat.dslash_improved(Fp, Np, xi, 1, oi), 20, 5))
             best = min(t, key=t.get)
-            lat.set_dslash_variant(prec, P.LGT_R18, hops0, best)
+            lat.set_dslash_improved_variant(prec, best, 256)
             ms = t[best]
             improved["dslash"][name] = {"us": round(ms * 1e3, 2), "GBps": round(by / (ms * 1e-3) / 1e9, 1),
                                         "GFLOPs": round(P.IMPROVED_FLOP_PER_SITE * Vh / (ms * 1e-3) / 1e9, 1),
@@ -747,12 +746,20 @@ def main():
         Ff, Nf = lat.fatten_links(Uh)
         tf = statistics.median(event_times(lat, lambda: lat.fatten_links(Uh, F=Ff, N=Nf), 5, 1))
         fat_flop = 20286 * 4 * V
+        # its chain rule (the improved force's last step), with F and N standing
+        # in for dS/dF and dS/dN: 222 complex 3x3 products per link
+        Gv = lat.fatten_links_vjp(Uh, Ff, Nf)
+        tv = statistics.median(event_times(lat, lambda: lat.fatten_links_vjp(Uh, Ff, Nf, G=Gv), 5, 1))
+        vjp_flop = 222 * 216 * 4 * V
         Ffp, Nfp = lat.pack_links(Ff, P.LGT_F64, P.LGT_R18), lat.pack_links(Nf, P.LGT_F64, P.LGT_R18)
-        del Uh, Ff, Nf
+        del Uh, Ff, Nf, Gv
         _, r = lat.cg_solve_improved(Ffp, Nfp, bi, ci["mass"], tol=ci["tol"])
         improved["fatten"] = {"ms": round(tf, 3), "flop_per_link": 20286, "path_sum_flop_per_link": 40320,
                               "GFLOPs": round(fat_flop / (tf * 1e-3) / 1e9, 1),
                               "frac_of_fp64_vector_peak": round(fat_flop / (tf * 1e-3) / 78.6e12, 4),
+                              "vjp": {"ms": round(tv, 3), "products_per_link": 222,
+                                      "GFLOPs": round(vjp_flop / (tv * 1e-3) / 1e9, 1),
+                                      "frac_of_fp64_vector_peak": round(vjp_flop / (tv * 1e-3) / 78.6e12, 4)},
                               "cg_fp64_on_fattened_haar": {"seconds": round(r.seconds, 4), "iters": r.iters,
                                                            "true_rel_resid": r.true_rel_resid, "status": r.status}}
         log(f"fatten: {improved['fatten']}")
@@ -783,6 +790,25 @@ def main():
                             "cg_solves": r["cg_solves"], "cg_iters": r["cg_iters"]}
             log(f"hmc {key}: {hmc_res[key]}")
         hmc_res["speedup_f32_vs_fp64"] = round(hmc_res["fp64"]["seconds"] / hmc_res["f32r12_reliable"]["seconds"], 3)
+        # the same trajectory with the improved operator (the application's
+        # action): asqtad weights with the tadpole factor u0 = (mean plaquette / 3)^(1/4)
+        # of the starting field, fattening and its chain rule at every step
+        u0 = (hl.plaquette(U0) / (6 * li.volume(ch["L"])) / 3.0) ** 0.25
+        w = P.asqtad_coeffs(u0)
+        if not args.no_tune:  # the improved operator's own variants, on the fattened starting field
+            F0, N0 = hl.fatten_links(U0, w)
+            for prec in (P.LGT_F64, P.LGT_F32):
+                hl.tune_dslash_improved(hl.pack_links(F0, prec, P.LGT_R18), hl.pack_links(N0, prec, P.LGT_R18))
+            del F0, N0
+        hl.hmc_trajectory_improved(U0.clone(), P0.clone(), Re, Ro, coeffs=w, **dict(kw, nsteps=1))
+        imp = {"u0": round(u0, 6)}
+        for key, sch in (("fp64", P.LGT_CG_FP64), ("f32r18_reliable", P.LGT_CG_RELIABLE)):
+            r = hl.hmc_trajectory_improved(U0.clone(), P0.clone(), Re, Ro, coeffs=w, scheme=sch, **kw)
+            imp[key] = {"seconds": round(r["seconds"], 4), "dH": r["dH"], "accepted": r["accepted"],
+                        "cg_solves": r["cg_solves"], "cg_iters": r["cg_iters"]}
+            log(f"hmc improved {key}: {imp[key]}")
+        imp["speedup_f32_vs_fp64"] = round(imp["fp64"]["seconds"] / imp["f32r18_reliable"]["seconds"], 3)
+        hmc_res["improved"] = imp
         hl.close()
         del U0, P0, Re, Ro
 

@@ -164,6 +164,22 @@ lgt_status lgt_get_dslash_workgroup(lgt_ctx *ctx, int32_t prec, int32_t recon, i
  * (device architecture, lattice, format) is used without timing unless
  * LGT_TUNE=force; new results are appended to that file. */
 lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[24]);
+/* The improved operator's Dslash (lgt_dslash_improved, lgt_cg_solve_improved,
+ * lgt_force_improved) keeps its own choice per precision (LGT_F64 or LGT_F32,
+ * 18 reals): streaming (1) or cached (0) link loads and the workgroup size (64,
+ * 128 or 256 sites; LGT_ERR_ARG otherwise), apart from the one-link
+ * operator's choice for the same format. Default: 256 sites, streaming when
+ * the fat and Naik fields together exceed 1.5 times the 256 MB Infinity Cache.
+ * Speed only, as for the one-link variants. */
+lgt_status lgt_set_dslash_improved_variant(lgt_ctx *ctx, int32_t prec, int32_t streaming, int32_t threads);
+lgt_status lgt_get_dslash_improved_variant(lgt_ctx *ctx, int32_t prec, int32_t *streaming, int32_t *threads);
+/* Time the improved operator's CG pair (as lgt_tune_dslash does) on fat and
+ * naik (one 18-real format) for streaming and cached link loads with 256-,
+ * 128- and 64-site workgroups (the smaller ones only below 1024 workgroups of
+ * 256 sites) and keep the first within 1 % of the fastest. times_us (host, may
+ * be NULL; 6 entries, -1 for untimed): (streaming, 256), (cached, 256),
+ * (streaming, 128), (cached, 128), (streaming, 64), (cached, 64). Synchronises. */
+lgt_status lgt_tune_dslash_improved(lgt_ctx *ctx, const lgt_links *fat, const lgt_links *naik, double times_us[6]);
 
 /* ---- geometry export (Sec. 1: unique 4-tuple per site, 8 neighbours) ------- */
 

@@ -102,6 +102,19 @@ lgt_status check_links(const lgt_links *U, bool need_f64, Fmt *f)
     return check_ptr(U->ptr, "link field");
 }
 
+lgt_status check_improved(const lgt_links *F, const lgt_links *N, bool need_f64, Fmt *f)
+{
+    lgt_status s;
+    Fmt ff, fn;
+    if ((s = check_links(F, need_f64, &ff)) != LGT_OK) return s;
+    if ((s = check_links(N, need_f64, &fn)) != LGT_OK) return s;
+    if (ff != fn) return fail(LGT_ERR_ARG, "fat and Naik links must have the same format");
+    if (ff != F64R18 && ff != F32R18)
+        return fail(LGT_ERR_UNSUPPORTED, "the improved operator takes 18-real links (F64 or F32)");
+    *f = ff;
+    return LGT_OK;
+}
+
 static lgt_status geom_check(const lgt_geom *g)
 {
     if (!g) return fail(LGT_ERR_ARG, "geometry is NULL");
@@ -257,6 +270,8 @@ lgt_status lgt_create(const lgt_geom *g, int32_t device, void *hip_stream, lgt_c
             c->hpi[f] = 8;
             c->ntl[f] = 0;
         }
+    // the improved operator reads two 18-real fields
+    for (int f = 0; f < FMT_COUNT; f++) c->intl[f] = 2 * V * 4 * link_bytes_per_site_dir((Fmt)f) > kMallBytes * 3 / 2;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     *out = c;
@@ -456,19 +471,6 @@ lgt_status check_cg_params(const lgt_cg_params *p)
 }
 
 // improved operator: fat and Naik fields in one 18-real format
-lgt_status check_improved(const lgt_links *F, const lgt_links *N, bool need_f64, Fmt *f)
-{
-    lgt_status s;
-    Fmt ff, fn;
-    if ((s = check_links(F, need_f64, &ff)) != LGT_OK) return s;
-    if ((s = check_links(N, need_f64, &fn)) != LGT_OK) return s;
-    if (ff != fn) return fail(LGT_ERR_ARG, "fat and Naik links must have the same format");
-    if (ff != F64R18 && ff != F32R18)
-        return fail(LGT_ERR_UNSUPPORTED, "the improved operator takes 18-real links (F64 or F32)");
-    *f = ff;
-    return LGT_OK;
-}
-
 } // namespace
 
 lgt_status lgt_cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, const lgt_cg_params *p,
@@ -504,8 +506,8 @@ lgt_status lgt_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_links
     a.g = c->g;
     a.par = out_parity;
     a.gate = GATE_NONE;
-    a.l = dslash_launch(c, f);
-    a.ntl = c->ntl[f];
+    a.l = dslash_launch_improved(c, f);
+    a.ntl = c->intl[f];
     LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
     return LGT_OK;
 }
@@ -633,9 +635,8 @@ lgt_status lgt_force_improved(lgt_ctx *c, const lgt_links *fat, const lgt_links 
     a.g = c->g;
     a.par = LGT_ODD;
     a.gate = GATE_NONE;
-    a.l = dslash_launch(c, f);
-    a.hpi = c->hpi[f];
-    a.ntl = c->ntl[f];
+    a.l = dslash_launch_improved(c, f);
+    a.ntl = c->intl[f];
     LGT_HIP(launch_dslash(f, EPI_PLAIN, a, c->stream));
     LGT_HIP(launch_force(Xn, Yn, scale, G_fat, c->g, c->stream, false));
     LGT_HIP(launch_force(Xn, Yn, scale, G_naik, c->g, c->stream, true));

@@ -28,6 +28,13 @@ struct lgt_ctx {
     // Dslash workgroup size per link format (64, 128 or 256 sites): small
     // lattices have too few 256-site workgroups to reach every CU
     int dbs[lgt::FMT_COUNT] = {256, 256, 256, 256, 256};
+    // the improved operator's Dslash (fat + Naik fields, 18-real formats):
+    // workgroup size and streaming link loads per format, kept apart from the
+    // one-link choices above (twice the link traffic, 16 neighbours). Set by
+    // lgt_set_dslash_improved_variant or lgt_tune_dslash_improved; lgt_create
+    // streams when the two fields exceed the Infinity Cache by half.
+    int ibs[lgt::FMT_COUNT] = {256, 256, 256, 256, 256};
+    int intl[lgt::FMT_COUNT] = {0, 0, 0, 0, 0};
     // multi-RHS Dslash: engine (0 lane per RHS, 1 four-lane VALU, 2 four-lane
     // MFMA) last set for all cases, and the variant per (link format, log2 N):
     // engine and groups of four lanes per site. Set by lgt_set_mrhs_engine,
@@ -70,6 +77,8 @@ inline bool fmt_is_f64(Fmt f) { return f == F64R18 || f == F64R12; }
 size_t link_bytes_per_site_dir(Fmt f);
 
 lgt_status check_links(const lgt_links *U, bool need_f64, Fmt *f);
+// fat and Naik fields of the improved operator: one 18-real format (F64, or F32 unless need_f64)
+lgt_status check_improved(const lgt_links *F, const lgt_links *N, bool need_f64, Fmt *f);
 lgt_status check_ptr(const void *p, const char *what);
 
 // make ctx's device current for the scope, restoring the previous one
@@ -95,6 +104,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
 
 // launch geometry of the one-link / improved Dslash for link format f
 inline Launch dslash_launch(const lgt_ctx *c, Fmt f) { return site_launch(c->g.Vh, c->dbs[f]); }
+inline Launch dslash_launch_improved(const lgt_ctx *c, Fmt f) { return site_launch(c->g.Vh, c->ibs[f]); }
 
 // the fermion force given its two native scratch vectors (X and Y = D_oe X)
 lgt_status force_run(lgt_ctx *c, const lgt_links *U, Fmt f, const double *X, double scale, double *G, double *Xn,

@@ -108,7 +108,9 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     void *xlo = mixed ? workspace(c, "cg.xlo", vlo) : x64;
     // Dslash launches of the two link formats (their workgroup sizes are
     // per-format choices, so their partial-sum counts may differ)
-    const Launch lhi = dslash_launch(c, fhi), llo = dslash_launch(c, flo);
+    const bool imp = U3hi != nullptr;
+    const Launch lhi = imp ? dslash_launch_improved(c, fhi) : dslash_launch(c, fhi);
+    const Launch llo = imp ? dslash_launch_improved(c, flo) : dslash_launch(c, flo);
     // two partial-sum buffers: the update reads D_eo's while writing its own
     const size_t np1 = (size_t)std::max(std::max(lhi.nblk_pad, llo.nblk_pad), l.nblk_pad);
     double *partials = (double *)workspace(c, "cg.partials", sizeof(double) * (np1 + (size_t)l.nblk_pad));
@@ -149,7 +151,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.partials = partials;
         a.st = dst;
         a.hpi = c->hpi[f];
-        a.ntl = c->ntl[f];
+        a.ntl = imp ? c->intl[f] : c->ntl[f];
         return launch_dslash(f, epi, a, s, e0, e1);
     };
     auto F = [&](const double *parts, int fin, int gate, int nparts) {

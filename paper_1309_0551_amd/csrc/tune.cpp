@@ -284,6 +284,110 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[24])
     return LGT_OK;
 }
 
+lgt_status lgt_set_dslash_improved_variant(lgt_ctx *c, int32_t prec, int32_t streaming, int32_t threads)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    if (!fmt_of(prec, LGT_R18, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported precision %d", prec);
+    if (streaming != 0 && streaming != 1) return fail(LGT_ERR_ARG, "streaming must be 0 or 1");
+    if (!dslash_bs_ok(threads)) return fail(LGT_ERR_ARG, "workgroup size must be 64, 128 or 256");
+    c->intl[f] = streaming;
+    c->ibs[f] = threads;
+    return LGT_OK;
+}
+
+lgt_status lgt_get_dslash_improved_variant(lgt_ctx *c, int32_t prec, int32_t *streaming, int32_t *threads)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (!streaming || !threads) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    Fmt f;
+    if (!fmt_of(prec, LGT_R18, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported precision %d", prec);
+    *streaming = c->intl[f];
+    *threads = c->ibs[f];
+    return LGT_OK;
+}
+
+lgt_status lgt_tune_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_links *naik, double times_us[6])
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    lgt_status st = check_improved(fat, naik, false, &f);
+    if (st != LGT_OK) return st;
+    DeviceScope ds(c->device);
+    const size_t vb = (size_t)c->g.Vh * (fmt_is_f64(f) ? 48 : 24);
+    const Launch l64 = site_launch(c->g.Vh, 64); // the most partial sums of any workgroup size
+    void *in = workspace(c, "tune.in", vb);
+    void *out = workspace(c, "tune.out", vb);
+    void *ap = workspace(c, "tune.ap", vb);
+    double *parts = (double *)workspace(c, "tune.partials", sizeof(double) * (size_t)l64.nblk_pad);
+    if (!in || !out || !ap || !parts) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
+    LGT_HIP(launch_zero(in, vb, c->stream));
+    hipEvent_t e0, e1;
+    LGT_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LGT_ERR_DEVICE, "hipEventCreate failed");
+    }
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.U = fat->ptr;
+    a.U3 = naik->ptr;
+    a.g = c->g;
+    a.gate = GATE_NONE;
+    a.m4 = 0.04;
+    a.partials = parts;
+    // the CG's pair, as for the one-link operator
+    auto pair = [&]() {
+        a.par = LGT_ODD;
+        a.in = in;
+        a.out = out;
+        a.aux0 = nullptr;
+        hipError_t r = launch_dslash(f, EPI_PLAIN, a, c->stream);
+        if (r != hipSuccess) return r;
+        a.par = LGT_EVEN;
+        a.in = out;
+        a.out = ap;
+        a.aux0 = in;
+        return launch_dslash(f, EPI_A, a, c->stream);
+    };
+    // (streaming, cached) x (256, 128, 64 sites); smaller workgroups only below
+    // 1024 workgroups of 256 sites, as for the one-link operator
+    constexpr int kN = 2 * kNumBs;
+    double t[kN];
+    double best_t = 1e300;
+    const int reps = 5;
+    const bool small = site_launch(c->g.Vh).nblk < 1024;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kN && e == hipSuccess; i++) {
+        t[i] = -1.0;
+        if (kBsList[i / 2] != 256 && !small) continue;
+        a.ntl = 1 - (i & 1);
+        a.l = site_launch(c->g.Vh, kBsList[i / 2]);
+        e = pair();
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = pair();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        t[i] = 1e3 * ms / (2 * reps);
+        if (e == hipSuccess && t[i] < best_t) best_t = t[i];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(LGT_ERR_DEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+    int best = 0;
+    while (best < kN - 1 && (t[best] < 0.0 || t[best] > 1.01 * best_t)) best++;
+    c->intl[f] = 1 - (best & 1);
+    c->ibs[f] = kBsList[best / 2];
+    if (times_us)
+        for (int i = 0; i < kN; i++) times_us[i] = t[i];
+    return LGT_OK;
+}
+
 } // extern "C"
 
 // ---------------------------------------------------------- multi-RHS ---

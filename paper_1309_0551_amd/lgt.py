@@ -148,6 +148,9 @@ def _setup(l):
         "lgt_set_dslash_workgroup": (st, [vp, i32, i32, i32]),
         "lgt_get_dslash_workgroup": (st, [vp, i32, i32, C.POINTER(C.c_int32)]),
         "lgt_tune_dslash": (st, [vp, C.POINTER(_Links), C.POINTER(C.c_double)]),
+        "lgt_set_dslash_improved_variant": (st, [vp, i32, i32, i32]),
+        "lgt_get_dslash_improved_variant": (st, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "lgt_tune_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), C.POINTER(C.c_double)]),
         "lgt_apply_normal": (st, [vp, C.POINTER(_Links), C.c_double, vp, vp, C.POINTER(C.c_double)]),
         "lgt_stream_copy": (st, [vp, vp, vp, C.c_size_t]),
         "lgt_stream_read": (st, [vp, vp, C.c_size_t, vp]),
@@ -331,6 +334,27 @@ class Lattice:
         w = C.c_int32()
         _check(lib().lgt_get_dslash_workgroup(self._ctx, prec, recon, C.byref(w)))
         return int(w.value)
+
+    # (streaming, workgroup size) in the order lgt_tune_dslash_improved reports them
+    TUNE_IMPROVED_VARIANTS = ((1, 256), (0, 256), (1, 128), (0, 128), (1, 64), (0, 64))
+
+    def set_dslash_improved_variant(self, prec: int, streaming: int, threads: int = 256):
+        """The improved operator's Dslash for 18-real links of precision prec:
+        streaming (1) or cached (0) link loads, 64/128/256-site workgroups."""
+        _check(lib().lgt_set_dslash_improved_variant(self._ctx, prec, int(streaming), int(threads)))
+
+    def dslash_improved_variant(self, prec: int) -> tuple:
+        st, w = C.c_int32(), C.c_int32()
+        _check(lib().lgt_get_dslash_improved_variant(self._ctx, prec, C.byref(st), C.byref(w)))
+        return int(st.value), int(w.value)
+
+    def tune_dslash_improved(self, F: "PackedLinks", N: "PackedLinks") -> dict:
+        """Time the improved operator's variants on (F, N) and keep the fastest;
+        returns {(streaming, workgroup size): us} for the timed ones."""
+        df, dn = F.desc(), N.desc()
+        t = (C.c_double * len(self.TUNE_IMPROVED_VARIANTS))()
+        _check(lib().lgt_tune_dslash_improved(self._ctx, C.byref(df), C.byref(dn), t))
+        return {v: t[i] for i, v in enumerate(self.TUNE_IMPROVED_VARIANTS) if t[i] >= 0}
 
     def cg_profile(self) -> dict:
         """Mean times (ms) of the vector kernels of the timed iterations of the last CG with timing on."""

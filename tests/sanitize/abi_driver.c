@@ -84,6 +84,9 @@ int main(void)
     EXPECT(lgt_force_improved(NULL, &Ul, &Ul, NULL, 1.0, NULL, NULL), LGT_ERR_ARG);
     EXPECT(lgt_fatten_links(NULL, NULL, &w, NULL, NULL), LGT_ERR_ARG);
     EXPECT(lgt_fatten_links_vjp(NULL, NULL, &w, NULL, NULL, 1.0, 0, NULL), LGT_ERR_ARG);
+    EXPECT(lgt_set_dslash_improved_variant(NULL, 0, 1, 256), LGT_ERR_ARG);
+    EXPECT(lgt_get_dslash_improved_variant(NULL, 0, &i32, &i32), LGT_ERR_ARG);
+    EXPECT(lgt_tune_dslash_improved(NULL, &Ul, &Ul, d), LGT_ERR_ARG);
     EXPECT(lgt_gauge_force(NULL, NULL, 5.6, 1.0, 0, NULL), LGT_ERR_ARG);
     EXPECT(lgt_momentum_update(NULL, NULL, NULL, 0.1, NULL), LGT_ERR_ARG);
     EXPECT(lgt_link_update(NULL, NULL, 0.1, NULL), LGT_ERR_ARG);

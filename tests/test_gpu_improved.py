@@ -208,3 +208,55 @@ def test_improved_autograd_action(dev):
     assert _rel(Ft.grad.cpu().numpy(), 1.5 * GFo) <= 1e-8
     assert _rel(Nt.grad.cpu().numpy(), 1.5 * GNo) <= 1e-8
     assert _rel(pt.grad.cpu().numpy(), 1.5 * 2 * Xo) <= 1e-8
+
+
+@pytest.mark.parametrize("fmt", sorted(FMTS))
+@pytest.mark.parametrize("streaming,bs", [(1, 256), (0, 256), (1, 128), (0, 128), (1, 64), (0, 64)])
+def test_improved_variants(dev, fmt, streaming, bs):
+    """Every improved-operator variant (link loads x workgroup size) against the
+    oracle at 12x16x16x18 (several hundred workgroups) and 10x8x12x6 (ragged),
+    and the one-link choice for the same format left as it was."""
+    prec, _ = FMTS[fmt]
+    for L, bc in (((12, 16, 16, 18), (1, 1, 1, -1)), ((10, 8, 12, 6), (-1, 1, 1, 1))):
+        F, N = li.improved_links(L, 431)
+        with P.Lattice(L, bc) as lat:
+            one_link = (lat.dslash_variant(prec, P.LGT_R18), lat.dslash_workgroup(prec, P.LGT_R18))
+            lat.set_dslash_improved_variant(prec, streaming, bs)
+            assert lat.dslash_improved_variant(prec) == (streaming, bs)
+            assert (lat.dslash_variant(prec, P.LGT_R18), lat.dslash_workgroup(prec, P.LGT_R18)) == one_link
+            Fp = lat.pack_links(_t(F, dev), prec, P.LGT_R18)
+            Np = lat.pack_links(_t(N, dev), prec, P.LGT_R18)
+            for par in (0, 1):
+                chi = li.vector(L, 432 + par)
+                got = lat.unpack_vec(lat.dslash_improved(Fp, Np, lat.pack_vec(_t(chi, dev), prec), par),
+                                     prec).cpu().numpy()
+                ref = oracle.dslash_imp(L, F, N, chi, par, bc)
+                if prec == P.LGT_F64:
+                    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (fmt, L, par)
+                else:
+                    lowprec.check_dslash_improved(got, L, F, N, chi, par, bc, None, (fmt, L, par))
+
+
+def test_improved_tuner_and_small_workgroup_solve(dev):
+    """lgt_tune_dslash_improved keeps one of the variants it timed; a mixed CG
+    and the force with 64-site workgroups match the oracle."""
+    L, mass, tol = (8, 8, 8, 8), 0.1, 1e-10
+    F, N = li.improved_links(L, 441)
+    b = li.vector(L, 442)
+    with P.Lattice(L) as lat:
+        Ft, Nt = _t(F, dev), _t(N, dev)
+        Fh, Nh = lat.pack_links(Ft, P.LGT_F64, P.LGT_R18), lat.pack_links(Nt, P.LGT_F64, P.LGT_R18)
+        Fl, Nl = lat.pack_links(Ft, P.LGT_F32, P.LGT_R18), lat.pack_links(Nt, P.LGT_F32, P.LGT_R18)
+        t = lat.tune_dslash_improved(Fh, Nh)
+        assert (1, 256) in t and (0, 64) in t  # 8^4: 8 workgroups of 256, so all six are timed
+        assert lat.dslash_improved_variant(P.LGT_F64) in t
+        for prec in (P.LGT_F64, P.LGT_F32):
+            lat.set_dslash_improved_variant(prec, 0, 64)
+        x, res = lat.cg_solve_improved(Fh, Nh, _t(b, dev), mass, tol=tol, scheme=P.LGT_CG_RELIABLE, F_lo=Fl, N_lo=Nl)
+        xg = x.cpu().numpy()
+        GF, GN = lat.force_improved(Fh, Nh, x)
+        GFo, GNo = oracle.force_imp(L, F, N, xg)
+    rr = float(np.linalg.norm(b - oracle.apply_A_imp(L, F, N, mass, xg)) / np.linalg.norm(b))
+    assert res.status == 0 and rr <= 1.05 * tol
+    for g, o in ((GF.cpu().numpy(), GFo), (GN.cpu().numpy(), GNo)):
+        assert np.abs(g - o).max() <= 1e-12 * np.abs(o).max()

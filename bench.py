@@ -452,19 +452,26 @@ def main():
     big = [batch_problem(c4["L"], c4["link_seed"], c4["src_seed"], c4["nrhs"])]
     mixed = [batch_problem(Lm, sd, sd + c4m["src_seed_offset"], c4m["nrhs"]) for Lm, sd in c4m["members"]]
     # autotuner: the multi-RHS tile shape of each batched lattice (its inner Dslash)
-    names = {(P.LGT_MRHS_LANE, 1): "lane", (P.LGT_MRHS_VALU4, 1): "valu4_g1", (P.LGT_MRHS_VALU4, 2): "valu4_g2",
-             (P.LGT_MRHS_VALU4, 4): "valu4_g4", (P.LGT_MRHS_MFMA, 1): "mfma_g1", (P.LGT_MRHS_MFMA, 2): "mfma_g2",
-             (P.LGT_MRHS_MFMA, 4): "mfma_g4"}
+    def vname(e, g, st):
+        base = {P.LGT_MRHS_LANE: "lane", P.LGT_MRHS_VALU4: "valu4", P.LGT_MRHS_MFMA: "mfma"}[e]
+        return base if e == P.LGT_MRHS_LANE else f"{base}_g{g}" + ("_lds" if st else "")
+
+    def chosen(lb, n):
+        return vname(*lb.mrhs_variant(P.LGT_F32, P.LGT_R12, n), lb.mrhs_staging(P.LGT_F32, P.LGT_R12, n))
+    # the standalone multi-RHS Dslash, every variant (the batched solver's
+    # inner Dslash runs the chosen engine and groups, with its own staging)
     mrhs_tune = {}
     for lb, uh, ul, bb in big + mixed:
         n = int(bb.shape[0])
         key = f"{'x'.join(map(str, lb.L))}_f32r12_N{n}"
         if args.no_tune:
-            mrhs_tune[key] = {"chosen": names[lb.mrhs_variant(P.LGT_F32, P.LGT_R12, n)]}
+            mrhs_tune[key] = {"chosen": chosen(lb, n)}
             continue
         t = lb.tune_dslash_mrhs(ul, n)
-        mrhs_tune[key] = {"chosen": names[lb.mrhs_variant(P.LGT_F32, P.LGT_R12, n)],
-                          "us": {names[k]: round(v, 2) for k, v in t.items()}}
+        best = min(t.values())
+        mrhs_tune[key] = {"chosen": chosen(lb, n), "us": {vname(*k): round(v, 2) for k, v in t.items()},
+                          "alg_bytes": lb.Vh * (8 * 48 + 2 * n * 24),
+                          "GBps_best": round(lb.Vh * (8 * 48 + 2 * n * 24) / (best * 1e-6) / 1e9, 1)}
         log(f"mrhs tune {key}: {mrhs_tune[key]}")
     torch.cuda.synchronize()
 

@@ -510,14 +510,27 @@ lgt_status lgt_set_mrhs_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32
                                 int32_t groups);
 lgt_status lgt_get_mrhs_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t *engine,
                                 int32_t *groups);
+/* LDS staging for lgt_dslash_mrhs with the four-lane engines (staged = 1, per
+ * format and nrhs; default 0): 512-lane workgroups each copy the input of
+ * their tile's x and y neighbourhood (the tile's cb range widened by Lx/2 on
+ * each side) into LDS once, with 16-byte coalesced loads, and read the x and y
+ * hops from there; only the z and t hops gather from memory. Applies where
+ * the staged tile (3 x (sites + Lx) x nrhs FP32 complex) fits 64 KB of LDS,
+ * else the unstaged kernel runs; lgt_get_mrhs_staging reports what runs. Not
+ * used by the batched solver (it stages its own inner Dslash). Speed only:
+ * results are bit-identical to the unstaged kernel of the same engine and
+ * groups. */
+lgt_status lgt_set_mrhs_staging(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t staged);
+lgt_status lgt_get_mrhs_staging(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t *staged);
 /* Autotuner of the multi-RHS tile shape: times every variant that applies to
  * U's format and nrhs on this lattice (10 launches each, alternating output
  * parity, zero input), keeps the fastest for that (format, nrhs) in the
- * context, and with LGT_TUNE_CACHE set caches it like lgt_tune_dslash.
- * times_us: NULL, or 7 doubles in this order: lane; VALU with 1, 2, 4 groups;
- * MFMA with 1, 2, 4 groups (-1 where a variant does not apply). Uses scratch
- * vectors of the context; synchronous. */
-lgt_status lgt_tune_dslash_mrhs(lgt_ctx *ctx, const lgt_links *U, int32_t nrhs, double times_us[7]);
+ * context (engine, groups and staging), and with LGT_TUNE_CACHE set caches it
+ * like lgt_tune_dslash. times_us: NULL, or 13 doubles in this order: lane;
+ * VALU with 1, 2, 4 groups; MFMA with 1, 2, 4 groups; then the same six
+ * LDS-staged (-1 where a variant does not apply). Uses scratch vectors of the
+ * context; synchronous. */
+lgt_status lgt_tune_dslash_mrhs(lgt_ctx *ctx, const lgt_links *U, int32_t nrhs, double times_us[13]);
 
 typedef struct {
     lgt_ctx *ctx;          /* the problem's lattice; all problems on one device */

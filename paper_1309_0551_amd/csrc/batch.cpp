@@ -141,7 +141,36 @@ lgt_status lgt_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t out_parity, i
     if (in == out) return fail(LGT_ERR_ARG, "in and out alias");
     DeviceScope ds(c->device);
     LGT_HIP(launch_dslash_mrhs(f, U->ptr, in, out, c->g, out_parity, logN, c->stream, c->mrhs_eng[f][logN],
-                               c->mrhs_gps[f][logN]));
+                               c->mrhs_gps[f][logN], c->mrhs_stage[f][logN] != 0));
+    return LGT_OK;
+}
+
+lgt_status lgt_set_mrhs_staging(lgt_ctx *c, int32_t prec, int32_t recon, int32_t nrhs, int32_t staged)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (staged != 0 && staged != 1) return fail(LGT_ERR_ARG, "staged must be 0 or 1");
+    c->mrhs_stage[f][logN] = staged;
+    return LGT_OK;
+}
+
+lgt_status lgt_get_mrhs_staging(lgt_ctx *c, int32_t prec, int32_t recon, int32_t nrhs, int32_t *staged)
+{
+    clear_error();
+    if (!c) return fail(LGT_ERR_ARG, "context is NULL");
+    if (!staged) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    Fmt f;
+    if (!fmt_of(prec, recon, &f)) return fail(LGT_ERR_UNSUPPORTED, "unsupported link format (%d, %d)", prec, recon);
+    const int logN = log2_rhs(nrhs);
+    if (logN < 0) return fail(LGT_ERR_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    // whether lgt_dslash_mrhs runs the staged kernel on this lattice
+    const int e = c->mrhs_eng[f][logN];
+    const int gps = mrhs_groups_valid(logN, c->mrhs_gps[f][logN]) ? c->mrhs_gps[f][logN] : 1;
+    *staged = c->mrhs_stage[f][logN] && mrhs_engine_applies(f, logN, c->g.Vh, e) && mrhs_staging_fits(c->g, logN, gps);
     return LGT_OK;
 }
 

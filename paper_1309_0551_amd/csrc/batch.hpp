@@ -112,8 +112,15 @@ bool mrhs_groups_valid(int logN, int gps);
 inline bool mrhs_size_ok(int Vh) { return (int64_t)Vh * 16 < ((int64_t)1 << 31); }
 
 // Standalone multi-RHS Dslash (plain epilogue): out = D in, N right-hand sides.
+// staged: the four-lane engines' LDS-staged variant (kStageBS-lane
+// workgroups) where its tile fits kMrhsStageMax of LDS; ignored otherwise.
+constexpr int kStageBS = 512;
+constexpr size_t kMrhsStageMax = 64 * 1024;
+// LDS of a staged tile of ts sites: 3 colours x (ts + Lx) sites x N FP32 complex
+inline size_t mrhs_stage_bytes(int ts, int hx, int logN) { return (size_t)3 * (ts + 2 * hx) * ((size_t)8 << logN); }
+bool mrhs_staging_fits(const Geom &g, int logN, int gps);
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                              hipStream_t s, int engine, int gps);
+                              hipStream_t s, int engine, int gps, bool staged = false);
 // nsrc: canonical right-hand sides present (the rest of the 2^logN are zero-padded / not written); -1: all
 hipError_t launch_pack_mrhs(bool f64, const double *src, void *dst, const Geom &g, int logN, hipStream_t s,
                             int nsrc = -1);

@@ -44,6 +44,9 @@ struct lgt_ctx {
                                        {2, 2, 2, 2, 2}};
     int mrhs_gps[lgt::FMT_COUNT][5] = {{1, 1, 1, 1, 1}, {1, 1, 1, 1, 1}, {1, 1, 1, 1, 1}, {1, 1, 1, 1, 1},
                                        {1, 1, 1, 1, 1}};
+    // standalone multi-RHS Dslash: 1 = the four-lane engines' LDS-staged
+    // variant, per (link format, log2 N); lgt_set_mrhs_staging or the tuner
+    int mrhs_stage[lgt::FMT_COUNT][5] = {};
     struct Buf {
         void *ptr = nullptr;
         size_t bytes = 0;

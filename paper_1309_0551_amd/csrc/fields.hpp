@@ -78,7 +78,24 @@ template <typename T> __device__ __forceinline__ void reconstruct(cx<T> u[9])
     }
 }
 
+// The value v of lane K (0..3) of this lane's quad (DPP quad_perm broadcast;
+// every lane of the quad must be active).
+template <int K> __device__ __forceinline__ uint32_t quad_bcast(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, K * 0x55, 0xF, 0xF, true);
+}
+template <int K> __device__ __forceinline__ float quad_bcast(float v)
+{
+    return __uint_as_float(quad_bcast<K>(__float_as_uint(v)));
+}
+
 // ---------------------------------------------------------------- links ---
+//
+// load: the whole link in every lane. load_quad (FP32 / BF16 formats): the
+// four lanes q = 0..3 of a quad that all need the same link each load a part
+// of it and assemble the rest from their neighbours with quad broadcasts, so
+// the vector-memory path returns the link's bytes about once per quad instead
+// of four times.
 
 struct LinkF64R18 {
     using real = double;
@@ -133,6 +150,24 @@ struct LinkF32R18 {
             u[k].im = v.y;
         }
     }
+    // planes q and q + 4 from lane q, plane 8 in every lane
+    template <bool NT>
+    __device__ static void load_quad(const void *U, size_t Vh, int pm, unsigned cb, cx<float> u[9], unsigned q)
+    {
+        const fv2 *base = (const fv2 *)U + (size_t)pm * 9 * Vh;
+        const fv2 a = ld<NT>(base, q * (unsigned)Vh + cb);
+        const fv2 b = ld<NT>(base, (q + 4u) * (unsigned)Vh + cb);
+        const fv2 c = ld<NT>(base, 8u * (unsigned)Vh + cb);
+        u[0] = cx<float>{quad_bcast<0>(a.x), quad_bcast<0>(a.y)};
+        u[1] = cx<float>{quad_bcast<1>(a.x), quad_bcast<1>(a.y)};
+        u[2] = cx<float>{quad_bcast<2>(a.x), quad_bcast<2>(a.y)};
+        u[3] = cx<float>{quad_bcast<3>(a.x), quad_bcast<3>(a.y)};
+        u[4] = cx<float>{quad_bcast<0>(b.x), quad_bcast<0>(b.y)};
+        u[5] = cx<float>{quad_bcast<1>(b.x), quad_bcast<1>(b.y)};
+        u[6] = cx<float>{quad_bcast<2>(b.x), quad_bcast<2>(b.y)};
+        u[7] = cx<float>{quad_bcast<3>(b.x), quad_bcast<3>(b.y)};
+        u[8] = cx<float>{c.x, c.y};
+    }
     __device__ static void store(void *U, size_t Vh, int pm, int cb, const double *s)
     {
         fv2 *p = (fv2 *)U + (size_t)pm * 9 * Vh + cb;
@@ -155,6 +190,19 @@ struct LinkF32R12 {
         }
         reconstruct(u);
     }
+    // plane q from lane q < 3 (lane 3 repeats plane 2: the same address)
+    template <bool NT>
+    __device__ static void load_quad(const void *U, size_t Vh, int pm, unsigned cb, cx<float> u[9], unsigned q)
+    {
+        const fv4 v = ld<NT>((const fv4 *)U + (size_t)pm * 3 * Vh, (q < 3u ? q : 2u) * (unsigned)Vh + cb);
+        u[0] = cx<float>{quad_bcast<0>(v.x), quad_bcast<0>(v.y)};
+        u[1] = cx<float>{quad_bcast<0>(v.z), quad_bcast<0>(v.w)};
+        u[2] = cx<float>{quad_bcast<1>(v.x), quad_bcast<1>(v.y)};
+        u[3] = cx<float>{quad_bcast<1>(v.z), quad_bcast<1>(v.w)};
+        u[4] = cx<float>{quad_bcast<2>(v.x), quad_bcast<2>(v.y)};
+        u[5] = cx<float>{quad_bcast<2>(v.z), quad_bcast<2>(v.w)};
+        reconstruct(u);
+    }
     __device__ static void store(void *U, size_t Vh, int pm, int cb, const double *s)
     {
         fv4 *p = (fv4 *)U + (size_t)pm * 3 * Vh + cb;
@@ -171,6 +219,22 @@ struct LinkBF16R12 {
         const uv4 a = ld<NT>((const uv4 *)U + (size_t)pm * Vh, cb);
         const uv2 b = ld<NT>((const uv2 *)((const uv4 *)U + 8 * Vh) + (size_t)pm * Vh, cb);
         const uint32_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            u[k].re = bf16_lo(w[k]);
+            u[k].im = bf16_hi(w[k]);
+        }
+        reconstruct(u);
+    }
+    // word q of the 16-byte part and word q % 2 of the 8-byte part from lane q
+    template <bool NT>
+    __device__ static void load_quad(const void *U, size_t Vh, int pm, unsigned cb, cx<float> u[9], unsigned q)
+    {
+        const uint32_t *a4 = (const uint32_t *)((const uv4 *)U + (size_t)pm * Vh);
+        const uint32_t *b2 = (const uint32_t *)((const uv2 *)((const uv4 *)U + 8 * Vh) + (size_t)pm * Vh);
+        const uint32_t a = ld<NT>(a4, 4u * cb + q), b = ld<NT>(b2, 2u * cb + (q & 1u));
+        const uint32_t w[6] = {quad_bcast<0>(a), quad_bcast<1>(a), quad_bcast<2>(a), quad_bcast<3>(a),
+                               quad_bcast<0>(b), quad_bcast<1>(b)};
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             u[k].re = bf16_lo(w[k]);

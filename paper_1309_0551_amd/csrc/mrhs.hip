@@ -69,35 +69,111 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs4(const void *__restrict__ U
     stm_r<float, R, true>(out, Vh, logN, site, rhs0, acc);
 }
 
-template <class LF, int R, int GPS>
-static void launch_mrhs4_rg(bool mf, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                            hipStream_t s)
+// Staged variant: kStageBS lanes per workgroup, a tile of TS = kStageBS /
+// (4 GPS) consecutive sites. The workgroup first copies the input of the
+// tile's x and y neighbourhood -- the input-parity cb range [first - Lx/2,
+// last + Lx/2], which holds every x and y neighbour of the tile except across
+// the y boundary -- into LDS as [3][ns][N] complex with 16-byte coalesced
+// loads, each element once; the x and y hops then read it there, so only the
+// z and t hops (and the y-boundary ones) gather through the vector-memory
+// path, which limits the unstaged kernel (texture units busy 83-91 %, HBM at
+// 54 %). The range costs (TS + Lx) / TS loads of each element against the
+// four x/y gathers per site it replaces.
+template <class LF, int R, int GPS, bool MFMA>
+__global__ __launch_bounds__(kStageBS) void k_dslash_mrhs4s(const void *__restrict__ U, const void *__restrict__ in,
+                                                            void *__restrict__ out, Geom g, int par, int logN,
+                                                            int nblk_pad, TileOrder o)
 {
-    const int64_t n = (int64_t)g.Vh * 4 * GPS;
-    const int nblk = (int)((n + kBS - 1) / kBS);
+    extern __shared__ __align__(16) unsigned char mrhs_lds[];
+    constexpr unsigned LPS = 4 * GPS;
+    constexpr int TS = kStageBS / LPS;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return; // the whole workgroup
+    const size_t Vh = (size_t)g.Vh;
+    const int s0 = blk * TS - g.hx, ns = TS + 2 * g.hx;
+    // stage: two complex numbers (one right-hand-side pair) per 16-byte load
+    const int hlog = logN - 1, per = ns << hlog; // fv4 per colour plane
+    const fv4 *in4 = (const fv4 *)in;
+    fv4 *lds4 = (fv4 *)mrhs_lds;
+    for (int i = threadIdx.x; i < 3 * per; i += kStageBS) {
+        const int c = i / per, rem = i - c * per;
+        const int n = s0 + (rem >> hlog);
+        if (n >= 0 && n < g.Vh) lds4[i] = in4[(((size_t)c * Vh + (size_t)n) << hlog) + (rem & ((1 << hlog) - 1))];
+    }
+    __syncthreads();
+    const unsigned idx = (unsigned)blk * kStageBS + threadIdx.x;
+    const unsigned site = idx / LPS, lane4 = idx & 3u;
+    // whole wavefronts leave together (V/2 % 16 == 0 for MFMA); no barrier follows
+    if (site >= (unsigned)g.Vh) return;
+    const unsigned rhs0 = (threadIdx.x % LPS) * R;
+    const fv2 *lds = (const fv2 *)mrhs_lds;
+    auto IN = [=](int n, cx<float> v[R][3]) __attribute__((always_inline)) {
+        const unsigned j = (unsigned)(n - s0);
+        if (j < (unsigned)ns) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const fv2 *q = lds + (((size_t)c * ns + j) << logN) + rhs0;
+                if constexpr (R % 2 == 0) {
+#pragma unroll
+                    for (int r = 0; r < R; r += 2) {
+                        const fv4 w = *(const fv4 *)(q + r);
+                        v[r][c] = cx<float>{w.x, w.y};
+                        v[r + 1][c] = cx<float>{w.z, w.w};
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; r++) v[r][c] = cx<float>{q[r].x, q[r].y};
+                }
+            }
+            return;
+        }
+        ldm_r<float, R>(in, Vh, logN, n, rhs0, v);
+    };
+    cx<float> acc[R][3];
+    dslash_site4<LF, R, MFMA>(g, par, U, site, lane4, IN, acc);
+    stm_r<float, R, true>(out, Vh, logN, site, rhs0, acc);
+}
+
+template <class LF, int R, int GPS>
+static void launch_mrhs4_rg(bool mf, bool staged, const void *U, const void *in, void *out, const Geom &g, int par,
+                            int logN, hipStream_t s)
+{
+    const int lanes = staged ? kStageBS : kBS, TS = lanes / (4 * GPS);
+    const int nblk = (int)(((int64_t)g.Vh + TS - 1) / TS);
     const int pad = (nblk + 7) / 8 * 8;
-    const TileOrder o = tile_order(g, kBS / (4 * GPS));
-    const dim3 grid(mrhs_grid(o, nblk)), block(kBS);
+    const TileOrder o = tile_order(g, TS);
+    const dim3 grid(mrhs_grid(o, nblk)), block(lanes);
+    if (staged) {
+        const size_t lds = mrhs_stage_bytes(TS, g.hx, logN);
+        if (mf) hipLaunchKernelGGL((k_dslash_mrhs4s<LF, R, GPS, true>), grid, block, lds, s, U, in, out, g, par, logN, pad, o);
+        else hipLaunchKernelGGL((k_dslash_mrhs4s<LF, R, GPS, false>), grid, block, lds, s, U, in, out, g, par, logN, pad, o);
+        return;
+    }
     if (mf) hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, true>), grid, block, 0, s, U, in, out, g, par, logN, pad, o);
     else hipLaunchKernelGGL((k_dslash_mrhs4<LF, R, GPS, false>), grid, block, 0, s, U, in, out, g, par, logN, pad, o);
 }
 
 template <class LF>
-static hipError_t launch_mrhs4(int engine, int gps, const void *U, const void *in, void *out, const Geom &g, int par,
-                               int logN, hipStream_t s)
+static hipError_t launch_mrhs4(int engine, int gps, bool st, const void *U, const void *in, void *out, const Geom &g,
+                               int par, int logN, hipStream_t s)
 {
     const bool mf = engine == MRHS_MFMA;
     const int key = logN * 8 + gps;
     switch (key) {
-    case 2 * 8 + 1: launch_mrhs4_rg<LF, 1, 1>(mf, U, in, out, g, par, logN, s); break;
-    case 3 * 8 + 1: launch_mrhs4_rg<LF, 2, 1>(mf, U, in, out, g, par, logN, s); break;
-    case 3 * 8 + 2: launch_mrhs4_rg<LF, 1, 2>(mf, U, in, out, g, par, logN, s); break;
-    case 4 * 8 + 1: launch_mrhs4_rg<LF, 4, 1>(mf, U, in, out, g, par, logN, s); break;
-    case 4 * 8 + 2: launch_mrhs4_rg<LF, 2, 2>(mf, U, in, out, g, par, logN, s); break;
-    case 4 * 8 + 4: launch_mrhs4_rg<LF, 1, 4>(mf, U, in, out, g, par, logN, s); break;
+    case 2 * 8 + 1: launch_mrhs4_rg<LF, 1, 1>(mf, st, U, in, out, g, par, logN, s); break;
+    case 3 * 8 + 1: launch_mrhs4_rg<LF, 2, 1>(mf, st, U, in, out, g, par, logN, s); break;
+    case 3 * 8 + 2: launch_mrhs4_rg<LF, 1, 2>(mf, st, U, in, out, g, par, logN, s); break;
+    case 4 * 8 + 1: launch_mrhs4_rg<LF, 4, 1>(mf, st, U, in, out, g, par, logN, s); break;
+    case 4 * 8 + 2: launch_mrhs4_rg<LF, 2, 2>(mf, st, U, in, out, g, par, logN, s); break;
+    case 4 * 8 + 4: launch_mrhs4_rg<LF, 1, 4>(mf, st, U, in, out, g, par, logN, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+bool mrhs_staging_fits(const Geom &g, int logN, int gps)
+{
+    return mrhs_stage_bytes(kStageBS / (4 * gps), g.hx, logN) <= kMrhsStageMax;
 }
 
 bool mrhs_engine_applies(Fmt f, int logN, int Vh, int engine)
@@ -112,14 +188,15 @@ bool mrhs_groups_valid(int logN, int gps)
 }
 
 hipError_t launch_dslash_mrhs(Fmt f, const void *U, const void *in, void *out, const Geom &g, int par, int logN,
-                              hipStream_t s, int engine, int gps)
+                              hipStream_t s, int engine, int gps, bool staged)
 {
     if (mrhs_engine_applies(f, logN, g.Vh, engine)) {
         if (!mrhs_groups_valid(logN, gps)) gps = 1;
+        const bool st = staged && mrhs_staging_fits(g, logN, gps);
         switch (f) {
-        case F32R18: return launch_mrhs4<LinkF32R18>(engine, gps, U, in, out, g, par, logN, s);
-        case F32R12: return launch_mrhs4<LinkF32R12>(engine, gps, U, in, out, g, par, logN, s);
-        case BF16R12: return launch_mrhs4<LinkBF16R12>(engine, gps, U, in, out, g, par, logN, s);
+        case F32R18: return launch_mrhs4<LinkF32R18>(engine, gps, st, U, in, out, g, par, logN, s);
+        case F32R12: return launch_mrhs4<LinkF32R12>(engine, gps, st, U, in, out, g, par, logN, s);
+        case BF16R12: return launch_mrhs4<LinkBF16R12>(engine, gps, st, U, in, out, g, par, logN, s);
         default: break;
         }
     }

@@ -241,10 +241,10 @@ __device__ __forceinline__ void dslash_site4(const Geom &g, int par, const void 
     for (int mu = 0; mu < 4; mu++) {
         const Hop h = hop_rt(g, c, cb, mu);
         cx<float> u[9], v[R][3];
-        LF::template load<false>(U, Vh, par * 4 + mu, cb, u);
+        LF::template load_quad<false>(U, Vh, par * 4 + mu, cb, u, lane4);
         in(h.f, v);
         hop_apply<R, MFMA>(u, true, h.fneg, v, lane4, acc, C);
-        LF::template load<false>(U, Vh, (1 - par) * 4 + mu, h.b, u);
+        LF::template load_quad<false>(U, Vh, (1 - par) * 4 + mu, h.b, u, lane4);
         in(h.b, v);
         // the adjoint hop enters with a minus sign: fold it into neg
         hop_apply<R, MFMA>(u, false, !h.bneg, v, lane4, acc, C);

@@ -394,9 +394,14 @@ lgt_status lgt_tune_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_
 
 namespace {
 
-constexpr int kNumMrhs = 7;
-const int kMrhsEngine[kNumMrhs] = {MRHS_LANE, MRHS_VALU4, MRHS_VALU4, MRHS_VALU4, MRHS_MFMA, MRHS_MFMA, MRHS_MFMA};
-const int kMrhsGroups[kNumMrhs] = {1, 1, 2, 4, 1, 2, 4};
+// lane; VALU and MFMA with 1, 2, 4 groups; the same six LDS-staged
+constexpr int kNumMrhs = 13;
+const int kMrhsEngine[kNumMrhs] = {MRHS_LANE, MRHS_VALU4, MRHS_VALU4, MRHS_VALU4, MRHS_MFMA, MRHS_MFMA, MRHS_MFMA,
+                                   MRHS_VALU4, MRHS_VALU4, MRHS_VALU4, MRHS_MFMA, MRHS_MFMA, MRHS_MFMA};
+const int kMrhsGroups[kNumMrhs] = {1, 1, 2, 4, 1, 2, 4, 1, 2, 4, 1, 2, 4};
+const int kMrhsStaged[kNumMrhs] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
+// the tuning cache stores (engine + 10 staged, groups)
+constexpr int kStagedCode = 10;
 
 int log2_n(int32_t n)
 {
@@ -405,17 +410,18 @@ int log2_n(int32_t n)
     return -1;
 }
 
-bool mrhs_variant_runs(Fmt f, int logN, int Vh, int v)
+bool mrhs_variant_runs(Fmt f, const Geom &g, int logN, int v)
 {
     if (kMrhsEngine[v] == MRHS_LANE) return true;
-    return mrhs_engine_applies(f, logN, Vh, kMrhsEngine[v]) && mrhs_groups_valid(logN, kMrhsGroups[v]);
+    return mrhs_engine_applies(f, logN, g.Vh, kMrhsEngine[v]) && mrhs_groups_valid(logN, kMrhsGroups[v]) &&
+           (!kMrhsStaged[v] || mrhs_staging_fits(g, logN, kMrhsGroups[v]));
 }
 
 } // namespace
 
 extern "C" {
 
-lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, double times_us[7])
+lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, double times_us[13])
 {
     clear_error();
     if (!c) return fail(LGT_ERR_ARG, "context is NULL");
@@ -433,15 +439,16 @@ lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, do
     const bool forced = force && std::strcmp(force, "force") == 0;
     if (!forced && !times_us) {
         int e, gr;
-        const int Vh = c->g.Vh;
         auto ok = [&](int a, int b) {
             for (int v = 0; v < kNumMrhs; v++)
-                if (kMrhsEngine[v] == a && kMrhsGroups[v] == b) return mrhs_variant_runs(f, logN, Vh, v);
+                if (kMrhsEngine[v] + kStagedCode * kMrhsStaged[v] == a && kMrhsGroups[v] == b)
+                    return mrhs_variant_runs(f, c->g, logN, v);
             return false;
         };
         if (cache_lookup_pair(key, &e, &gr, ok)) {
-            c->mrhs_eng[f][logN] = e;
+            c->mrhs_eng[f][logN] = e % kStagedCode;
             c->mrhs_gps[f][logN] = gr;
+            c->mrhs_stage[f][logN] = e / kStagedCode;
             return LGT_OK;
         }
     }
@@ -463,9 +470,10 @@ lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, do
     hipError_t e = hipSuccess;
     for (int v = 0; v < kNumMrhs && e == hipSuccess; v++) {
         t[v] = -1.0;
-        if (!mrhs_variant_runs(f, logN, c->g.Vh, v)) continue;
+        if (!mrhs_variant_runs(f, c->g, logN, v)) continue;
         auto run = [&](int par) {
-            return launch_dslash_mrhs(f, U->ptr, in, out, c->g, par, logN, c->stream, kMrhsEngine[v], kMrhsGroups[v]);
+            return launch_dslash_mrhs(f, U->ptr, in, out, c->g, par, logN, c->stream, kMrhsEngine[v], kMrhsGroups[v],
+                                      kMrhsStaged[v] != 0);
         };
         for (int w = 0; w < 2 && e == hipSuccess; w++) e = run(w & 1);
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
@@ -485,7 +493,8 @@ lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, do
     if (e != hipSuccess) return fail(LGT_ERR_DEVICE, "tuning launch failed: %s", hipGetErrorString(e));
     c->mrhs_eng[f][logN] = kMrhsEngine[best];
     c->mrhs_gps[f][logN] = kMrhsGroups[best];
-    cache_store_pair(key, kMrhsEngine[best], kMrhsGroups[best], t, kNumMrhs);
+    c->mrhs_stage[f][logN] = kMrhsStaged[best];
+    cache_store_pair(key, kMrhsEngine[best] + kStagedCode * kMrhsStaged[best], kMrhsGroups[best], t, kNumMrhs);
     if (times_us)
         for (int v = 0; v < kNumMrhs; v++) times_us[v] = t[v];
     return LGT_OK;

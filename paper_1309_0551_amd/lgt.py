@@ -161,6 +161,8 @@ def _setup(l):
         "lgt_set_mrhs_engine": (st, [vp, i32]),
         "lgt_get_mrhs_engine": (st, [vp, C.POINTER(C.c_int32)]),
         "lgt_set_mrhs_variant": (st, [vp, i32, i32, i32, i32, i32]),
+        "lgt_set_mrhs_staging": (st, [vp, i32, i32, i32, i32]),
+        "lgt_get_mrhs_staging": (st, [vp, i32, i32, i32, C.POINTER(i32)]),
         "lgt_get_mrhs_variant": (st, [vp, i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "lgt_tune_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, C.POINTER(C.c_double)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
@@ -387,23 +389,36 @@ class Lattice:
     def set_mrhs_variant(self, prec: int, recon: int, nrhs: int, engine: int, groups: int = 1):
         _check(lib().lgt_set_mrhs_variant(self._ctx, prec, recon, int(nrhs), int(engine), int(groups)))
 
+    def set_mrhs_staging(self, prec: int, recon: int, nrhs: int, staged: bool):
+        """LDS-staged multi-RHS Dslash (four-lane engines) for this format and nrhs."""
+        _check(lib().lgt_set_mrhs_staging(self._ctx, prec, recon, int(nrhs), int(bool(staged))))
+
+    def mrhs_staging(self, prec: int, recon: int, nrhs: int) -> bool:
+        """Whether lgt_dslash_mrhs runs the staged kernel for this format and nrhs."""
+        st = C.c_int32()
+        _check(lib().lgt_get_mrhs_staging(self._ctx, prec, recon, int(nrhs), C.byref(st)))
+        return bool(st.value)
+
     def mrhs_variant(self, prec: int, recon: int, nrhs: int) -> tuple[int, int]:
         """(engine, groups of four lanes per site) that lgt_dslash_mrhs runs for this format and nrhs."""
         e, g = C.c_int32(), C.c_int32()
         _check(lib().lgt_get_mrhs_variant(self._ctx, prec, recon, int(nrhs), C.byref(e), C.byref(g)))
         return int(e.value), int(g.value)
 
-    MRHS_VARIANTS = ((LGT_MRHS_LANE, 1), (LGT_MRHS_VALU4, 1), (LGT_MRHS_VALU4, 2), (LGT_MRHS_VALU4, 4),
-                     (LGT_MRHS_MFMA, 1), (LGT_MRHS_MFMA, 2), (LGT_MRHS_MFMA, 4))
+    # (engine, groups, LDS-staged) in the order lgt_tune_dslash_mrhs reports them
+    MRHS_VARIANTS = tuple((e, g, 0) for e, g in ((LGT_MRHS_LANE, 1), (LGT_MRHS_VALU4, 1), (LGT_MRHS_VALU4, 2),
+                                                 (LGT_MRHS_VALU4, 4), (LGT_MRHS_MFMA, 1), (LGT_MRHS_MFMA, 2),
+                                                 (LGT_MRHS_MFMA, 4))) + \
+        tuple((e, g, 1) for e in (LGT_MRHS_VALU4, LGT_MRHS_MFMA) for g in (1, 2, 4))
 
     def tune_dslash_mrhs(self, U: "PackedLinks", nrhs: int, report: bool = True):
         """Time every multi-RHS variant on U for nrhs and keep the fastest;
-        returns {(engine, groups): us} (variants that do not apply omitted) or None."""
+        returns {(engine, groups, staged): us} (variants that do not apply omitted) or None."""
         d = U.desc()
         if not report:
             _check(lib().lgt_tune_dslash_mrhs(self._ctx, C.byref(d), int(nrhs), None))
             return None
-        t = (C.c_double * 7)()
+        t = (C.c_double * len(self.MRHS_VARIANTS))()
         _check(lib().lgt_tune_dslash_mrhs(self._ctx, C.byref(d), int(nrhs), t))
         return {v: t[i] for i, v in enumerate(self.MRHS_VARIANTS) if t[i] >= 0}
 

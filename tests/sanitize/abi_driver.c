@@ -85,6 +85,8 @@ int main(void)
     EXPECT(lgt_fatten_links(NULL, NULL, &w, NULL, NULL), LGT_ERR_ARG);
     EXPECT(lgt_fatten_links_vjp(NULL, NULL, &w, NULL, NULL, 1.0, 0, NULL), LGT_ERR_ARG);
     EXPECT(lgt_set_dslash_improved_variant(NULL, 0, 1, 256), LGT_ERR_ARG);
+    EXPECT(lgt_set_mrhs_staging(NULL, 1, 12, 16, 1), LGT_ERR_ARG);
+    EXPECT(lgt_get_mrhs_staging(NULL, 1, 12, 16, &i32), LGT_ERR_ARG);
     EXPECT(lgt_get_dslash_improved_variant(NULL, 0, &i32, &i32), LGT_ERR_ARG);
     EXPECT(lgt_tune_dslash_improved(NULL, &Ul, &Ul, d), LGT_ERR_ARG);
     EXPECT(lgt_gauge_force(NULL, NULL, 5.6, 1.0, 0, NULL), LGT_ERR_ARG);

@@ -154,6 +154,8 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_fatten_links": (None, None, None, None, None),
         "lgt_fatten_links_vjp": (None, None, None, None, None, 1.0, 0, None),
         "lgt_set_dslash_improved_variant": (None, 0, 1, 256),
+        "lgt_set_mrhs_staging": (None, 1, 12, 16, 1),
+        "lgt_get_mrhs_staging": (None, 1, 12, 16, C.byref(i)),
         "lgt_get_dslash_improved_variant": (None, 0, C.byref(i), C.byref(i)),
         "lgt_tune_dslash_improved": (None, None, None, None),
         "lgt_hmc_trajectory_improved": (None, None, None, None, None, None, None, None),

@@ -123,6 +123,60 @@ def test_dslash_mrhs_groups(dev, engine, groups, fmt, nrhs):
                 _per_element(got[r], L, U, chis[r], par, prec, recon, bc, ref, (engine, groups, fmt, nrhs, par, r))
 
 
+@pytest.mark.parametrize("engine,groups,nrhs", SHAPES)
+@pytest.mark.parametrize("fmt", ["f32r18", "f32r12", "bf16r12"])
+def test_dslash_mrhs_staged(dev, engine, groups, fmt, nrhs):
+    """The LDS-staged kernel of every four-lane tile shape: bit-identical to the
+    unstaged one (same products in the same order, only the load path differs)
+    and within the per-element bound of the oracle, at 8^3x12, at 12x8x8x16
+    (z-ordered tiles, x/y neighbourhood split across tiles) and at 6x6x6x8
+    (V/2 = 864: a ragged last tile, the MFMA engine running one lane per rhs)."""
+    prec, recon, tol = FMTS[fmt]
+    bc = (1, 1, 1, -1)
+    for L in ((8, 8, 8, 12), (12, 8, 8, 16), (6, 6, 6, 8)):
+        U = li.links(L, "haar", 171)
+        chis = li.vectors(L, 172, nrhs)
+        with P.Lattice(L, bc) as lat:
+            lat.set_mrhs_variant(prec, recon, nrhs, ENGINES[engine], groups)
+            Up = lat.pack_links(_t(U, dev), prec, recon)
+            x = lat.pack_vec_mrhs(_t(chis, dev), P.LGT_F32)
+            for par in (0, 1):
+                lat.set_mrhs_staging(prec, recon, nrhs, False)
+                plain = lat.dslash_mrhs(Up, x, par).clone()
+                lat.set_mrhs_staging(prec, recon, nrhs, True)
+                four = lat.mrhs_variant(prec, recon, nrhs)[0] != ENGINES["lane"]
+                assert lat.mrhs_staging(prec, recon, nrhs) == four, (L, engine)
+                staged = lat.dslash_mrhs(Up, x, par)
+                assert torch.equal(staged, plain), (engine, groups, fmt, nrhs, L, par)
+                got = lat.unpack_vec_mrhs(staged, P.LGT_F32).cpu().numpy()
+                for r in range(nrhs):
+                    ref = oracle.dslash(L, U, chis[r], par, bc)
+                    _per_element(got[r], L, U, chis[r], par, prec, recon, bc, ref, (engine, groups, fmt, L, par, r))
+
+
+def test_dslash_mrhs_staging_falls_back_when_the_tile_does_not_fit(dev):
+    """Lx = 48, 16 rhs, one group: 3 x (128 + 48) sites x 16 x 8 B = 66 KB > 64 KB
+    of LDS, so the unstaged kernel runs (and reports so)."""
+    L, bc = (48, 4, 4, 4), (1, 1, 1, -1)
+    U = li.links(L, "haar", 181)
+    chis = li.vectors(L, 182, 16)
+    with P.Lattice(L, bc) as lat:
+        lat.set_mrhs_variant(P.LGT_F32, P.LGT_R12, 16, ENGINES["mfma"], 1)
+        lat.set_mrhs_staging(P.LGT_F32, P.LGT_R12, 16, True)
+        assert not lat.mrhs_staging(P.LGT_F32, P.LGT_R12, 16)
+        lat.set_mrhs_variant(P.LGT_F32, P.LGT_R12, 16, ENGINES["mfma"], 2)  # 64-site tiles fit
+        assert lat.mrhs_staging(P.LGT_F32, P.LGT_R12, 16)
+        lat.set_mrhs_variant(P.LGT_F32, P.LGT_R12, 16, ENGINES["mfma"], 1)
+        Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        x = lat.pack_vec_mrhs(_t(chis, dev), P.LGT_F32)
+        got = lat.unpack_vec_mrhs(lat.dslash_mrhs(Up, x, 0), P.LGT_F32).cpu().numpy()
+        for r in range(16):
+            ref = oracle.dslash(L, U, chis[r], 0, bc)
+            _per_element(got[r], L, U, chis[r], 0, P.LGT_F32, P.LGT_R12, bc, ref, ("fallback", r))
+        with pytest.raises(P.LgtError):
+            lat.set_mrhs_staging(P.LGT_F32, P.LGT_R12, 6, True)
+
+
 def test_mrhs_variant_arguments(dev):
     with P.Lattice((4, 4, 4, 4)) as lat:
         for bad in ((P.LGT_F32, P.LGT_R12, 8, ENGINES["mfma"], 4),   # 4 groups need 16 rhs
@@ -146,10 +200,13 @@ def test_tune_dslash_mrhs(dev, tmp_path, monkeypatch):
     with P.Lattice(L) as lat:
         Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
         times = lat.tune_dslash_mrhs(Up, 16)
-        # all seven shapes apply at N = 16 with V/2 a multiple of 16
+        # all thirteen shapes apply at N = 16 with V/2 a multiple of 16 (staged tiles fit)
         assert set(times) == set(P.Lattice.MRHS_VARIANTS) and all(t > 0 for t in times.values())
+
+        def kept(lt):
+            return lt.mrhs_variant(P.LGT_F32, P.LGT_R12, 16) + (int(lt.mrhs_staging(P.LGT_F32, P.LGT_R12, 16)),)
         best = min(times, key=times.get)
-        assert lat.mrhs_variant(P.LGT_F32, P.LGT_R12, 16) == best
+        assert kept(lat) == best
         x = lat.pack_vec_mrhs(_t(chis, dev), P.LGT_F32)
         got = lat.unpack_vec_mrhs(lat.dslash_mrhs(Up, x, 1), P.LGT_F32).cpu().numpy()
         for r in range(16):
@@ -158,14 +215,14 @@ def test_tune_dslash_mrhs(dev, tmp_path, monkeypatch):
         lat2 = P.Lattice((6, 6, 6, 6))
         U2 = lat2.pack_links(_t(li.links((6, 6, 6, 6), "haar", 173), dev), P.LGT_F32, P.LGT_R12)
         t2 = lat2.tune_dslash_mrhs(U2, 4)
-        assert set(t2) == {(ENGINES["lane"], 1), (ENGINES["valu4"], 1)}
+        assert set(t2) == {(ENGINES["lane"], 1, 0), (ENGINES["valu4"], 1, 0), (ENGINES["valu4"], 1, 1)}
         lat2.close()
     assert "mrhs16" in cache.read_text()
     # a new context picks the cached choice without timing
     with P.Lattice(L) as lat:
         Up = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
         lat.tune_dslash_mrhs(Up, 16, report=False)
-        assert lat.mrhs_variant(P.LGT_F32, P.LGT_R12, 16) == best
+        assert kept(lat) == best
 
 
 def test_mrhs_engine_rejects_unknown(dev):

@@ -347,6 +347,61 @@ def probe_dslash(L, fmt, launches, hops, streaming):
             "us_per_launch": round(us, 2), "alg_bytes_per_launch": alg, "alg_GBps": round(alg / us / 1e3, 1)}
 
 
+def probe_dslash_mrhs(L, fmt, nrhs, launches):
+    """--probe with --nrhs N > 1: the standalone multi-RHS Dslash on the same
+    kind of links, every variant that applies (engine, groups of four lanes,
+    LDS staging), each `launches` plain applications (output parity odd) after
+    one warm-up, timed with events; algorithmic bytes per output site: 8 links
+    and N input and N output vectors. Under rocprofv3 the kernel names tell the
+    variants apart (k_dslash_mrhs4s: staged; template arguments R, groups,
+    MFMA)."""
+    import math
+
+    import torch
+
+    import lgt_inputs as li
+    import paper_1309_0551_amd as P
+    dev = torch.device("cuda", 0)
+    V = math.prod(L)
+    prec, recon = PROBE_FMTS[fmt]
+    if prec == P.LGT_F64:
+        raise SystemExit("--nrhs probes the FP32 / BF16 link formats")
+    pool = torch.from_numpy(li.to_real(li.haar_su3(1 << 16, li.rng(7)))).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    out = {"probe": "dslash_mrhs", "L": list(L), "fmt": fmt, "nrhs": nrhs, "launches": launches, "variants": {}}
+    with P.Lattice(L) as lat:
+        U = pool[torch.randint(0, pool.shape[0], (4 * V,), device=dev, generator=g)].reshape(4, V, 3, 3, 2)
+        Up = lat.pack_links(U.contiguous(), prec, recon)
+        del U, pool
+        torch.cuda.empty_cache()
+        x = torch.randn((3, lat.Vh, nrhs, 2), dtype=torch.float32, device=dev, generator=g)
+        y = torch.empty_like(x)
+        alg = lat.Vh * (8 * P.link_bytes_per_dir(prec, recon) + 2 * nrhs * 24)
+        out["alg_bytes_per_launch"] = alg
+        for e, gr, st in P.Lattice.MRHS_VARIANTS:
+            if e != P.LGT_MRHS_LANE and 4 * gr > nrhs:
+                continue
+            lat.set_mrhs_variant(prec, recon, nrhs, e, gr)
+            lat.set_mrhs_staging(prec, recon, nrhs, bool(st))
+            runs = lat.mrhs_variant(prec, recon, nrhs) + (int(lat.mrhs_staging(prec, recon, nrhs)),)
+            if runs != (e, gr, st):
+                continue  # does not apply on this lattice
+            lat.dslash_mrhs(Up, x, 1, y)  # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(lat.stream)
+            for _ in range(launches):
+                lat.dslash_mrhs(Up, x, 1, y)
+            e1.record(lat.stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / launches
+            name = {P.LGT_MRHS_LANE: "lane", P.LGT_MRHS_VALU4: "valu4", P.LGT_MRHS_MFMA: "mfma"}[e]
+            name += "" if e == P.LGT_MRHS_LANE else f"_g{gr}" + ("_lds" if st else "")
+            out["variants"][name] = {"us_per_launch": round(us, 2), "alg_GBps": round(alg / us / 1e3, 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +427,8 @@ def main():
                     help="instead of the benchmark: time the plain Dslash alone on this lattice and print one "
                          "JSON line (options --fmt, --launches, --hops, --streaming)")
     ap.add_argument("--fmt", default="f64r18", choices=sorted(PROBE_FMTS))
+    ap.add_argument("--nrhs", type=int, default=1, choices=(1, 4, 8, 16),
+                    help="with --probe: N > 1 probes the multi-RHS Dslash, every variant")
     ap.add_argument("--launches", type=int, default=12)
     ap.add_argument("--hops", type=int, default=0, choices=(0, 1, 2, 4, 8), help="0: the library's default")
     ap.add_argument("--streaming", type=int, default=1, choices=(0, 1))
@@ -380,6 +437,9 @@ def main():
         print("bench.py measures one GPU: this library has no multi-GPU path (its domain decomposition "
               "over several GPUs is a design only); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.probe and args.nrhs > 1:
+        print(json.dumps(probe_dslash_mrhs(tuple(args.probe), args.fmt, args.nrhs, args.launches)), flush=True)
+        return
     if args.probe:
         print(json.dumps(probe_dslash(tuple(args.probe), args.fmt, args.launches, args.hops, args.streaming)),
               flush=True)

@@ -18,6 +18,8 @@ constexpr int kMaxRhs = 16;        // right-hand sides per problem (power of two
 constexpr int kMaxProblems = 64;   // problems per batched launch
 constexpr int kMaxTotalRhs = 256;  // right-hand sides per batched launch
 constexpr int kBB = 1024;          // threads per workgroup of the batched solver
+// (site, rhs) pairs of a batch from which its step 1 runs as two passes
+constexpr size_t kBatchSplitPairs = (size_t)1 << 21;
 // LDS per workgroup of the batched solver for the staged input tiles of its
 // four-lane Dslash steps: 3 colours x (sites of a tile + Lx) x N right-hand
 // sides of FP32 complex (8 B) must fit
@@ -74,10 +76,10 @@ struct BatchCtl {
 // steps 1 (D_oe with p' and <p', A p'>) and 2 (D_eo with the update of x and r
 // and |r|^2) as this workgroup's own work, the waits at the barriers after
 // them (imbalance + barrier), the scalar steps after the barriers, and the
-// FP64 reliable updates / refinement steps. (PH_STEP3 / PH_WAIT3 stay zero:
-// the update is part of step 2.)
+// FP64 reliable updates / refinement steps; with step 1 split (BatchArgs::split),
+// its first pass (p' = r + beta p) and the wait after it.
 enum BatchPhase {
-    PH_SETUP = 0, PH_STEP1, PH_WAIT1, PH_STEP2, PH_WAIT2, PH_STEP3, PH_WAIT3, PH_SCALAR, PH_FP64, kBatchPhases
+    PH_SETUP = 0, PH_STEP1, PH_WAIT1, PH_STEP2, PH_WAIT2, PH_STEP1P, PH_WAIT1P, PH_SCALAR, PH_FP64, kBatchPhases
 };
 
 struct BatchArgs {
@@ -88,7 +90,7 @@ struct BatchArgs {
     int scheme;
     int ru_interval;
     int max_iter;
-    int pad;
+    int split;          // 1: step 1 as two passes (p' elementwise, then D_oe p') with a barrier between
     double tol, inner;  // relative tolerance; REFINE inner tolerance or RELIABLE factor
     CgState *states;    // [total_rhs], written at the end of the launch
     double *rows[2];    // partial-sum rows [grid][total_rhs], two buffers

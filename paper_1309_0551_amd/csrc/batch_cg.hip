@@ -451,7 +451,94 @@ __device__ __forceinline__ void step2_lane(const BatchProb &P, const Shared &S, 
     stm<T>(P.r, Vh, logN, site, rhs, rr);
 }
 
+// ---- step 1 split in two passes (BatchArgs::split): (a) p' = r + beta p over
+// the even sites, elementwise, with the partial m4 |p'|^2; a grid barrier;
+// (b) t = D_oe p' gathering one vector, with the partial |t|^2. Same
+// arithmetic per element as the fused step 1.
+
+template <typename T>
+__device__ __forceinline__ void step1_p(const BatchProb &P, const Shared &S, int lt, const void *pold, void *pnew,
+                                        double v[4])
+{
+    const unsigned idx = (unsigned)lt * kBB + threadIdx.x;
+    const unsigned site = idx >> P.logN, rhs = idx & ((1u << P.logN) - 1u);
+    if (site >= (unsigned)P.g.Vh) return;
+    const size_t Vh = (size_t)P.g.Vh;
+    const T beta = (T)S.coef[P.rhs0 + rhs];
+    cx<T> r[3], p[3];
+    ldm<T>(P.r, Vh, P.logN, site, rhs, r);
+    ldm<T>(pold, Vh, P.logN, site, rhs, p);
+    double qq = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        r[c].re = fma(beta, p[c].re, r[c].re);
+        r[c].im = fma(beta, p[c].im, r[c].im);
+        qq += (double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im;
+    }
+    stm<T>(pnew, Vh, P.logN, site, rhs, r);
+    if (S.run[P.rhs0 + rhs]) v[0] += P.m4 * qq;
+}
+
+template <class LF, int R, int GPS, bool MFMA>
+__device__ __forceinline__ void step1_d_four(const BatchProb &P, const Shared &S, int dt, const void *pnew, double v[4])
+{
+    constexpr int LPS = 4 * GPS;
+    const unsigned s = (unsigned)dt * (kBB / LPS) + threadIdx.x / LPS, lane4 = threadIdx.x & 3u;
+    if (s >= (unsigned)P.g.Vh) return;
+    const size_t Vh = (size_t)P.g.Vh;
+    const int logN = P.logN;
+    const unsigned r0 = (threadIdx.x % LPS) * R;
+    auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(pnew, Vh, logN, n, r0, u); };
+    cx<float> acc[R][3];
+    dslash_site4<LF, R, MFMA>(P.g, kOdd, P.Ulo, s, lane4, IN, acc);
+    stm_r<float, R>(P.t, Vh, logN, s, r0, acc);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        double tt = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            tt += (double)acc[r][c].re * (double)acc[r][c].re + (double)acc[r][c].im * (double)acc[r][c].im;
+        if (S.run[P.rhs0 + r0 + r]) v[r] += tt;
+    }
+}
+
+template <class LF>
+__device__ __forceinline__ void step1_d_lane(const BatchProb &P, const Shared &S, int lt, const void *pnew, double v[4])
+{
+    using T = typename LF::real;
+    const unsigned idx = (unsigned)lt * kBB + threadIdx.x;
+    const unsigned site = idx >> P.logN, rhs = idx & ((1u << P.logN) - 1u);
+    if (site >= (unsigned)P.g.Vh) return;
+    const size_t Vh = (size_t)P.g.Vh;
+    const int logN = P.logN;
+    auto IN = [=](int n, cx<T> u[3]) __attribute__((always_inline)) { ldm<T>(pnew, Vh, logN, n, rhs, u); };
+    cx<T> acc[3];
+    dslash_mrhs<LF>(P.g, kOdd, P.Ulo, site, IN, acc);
+    stm<T>(P.t, Vh, logN, site, rhs, acc);
+    double tt = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; c++) tt += (double)acc[c].re * (double)acc[c].re + (double)acc[c].im * (double)acc[c].im;
+    if (S.run[P.rhs0 + rhs]) v[0] += tt;
+}
+
 // engine dispatch for the inner steps (four-lane engines for F32/BF16 links only)
+template <class LF>
+__device__ __forceinline__ void step1_d(const BatchProb &P, const Shared &S, int dt, const void *pnew, double v[4])
+{
+    if constexpr (!std::is_same<typename LF::real, double>::value) {
+        if (P.eng != MRHS_LANE) {
+            const bool mf = P.eng == MRHS_MFMA;
+#define LGT_STEP1D(R, G) (mf ? step1_d_four<LF, R, G, true>(P, S, dt, pnew, v) : step1_d_four<LF, R, G, false>(P, S, dt, pnew, v))
+            if (P.logN == 2) LGT_STEP1D(1, 1);
+            else if (P.logN == 3) P.gps == 2 ? LGT_STEP1D(1, 2) : LGT_STEP1D(2, 1);
+            else P.gps == 4 ? LGT_STEP1D(1, 4) : LGT_STEP1D(2, 2);
+#undef LGT_STEP1D
+            return;
+        }
+    }
+    step1_d_lane<LF>(P, S, dt, pnew, v);
+}
+
 template <class LF>
 __device__ __forceinline__ void step1(const BatchProb &P, const Shared &S, int dt, const void *pold, void *pnew,
                                       double v[4], fv2 *lds)
@@ -643,14 +730,29 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
     for (int it = 0; ok && S.any_run && it < cap; it++) {
         // 1. t = D_oe p', p' = r + beta p (written to the other p buffer),
         //    <p', A p'> = m4 |p'|^2 + |t|^2  -> alpha
-        tiles<true>(
-            A, S.prun,
-            [&](const BatchProb &P, int dt) {
-                const void *po = (it & 1) ? P.pb : P.pa;
-                void *pn = (it & 1) ? P.pa : P.pb;
-                step1<LF>(P, S, dt, po, pn, v, lds);
-            },
-            [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
+        if (A->split) {
+            tiles<false>(
+                A, S.prun,
+                [&](const BatchProb &P, int lt) {
+                    step1_p<T>(P, S, lt, (it & 1) ? P.pb : P.pa, (it & 1) ? P.pa : P.pb, v);
+                },
+                flush_lane);
+            mark(A, S, PH_STEP1P);
+            if (!(ok = grid_sync(ctl, lim, S))) break;
+            mark(A, S, PH_WAIT1P);
+            tiles<true>(
+                A, S.prun, [&](const BatchProb &P, int dt) { step1_d<LF>(P, S, dt, (it & 1) ? P.pa : P.pb, v); },
+                [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
+        } else {
+            tiles<true>(
+                A, S.prun,
+                [&](const BatchProb &P, int dt) {
+                    const void *po = (it & 1) ? P.pb : P.pa;
+                    void *pn = (it & 1) ? P.pa : P.pb;
+                    step1<LF>(P, S, dt, po, pn, v, lds);
+                },
+                [&](int p) { flush_prob(S, v, A->prob[p], mixed && A->prob[p].eng != MRHS_LANE); });
+        }
         write_row(A, A->rows[0], S);
         mark(A, S, PH_STEP1);
         if (!(ok = grid_sync(ctl, lim, S))) break;

@@ -365,7 +365,7 @@ class Lattice:
         _check(lib().lgt_cg_profile(self._ctx, ms, C.byref(n)))
         return {"xpay": ms[0], "update": ms[1], "beta_step": ms[2], "alpha_step": ms[3], "iters_timed": int(n.value)}
 
-    BATCH_PHASES = ("setup_and_final", "step1_doe", "wait1", "step2_deo_update", "wait2", "step3_update", "wait3",
+    BATCH_PHASES = ("setup_and_final", "step1_doe", "wait1", "step2_deo_update", "wait2", "step1_p", "wait1_p",
                     "scalar", "fp64_updates")
 
     def batch_profile(self) -> dict:

@@ -359,6 +359,37 @@ def test_batch_matches_single_solves_c4_shape(dev):
             assert np.linalg.norm(r) / np.linalg.norm(b[j]) <= 1.05 * tol
 
 
+@pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12)),
+                                       (P.LGT_CG_REFINE, (P.LGT_BF16, P.LGT_R12))],
+                         ids=["fp64", "rel_f32r12", "ir_bf16r12"])
+def test_batch_two_pass_step1(dev, scheme, lo):
+    """24^4 x 16 (2.65M site-rhs pairs: step 1 runs as two passes, p' and then
+    D_oe p') next to 8^4 x 4 in the same launch: every right-hand side checked
+    against the oracle's FP64 residual, the large lattice's against the single
+    solver's solution."""
+    mass, tol = 0.05, 1e-10
+    Lb, Ls = (24, 24, 24, 24), (8, 8, 8, 8)
+    Ub, Us = li.links(Lb, "expih", 4501, c=0.3), li.links(Ls, "haar", 4502)
+    bb, bs = li.vectors(Lb, 4503, 16), li.vectors(Ls, 4504, 4)
+    with P.Lattice(Lb) as lb, P.Lattice(Ls) as ls:
+        probs = []
+        for lat, U, b in ((lb, Ub, bb), (ls, Us, bs)):
+            Ut = _t(U, dev)
+            ul = lat.pack_links(Ut, *lo) if lo else None
+            probs.append((lat, lat.pack_links(Ut, P.LGT_F64, P.LGT_R18), ul, _t(b, dev)))
+        xs, res = P.cg_solve_batch(probs, mass, tol=tol, scheme=scheme,
+                                   inner_tol=0.1 if scheme == P.LGT_CG_REFINE else 0.0)
+        xb = xs[0].cpu().numpy()
+        xj, rj = lb.cg_solve(probs[0][1], probs[0][3][5], mass, tol=tol, scheme=scheme, U_lo=probs[0][2],
+                             inner_tol=0.1 if scheme == P.LGT_CG_REFINE else 0.0)
+    assert rj.status == 0
+    assert np.linalg.norm(xb[5] - xj.cpu().numpy()) <= 2.1 * tol * np.linalg.norm(bb[5]) / (4 * mass * mass)
+    for j in (0, 5, 15):
+        _check_solution(Lb, Ub, mass, bb[j], xb[j], res[0][j], tol)
+    for j in range(4):
+        _check_solution(Ls, Us, mass, bs[j], xs[1].cpu().numpy()[j], res[1][j], tol)
+
+
 def test_batch_iteration_cap_and_determinism(dev):
     L = (4, 4, 4, 4)
     U = li.links(L, "haar", 4401)

@@ -16,10 +16,12 @@ One step = the whole hot path:
      kernel backward.
 `value` is the FP64 Dslash bandwidth in algorithmic bytes (8 links + the
 input vector read once + the output written once per site) over the kernel
-time, where the kernel time is measured with HIP events that the library
-records on its own stream around the FP64 Dslash launches of every 16th
-iteration (and of every FP64 update) inside the timed FP64 solves. Inputs are resident in HBM before the timed region; link packing
-is done once per gauge field, outside it.
+time of the CG iteration's D_oe launch (whose epilogue also forms the
+<p, A p> partials), measured with HIP events that the library records on the
+launch's own dispatch packet in every 16th iteration of the timed FP64 solves.
+The iteration's D_eo launch, which also applies the update of r, is reported
+beside it with its own bytes. Inputs are resident in HBM before the timed
+region; link packing is done once per gauge field, outside it.
 """
 from __future__ import annotations
 
@@ -567,6 +569,7 @@ def main():
     def solves():
         out = {}
         last_x["fp64"], out["fp64"] = lat.cg_solve(packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_FP64)
+        out["fp64_dslash_kinds"] = lat.cg_dslash_profile()  # host-side copy of the solve's own event times
         last_x["f32r12_reliable"], out["f32r12_reliable"] = lat.cg_solve(
             packed["f64r18"], bt, args.mass, tol=1e-10, scheme=P.LGT_CG_RELIABLE, U_lo=packed["f32r12"],
             ru_interval=50)
@@ -588,24 +591,29 @@ def main():
     wall = time.perf_counter() - t_start
     lat.set_timing(False)
 
-    ms_hi = sum(s["fp64"].dslash_ms_hi for s in steps)
-    n_hi = sum(s["fp64"].dslash_timed_hi for s in steps)
-    avg_ms = ms_hi / max(n_hi, 1)
-    # Algorithmic bytes of the timed FP64 launches (per output site): a CG
-    # iteration's pair is a plain D_oe and a D_eo that also reads p for 4m^2 p
-    # (+48 B); an FP64 update's pair is a plain D_oe and a D_eo reading x and b
-    # (+96 B). One update pair is timed per update.
+    # The headline kernel: the FP64 CG's iteration D_oe (t = D_oe p; its epilogue
+    # also reads p at the same cb for the <p, A p> partials), timed by events on
+    # its own dispatch packets in every sampled iteration. Its bytes: the
+    # Dslash's own 8 links + input once + output once = 1248 B per output site
+    # (the value), 1296 with the epilogue's read of p. The iteration's D_eo also
+    # carries the update r -= alpha (4m^2 p - D_eo t): its 8 links and input,
+    # p and r read, r written (Ap is never stored) = 1248 + 96 = 1344 B per
+    # site, reported beside it.
+    def kind(k):
+        ms = sum(s["fp64_dslash_kinds"][k]["ms"] * s["fp64_dslash_kinds"][k]["n"] for s in steps)
+        n = sum(s["fp64_dslash_kinds"][k]["n"] for s in steps)
+        return ms / max(n, 1), n
+    avg_ms, n_hi = kind("iter_doe")
+    deo_ms, n_deo = kind("iter_deo_update")
     base = alg_bytes_per_site(P.LGT_F64, P.LGT_R18)
     vb = P.vec_bytes_per_site(P.LGT_F64)
-    it_pair, ru_pair = base + (base + vb), base + (base + 2 * vb)
-    n_ru = sum(s["fp64"].updates for s in steps)
-    n_it = n_hi // 2 - n_ru
-    by64 = (n_it * it_pair + n_ru * ru_pair) * Vh / max(n_hi, 1)
-    gbs_fused = by64 / (avg_ms * 1e-3) / 1e9
-    # headline: the Dslash's own algorithmic bytes, 8 links + input once + output
-    # once = 1248 B per output site, whatever epilogue the CG fuses into it
+    doe_bytes, deo_bytes = base + vb, base + 2 * vb
+    gbs_fused = doe_bytes * Vh / (avg_ms * 1e-3) / 1e9
     gbs = base * Vh / (avg_ms * 1e-3) / 1e9
     gflops = P.DSLASH_FLOP_PER_SITE * Vh / (avg_ms * 1e-3) / 1e9
+    deo = {"bytes_per_site": deo_bytes, "avg_launch_us": round(deo_ms * 1e3, 2), "launches_timed": n_deo,
+           "GBps": round(deo_bytes * Vh / (deo_ms * 1e-3) / 1e9, 1),
+           "frac": round(deo_bytes * Vh / (deo_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     def summ(key):
         rs = [s[key] for s in steps]
@@ -934,12 +942,13 @@ def main():
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic,
-                     "kernel": "k_dslash<LinkF64R18,*> inside the FP64 CG: plain D_oe and D_eo with the "
-                               "4m^2 p epilogue and <p,Ap> partials",
+                     "kernel": "k_dslash<LinkF64R18, EPI_PAP, *> inside the FP64 CG: the iteration's D_oe "
+                               "(t = D_oe p with the <p, A p> partials)",
                      "alg_bytes_per_site": base, "alg_bytes_per_launch": base * Vh,
                      "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": n_hi,
-                     "with_epilogue_reads": {"bytes_per_site": round(by64 / Vh, 1), "GBps": round(gbs_fused, 1),
+                     "with_epilogue_reads": {"bytes_per_site": doe_bytes, "GBps": round(gbs_fused, 1),
                                              "frac": round(gbs_fused / HBM_PEAK_GBS, 4)},
+                     "deo_with_update": deo,
                      "measured_ceiling_GBps": {"read_1GiB_single_stream": ceil["read_GBps"],
                                                "copy_1GiB": ceil["copy_GBps"],
                                                "dslash_link_read_pattern": link_read["GBps"]},

@@ -119,12 +119,18 @@ lgt_status lgt_set_timing(lgt_ctx *ctx, int32_t every);
 /* The rest of a timed CG iteration: for the last lgt_cg_solve* on this context
  * with timing on, ms[4] receives the mean kernel time (ms) per timed iteration
  * of the vector kernels around the Dslash pair -- (0) x += alpha p with
- * p = r + beta p, (1) the update r -= alpha Ap with the |r|^2 partials, (2)
- * the one-workgroup step for beta and the stop tests, (3) the one-workgroup
- * alpha step (0 where the update sums the <p, Ap> partials itself) -- and n
- * the number of iterations timed (their Dslash pairs are in lgt_cg_result).
- * Host only. */
+ * p = r + beta p, (1) always 0: the update r -= alpha Ap runs inside the D_eo
+ * launch (its time is in lgt_cg_result's Dslash figures), (2) the
+ * one-workgroup step for beta and the stop tests, (3) the one-workgroup alpha
+ * step (0 where D_eo sums D_oe's <p, A p> partials itself) -- and n the number
+ * of iterations timed (their Dslash pairs are in lgt_cg_result). Host only. */
 lgt_status lgt_cg_profile(lgt_ctx *ctx, double ms[4], int32_t *n);
+/* The timed Dslash launches of that solve by kind: ms[k] receives the mean
+ * kernel time (ms) and n[k] the number timed of (0) the iteration's D_oe
+ * (t = D_oe p with the <p, A p> partials), (1) the iteration's D_eo (with the
+ * update r -= alpha (4m^2 p - D_eo t) and the |r|^2 partials), (2) and (3) the
+ * D_oe and D_eo of the FP64 updates (the residual b - A x). Host only. */
+lgt_status lgt_cg_dslash_profile(lgt_ctx *ctx, double ms[4], int32_t n[4]);
 
 /* ---- kernel variants and autotuning ---------------------------------------- */
 

@@ -301,6 +301,17 @@ lgt_status lgt_cg_profile(lgt_ctx *c, double ms[4], int32_t *n)
     return LGT_OK;
 }
 
+lgt_status lgt_cg_dslash_profile(lgt_ctx *c, double ms[4], int32_t n[4])
+{
+    CHECK_CTX(c);
+    if (!ms || !n) return fail(LGT_ERR_ARG, "output pointer is NULL");
+    for (int k = 0; k < 4; k++) {
+        ms[k] = c->cg_dsl_ms[k];
+        n[k] = c->cg_dsl_n[k];
+    }
+    return LGT_OK;
+}
+
 lgt_status lgt_set_timing(lgt_ctx *c, int32_t every)
 {
     CHECK_CTX(c);

@@ -88,66 +88,6 @@ hipError_t launch_x_pending(bool f64, const VecArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// alpha = rho / <p, Ap>, then r -= alpha Ap ; partial |r|^2 (FP64); x += alpha p
-// is left pending for the next k_xpay (or k_x_pending). With nparts_in > 0
-// every workgroup sums the partials of the preceding D_eo itself, in
-// k_finalize's order, so all of them get the same alpha bit for bit without a
-// launch of their own; workgroup 0 records the step in the solver state
-// (fields no other workgroup reads in this kernel). A breakdown (<p, Ap> not
-// positive or not finite) marks the state failed and skips the update. With
-// nparts_in == 0 a FIN_ALPHA finalize has already done all of that, and a
-// breakdown has closed this kernel's gate.
-template <typename T>
-__global__ __launch_bounds__(kBS) void k_update(VecArgs a)
-{
-    if (!gate_open(a.gate, a.st)) return;
-    const int blk = blockIdx.x;
-    const int cb = blk * kBS + threadIdx.x;
-    // the vector loads do not depend on alpha: issue them before the sum
-    cx<T> r[3], q[3];
-    if (cb < a.Vh) {
-        VecFmt<T>::template load<false>(a.r, (size_t)a.Vh, cb, r);
-        VecFmt<T>::template load<false>(a.Ap, (size_t)a.Vh, cb, q);
-    }
-    double alpha64;
-    if (a.nparts_in > 0) {
-        __shared__ double lds[kBS / 64];
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < a.nparts_in; i += kBS) acc += a.parts_in[i];
-        const double pAp = block_sum_all(acc, lds);
-        const bool bad = !(pAp > 0.0) || !isfinite(pAp);
-        alpha64 = a.st->rho / pAp;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.st->pAp = pAp;
-            a.st->pend = 0; // the previous alpha p went into x in k_xpay
-            if (bad) a.st->state = ST_FAIL;
-            else a.st->alpha = alpha64;
-        }
-        if (bad) return;
-    } else {
-        alpha64 = a.st->alpha;
-    }
-    double part = 0.0;
-    if (cb < a.Vh) {
-        const T alpha = (T)alpha64;
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            r[i].re = fma(-alpha, q[i].re, r[i].re);
-            r[i].im = fma(-alpha, q[i].im, r[i].im);
-            part += (double)r[i].re * (double)r[i].re + (double)r[i].im * (double)r[i].im;
-        }
-        VecFmt<T>::template store<false>(a.r, (size_t)a.Vh, cb, r);
-    }
-    write_partial(part, a.partials, blk);
-}
-
-hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
-{
-    if (f64) launch_ev(k_update<double>, dim3(a.l.nblk), dim3(kBS), s, e0, e1, a);
-    else launch_ev(k_update<float>, dim3(a.l.nblk), dim3(kBS), s, e0, e1, a);
-    return hipGetLastError();
-}
-
 // Sum n partials in index order (fixed tree inside one workgroup, so the
 // result is bit-reproducible) and run the scalar step `fin`. Gated exactly
 // like the kernel that wrote the partials.

@@ -63,6 +63,11 @@ struct lgt_ctx {
     // step (0 when fused into the update), and the number of those iterations
     double cg_prof_ms[4] = {};
     int cg_prof_n = 0;
+    // mean kernel times (ms) of the timed Dslash launches of that solve by
+    // kind: iteration D_oe (with the <p, A p> partials), iteration D_eo (with
+    // the update of r), FP64-update D_oe, FP64-update D_eo (the residual)
+    double cg_dsl_ms[4] = {};
+    int cg_dsl_n[4] = {};
 };
 
 namespace lgt {

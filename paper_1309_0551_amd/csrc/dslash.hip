@@ -64,10 +64,11 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
         __syncthreads();
     }
     double part = 0.0;
+    cx<T> acc[3];
+    [[maybe_unused]] cx<T> pu[3], ru[3]; // EPI_UPD: p and r at this site, loaded before alpha
     if (cb < a.g.Vh) {
         int c[4];
         decode(a.g, a.par, cb, c);
-        cx<T> acc[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) acc[i].re = acc[i].im = T(0);
         if constexpr (HPI == 0) {
@@ -167,8 +168,58 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 else amv_sub(u, v, acc);
             }
         }
+        if constexpr (EPI == EPI_UPD) {
+            VF::template load<false>(a.aux0, Vh, cb, pu);
+            VF::template load<false>(a.rw, Vh, cb, ru);
+        }
+    }
+    [[maybe_unused]] double alpha64 = 0.0;
+    if constexpr (EPI == EPI_UPD) {
+        // alpha after the hops, so that this sum waits while the hops of other
+        // workgroups run (every thread of the workgroup takes part)
+        if (a.nparts_in > 0) {
+            __shared__ double red[kBS / 64];
+            double acc = 0.0;
+            for (int i = threadIdx.x; i < a.nparts_in; i += bs) acc += a.parts_in[i];
+            const double pAp = block_sum_all(acc, red);
+            const bool bad = !(pAp > 0.0) || !isfinite(pAp);
+            alpha64 = a.st->rho / pAp;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                // fields no other workgroup reads in this kernel
+                a.st->pAp = pAp;
+                a.st->pend = 0; // the previous alpha p went into x in k_xpay
+                if (bad) a.st->state = ST_FAIL;
+                else a.st->alpha = alpha64;
+            }
+            if (bad) return; // the whole workgroup; the beta step is gated off
+        } else {
+            alpha64 = a.st->alpha;
+        }
+    }
+    if (cb < a.g.Vh) {
         if constexpr (EPI == EPI_PLAIN) {
             VF::template store<true>(a.out, Vh, cb, acc);
+        } else if constexpr (EPI == EPI_PAP) {
+            // out = D in ; partial m4 |p|^2 + |out|^2 (p at the same cb of the other parity)
+            cx<T> p[3];
+            VF::template load<false>(a.aux0, Vh, cb, p);
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                part += a.m4 * ((double)p[i].re * (double)p[i].re + (double)p[i].im * (double)p[i].im) +
+                        ((double)acc[i].re * (double)acc[i].re + (double)acc[i].im * (double)acc[i].im);
+            VF::template store<true>(a.out, Vh, cb, acc);
+        } else if constexpr (EPI == EPI_UPD) {
+            // Ap = m4 p - D in ; r -= alpha Ap ; partial |r|^2
+            const T m4 = (T)a.m4, alpha = (T)alpha64;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const T apr = m4 * pu[i].re - acc[i].re;
+                const T api = m4 * pu[i].im - acc[i].im;
+                ru[i].re = fma(-alpha, apr, ru[i].re);
+                ru[i].im = fma(-alpha, api, ru[i].im);
+                part += (double)ru[i].re * (double)ru[i].re + (double)ru[i].im * (double)ru[i].im;
+            }
+            VF::template store<false>(a.rw, Vh, cb, ru);
         } else if constexpr (EPI == EPI_A) {
             // out = m4 p - D in ; partial Re <p, out>
             cx<T> p[3];
@@ -229,6 +280,8 @@ static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s, hipEve
     switch (epi) {
     case EPI_PLAIN: launch_k(k_dslash<LF, EPI_PLAIN, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_A: launch_k(k_dslash<LF, EPI_A, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
+    case EPI_PAP: launch_k(k_dslash<LF, EPI_PAP, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
+    case EPI_UPD: launch_k(k_dslash<LF, EPI_UPD, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_RES:
     case EPI_RES_LO:
         if constexpr (std::is_same<typename LF::real, double>::value) {

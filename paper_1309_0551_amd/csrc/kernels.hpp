@@ -74,7 +74,7 @@ inline Launch site_launch(int Vh, int bs = kBS)
 inline bool dslash_bs_ok(int bs) { return bs == 64 || bs == 128 || bs == 256; }
 
 // ---- Dslash family ------------------------------------------------------
-enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3 };
+enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3, EPI_PAP = 4, EPI_UPD = 5 };
 
 struct DslashArgs {
     const void *U;   // packed links (the fat one-link field of the improved operator)
@@ -87,9 +87,18 @@ struct DslashArgs {
     Launch l;
     // EPI_A:   out = m4*aux0 - D in, partial <aux0, out>
     // EPI_RES: r = aux1 - (m4*aux0 - D in) in FP64 into out (or out_lo), partial |r|^2
+    // EPI_PAP: out = D in (D_oe p), partial m4 |aux0|^2 + |out|^2 at the same cb,
+    //          which sums to <p, A p> (A = m4 - D_eo D_oe, D_eo = -D_oe^dag)
+    // EPI_UPD: rw -= alpha (m4*aux0 - D in) (D_eo t, Ap never stored), partial
+    //          |rw|^2; alpha = rho / (sum of the nparts_in partials parts_in of the
+    //          preceding EPI_PAP), every workgroup summing them in the same order
+    //          (workgroup 0 records it in st), or st->alpha when nparts_in == 0
     const void *aux0;
     const void *aux1;
     void *out_lo;
+    void *rw;
+    const double *parts_in;
+    int nparts_in;
     double m4;
     double *partials;
     CgState *st;
@@ -109,12 +118,8 @@ hipError_t launch_index_maps(int32_t *lex_of_eo, int32_t *nbr, const Geom &g, hi
 // ---- vector kernels (solver.hip) -----------------------------------------
 struct VecArgs {
     void *x, *r, *p;
-    const void *Ap;
     int Vh;
     Launch l;
-    const double *parts_in; // <p, Ap> partials of the preceding D_eo
-    int nparts_in;          // 0: alpha is already in the state (FIN_ALPHA ran)
-    double *partials;       // |r|^2 partials written by the update
     CgState *st;
     int gate;
 };
@@ -122,8 +127,6 @@ struct VecArgs {
 hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // x += alpha p when the state holds a pending update (gate: a.gate)
 hipError_t launch_x_pending(bool f64, const VecArgs &a, hipStream_t s);
-hipError_t launch_update(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
-                         hipEvent_t e1 = nullptr);
 hipError_t launch_ru_accum(double *x64, void *xlo, int Vh, CgState *st, int gate, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol,

@@ -4,16 +4,19 @@
 // beta = rho'/rho, p = r + beta p) with every scalar kept in device memory:
 // the kernels compute alpha and beta themselves from FP64 reductions, and a
 // solver state word makes every later kernel of a finished solve exit at
-// once. An iteration is five launches: x += alpha p (the previous update's) and
-// p = r + beta p; D_oe; D_eo with 4m^2 p and the partials of <p, Ap>; the
-// update r -= alpha Ap (which sums those partials itself for alpha) with the
-// partials of |r|^2; and the one-workgroup step for beta and the stop tests. On lattices with more than kFuseAlphaMaxParts Dslash
-// workgroups a one-workgroup alpha step runs before the update instead (six
-// launches), since the redundant sums grow with the square of the lattice
-// size. (Forming r + beta p inside D_oe instead saves the xpay
-// pass but gathers two vectors at every neighbour, which costs more cache
-// misses than the pass it saves.) The host enqueues iterations in chunks and reads the state
-// back once per chunk, one chunk behind, so the GPU never waits for the host.
+// once. Since D_eo = -D_oe^dag, <p, A p> = 4m^2 |p|^2 + |D_oe p|^2, so alpha is
+// known once D_oe has run, and D_eo can apply the update itself. An iteration
+// is four launches: x += alpha p (the previous update's) and p = r + beta p;
+// t = D_oe p with the partials of <p, A p>; D_eo t with r -= alpha (4m^2 p -
+// D_eo t) (Ap is never stored; every workgroup sums D_oe's partials itself for
+// alpha) and the partials of |r|^2; and the one-workgroup step for beta and the
+// stop tests. On lattices with more than kFuseAlphaMaxParts Dslash workgroups
+// a one-workgroup alpha step runs between the two Dslash launches instead,
+// since the redundant sums grow with the square of the lattice size. (Forming
+// r + beta p inside D_oe instead saves the xpay pass but gathers two vectors
+// at every neighbour, which costs more cache misses than the pass it saves.)
+// The host enqueues iterations in chunks and reads the state back once per
+// chunk, one chunk behind, so the GPU never waits for the host.
 //
 // Precision forms (single precision gains more than double, Sec. 4):
 //  FP64      all in FP64; at inner convergence the true residual b - A x is
@@ -103,7 +106,6 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     double *q64 = (double *)workspace(c, "cg.q64", v64); // scratch FP64 residual
     void *r = workspace(c, "cg.r", vlo);
     void *pp = workspace(c, "cg.p", vlo);
-    void *Ap = workspace(c, "cg.Ap", vlo);
     void *t = workspace(c, "cg.t", vlo);
     void *xlo = mixed ? workspace(c, "cg.xlo", vlo) : x64;
     // Dslash launches of the two link formats (their workgroup sizes are
@@ -111,13 +113,13 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     const bool imp = U3hi != nullptr;
     const Launch lhi = imp ? dslash_launch_improved(c, fhi) : dslash_launch(c, fhi);
     const Launch llo = imp ? dslash_launch_improved(c, flo) : dslash_launch(c, flo);
-    // two partial-sum buffers: the update reads D_eo's while writing its own
+    // two partial-sum buffers: D_eo reads D_oe's while writing its own
     const size_t np1 = (size_t)std::max(std::max(lhi.nblk_pad, llo.nblk_pad), l.nblk_pad);
-    double *partials = (double *)workspace(c, "cg.partials", sizeof(double) * (np1 + (size_t)l.nblk_pad));
+    double *partials = (double *)workspace(c, "cg.partials", sizeof(double) * 2 * np1);
     double *partials2 = partials ? partials + np1 : nullptr;
     CgState *dst = (CgState *)workspace(c, "cg.state", sizeof(CgState));
     CgState *host = (CgState *)pinned(c, 3 * sizeof(CgState));
-    if (!b64 || !x64 || !t64 || !q64 || !r || !pp || !Ap || !t || !xlo || !partials || !dst || !host)
+    if (!b64 || !x64 || !t64 || !q64 || !r || !pp || !t || !xlo || !partials || !dst || !host)
         return fail(LGT_ERR_OOM, "cannot allocate the solver workspace");
 
     const bool timing = c->timing > 0;
@@ -126,14 +128,15 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     Events evs, tev, vev;
     LGT_HIP(evs.make(4)); // 0 start, 1 end, 2/3 chunk slots
     if (timing) LGT_HIP(tev.make((size_t)2 * 2 * pairs));
-    // the vector kernels of the timed iterations: xpay, update, beta step, alpha step
+    // the vector kernels of the timed iterations: xpay, (update: inside D_eo), beta step, alpha step
     constexpr int kVec = 4;
     if (timing) LGT_HIP(vev.make((size_t)2 * chunk * kVec * 2));
 
-    // Dslash launch; the reducing epilogues (EPI_A, EPI_RES*) leave one
-    // partial sum per workgroup for the finalize kernel that follows.
+    // Dslash launch; the reducing epilogues (EPI_PAP, EPI_UPD, EPI_RES*) leave
+    // one partial sum per workgroup for the kernel that follows.
     auto D = [&](Fmt f, int epi, int par, const void *U, const void *in, void *out, int gate, const void *aux0,
-                 const void *aux1, void *out_lo, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+                 const void *aux1, void *out_lo, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                 void *rw = nullptr, double *parts = nullptr, const double *parts_in = nullptr, int nparts_in = 0) {
         DslashArgs a;
         a.U = U;
         // the improved operator's Naik field that goes with this fat field
@@ -148,7 +151,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.aux1 = aux1;
         a.out_lo = out_lo;
         a.m4 = m4;
-        a.partials = partials;
+        a.partials = parts ? parts : partials;
+        a.rw = rw;
+        a.parts_in = parts_in;
+        a.nparts_in = nparts_in;
         a.st = dst;
         a.hpi = c->hpi[f];
         a.ntl = imp ? c->intl[f] : c->ntl[f];
@@ -173,15 +179,11 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     va.x = xlo;
     va.r = r;
     va.p = pp;
-    va.Ap = Ap;
     va.Vh = Vh;
     va.l = l;
     // partial slots from nblk on belong to idle workgroups (zeros): sum nblk
-    // (the iteration's D_eo runs in the inner format's launch geometry)
+    // (the iteration's Dslash pair runs in the inner format's launch geometry)
     const bool fuse_alpha = llo.nblk <= fuse_alpha_max();
-    va.parts_in = fuse_alpha ? partials : nullptr;
-    va.nparts_in = fuse_alpha ? llo.nblk : 0;
-    va.partials = partials2;
     va.st = dst;
     va.gate = GATE_ITER;
 
@@ -224,6 +226,8 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     int prev_iter = 0, prev_upd = 0;
     double ms_hi = 0.0, ms_lo = 0.0;
     int n_hi = 0, n_lo = 0;
+    double dsl_ms[4] = {0.0, 0.0, 0.0, 0.0}; // by kind: iteration D_oe, D_eo; update D_oe, D_eo
+    int dsl_n[4] = {0, 0, 0, 0};
     // every chunk that starts running does at least one iteration, and the
     // kernels stop at max_iter, so this bound is never the one that ends the loop
     const int max_chunks = p->max_iter + 4;
@@ -232,7 +236,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         const int nreal = std::min(end.iter - prev_iter, chunk);
         for (int i = 0; i < nreal; i += every) {
             for (int k = 0; k < kVec; k++) {
-                if (k == 3 && fuse_alpha) continue;
+                if (k == 1 || (k == 3 && fuse_alpha)) continue; // the update runs inside D_eo
                 float ms = 0.f;
                 hipError_t e = hipEventElapsedTime(&ms, vv(slot, i, k, true), vv(slot, i, k, false));
                 if (e != hipSuccess) return e;
@@ -253,6 +257,8 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                 ms_lo += ms;
                 n_lo++;
             }
+            dsl_ms[i & 1] += ms;
+            dsl_n[i & 1]++;
         }
         if (end.updates > prev_upd) {
             for (int i = 2 * chunk; i < 2 * chunk + 2; i++) {
@@ -262,6 +268,8 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                 if (e != hipSuccess) return e;
                 ms_hi += ms;
                 n_hi++;
+                dsl_ms[2 + (i & 1)] += ms;
+                dsl_n[2 + (i & 1)]++;
             }
         }
         return hipSuccess;
@@ -273,15 +281,18 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
             const int ts = i % every == 0 ? slot : -1;
             const void *Ui = mixed ? Ulo->ptr : Uhi->ptr;
             LGT_HIP(launch_xpay(lo_is_f64, va, s, vv(ts, i, 0, true), vv(ts, i, 0, false)));
-            LGT_HIP(D(flo, EPI_PLAIN, LGT_ODD, Ui, pp, t, GATE_ITER, nullptr, nullptr, nullptr, ev(ts, 2 * i, true),
+            // t = D_oe p with the partials of <p, A p> = m4 |p|^2 + |t|^2
+            LGT_HIP(D(flo, EPI_PAP, LGT_ODD, Ui, pp, t, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i, true),
                       ev(ts, 2 * i, false)));
-            LGT_HIP(D(flo, EPI_A, LGT_EVEN, Ui, t, Ap, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
-                      ev(ts, 2 * i + 1, false)));
             if (!fuse_alpha)
                 LGT_HIP(launch_finalize(partials, llo.nblk, dst, FIN_ALPHA, GATE_ITER, s, vv(ts, i, 3, true),
                                         vv(ts, i, 3, false)));
-            LGT_HIP(launch_update(lo_is_f64, va, s, vv(ts, i, 1, true), vv(ts, i, 1, false)));
-            LGT_HIP(launch_finalize(partials2, l.nblk, dst, FIN_UPDATE, GATE_ITER, s, vv(ts, i, 2, true),
+            // r -= alpha (m4 p - D_eo t) with the partials of |r|^2 (alpha summed
+            // from D_oe's partials in every workgroup when fused)
+            LGT_HIP(D(flo, EPI_UPD, LGT_EVEN, Ui, t, nullptr, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
+                      ev(ts, 2 * i + 1, false), r, partials2, fuse_alpha ? partials : nullptr,
+                      fuse_alpha ? llo.nblk : 0));
+            LGT_HIP(launch_finalize(partials2, llo.nblk, dst, FIN_UPDATE, GATE_ITER, s, vv(ts, i, 2, true),
                                     vv(ts, i, 2, false)));
         }
         LGT_HIP(reliable(GATE_RU, timing ? slot : -1, FIN_RU));
@@ -328,6 +339,10 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     if (timing) {
         for (int k = 0; k < kVec; k++) c->cg_prof_ms[k] = vn ? vms[k] / vn : 0.0;
         c->cg_prof_n = vn;
+        for (int k = 0; k < 4; k++) {
+            c->cg_dsl_ms[k] = dsl_n[k] ? dsl_ms[k] / dsl_n[k] : 0.0;
+            c->cg_dsl_n[k] = dsl_n[k];
+        }
     }
     lgt_status ret;
     if (e.state == ST_DONE) ret = LGT_OK;

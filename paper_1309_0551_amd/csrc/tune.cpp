@@ -209,8 +209,11 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[24])
     void *out = workspace(c, "tune.out", vb);
     void *ap = workspace(c, "tune.ap", vb);
     double *parts = (double *)workspace(c, "tune.partials", sizeof(double) * (size_t)l.nblk_pad);
-    if (!in || !out || !ap || !parts) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
+    CgState *cgs = (CgState *)workspace(c, "tune.state", sizeof(CgState));
+    if (!in || !out || !ap || !parts || !cgs) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
     LGT_HIP(launch_zero(in, vb, c->stream));
+    LGT_HIP(launch_zero(ap, vb, c->stream));
+    LGT_HIP(launch_zero(cgs, sizeof(CgState), c->stream));
     hipEvent_t e0, e1;
     LGT_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -227,25 +230,27 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[24])
     a.l = l;
     a.m4 = 0.04;
     a.partials = parts;
+    a.st = cgs;
     constexpr int kN = kNumVariants * kNumBs;
     double t[kN] = {};
     double best_t = 1e300;
     const int reps = 5;
     hipError_t e = hipSuccess;
-    // the CG's pair: plain D_oe, then D_eo with the 4m^2 p epilogue and its
-    // partial sums (both halves of the link field touched in turn)
+    // the CG's pair: D_oe with the <p, A p> partials, then D_eo with the update
+    // of r (alpha from the zeroed state) and its partials (both halves of the
+    // link field touched in turn)
     auto pair = [&]() {
         a.par = LGT_ODD;
         a.in = in;
         a.out = out;
-        a.aux0 = nullptr;
-        hipError_t r = launch_dslash(f, EPI_PLAIN, a, c->stream);
+        a.aux0 = in;
+        hipError_t r = launch_dslash(f, EPI_PAP, a, c->stream);
         if (r != hipSuccess) return r;
         a.par = LGT_EVEN;
         a.in = out;
-        a.out = ap;
-        a.aux0 = in;
-        return launch_dslash(f, EPI_A, a, c->stream);
+        a.out = nullptr;
+        a.rw = ap;
+        return launch_dslash(f, EPI_UPD, a, c->stream);
     };
     // Smaller workgroups only pay where 256-site ones are too few to keep every
     // CU busy; elsewhere they only multiply the CG's per-workgroup partial
@@ -323,8 +328,11 @@ lgt_status lgt_tune_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_
     void *out = workspace(c, "tune.out", vb);
     void *ap = workspace(c, "tune.ap", vb);
     double *parts = (double *)workspace(c, "tune.partials", sizeof(double) * (size_t)l64.nblk_pad);
-    if (!in || !out || !ap || !parts) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
+    CgState *cgs = (CgState *)workspace(c, "tune.state", sizeof(CgState));
+    if (!in || !out || !ap || !parts || !cgs) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
     LGT_HIP(launch_zero(in, vb, c->stream));
+    LGT_HIP(launch_zero(ap, vb, c->stream));
+    LGT_HIP(launch_zero(cgs, sizeof(CgState), c->stream));
     hipEvent_t e0, e1;
     LGT_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -339,19 +347,20 @@ lgt_status lgt_tune_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_
     a.gate = GATE_NONE;
     a.m4 = 0.04;
     a.partials = parts;
+    a.st = cgs;
     // the CG's pair, as for the one-link operator
     auto pair = [&]() {
         a.par = LGT_ODD;
         a.in = in;
         a.out = out;
-        a.aux0 = nullptr;
-        hipError_t r = launch_dslash(f, EPI_PLAIN, a, c->stream);
+        a.aux0 = in;
+        hipError_t r = launch_dslash(f, EPI_PAP, a, c->stream);
         if (r != hipSuccess) return r;
         a.par = LGT_EVEN;
         a.in = out;
-        a.out = ap;
-        a.aux0 = in;
-        return launch_dslash(f, EPI_A, a, c->stream);
+        a.out = nullptr;
+        a.rw = ap;
+        return launch_dslash(f, EPI_UPD, a, c->stream);
     };
     // (streaming, cached) x (256, 128, 64 sites); smaller workgroups only below
     // 1024 workgroups of 256 sites, as for the one-link operator

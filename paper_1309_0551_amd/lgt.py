@@ -167,6 +167,7 @@ def _setup(l):
         "lgt_tune_dslash_mrhs": (st, [vp, C.POINTER(_Links), i32, C.POINTER(C.c_double)]),
         "lgt_cg_solve_batch": (st, [C.POINTER(_CgProblem), i32, C.POINTER(_CgParams)]),
         "lgt_batch_profile": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "lgt_cg_dslash_profile": (st, [vp, C.POINTER(C.c_double), C.POINTER(i32)]),
         "lgt_cg_profile": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "lgt_dslash_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), i32, vp, vp]),
         "lgt_force_improved": (st, [vp, C.POINTER(_Links), C.POINTER(_Links), vp, C.c_double, vp, vp]),
@@ -364,6 +365,15 @@ class Lattice:
         n = C.c_int32()
         _check(lib().lgt_cg_profile(self._ctx, ms, C.byref(n)))
         return {"xpay": ms[0], "update": ms[1], "beta_step": ms[2], "alpha_step": ms[3], "iters_timed": int(n.value)}
+
+    def cg_dslash_profile(self) -> dict:
+        """Mean kernel times (ms) and counts of the timed Dslash launches of the
+        last CG with timing on, by kind (iteration D_oe / D_eo, update D_oe / D_eo)."""
+        ms = (C.c_double * 4)()
+        n = (C.c_int32 * 4)()
+        _check(lib().lgt_cg_dslash_profile(self._ctx, ms, n))
+        keys = ("iter_doe", "iter_deo_update", "ru_doe", "ru_deo_residual")
+        return {k: {"ms": ms[i], "n": int(n[i])} for i, k in enumerate(keys)}
 
     BATCH_PHASES = ("setup_and_final", "step1_doe", "wait1", "step2_deo_update", "wait2", "step1_p", "wait1_p",
                     "scalar", "fp64_updates")

@@ -66,6 +66,10 @@ int main(void)
     EXPECT(lgt_destroy(NULL), LGT_ERR_ARG);
     EXPECT(lgt_set_timing(NULL, 1), LGT_ERR_ARG);
     EXPECT(lgt_cg_profile(NULL, d, &i32), LGT_ERR_ARG);
+    {
+        int32_t n4[4];
+        EXPECT(lgt_cg_dslash_profile(NULL, d, n4), LGT_ERR_ARG);
+    }
     EXPECT(lgt_set_dslash_variant(NULL, 0, 18, 8, 1), LGT_ERR_ARG);
     EXPECT(lgt_get_dslash_variant(NULL, 0, 18, &i32, &i32), LGT_ERR_ARG);
     EXPECT(lgt_set_dslash_workgroup(NULL, 0, 18, 64), LGT_ERR_ARG);

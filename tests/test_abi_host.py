@@ -167,6 +167,7 @@ def test_every_context_call_rejects_a_null_context():
         "lgt_get_dslash_workgroup": (None, 0, 18, C.byref(i)),
         "lgt_batch_profile": (None, (C.c_double * 9)(), C.byref(i)),
         "lgt_cg_profile": (None, (C.c_double * 4)(), C.byref(i)),
+        "lgt_cg_dslash_profile": (None, (C.c_double * 4)(), (C.c_int32 * 4)()),
     }
     for name, args in calls.items():
         assert getattr(l, name)(*args) == -1, name

@@ -547,12 +547,38 @@ def test_cg_deterministic(dev):
             assert torch.equal(x1, x2) and r1.iters == r2.iters
 
 
+def test_cg_dslash_profile_by_kind(dev):
+    """With timing on every iteration, lgt_cg_dslash_profile counts one
+    iteration D_oe and one D_eo per iteration, and the FP64-update pairs of a
+    mixed solve; every mean time is positive, and timing leaves the solve
+    bit-identical."""
+    L = (8, 8, 8, 8)
+    U = li.links(L, "haar", 431)
+    b = li.vector(L, 432)
+    with P.Lattice(L) as lat:
+        Uh = lat.pack_links(_t(U, dev))
+        Ul = lat.pack_links(_t(U, dev), P.LGT_F32, P.LGT_R12)
+        for scheme, lo in ((P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, Ul)):
+            x0, r0 = lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo)
+            lat.set_timing(1)
+            x1, r1 = lat.cg_solve(Uh, _t(b, dev), 0.1, scheme=scheme, U_lo=lo)
+            lat.set_timing(0)
+            prof = lat.cg_dslash_profile()
+            assert torch.equal(x0, x1) and r0.iters == r1.iters
+            assert prof["iter_doe"]["n"] == prof["iter_deo_update"]["n"] == r1.iters
+            assert prof["iter_doe"]["ms"] > 0 and prof["iter_deo_update"]["ms"] > 0
+            if scheme == P.LGT_CG_RELIABLE:
+                assert prof["ru_doe"]["n"] == prof["ru_deo_residual"]["n"] >= 1
+                assert prof["ru_doe"]["ms"] > 0 and prof["ru_deo_residual"]["ms"] > 0
+
+
 @pytest.mark.parametrize("L", [(8, 8, 8, 8), (16, 16, 16, 32)])
 def test_cg_alpha_step_fused_or_separate(dev, L, monkeypatch):
-    """alpha = rho / <p, Ap> summed by every update workgroup (small
-    lattices) or by one finalize workgroup first (large lattices; forced here
-    with LGT_FUSE_ALPHA_MAX=0): the same solve bit for bit, in every scheme,
-    and a non-finite source still ends in LGT_ERR_NONFINITE."""
+    """alpha = rho / <p, Ap> summed from D_oe's partials by every workgroup of
+    the D_eo that applies the update (small lattices) or by one finalize
+    workgroup first (large lattices; forced here with LGT_FUSE_ALPHA_MAX=0):
+    the same solve bit for bit, in every scheme, and a non-finite source still
+    ends in LGT_ERR_NONFINITE."""
     U = li.links(L, "haar", 421)
     b = li.vector(L, 422)
     with P.Lattice(L) as lat:

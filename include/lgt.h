@@ -551,7 +551,17 @@ typedef struct {
 /* Independent even-odd CGs (own alpha, beta and stop test per right-hand
  * side; not block CG) for every right-hand side of every problem, lattices of
  * different sizes included, in ONE cooperative persistent launch (one
- * workgroup per CU) on the stream of probs[0].ctx. Not from the paper, which
+ * workgroup per CU) on the stream of probs[0].ctx -- except for one problem
+ * with a mixed scheme, a four-lane inner engine (F32/BF16 links, nrhs > 2)
+ * and at least 2^21 (site, rhs) pairs (V/2 times nrhs rounded up to a power
+ * of two), which runs the same iteration as a sequence of kernel launches
+ * (five per iteration, one chunk of ru_interval iterations -- refinement:
+ * check_interval, 10 when 0 -- enqueued ahead of the host's read-back of the
+ * states, the FP64 steps between chunks; a right-hand side that meets its
+ * inner stop test inside a chunk waits for the chunk's end). The environment
+ * variable LGT_BATCH_LAUNCHED = 1 takes that form whenever the problem
+ * qualifies apart from its size, 0 never (other values: LGT_ERR_ARG). Not
+ * from the paper, which
  * solves one system at a time: each right-hand side runs the CG iteration of
  * lgt_cg_solve, with <p, A p> taken as 4m^2 |p|^2 + |D_oe p|^2 (the same number,
  * since D_eo = -D_oe^dag) so that alpha is known before D_eo, and batching
@@ -576,13 +586,17 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
 /* Phase profile of the last lgt_cg_solve_batch whose first problem's context
  * had timing on (lgt_set_timing > 0): ms[9] receives the milliseconds that
  * workgroup 0 of the persistent launch spent in (0) set-up and the final FP64
- * step, (1) the inner D_oe step with p = r + beta p and <p, A p>, (2) the
- * wait at the barrier after it, (3) the inner D_eo step with the update of x
- * and r and |r|^2, (4) its barrier wait, (5, 6) zero (kept for a separate
- * update step), (7) the scalar steps, (8) the FP64 reliable updates /
- * refinement steps; iters the
- * iterations run. A wait is the slowest workgroup's extra time plus the
- * barrier itself. Zeros before any such solve. Host only. */
+ * step, (1) the inner D_oe step with <p, A p> (and p = r + beta p unless
+ * that runs as a pass of its own), (2) the wait at the barrier after it, (3)
+ * the inner D_eo step with the update of x and r and |r|^2, (4) its barrier
+ * wait, (5) the pass p = r + beta p where it runs on its own (batches of at
+ * least 2^21 (site, rhs) pairs), (6) the wait after it, (7) the scalar steps,
+ * (8) the FP64 reliable updates / refinement steps; iters the iterations run
+ * (the most of any right-hand side, for the launched form). A wait is the
+ * slowest workgroup's extra time plus the barrier itself. For the launched
+ * form (lgt_cg_solve_batch) the entries are the summed kernel times of each
+ * kind, measured with events around every launch, and the waits are zero.
+ * Zeros before any such solve. Host only. */
 lgt_status lgt_batch_profile(lgt_ctx *ctx, double ms[9], int32_t *iters);
 
 /* ---- reductions ------------------------------------------------------------ */

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "liblgt.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["dslash.hip", "blas.hip", "force.hip", "probe.hip", "mrhs.hip", "batch_cg.hip", "routines.hip", "hmc.hip", "fatten.hip", "noalloc.hip", "solver.cpp", "tune.cpp", "batch.cpp", "hmc_abi.cpp", "abi.cpp"]
+SOURCES = ["dslash.hip", "blas.hip", "force.hip", "probe.hip", "mrhs.hip", "batch_cg.hip", "routines.hip", "hmc.hip", "fatten.hip", "noalloc.hip", "mcg.hip", "solver.cpp", "tune.cpp", "batch.cpp", "mcg_host.cpp", "hmc_abi.cpp", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 

@@ -222,6 +222,28 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     DeviceScope ds(c0->device);
     const hipStream_t s = c0->stream;
 
+    // One large mixed-precision problem: the iteration as kernel launches
+    // (mcg_host.cpp), whose Dslash steps keep more waves in flight than the
+    // persistent launch can. LGT_BATCH_LAUNCHED = 1 takes that form whenever it
+    // applies, 0 never; unset, from kBatchLaunchedPairs (site, rhs) pairs on.
+    if (nprob == 1 && mixed) {
+        int mode = -1;
+        if (const char *e = std::getenv("LGT_BATCH_LAUNCHED")) {
+            if (!std::strcmp(e, "0")) mode = 0;
+            else if (!std::strcmp(e, "1")) mode = 1;
+            else if (*e) return fail(LGT_ERR_ARG, "LGT_BATCH_LAUNCHED must be 0 or 1");
+        }
+        const lgt_cg_problem &q = probs[0];
+        lgt_ctx *c = q.ctx;
+        const int logN = log2_rhs_padded(q.nrhs);
+        int eng = c->mrhs_eng[flo][logN];
+        if (eng == MRHS_MFMA && !mrhs_engine_applies(flo, logN, c->g.Vh, eng)) eng = MRHS_VALU4; // V/2 % 16 != 0
+        const int gps = mrhs_groups_valid(logN, c->mrhs_gps[flo][logN]) ? c->mrhs_gps[flo][logN] : 1;
+        const bool big = ((size_t)c->g.Vh << logN) >= kBatchLaunchedPairs;
+        if (mrhs_engine_applies(flo, logN, c->g.Vh, eng) && (mode == 1 || (mode < 0 && big)))
+            return mcg_solve(q, p, flo, logN, eng, gps);
+    }
+
     // grid: one workgroup per CU, all resident at once (cooperative launch)
     int coop = 0, ncu = 0;
     LGT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c0->device));

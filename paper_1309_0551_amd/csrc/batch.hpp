@@ -20,6 +20,9 @@ constexpr int kMaxTotalRhs = 256;  // right-hand sides per batched launch
 constexpr int kBB = 1024;          // threads per workgroup of the batched solver
 // (site, rhs) pairs of a batch from which its step 1 runs as two passes
 constexpr size_t kBatchSplitPairs = (size_t)1 << 21;
+// (site, rhs) pairs of a one-problem mixed-precision batch from which its
+// iteration runs as kernel launches (mcg.hip) instead of the persistent launch
+constexpr size_t kBatchLaunchedPairs = (size_t)1 << 21;
 // LDS per workgroup of the batched solver for the staged input tiles of its
 // four-lane Dslash steps: 3 colours x (sites of a tile + Lx) x N right-hand
 // sides of FP32 complex (8 B) must fit
@@ -132,5 +135,42 @@ hipError_t launch_unpack_mrhs(bool f64, const void *src, double *dst, const Geom
 // threads). lo = inner link format; a_dev = BatchArgs in device memory.
 hipError_t launch_batch_cg(Fmt lo, const BatchArgs *a_dev, int grid, hipStream_t s);
 int batch_cg_max_blocks_per_cu(Fmt lo);
+
+// ---- the batched CG of one lattice as kernel launches (mcg.hip) -------------
+// Mixed precision, a four-lane inner engine, N = 2^logN >= 4 right-hand sides.
+struct McgArgs {
+    Geom g;
+    int logN;
+    int engine, gps;   // inner multi-RHS engine (MRHS_VALU4 or MRHS_MFMA), groups of four lanes
+    double m4;         // 4 m^2
+    const void *Ulo, *Uhi; // inner links (F32/BF16), F64 x 18 links
+    const double *b64; // FP64 multi-RHS vectors
+    double *x64, *t64;
+    void *xlo, *r, *p, *t; // FP32 multi-RHS vectors
+    CgState *st;       // [N]
+    double *parts;     // partial sums [N][stride]
+    size_t stride;     // >= the workgroups of every reducing launch
+};
+// workgroups that do work in the inner Dslash launches (the rows' length of
+// their partials) and in the one-lane-per-(site, rhs) launches
+int mcg_iter_blocks(const Geom &g, int gps);
+int mcg_lane_blocks(const Geom &g, int logN);
+hipError_t launch_mcg_init(const McgArgs &a, int scheme, int ru_fixed, int max_iter, double tol, double inner,
+                           hipStream_t s);
+// partials of |b|^2 (mcg_lane_blocks of them per right-hand side)
+hipError_t launch_mcg_norm(const McgArgs &a, hipStream_t s);
+// per right-hand side: the sum of the first n partials of its row, then the
+// scalar step fin where its gate is open (one workgroup per right-hand side)
+hipError_t launch_mcg_fin(const McgArgs &a, int n, int fin, int gate, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+hipError_t launch_mcg_xpay(const McgArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// which = 0: t = D_oe p with the <p, A p> partials; 1: D_eo t with the update
+// of x and r and the |r|^2 partials
+hipError_t launch_mcg_dslash(Fmt lo, const McgArgs &a, int which, hipStream_t s, hipEvent_t e0 = nullptr,
+                             hipEvent_t e1 = nullptr);
+// FP64 step for the right-hand sides whose gate is open: x64 += x_lo, x_lo = 0,
+// r = b - A x64 rounded into r, partials of |b - A x64|^2
+hipError_t launch_mcg_fp64(const McgArgs &a, int gate, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 
 } // namespace lgt

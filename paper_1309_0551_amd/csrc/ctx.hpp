@@ -110,6 +110,11 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                     const double *b, double *x, lgt_cg_result *res, const lgt_links *U3hi = nullptr,
                     const lgt_links *U3lo = nullptr);
 
+// The batched CG of one lattice with N = 2^logN >= 4 right-hand sides as
+// kernel launches (mcg_host.cpp): mixed schemes, a four-lane inner engine with gps
+// groups; q.U_hi F64 x 18, q.U_lo in format flo.
+lgt_status mcg_solve(const lgt_cg_problem &q, const lgt_cg_params *p, Fmt flo, int logN, int engine, int gps);
+
 // launch geometry of the one-link / improved Dslash for link format f
 inline Launch dslash_launch(const lgt_ctx *c, Fmt f) { return site_launch(c->g.Vh, c->dbs[f]); }
 inline Launch dslash_launch_improved(const lgt_ctx *c, Fmt f) { return site_launch(c->g.Vh, c->ibs[f]); }

@@ -1,0 +1,421 @@
+// mcg.hip -- the batched CG of one lattice with N right-hand sides as a
+// sequence of kernel launches: the form for large batches.
+//
+// The persistent batched solver (batch_cg.hip) holds one 1024-lane
+// workgroup per CU for the whole solve; its register budget (set by the FP64
+// and control paths in the same kernel) leaves 16 waves per CU, and its
+// multi-RHS Dslash steps run about a third slower than the standalone
+// kernels, which keep twice as many waves in flight. On a large batch that
+// outweighs the launches it saves, so there each iteration runs as launches,
+// with the same algorithm: independent CGs, one state per right-hand side
+// (reduce.hpp), per right-hand-side FP64 sums in a fixed order.
+//   xpay   p = r + beta p                     (right-hand sides that iterate)
+//   doe    t = D_oe p, partials of 4m^2 |p|^2 + |t|^2 = <p, A p>
+//   fin    alpha
+//   deo    D_eo t; x += alpha p, r -= alpha (4m^2 p - D_eo t), partials of |r|^2
+//   fin    beta, stop tests
+// (D_eo = -D_oe^dag makes <p, A p> = 4m^2 |p|^2 + |D_oe p|^2.) The FP64 steps
+// (reliable updates, refinement residuals, the final residual) run between
+// chunks of iterations for the right-hand sides whose state asks for one,
+// with x64 += x_lo folded into the residual pass.
+//
+// Partial sums: a reducing kernel leaves, per workgroup, one FP64 sum per
+// right-hand side in row rhs of a [N][stride] array (plain stores of N
+// lanes); the finalize kernel runs one workgroup per right-hand side, which
+// reads its row contiguously and sums it in a fixed order.
+#include "batch.hpp"
+#include "fields.hpp"
+#include "mrhs_dev.hpp"
+#include "reduce.hpp"
+
+namespace lgt {
+
+namespace {
+
+constexpr int kMB = kBS;     // lanes per workgroup of the vector, Dslash and FP64 kernels
+constexpr int kFinBS = 1024; // lanes of a finalize workgroup
+
+// Whether any right-hand side's gate is open (uniform over the workgroup:
+// every lane reads the same N states, written by an earlier launch)
+__device__ __forceinline__ bool any_open(const CgState *st, int N, int gate)
+{
+    bool a = false;
+    for (int q = 0; q < N; q++) a |= gate_open(gate, &st[q]);
+    return a;
+}
+
+// Per right-hand-side sums of a workgroup whose lane li holds v[r] for
+// right-hand side (li % LPS) R + r: a butterfly over the lanes of a wavefront
+// that share (li % LPS), then the wavefronts in index order. Writes
+// out[rhs * stride] for the N = LPS R right-hand sides. Every lane of the
+// workgroup calls it.
+template <int R, int LPS>
+__device__ __forceinline__ void wg_rhs_sums(double v[R], double *out, size_t stride)
+{
+    for (int o = LPS; o < 64; o <<= 1) {
+#pragma unroll
+        for (int r = 0; r < R; r++) v[r] += __shfl_xor(v[r], o, 64);
+    }
+    __shared__ double red[kMB / 64][kMaxRhs];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane < LPS) {
+#pragma unroll
+        for (int r = 0; r < R; r++) red[w][lane * R + r] = v[r];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < LPS * R) {
+        double s = 0.0;
+        for (int k = 0; k < kMB / 64; k++) s += red[k][threadIdx.x];
+        out[threadIdx.x * stride] = s;
+    }
+}
+
+// the same for one lane per (site, rhs), rhs = li % N
+__device__ __forceinline__ void wg_rhs_sums_lane(double v, int N, double *out, size_t stride)
+{
+    for (int o = N; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    __shared__ double red[kMB / 64][kMaxRhs];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane < N) red[w][lane] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < N) {
+        double s = 0.0;
+        for (int k = 0; k < kMB / 64; k++) s += red[k][threadIdx.x];
+        out[threadIdx.x * stride] = s;
+    }
+}
+
+__global__ void k_mcg_init(CgState *st, int N, int scheme, int ru_fixed, int max_iter, double tol, double inner)
+{
+    const int q = threadIdx.x;
+    if (q >= N) return;
+    CgState &s = st[q];
+    s.rho = s.rho_prev = s.alpha = s.beta = s.pAp = 0.0;
+    s.bnorm2 = 0.0;
+    s.stop_outer = tol * tol; // multiplied by |b|^2 in FIN_INIT
+    s.stop_inner = 0.0;
+    s.inner2 = scheme == SCH_REFINE ? inner * inner : (inner * tol) * (inner * tol);
+    s.last_true = 0.0;
+    s.iter = 0;
+    s.updates = 0;
+    s.state = ST_INIT;
+    s.max_iter = max_iter;
+    s.scheme = scheme;
+    s.ru_fixed = ru_fixed;
+    s.pend = s.pad1 = 0;
+}
+
+// partials of |b|^2
+__global__ __launch_bounds__(kMB) void k_mcg_norm(const double *__restrict__ b64, int Vh, int logN,
+                                                  double *__restrict__ parts, size_t stride)
+{
+    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
+    const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
+    double v = 0.0;
+    if (site < (unsigned)Vh) {
+        cx<double> bb[3];
+        ldm<double>(b64, (size_t)Vh, logN, site, rhs, bb);
+#pragma unroll
+        for (int c = 0; c < 3; c++) v += bb[c].re * bb[c].re + bb[c].im * bb[c].im;
+    }
+    wg_rhs_sums_lane(v, 1 << logN, parts + blockIdx.x, stride);
+}
+
+// Workgroup q: the sum of row q's first n partials (lane t adds entries
+// t, t + kFinBS, ..., then the lanes in block_sum's order), then the scalar
+// step fin where right-hand side q's gate is open.
+__global__ __launch_bounds__(kFinBS) void k_mcg_fin(const double *__restrict__ parts, size_t stride, int n,
+                                                    CgState *st, int fin, int gate)
+{
+    const int q = blockIdx.x;
+    if (!gate_open(gate, &st[q])) return; // uniform
+    const double *row = parts + (size_t)q * stride;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < n; b += kFinBS) s += row[b];
+    __shared__ double lds[kFinBS / 64];
+    const double tot = block_sum(s, lds);
+    if (threadIdx.x == 0) finalize(fin, &st[q], tot);
+}
+
+// p = r + beta p for the right-hand sides that iterate; the others keep p
+__global__ __launch_bounds__(kMB) void k_mcg_xpay(const void *__restrict__ r, void *__restrict__ p, int Vh, int logN,
+                                                  const CgState *st)
+{
+    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
+    const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
+    if (site >= (unsigned)Vh || st[rhs].state != ST_RUN) return;
+    const float beta = (float)st[rhs].beta;
+    cx<float> rr[3], pp[3];
+    ldm<float>(r, (size_t)Vh, logN, site, rhs, rr);
+    ldm<float>(p, (size_t)Vh, logN, site, rhs, pp);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        pp[c].re = fmaf(beta, pp[c].re, rr[c].re);
+        pp[c].im = fmaf(beta, pp[c].im, rr[c].im);
+    }
+    stm<float>(p, (size_t)Vh, logN, site, rhs, pp);
+}
+
+// t = D_oe p (four lanes per site), partials of 4m^2 |p|^2 + |t|^2 with p
+// taken at the same checkerboard index (the sum over all indices is |p|^2)
+template <class LF, int R, int GPS, bool MFMA>
+__global__ __launch_bounds__(kMB) void k_mcg_doe(const void *__restrict__ U, const void *__restrict__ p,
+                                                 void *__restrict__ t, Geom g, int logN, int nblk_pad, TileOrder o,
+                                                 double m4, const CgState *st, double *__restrict__ parts,
+                                                 size_t stride)
+{
+    constexpr unsigned LPS = 4 * GPS;
+    if (!any_open(st, LPS * R, GATE_ITER)) return;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return; // the whole workgroup
+    const unsigned idx = (unsigned)blk * kMB + threadIdx.x;
+    const unsigned site = idx / LPS, lane4 = idx & 3u;
+    const size_t Vh = (size_t)g.Vh;
+    const unsigned r0 = (threadIdx.x % LPS) * R;
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) v[r] = 0.0;
+    // whole quads are in or out of range; the MFMA engine needs whole
+    // wavefronts, which V/2 % 16 == 0 gives it
+    if (site < (unsigned)g.Vh) {
+        auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(p, Vh, logN, n, r0, u); };
+        cx<float> acc[R][3], pp[R][3];
+        dslash_site4<LF, R, MFMA>(g, kOdd, U, site, lane4, IN, acc);
+        stm_r<float, R>(t, Vh, logN, site, r0, acc);
+        ldm_r<float, R>(p, Vh, logN, site, r0, pp);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            double qq = 0.0, tt = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                qq += (double)pp[r][c].re * (double)pp[r][c].re + (double)pp[r][c].im * (double)pp[r][c].im;
+                tt += (double)acc[r][c].re * (double)acc[r][c].re + (double)acc[r][c].im * (double)acc[r][c].im;
+            }
+            v[r] = m4 * qq + tt;
+        }
+    }
+    wg_rhs_sums<R, LPS>(v, parts + blk, stride);
+}
+
+// D_eo t with the update: x += alpha p, r -= alpha (4m^2 p - D_eo t) for the
+// right-hand sides that iterate (the others' x and r are stored back as they
+// were), partials of |r|^2
+template <class LF, int R, int GPS, bool MFMA>
+__global__ __launch_bounds__(kMB) void k_mcg_deo(const void *__restrict__ U, const void *__restrict__ t,
+                                                 const void *__restrict__ p, void *__restrict__ x, void *__restrict__ r,
+                                                 Geom g, int logN, int nblk_pad, TileOrder o, double m4,
+                                                 const CgState *st, double *__restrict__ parts, size_t stride)
+{
+    constexpr unsigned LPS = 4 * GPS;
+    if (!any_open(st, LPS * R, GATE_ITER)) return;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return;
+    const unsigned idx = (unsigned)blk * kMB + threadIdx.x;
+    const unsigned site = idx / LPS, lane4 = idx & 3u;
+    const size_t Vh = (size_t)g.Vh;
+    const unsigned r0 = (threadIdx.x % LPS) * R;
+    double v[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) v[k] = 0.0;
+    if (site < (unsigned)g.Vh) {
+        auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(t, Vh, logN, n, r0, u); };
+        cx<float> acc[R][3], pp[R][3], xx[R][3], rr[R][3];
+        dslash_site4<LF, R, MFMA>(g, kEven, U, site, lane4, IN, acc);
+        ldm_r<float, R>(p, Vh, logN, site, r0, pp);
+        ldm_r<float, R>(x, Vh, logN, site, r0, xx);
+        ldm_r<float, R>(r, Vh, logN, site, r0, rr);
+        const float m4f = (float)m4;
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            if (st[r0 + k].state != ST_RUN) continue; // x and r stay as they are
+            const float alpha = (float)st[r0 + k].alpha;
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const float apr = m4f * pp[k][c].re - acc[k][c].re;
+                const float api = m4f * pp[k][c].im - acc[k][c].im;
+                xx[k][c].re = fmaf(alpha, pp[k][c].re, xx[k][c].re);
+                xx[k][c].im = fmaf(alpha, pp[k][c].im, xx[k][c].im);
+                rr[k][c].re = fmaf(-alpha, apr, rr[k][c].re);
+                rr[k][c].im = fmaf(-alpha, api, rr[k][c].im);
+                d += (double)rr[k][c].re * (double)rr[k][c].re + (double)rr[k][c].im * (double)rr[k][c].im;
+            }
+            v[k] = d;
+        }
+        stm_r<float, R>(x, Vh, logN, site, r0, xx);
+        stm_r<float, R>(r, Vh, logN, site, r0, rr);
+    }
+    wg_rhs_sums<R, LPS>(v, parts + blk, stride);
+}
+
+// FP64 step, first half: t64 = D_oe (x64 + x_lo) for the right-hand sides
+// whose gate is open (one lane per (site, rhs), FP64 links)
+__global__ __launch_bounds__(kMB) void k_mcg_fp64_doe(const void *__restrict__ Uhi, const double *__restrict__ x64,
+                                                      const void *__restrict__ xlo, double *__restrict__ t64, Geom g,
+                                                      int logN, const CgState *st, int gate)
+{
+    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
+    const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
+    if (site >= (unsigned)g.Vh || !gate_open(gate, &st[rhs])) return;
+    const size_t Vh = (size_t)g.Vh;
+    auto IN = [=](int n, cx<double> u[3]) __attribute__((always_inline)) {
+        cx<float> e[3];
+        ldm<double>(x64, Vh, logN, n, rhs, u);
+        ldm<float>(xlo, Vh, logN, n, rhs, e);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            u[c].re += (double)e[c].re;
+            u[c].im += (double)e[c].im;
+        }
+    };
+    cx<double> acc[3];
+    dslash_mrhs<LinkF64R18>(g, kOdd, Uhi, site, IN, acc);
+    stm<double>(t64, Vh, logN, site, rhs, acc);
+}
+
+// FP64 step, second half: x64 += x_lo, x_lo = 0, r = b - (4m^2 x64 - D_eo t64)
+// in FP64, rounded into r_lo; partials of |r|^2
+__global__ __launch_bounds__(kMB) void k_mcg_fp64_res(const void *__restrict__ Uhi, const double *__restrict__ t64,
+                                                      double *__restrict__ x64, void *__restrict__ xlo,
+                                                      const double *__restrict__ b64, void *__restrict__ rlo, Geom g,
+                                                      int logN, double m4, const CgState *st, int gate,
+                                                      double *__restrict__ parts, size_t stride)
+{
+    const int N = 1 << logN;
+    if (!any_open(st, N, gate)) return; // uniform; no partial of a closed gate is read
+    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
+    const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
+    double v = 0.0;
+    if (site < (unsigned)g.Vh && gate_open(gate, &st[rhs])) {
+        const size_t Vh = (size_t)g.Vh;
+        auto IN = [=](int n, cx<double> u[3]) __attribute__((always_inline)) { ldm<double>(t64, Vh, logN, n, rhs, u); };
+        cx<double> acc[3], x[3], bb[3];
+        cx<float> e[3], lo[3];
+        dslash_mrhs<LinkF64R18>(g, kEven, Uhi, site, IN, acc);
+        ldm<double>(x64, Vh, logN, site, rhs, x);
+        ldm<double>(b64, Vh, logN, site, rhs, bb);
+        ldm<float>(xlo, Vh, logN, site, rhs, e);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            x[c].re += (double)e[c].re;
+            x[c].im += (double)e[c].im;
+            e[c].re = e[c].im = 0.f;
+            acc[c].re = bb[c].re - (m4 * x[c].re - acc[c].re);
+            acc[c].im = bb[c].im - (m4 * x[c].im - acc[c].im);
+            v += acc[c].re * acc[c].re + acc[c].im * acc[c].im;
+            lo[c].re = (float)acc[c].re;
+            lo[c].im = (float)acc[c].im;
+        }
+        stm<double>(x64, Vh, logN, site, rhs, x);
+        stm<float>(xlo, Vh, logN, site, rhs, e);
+        stm<float>(rlo, Vh, logN, site, rhs, lo);
+    }
+    wg_rhs_sums_lane(v, N, parts + blockIdx.x, stride);
+}
+
+template <class LF, int R, int GPS>
+hipError_t launch_iter_rg(const McgArgs &a, bool mf, int which, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    const int TS = kMB / (4 * GPS), nblk = (a.g.Vh + TS - 1) / TS, pad = (nblk + 7) / 8 * 8;
+    const TileOrder o = tile_order(a.g, TS);
+    const dim3 grid(mrhs_grid(o, nblk)), block(kMB);
+    if (e0) (void)hipEventRecord(e0, s);
+    if (which == 0) {
+        if (mf)
+            hipLaunchKernelGGL((k_mcg_doe<LF, R, GPS, true>), grid, block, 0, s, a.Ulo, a.p, a.t, a.g, a.logN, pad, o,
+                               a.m4, a.st, a.parts, a.stride);
+        else
+            hipLaunchKernelGGL((k_mcg_doe<LF, R, GPS, false>), grid, block, 0, s, a.Ulo, a.p, a.t, a.g, a.logN, pad,
+                               o, a.m4, a.st, a.parts, a.stride);
+    } else {
+        if (mf)
+            hipLaunchKernelGGL((k_mcg_deo<LF, R, GPS, true>), grid, block, 0, s, a.Ulo, a.t, a.p, a.xlo, a.r, a.g,
+                               a.logN, pad, o, a.m4, a.st, a.parts, a.stride);
+        else
+            hipLaunchKernelGGL((k_mcg_deo<LF, R, GPS, false>), grid, block, 0, s, a.Ulo, a.t, a.p, a.xlo, a.r, a.g,
+                               a.logN, pad, o, a.m4, a.st, a.parts, a.stride);
+    }
+    if (e1) (void)hipEventRecord(e1, s);
+    return hipGetLastError();
+}
+
+template <class LF>
+hipError_t launch_iter_fmt(const McgArgs &a, int which, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    const bool mf = a.engine == MRHS_MFMA;
+    switch (a.logN * 8 + a.gps) {
+    case 2 * 8 + 1: return launch_iter_rg<LF, 1, 1>(a, mf, which, s, e0, e1);
+    case 3 * 8 + 1: return launch_iter_rg<LF, 2, 1>(a, mf, which, s, e0, e1);
+    case 3 * 8 + 2: return launch_iter_rg<LF, 1, 2>(a, mf, which, s, e0, e1);
+    case 4 * 8 + 1: return launch_iter_rg<LF, 4, 1>(a, mf, which, s, e0, e1);
+    case 4 * 8 + 2: return launch_iter_rg<LF, 2, 2>(a, mf, which, s, e0, e1);
+    case 4 * 8 + 4: return launch_iter_rg<LF, 1, 4>(a, mf, which, s, e0, e1);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace
+
+int mcg_iter_blocks(const Geom &g, int gps)
+{
+    const int TS = kMB / (4 * gps);
+    return (g.Vh + TS - 1) / TS;
+}
+int mcg_lane_blocks(const Geom &g, int logN) { return (int)((((int64_t)g.Vh << logN) + kMB - 1) / kMB); }
+
+hipError_t launch_mcg_init(const McgArgs &a, int scheme, int ru_fixed, int max_iter, double tol, double inner,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mcg_init, dim3(1), dim3(64), 0, s, a.st, 1 << a.logN, scheme, ru_fixed, max_iter, tol,
+                       inner);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcg_norm(const McgArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mcg_norm, dim3(mcg_lane_blocks(a.g, a.logN)), dim3(kMB), 0, s, a.b64, a.g.Vh, a.logN,
+                       a.parts, a.stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcg_fin(const McgArgs &a, int n, int fin, int gate, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0) (void)hipEventRecord(e0, s);
+    hipLaunchKernelGGL(k_mcg_fin, dim3(1 << a.logN), dim3(kFinBS), 0, s, a.parts, a.stride, n, a.st, fin, gate);
+    if (e1) (void)hipEventRecord(e1, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcg_xpay(const McgArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0) (void)hipEventRecord(e0, s);
+    hipLaunchKernelGGL(k_mcg_xpay, dim3(mcg_lane_blocks(a.g, a.logN)), dim3(kMB), 0, s, a.r, a.p, a.g.Vh, a.logN,
+                       a.st);
+    if (e1) (void)hipEventRecord(e1, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcg_dslash(Fmt lo, const McgArgs &a, int which, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    switch (lo) {
+    case F32R18: return launch_iter_fmt<LinkF32R18>(a, which, s, e0, e1);
+    case F32R12: return launch_iter_fmt<LinkF32R12>(a, which, s, e0, e1);
+    case BF16R12: return launch_iter_fmt<LinkBF16R12>(a, which, s, e0, e1);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_mcg_fp64(const McgArgs &a, int gate, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    const dim3 grid(mcg_lane_blocks(a.g, a.logN)), block(kMB);
+    if (e0) (void)hipEventRecord(e0, s);
+    hipLaunchKernelGGL(k_mcg_fp64_doe, grid, block, 0, s, a.Uhi, a.x64, a.xlo, a.t64, a.g, a.logN, a.st, gate);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mcg_fp64_res, grid, block, 0, s, a.Uhi, a.t64, a.x64, a.xlo, a.b64, a.r, a.g, a.logN, a.m4,
+                       a.st, gate, a.parts, a.stride);
+    if (e1) (void)hipEventRecord(e1, s);
+    return hipGetLastError();
+}
+
+} // namespace lgt

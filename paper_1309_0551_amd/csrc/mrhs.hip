@@ -13,19 +13,6 @@ namespace lgt {
 
 // ------------------------------------------------------- standalone ---
 
-// logical block (a tile of consecutive sites) of this workgroup, or -1
-__device__ __forceinline__ int mrhs_block(const TileOrder &o, int nblk_pad)
-{
-    if (o.n_ts) return zorder_tile(o, blockIdx.x & 7, blockIdx.x >> 3);
-    return xcd_block(blockIdx.x, nblk_pad);
-}
-
-// blocks to launch for nblk tiles under order o
-static int mrhs_grid(const TileOrder &o, int nblk)
-{
-    return o.n_ts ? 8 * o.per : (nblk + 7) / 8 * 8;
-}
-
 template <class LF>
 __global__ __launch_bounds__(kBS) void k_dslash_mrhs(const void *__restrict__ U, const void *__restrict__ in,
                                                      void *__restrict__ out, Geom g, int par, int logN, int nblk_pad,

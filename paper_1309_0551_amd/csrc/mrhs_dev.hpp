@@ -36,6 +36,16 @@ namespace lgt {
 
 constexpr int kEven = 0, kOdd = 1; // output parity of a half-Dslash
 
+// logical block (a tile of consecutive sites) of this workgroup, or -1
+__device__ __forceinline__ int mrhs_block(const TileOrder &o, int nblk_pad)
+{
+    if (o.n_ts) return zorder_tile(o, blockIdx.x & 7, blockIdx.x >> 3);
+    return xcd_block(blockIdx.x, nblk_pad);
+}
+
+// blocks to launch for nblk tiles under order o
+inline int mrhs_grid(const TileOrder &o, int nblk) { return o.n_ts ? 8 * o.per : (nblk + 7) / 8 * 8; }
+
 template <typename T> struct V2of;
 template <> struct V2of<double> { using type = dv2; };
 template <> struct V2of<float> { using type = fv2; };

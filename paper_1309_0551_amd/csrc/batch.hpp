@@ -150,21 +150,27 @@ struct McgArgs {
     CgState *st;       // [N]
     double *parts;     // partial sums [N][stride]
     size_t stride;     // >= the workgroups of every reducing launch
+    double *parts_p;   // partials of 4m^2 |p|^2 from the p = r + beta p pass [N][stride_p]
+    size_t stride_p;   // >= its workgroups (mcg_xpay_blocks)
 };
-// workgroups that do work in the inner Dslash launches (the rows' length of
-// their partials) and in the one-lane-per-(site, rhs) launches
-int mcg_iter_blocks(const Geom &g, int gps);
+// partials per right-hand side that the inner Dslash launches write (padded:
+// including their idle workgroups), and workgroups of the one-lane-per-(site,
+// rhs) launches and of the p = r + beta p pass
+int mcg_iter_parts(const Geom &g, int gps, bool padded);
 int mcg_lane_blocks(const Geom &g, int logN);
+int mcg_xpay_blocks(const Geom &g, int logN);
 hipError_t launch_mcg_init(const McgArgs &a, int scheme, int ru_fixed, int max_iter, double tol, double inner,
                            hipStream_t s);
 // partials of |b|^2 (mcg_lane_blocks of them per right-hand side)
 hipError_t launch_mcg_norm(const McgArgs &a, hipStream_t s);
-// per right-hand side: the sum of the first n partials of its row, then the
-// scalar step fin where its gate is open (one workgroup per right-hand side)
+// per right-hand side: the sum of the first n partials of its row (and of
+// the first n_p of its row of parts_p), then the scalar step fin where its
+// gate is open (one workgroup per right-hand side)
 hipError_t launch_mcg_fin(const McgArgs &a, int n, int fin, int gate, hipStream_t s, hipEvent_t e0 = nullptr,
-                          hipEvent_t e1 = nullptr);
+                          hipEvent_t e1 = nullptr, int n_p = 0);
+// p = r + beta p with the partials of 4m^2 |p|^2 into parts_p
 hipError_t launch_mcg_xpay(const McgArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// which = 0: t = D_oe p with the <p, A p> partials; 1: D_eo t with the update
+// which = 0: t = D_oe p with the |t|^2 partials; 1: D_eo t with the update
 // of x and r and the |r|^2 partials
 hipError_t launch_mcg_dslash(Fmt lo, const McgArgs &a, int which, hipStream_t s, hipEvent_t e0 = nullptr,
                              hipEvent_t e1 = nullptr);

@@ -9,9 +9,9 @@
 // outweighs the launches it saves, so there each iteration runs as launches,
 // with the same algorithm: independent CGs, one state per right-hand side
 // (reduce.hpp), per right-hand-side FP64 sums in a fixed order.
-//   xpay   p = r + beta p                     (right-hand sides that iterate)
-//   doe    t = D_oe p, partials of 4m^2 |p|^2 + |t|^2 = <p, A p>
-//   fin    alpha
+//   xpay   p = r + beta p (right-hand sides that iterate), partials of 4m^2 |p|^2
+//   doe    t = D_oe p, partials of |t|^2
+//   fin    alpha = rho / <p, A p> from both rows of partials
 //   deo    D_eo t; x += alpha p, r -= alpha (4m^2 p - D_eo t), partials of |r|^2
 //   fin    beta, stop tests
 // (D_eo = -D_oe^dag makes <p, A p> = 4m^2 |p|^2 + |D_oe p|^2.) The FP64 steps
@@ -32,8 +32,13 @@ namespace lgt {
 
 namespace {
 
-constexpr int kMB = kBS;     // lanes per workgroup of the vector, Dslash and FP64 kernels
-constexpr int kFinBS = 1024; // lanes of a finalize workgroup
+// Sizes measured at 24^3 x 48 x 16 (the iteration in us): 512-lane
+// workgroups +3, finalize workgroups of 256 / 512 lanes +6 / +1.5, 2 or 8
+// pairs per lane in the p pass +3, workgroups that walk several tiles (fewer
+// partials) +4 to +37, one partial per wavefront instead of per workgroup +18.
+constexpr int kMB = kBS;      // lanes per workgroup of the vector, Dslash and FP64 kernels
+constexpr int kFinBS = 1024;  // lanes of a finalize workgroup
+constexpr int kXpayPairs = 4; // (site, rhs) pairs per lane of the p = r + beta p pass
 
 // Whether any right-hand side's gate is open (uniform over the workgroup:
 // every lane reads the same N states, written by an earlier launch)
@@ -121,48 +126,76 @@ __global__ __launch_bounds__(kMB) void k_mcg_norm(const double *__restrict__ b64
     wg_rhs_sums_lane(v, 1 << logN, parts + blockIdx.x, stride);
 }
 
-// Workgroup q: the sum of row q's first n partials (lane t adds entries
-// t, t + kFinBS, ..., then the lanes in block_sum's order), then the scalar
+// sum of row[0..n) by lane t: entries t, t + kFinBS, ... into four
+// accumulators in a fixed order, four loads in flight
+__device__ __forceinline__ double lane_row_sum(const double *__restrict__ row, int n)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kFinBS < n; b += 4 * kFinBS) {
+        s0 += row[b];
+        s1 += row[b + kFinBS];
+        s2 += row[b + 2 * kFinBS];
+        s3 += row[b + 3 * kFinBS];
+    }
+    for (; b < n; b += kFinBS) s0 += row[b];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Workgroup q: the sum of row q's first n partials (and of the first n2 of
+// row q of parts2 when n2 > 0; lanes in block_sum's order), then the scalar
 // step fin where right-hand side q's gate is open.
 __global__ __launch_bounds__(kFinBS) void k_mcg_fin(const double *__restrict__ parts, size_t stride, int n,
+                                                    const double *__restrict__ parts2, size_t stride2, int n2,
                                                     CgState *st, int fin, int gate)
 {
     const int q = blockIdx.x;
     if (!gate_open(gate, &st[q])) return; // uniform
-    const double *row = parts + (size_t)q * stride;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < n; b += kFinBS) s += row[b];
+    double s = lane_row_sum(parts + (size_t)q * stride, n);
+    if (n2 > 0) s += lane_row_sum(parts2 + (size_t)q * stride2, n2);
     __shared__ double lds[kFinBS / 64];
     const double tot = block_sum(s, lds);
     if (threadIdx.x == 0) finalize(fin, &st[q], tot);
 }
 
-// p = r + beta p for the right-hand sides that iterate; the others keep p
+// p = r + beta p for the right-hand sides that iterate (the others keep p),
+// four (site, rhs) pairs per lane kMB apart, and the partials of 4m^2 |p|^2,
+// the first term of <p, A p> = 4m^2 |p|^2 + |D_oe p|^2
 __global__ __launch_bounds__(kMB) void k_mcg_xpay(const void *__restrict__ r, void *__restrict__ p, int Vh, int logN,
-                                                  const CgState *st)
+                                                  double m4, const CgState *st, double *__restrict__ parts,
+                                                  size_t stride)
 {
-    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
-    const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
-    if (site >= (unsigned)Vh || st[rhs].state != ST_RUN) return;
+    const int N = 1 << logN;
+    if (!any_open(st, N, GATE_ITER)) return;
+    const unsigned rhs = threadIdx.x & (unsigned)(N - 1); // kMB is a multiple of N
+    const bool run = st[rhs].state == ST_RUN;
     const float beta = (float)st[rhs].beta;
-    cx<float> rr[3], pp[3];
-    ldm<float>(r, (size_t)Vh, logN, site, rhs, rr);
-    ldm<float>(p, (size_t)Vh, logN, site, rhs, pp);
+    double v = 0.0;
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        pp[c].re = fmaf(beta, pp[c].re, rr[c].re);
-        pp[c].im = fmaf(beta, pp[c].im, rr[c].im);
+    for (int k = 0; k < kXpayPairs; k++) {
+        const unsigned idx = (blockIdx.x * kXpayPairs + k) * kMB + threadIdx.x;
+        const unsigned site = idx >> logN;
+        if (site >= (unsigned)Vh || !run) continue;
+        cx<float> rr[3], pp[3];
+        ldm<float>(r, (size_t)Vh, logN, site, rhs, rr);
+        ldm<float>(p, (size_t)Vh, logN, site, rhs, pp);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            pp[c].re = fmaf(beta, pp[c].re, rr[c].re);
+            pp[c].im = fmaf(beta, pp[c].im, rr[c].im);
+            v += (double)pp[c].re * (double)pp[c].re + (double)pp[c].im * (double)pp[c].im;
+        }
+        stm<float>(p, (size_t)Vh, logN, site, rhs, pp);
     }
-    stm<float>(p, (size_t)Vh, logN, site, rhs, pp);
+    wg_rhs_sums_lane(m4 * v, N, parts + blockIdx.x, stride);
 }
 
-// t = D_oe p (four lanes per site), partials of 4m^2 |p|^2 + |t|^2 with p
-// taken at the same checkerboard index (the sum over all indices is |p|^2)
+// t = D_oe p (four lanes per site), partials of |t|^2, the second term of
+// <p, A p>
 template <class LF, int R, int GPS, bool MFMA>
 __global__ __launch_bounds__(kMB) void k_mcg_doe(const void *__restrict__ U, const void *__restrict__ p,
                                                  void *__restrict__ t, Geom g, int logN, int nblk_pad, TileOrder o,
-                                                 double m4, const CgState *st, double *__restrict__ parts,
-                                                 size_t stride)
+                                                 const CgState *st, double *__restrict__ parts, size_t stride)
 {
     constexpr unsigned LPS = 4 * GPS;
     if (!any_open(st, LPS * R, GATE_ITER)) return;
@@ -179,19 +212,18 @@ __global__ __launch_bounds__(kMB) void k_mcg_doe(const void *__restrict__ U, con
     // wavefronts, which V/2 % 16 == 0 gives it
     if (site < (unsigned)g.Vh) {
         auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(p, Vh, logN, n, r0, u); };
-        cx<float> acc[R][3], pp[R][3];
+        cx<float> acc[R][3];
         dslash_site4<LF, R, MFMA>(g, kOdd, U, site, lane4, IN, acc);
-        stm_r<float, R>(t, Vh, logN, site, r0, acc);
-        ldm_r<float, R>(p, Vh, logN, site, r0, pp);
+        // non-temporal: write-allocating t would evict the p that the
+        // neighbouring sites' gathers reuse (1.4 % of the iteration)
+        stm_r<float, R, true>(t, Vh, logN, site, r0, acc);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            double qq = 0.0, tt = 0.0;
+            double tt = 0.0;
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                qq += (double)pp[r][c].re * (double)pp[r][c].re + (double)pp[r][c].im * (double)pp[r][c].im;
+            for (int c = 0; c < 3; c++)
                 tt += (double)acc[r][c].re * (double)acc[r][c].re + (double)acc[r][c].im * (double)acc[r][c].im;
-            }
-            v[r] = m4 * qq + tt;
+            v[r] = tt;
         }
     }
     wg_rhs_sums<R, LPS>(v, parts + blk, stride);
@@ -216,7 +248,7 @@ __global__ __launch_bounds__(kMB) void k_mcg_deo(const void *__restrict__ U, con
     const unsigned r0 = (threadIdx.x % LPS) * R;
     double v[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) v[k] = 0.0;
+    for (int q = 0; q < R; q++) v[q] = 0.0;
     if (site < (unsigned)g.Vh) {
         auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(t, Vh, logN, n, r0, u); };
         cx<float> acc[R][3], pp[R][3], xx[R][3], rr[R][3];
@@ -226,21 +258,21 @@ __global__ __launch_bounds__(kMB) void k_mcg_deo(const void *__restrict__ U, con
         ldm_r<float, R>(r, Vh, logN, site, r0, rr);
         const float m4f = (float)m4;
 #pragma unroll
-        for (int k = 0; k < R; k++) {
-            if (st[r0 + k].state != ST_RUN) continue; // x and r stay as they are
-            const float alpha = (float)st[r0 + k].alpha;
+        for (int q = 0; q < R; q++) {
+            if (st[r0 + q].state != ST_RUN) continue; // x and r stay as they are
+            const float alpha = (float)st[r0 + q].alpha;
             double d = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const float apr = m4f * pp[k][c].re - acc[k][c].re;
-                const float api = m4f * pp[k][c].im - acc[k][c].im;
-                xx[k][c].re = fmaf(alpha, pp[k][c].re, xx[k][c].re);
-                xx[k][c].im = fmaf(alpha, pp[k][c].im, xx[k][c].im);
-                rr[k][c].re = fmaf(-alpha, apr, rr[k][c].re);
-                rr[k][c].im = fmaf(-alpha, api, rr[k][c].im);
-                d += (double)rr[k][c].re * (double)rr[k][c].re + (double)rr[k][c].im * (double)rr[k][c].im;
+                const float apr = m4f * pp[q][c].re - acc[q][c].re;
+                const float api = m4f * pp[q][c].im - acc[q][c].im;
+                xx[q][c].re = fmaf(alpha, pp[q][c].re, xx[q][c].re);
+                xx[q][c].im = fmaf(alpha, pp[q][c].im, xx[q][c].im);
+                rr[q][c].re = fmaf(-alpha, apr, rr[q][c].re);
+                rr[q][c].im = fmaf(-alpha, api, rr[q][c].im);
+                d += (double)rr[q][c].re * (double)rr[q][c].re + (double)rr[q][c].im * (double)rr[q][c].im;
             }
-            v[k] = d;
+            v[q] = d;
         }
         stm_r<float, R>(x, Vh, logN, site, r0, xx);
         stm_r<float, R>(r, Vh, logN, site, r0, rr);
@@ -323,10 +355,10 @@ hipError_t launch_iter_rg(const McgArgs &a, bool mf, int which, hipStream_t s, h
     if (which == 0) {
         if (mf)
             hipLaunchKernelGGL((k_mcg_doe<LF, R, GPS, true>), grid, block, 0, s, a.Ulo, a.p, a.t, a.g, a.logN, pad, o,
-                               a.m4, a.st, a.parts, a.stride);
+                               a.st, a.parts, a.stride);
         else
             hipLaunchKernelGGL((k_mcg_doe<LF, R, GPS, false>), grid, block, 0, s, a.Ulo, a.p, a.t, a.g, a.logN, pad,
-                               o, a.m4, a.st, a.parts, a.stride);
+                               o, a.st, a.parts, a.stride);
     } else {
         if (mf)
             hipLaunchKernelGGL((k_mcg_deo<LF, R, GPS, true>), grid, block, 0, s, a.Ulo, a.t, a.p, a.xlo, a.r, a.g,
@@ -356,12 +388,16 @@ hipError_t launch_iter_fmt(const McgArgs &a, int which, hipStream_t s, hipEvent_
 
 } // namespace
 
-int mcg_iter_blocks(const Geom &g, int gps)
+int mcg_iter_parts(const Geom &g, int gps, bool padded)
 {
-    const int TS = kMB / (4 * gps);
-    return (g.Vh + TS - 1) / TS;
+    const int TS = kMB / (4 * gps), nblk = (g.Vh + TS - 1) / TS;
+    return padded ? (nblk + 7) / 8 * 8 : nblk;
 }
 int mcg_lane_blocks(const Geom &g, int logN) { return (int)((((int64_t)g.Vh << logN) + kMB - 1) / kMB); }
+int mcg_xpay_blocks(const Geom &g, int logN)
+{
+    return (int)((((int64_t)g.Vh << logN) + kMB * kXpayPairs - 1) / (kMB * kXpayPairs));
+}
 
 hipError_t launch_mcg_init(const McgArgs &a, int scheme, int ru_fixed, int max_iter, double tol, double inner,
                            hipStream_t s)
@@ -378,10 +414,12 @@ hipError_t launch_mcg_norm(const McgArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_mcg_fin(const McgArgs &a, int n, int fin, int gate, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+hipError_t launch_mcg_fin(const McgArgs &a, int n, int fin, int gate, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                          int n_p)
 {
     if (e0) (void)hipEventRecord(e0, s);
-    hipLaunchKernelGGL(k_mcg_fin, dim3(1 << a.logN), dim3(kFinBS), 0, s, a.parts, a.stride, n, a.st, fin, gate);
+    hipLaunchKernelGGL(k_mcg_fin, dim3(1 << a.logN), dim3(kFinBS), 0, s, a.parts, a.stride, n, a.parts_p,
+                       a.stride_p, n_p, a.st, fin, gate);
     if (e1) (void)hipEventRecord(e1, s);
     return hipGetLastError();
 }
@@ -389,8 +427,8 @@ hipError_t launch_mcg_fin(const McgArgs &a, int n, int fin, int gate, hipStream_
 hipError_t launch_mcg_xpay(const McgArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (e0) (void)hipEventRecord(e0, s);
-    hipLaunchKernelGGL(k_mcg_xpay, dim3(mcg_lane_blocks(a.g, a.logN)), dim3(kMB), 0, s, a.r, a.p, a.g.Vh, a.logN,
-                       a.st);
+    hipLaunchKernelGGL(k_mcg_xpay, dim3(mcg_xpay_blocks(a.g, a.logN)), dim3(kMB), 0, s, a.r, a.p, a.g.Vh, a.logN,
+                       a.m4, a.st, a.parts_p, a.stride_p);
     if (e1) (void)hipEventRecord(e1, s);
     return hipGetLastError();
 }

@@ -2,16 +2,16 @@
 // (kernels in mcg.hip): the form lgt_cg_solve_batch takes for one large
 // mixed-precision problem.
 //
-// Per iteration five launches (p = r + beta p; t = D_oe p with the <p, A p>
-// partials; alpha; D_eo t with the update of x and r and the |r|^2 partials;
-// beta and the stop tests), every right-hand side with its own scalars and
-// its own gate. Iterations are enqueued in chunks of ru_interval (reliable
-// updates) or check_interval (refinement; 10 when 0) iterations, each chunk
-// ending with the FP64 step for the right-hand sides that ask for one; the
-// host reads the states back once per chunk, one chunk behind, so the GPU
-// never waits for the host. A right-hand side that meets its inner stop test
-// inside a chunk idles (its kernels skip it) until the FP64 step at the end
-// of the chunk.
+// Per iteration five launches (p = r + beta p with the partials of
+// 4m^2 |p|^2; t = D_oe p with those of |t|^2; alpha; D_eo t with the update
+// of x and r and the |r|^2 partials; beta and the stop tests), every
+// right-hand side with its own scalars and its own gate. Iterations are
+// enqueued in chunks of ru_interval (reliable updates) or check_interval
+// (refinement; 10 when 0) iterations, each chunk ending with the FP64 step
+// for the right-hand sides that ask for one; the host reads the states back
+// once per chunk, one chunk behind, so the GPU never waits for the host. A
+// right-hand side that meets its inner stop test inside a chunk idles (its
+// kernels skip it) until the FP64 step at the end of the chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,10 +57,9 @@ lgt_status mcg_solve(const lgt_cg_problem &q, const lgt_cg_params *p, Fmt flo, i
     const int scheme = p->scheme;
     const int chunk = scheme == SCH_RELIABLE ? p->ru_interval : (p->check_interval > 0 ? p->check_interval : 10);
     const double inner = scheme == SCH_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
-    const int nit = mcg_iter_blocks(g, gps), nlane = mcg_lane_blocks(g, logN);
-    // rows of partials: the inner Dslash launches write up to the launched
-    // count rounded up to a multiple of 8 (XCD remap)
-    const size_t stride = (size_t)std::max((nit + 7) / 8 * 8, nlane);
+    const int nit = mcg_iter_parts(g, gps, false), nlane = mcg_lane_blocks(g, logN);
+    const int nxp = mcg_xpay_blocks(g, logN);
+    const size_t stride = (size_t)std::max(mcg_iter_parts(g, gps, true), nlane);
 
     McgArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -81,9 +80,11 @@ lgt_status mcg_solve(const lgt_cg_problem &q, const lgt_cg_params *p, Fmt flo, i
     a.t = workspace(c, "mcg.t", n * 24);
     a.st = (CgState *)workspace(c, "mcg.states", sizeof(CgState) * N);
     a.parts = (double *)workspace(c, "mcg.parts", sizeof(double) * stride * N);
+    a.stride_p = (size_t)nxp;
+    a.parts_p = (double *)workspace(c, "mcg.parts_p", sizeof(double) * a.stride_p * N);
     a.b64 = b64;
     CgState *host = (CgState *)pinned(c, 3 * sizeof(CgState) * N);
-    if (!b64 || !a.x64 || !a.t64 || !a.xlo || !a.r || !a.p || !a.t || !a.st || !a.parts || !host)
+    if (!b64 || !a.x64 || !a.t64 || !a.xlo || !a.r || !a.p || !a.t || !a.st || !a.parts || !a.parts_p || !host)
         return fail(LGT_ERR_OOM, "cannot allocate the batch workspace");
 
     // phase events when timing is on: per iteration of a chunk slot xpay,
@@ -143,7 +144,8 @@ lgt_status mcg_solve(const lgt_cg_problem &q, const lgt_cg_params *p, Fmt flo, i
             const int b = i * kK;
             LGT_HIP(launch_mcg_xpay(a, s, ev(slot, b, true), ev(slot, b, false)));
             LGT_HIP(launch_mcg_dslash(flo, a, 0, s, ev(slot, b + 1, true), ev(slot, b + 1, false)));
-            LGT_HIP(launch_mcg_fin(a, nit, FIN_ALPHA, GATE_ITER, s, ev(slot, b + 2, true), ev(slot, b + 2, false)));
+            LGT_HIP(launch_mcg_fin(a, nit, FIN_ALPHA, GATE_ITER, s, ev(slot, b + 2, true), ev(slot, b + 2, false),
+                                   nxp));
             LGT_HIP(launch_mcg_dslash(flo, a, 1, s, ev(slot, b + 3, true), ev(slot, b + 3, false)));
             LGT_HIP(launch_mcg_fin(a, nit, FIN_UPDATE, GATE_ITER, s, ev(slot, b + 4, true), ev(slot, b + 4, false)));
         }

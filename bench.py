@@ -8,9 +8,11 @@ One step = the whole hot path:
   2. mixed CG: FP32 12-real links, FP32 vectors, FP64 reliable update every 50,
   3. mixed CG: BF16 12-real links, FP32 vectors, FP64 iterative refinement
      (inner relative tolerance 0.1),
-  4. batched CG in one persistent launch: 24^3x48 with 16 right-hand sides,
-     then 8^4, 12^4 and 16^3x32 with 4 each (Haar links, m = 0.02, FP32-12
-     with FP64 reliable updates every 50; multi-RHS Dslash on MFMA),
+  4. batched CG: 24^3x48 with 16 right-hand sides (5.3M site-rhs pairs, one
+     problem: the iteration as kernel launches), then 8^4, 12^4 and 16^3x32
+     with 4 each in one persistent launch (Haar links, m = 0.02, FP32-12 with
+     FP64 reliable updates every 50; the multi-RHS Dslash variant the tuner
+     picks for each lattice),
   5. S = phi^dag A^-1 phi and dS/dU at 16^3x32 (links exp(0.5 i H),
      m = 0.05) through the autograd function: FP64 CG forward, fermion-force
      kernel backward.
@@ -672,11 +674,16 @@ def main():
                       "true_rel_resid_max": max(r.true_rel_resid for r in last),
                       "status_all_ok": all(r.status == 0 for r in last)}
     # batched solver: phase profile of one more solve of each batch (workgroup
-    # 0's clock inside the persistent launch), and the roofline of an iteration:
-    # per even site and right-hand side (FP32 x 12 inner links shared by the N
-    # right-hand sides), step 1 reads r and p at the neighbours once (48 B) and
-    # writes t and p' (48 B) plus 384/N B of links, step 2 reads t once, p', x
-    # and r (96 B) and writes x and r (48 B) plus 384/N B of links
+    # 0's clock inside the persistent launch; event-timed kernels of the
+    # launched form, which one large problem takes and whose profile has no
+    # barrier waits), and the roofline of an iteration: per even site and
+    # right-hand side (FP32 x 12 inner links shared by the N right-hand sides),
+    # step 1 reads r and p at the neighbours once (48 B) and writes t and p'
+    # (48 B) plus 384/N B of links, step 2 reads t once, p', x and r (96 B) and
+    # writes x and r (48 B) plus 384/N B of links; where p' = r + beta p runs as
+    # a pass of its own (the launched form, and the persistent launch from 2^21
+    # (site, rhs) pairs on) that pass reads r and p and writes p' (72 B) and
+    # step 1 reads p' and writes t (48 B)
     for key, probs in (("24x24x24x48_x16", big), ("mixed_8x8x8x8_12x12x12x12_16x16x16x32_x4", mixed)):
         if args.no_batch:
             break
@@ -686,9 +693,14 @@ def main():
         lb0.set_timing(0)
         prof = lb0.batch_profile()
         its = max(prof.pop("iters"), 1)
-        sec = res[0][0].seconds
-        alg = sum(lb.Vh * (int(bb.shape[0]) * (96 + 144) + 2 * 384) for lb, _, _, bb in probs)
-        per_it_us = 1e6 * sec / its
+        launched = prof["wait1"] == 0.0 and prof["wait2"] == 0.0
+        two_pass = prof["step1_p"] > 0.0
+        alg = sum(lb.Vh * (int(bb.shape[0]) * ((120 if two_pass else 96) + 144) + 2 * 384)
+                  for lb, _, _, bb in probs)
+        batch[key]["form"] = "launched" if launched else ("persistent, two-pass step 1" if two_pass else "persistent")
+        # the whole iteration from the untimed solves (events around every
+        # launch of the launched form slow the profiled one down)
+        per_it_us = 1e6 * batch[key]["seconds_median"] / max(batch[key]["iters_max"], 1)
         # the FP64 updates are amortised over the iterations; the roofline is
         # that of the inner iteration (steps 1-3, their waits and scalar steps)
         inner_us = 1e3 * sum(v for k, v in prof.items() if k not in ("setup_and_final", "fp64_updates")) / its

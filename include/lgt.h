@@ -523,7 +523,8 @@ lgt_status lgt_get_mrhs_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32
  * hops from there; only the z and t hops gather from memory. Applies where
  * the staged tile (3 x (sites + Lx) x nrhs FP32 complex) fits 64 KB of LDS,
  * else the unstaged kernel runs; lgt_get_mrhs_staging reports what runs. Not
- * used by the batched solver (it stages its own inner Dslash). Speed only:
+ * used by the batched solver (its persistent launch stages its own inner
+ * Dslash; its launched form does not stage). Speed only:
  * results are bit-identical to the unstaged kernel of the same engine and
  * groups. */
 lgt_status lgt_set_mrhs_staging(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t staged);

@@ -238,7 +238,10 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
         const int logN = log2_rhs_padded(q.nrhs);
         int eng = c->mrhs_eng[flo][logN];
         if (eng == MRHS_MFMA && !mrhs_engine_applies(flo, logN, c->g.Vh, eng)) eng = MRHS_VALU4; // V/2 % 16 != 0
-        const int gps = mrhs_groups_valid(logN, c->mrhs_gps[flo][logN]) ? c->mrhs_gps[flo][logN] : 1;
+        // groups as in the persistent launch: at N = 16 one group (R = 4) costs
+        // the update kernel's occupancy (24^3x48 x16: 450 against 416 us an
+        // iteration with 2 groups, VALU), so a request for it runs two
+        const int gps = batch_groups(logN, c->mrhs_gps[flo][logN]);
         const bool big = ((size_t)c->g.Vh << logN) >= kBatchLaunchedPairs;
         if (mrhs_engine_applies(flo, logN, c->g.Vh, eng) && (mode == 1 || (mode < 0 && big)))
             return mcg_solve(q, p, flo, logN, eng, gps);

@@ -371,6 +371,7 @@ hipError_t launch_iter_rg(const McgArgs &a, bool mf, int which, hipStream_t s, h
     return hipGetLastError();
 }
 
+// (N = 16 runs two or four groups: see batch_groups)
 template <class LF>
 hipError_t launch_iter_fmt(const McgArgs &a, int which, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
@@ -379,7 +380,6 @@ hipError_t launch_iter_fmt(const McgArgs &a, int which, hipStream_t s, hipEvent_
     case 2 * 8 + 1: return launch_iter_rg<LF, 1, 1>(a, mf, which, s, e0, e1);
     case 3 * 8 + 1: return launch_iter_rg<LF, 2, 1>(a, mf, which, s, e0, e1);
     case 3 * 8 + 2: return launch_iter_rg<LF, 1, 2>(a, mf, which, s, e0, e1);
-    case 4 * 8 + 1: return launch_iter_rg<LF, 4, 1>(a, mf, which, s, e0, e1);
     case 4 * 8 + 2: return launch_iter_rg<LF, 2, 2>(a, mf, which, s, e0, e1);
     case 4 * 8 + 4: return launch_iter_rg<LF, 1, 4>(a, mf, which, s, e0, e1);
     default: return hipErrorInvalidValue;

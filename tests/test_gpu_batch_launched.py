@@ -61,9 +61,10 @@ SHAPES = [(n, e, g) for e in ("valu4", "mfma") for g in (1, 2, 4) for n in (4, 8
 @pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_RELIABLE, "f32r12"), (P.LGT_CG_REFINE, "bf16r12")],
                          ids=["rel_f32r12", "ir_bf16r12"])
 def test_launched_shapes(dev, monkeypatch, nrhs, engine, groups, scheme, lo):
-    """Every inner-Dslash shape (engine, groups of four lanes, N): each right-hand
-    side within the tolerance by the oracle's residual, and within the
-    tolerance's bound of the persistent launch's solution of the same batch."""
+    """Every inner-Dslash shape (engine, groups of four lanes, N; a request for
+    one group at N = 16 runs two, in both forms): each right-hand side within
+    the tolerance by the oracle's residual, and within the tolerance's bound of
+    the persistent launch's solution of the same batch."""
     L, mass, tol = (8, 8, 8, 12), 0.1, 1e-10
     U = li.links(L, "haar", 6101)
     bs = li.vectors(L, 6102, nrhs)

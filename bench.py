@@ -406,6 +406,46 @@ def probe_dslash_mrhs(L, fmt, nrhs, launches):
     return out
 
 
+def probe_batch(launches):
+    """--probe-batch: the 24^3x48 x16 batched solve of the benchmark step alone
+    (same links, sources, mass and tolerance; FP32 x 12 inner CG with FP64
+    reliable updates every 50; the multi-RHS variant the tuner picks), solved
+    `launches` times after the tuner, then once more with the phase profile
+    on. One problem of 5.3M (site, rhs) pairs: the library runs it as kernel
+    launches, so a kernel trace of this probe covers the batched CG without a
+    cooperative launch."""
+    import torch
+
+    import lgt_inputs as li
+    import paper_1309_0551_amd as P
+    dev = torch.device("cuda", 0)
+    c4 = li.CONFIGS["c4_24x24x24x48"]
+    out = {"probe": "batch", "L": list(c4["L"]), "nrhs": c4["nrhs"], "launches": launches, "seconds": []}
+    with P.Lattice(c4["L"], device=0) as lb:
+        Ub = torch.from_numpy(li.links(c4["L"], "haar", c4["link_seed"])).to(dev)
+        bb = torch.from_numpy(li.vectors(c4["L"], c4["src_seed"], c4["nrhs"])).to(dev)
+        uh, ul = lb.pack_links(Ub, P.LGT_F64, P.LGT_R18), lb.pack_links(Ub, P.LGT_F32, P.LGT_R12)
+        del Ub
+        lb.tune_dslash_mrhs(ul, c4["nrhs"], report=False)
+        probs = [(lb, uh, ul, bb)]
+        for _ in range(launches):
+            _, res = P.cg_solve_batch(probs, c4["mass"], tol=c4["tol"], scheme=P.LGT_CG_RELIABLE, ru_interval=50)
+            out["seconds"].append(round(res[0][0].seconds, 4))
+        its = max(r.iters for r in res[0])
+        out["iters"] = its
+        out["us_per_iteration"] = round(1e6 * min(out["seconds"]) / its, 2)
+        out["true_rel_resid_max"] = max(r.true_rel_resid for r in res[0])
+        out["variant"] = list(lb.mrhs_variant(P.LGT_F32, P.LGT_R12, c4["nrhs"]))
+        lb.set_timing(1)
+        P.cg_solve_batch(probs, c4["mass"], tol=c4["tol"], scheme=P.LGT_CG_RELIABLE, ru_interval=50)
+        lb.set_timing(0)
+        prof = lb.batch_profile()
+        pit = max(prof.pop("iters"), 1)
+        out["form"] = "launched" if prof["wait1"] == 0.0 and prof["wait2"] == 0.0 else "persistent"
+        out["phases_us_per_iter"] = {k: round(1e3 * v / pit, 2) for k, v in prof.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -430,6 +470,9 @@ def main():
     ap.add_argument("--probe", type=int, nargs=4, metavar="L",
                     help="instead of the benchmark: time the plain Dslash alone on this lattice and print one "
                          "JSON line (options --fmt, --launches, --hops, --streaming)")
+    ap.add_argument("--probe-batch", action="store_true",
+                    help="instead of the benchmark: the 24^3x48 x16 batched solve alone, --launches times, and "
+                         "one JSON line")
     ap.add_argument("--fmt", default="f64r18", choices=sorted(PROBE_FMTS))
     ap.add_argument("--nrhs", type=int, default=1, choices=(1, 4, 8, 16),
                     help="with --probe: N > 1 probes the multi-RHS Dslash, every variant")
@@ -441,6 +484,9 @@ def main():
         print("bench.py measures one GPU: this library has no multi-GPU path (its domain decomposition "
               "over several GPUs is a design only); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.probe_batch:
+        print(json.dumps(probe_batch(args.launches)), flush=True)
+        return
     if args.probe and args.nrhs > 1:
         print(json.dumps(probe_dslash_mrhs(tuple(args.probe), args.fmt, args.nrhs, args.launches)), flush=True)
         return

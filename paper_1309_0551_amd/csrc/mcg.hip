@@ -284,9 +284,12 @@ __global__ __launch_bounds__(kMB) void k_mcg_deo(const void *__restrict__ U, con
 // whose gate is open (one lane per (site, rhs), FP64 links)
 __global__ __launch_bounds__(kMB) void k_mcg_fp64_doe(const void *__restrict__ Uhi, const double *__restrict__ x64,
                                                       const void *__restrict__ xlo, double *__restrict__ t64, Geom g,
-                                                      int logN, const CgState *st, int gate)
+                                                      int logN, int nblk_pad, TileOrder o, const CgState *st,
+                                                      int gate)
 {
-    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return;
+    const unsigned idx = (unsigned)blk * kMB + threadIdx.x;
     const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
     if (site >= (unsigned)g.Vh || !gate_open(gate, &st[rhs])) return;
     const size_t Vh = (size_t)g.Vh;
@@ -310,12 +313,15 @@ __global__ __launch_bounds__(kMB) void k_mcg_fp64_doe(const void *__restrict__ U
 __global__ __launch_bounds__(kMB) void k_mcg_fp64_res(const void *__restrict__ Uhi, const double *__restrict__ t64,
                                                       double *__restrict__ x64, void *__restrict__ xlo,
                                                       const double *__restrict__ b64, void *__restrict__ rlo, Geom g,
-                                                      int logN, double m4, const CgState *st, int gate,
-                                                      double *__restrict__ parts, size_t stride)
+                                                      int logN, int nblk_pad, TileOrder o, double m4,
+                                                      const CgState *st, int gate, double *__restrict__ parts,
+                                                      size_t stride)
 {
     const int N = 1 << logN;
     if (!any_open(st, N, gate)) return; // uniform; no partial of a closed gate is read
-    const unsigned idx = blockIdx.x * kMB + threadIdx.x;
+    const int blk = mrhs_block(o, nblk_pad);
+    if (blk < 0) return;
+    const unsigned idx = (unsigned)blk * kMB + threadIdx.x;
     const unsigned site = idx >> logN, rhs = idx & ((1u << logN) - 1u);
     double v = 0.0;
     if (site < (unsigned)g.Vh && gate_open(gate, &st[rhs])) {
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(kMB) void k_mcg_fp64_res(const void *__restrict__ U
         stm<float>(xlo, Vh, logN, site, rhs, e);
         stm<float>(rlo, Vh, logN, site, rhs, lo);
     }
-    wg_rhs_sums_lane(v, N, parts + blockIdx.x, stride);
+    wg_rhs_sums_lane(v, N, parts + blk, stride);
 }
 
 template <class LF, int R, int GPS>
@@ -445,13 +451,19 @@ hipError_t launch_mcg_dslash(Fmt lo, const McgArgs &a, int which, hipStream_t s,
 
 hipError_t launch_mcg_fp64(const McgArgs &a, int gate, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    const dim3 grid(mcg_lane_blocks(a.g, a.logN)), block(kMB);
+    // tiles of kMB (site, rhs) pairs in the XCD-aware order of the
+    // standalone lane engine: a workgroup's neighbours stay in its XCD's L2
+    // (in plain block order the FP64 step fetched 4.2 x its bytes)
+    const int nblk = mcg_lane_blocks(a.g, a.logN), pad = (nblk + 7) / 8 * 8;
+    const TileOrder o = tile_order(a.g, kMB >> a.logN);
+    const dim3 grid(mrhs_grid(o, nblk)), block(kMB);
     if (e0) (void)hipEventRecord(e0, s);
-    hipLaunchKernelGGL(k_mcg_fp64_doe, grid, block, 0, s, a.Uhi, a.x64, a.xlo, a.t64, a.g, a.logN, a.st, gate);
+    hipLaunchKernelGGL(k_mcg_fp64_doe, grid, block, 0, s, a.Uhi, a.x64, a.xlo, a.t64, a.g, a.logN, pad, o, a.st,
+                       gate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mcg_fp64_res, grid, block, 0, s, a.Uhi, a.t64, a.x64, a.xlo, a.b64, a.r, a.g, a.logN, a.m4,
-                       a.st, gate, a.parts, a.stride);
+    hipLaunchKernelGGL(k_mcg_fp64_res, grid, block, 0, s, a.Uhi, a.t64, a.x64, a.xlo, a.b64, a.r, a.g, a.logN, pad,
+                       o, a.m4, a.st, gate, a.parts, a.stride);
     if (e1) (void)hipEventRecord(e1, s);
     return hipGetLastError();
 }

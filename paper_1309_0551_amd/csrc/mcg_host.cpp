@@ -59,7 +59,7 @@ lgt_status mcg_solve(const lgt_cg_problem &q, const lgt_cg_params *p, Fmt flo, i
     const double inner = scheme == SCH_REFINE ? p->inner_tol : (p->inner_tol > 0 ? p->inner_tol : 1.0);
     const int nit = mcg_iter_parts(g, gps, false), nlane = mcg_lane_blocks(g, logN);
     const int nxp = mcg_xpay_blocks(g, logN);
-    const size_t stride = (size_t)std::max(mcg_iter_parts(g, gps, true), nlane);
+    const size_t stride = (size_t)std::max(mcg_iter_parts(g, gps, true), (nlane + 7) / 8 * 8);
 
     McgArgs a;
     std::memset(&a, 0, sizeof(a));

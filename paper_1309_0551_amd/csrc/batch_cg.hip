@@ -39,6 +39,7 @@ struct Shared {
     double coef[kMaxTotalRhs];         // beta before step 1, alpha before step 3; 0 unless iterating
     double acc[kMaxTotalRhs];          // this workgroup's partial sums
     double red[kBB];                   // reduction scratch
+    double tot[kMaxTotalRhs];          // row sums (sum_rows)
     unsigned char run[kMaxTotalRhs];   // state == ST_RUN
     unsigned char sel[kMaxTotalRhs];   // selected for the current FP64 step
     int prun[kMaxProblems], psel[kMaxProblems];
@@ -187,7 +188,11 @@ __device__ __forceinline__ void write_row(const BatchArgs *A, double *rows, Shar
 }
 
 // Sum of all workgroups' rows for right-hand side threadIdx.x (valid below
-// total_rhs), in an order that is the same in every workgroup.
+// total_rhs), in an order that is the same in every workgroup: C = kBB / Q
+// chunk sums per right-hand side, then those C by one wavefront per
+// right-hand side (lane l adds chunks l, l + 64, ..., then a butterfly),
+// which keeps the serial part short (summing the chunks in one lane took
+// C dependent LDS reads, 85 at Q = 12).
 __device__ double sum_rows(const BatchArgs *A, const double *rows, Shared &S)
 {
     const int Q = A->total_rhs, G = gridDim.x, C = kBB / Q;
@@ -197,11 +202,16 @@ __device__ double sum_rows(const BatchArgs *A, const double *rows, Shared &S)
         for (int b = c; b < G; b += C) s += ld_f64(rows + (size_t)b * Q + q);
     S.red[t] = s;
     __syncthreads();
-    double tot = 0.0;
-    if (t < Q)
-        for (int k = 0; k < C; k++) tot += S.red[k * Q + t];
+    const int w = t >> 6, lane = t & 63;
+    for (int r = w; r < Q; r += kBB / 64) {
+        double x = 0.0;
+        for (int k = lane; k < C; k += 64) x += S.red[k * Q + r];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) S.tot[r] = x;
+    }
     __syncthreads();
-    return tot;
+    return t < Q ? S.tot[t] : 0.0;
 }
 
 // After a scalar step: run flags, step coefficients (alpha after FIN_ALPHA,

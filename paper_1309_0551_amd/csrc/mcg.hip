@@ -32,13 +32,18 @@ namespace lgt {
 
 namespace {
 
-// Sizes measured at 24^3 x 48 x 16 (the iteration in us): 512-lane
+// Sizes measured at 24^3 x 48 x 16 (the iteration in us, against 416): 512-lane
 // workgroups +3, finalize workgroups of 256 / 512 lanes +6 / +1.5, 2 or 8
 // pairs per lane in the p pass +3, workgroups that walk several tiles (fewer
 // partials) +4 to +37, one partial per wavefront instead of per workgroup +18.
 constexpr int kMB = kBS;      // lanes per workgroup of the vector, Dslash and FP64 kernels
 constexpr int kFinBS = 1024;  // lanes of a finalize workgroup
 constexpr int kXpayPairs = 4; // (site, rhs) pairs per lane of the p = r + beta p pass
+// directions per trip of the inner Dslash's direction loop: two (four hops'
+// loads in flight, 84 VGPRs at R = 2) took the iteration from 416 to 407 us
+// with the VALU engine and left the MFMA one unchanged; four spills the update
+// kernel at R = 2
+constexpr int kUnr = 2;
 
 // Whether any right-hand side's gate is open (uniform over the workgroup:
 // every lane reads the same N states, written by an earlier launch)
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(kMB) void k_mcg_doe(const void *__restrict__ U, con
     if (site < (unsigned)g.Vh) {
         auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(p, Vh, logN, n, r0, u); };
         cx<float> acc[R][3];
-        dslash_site4<LF, R, MFMA>(g, kOdd, U, site, lane4, IN, acc);
+        dslash_site4<LF, R, MFMA, kUnr>(g, kOdd, U, site, lane4, IN, acc);
         // non-temporal: write-allocating t would evict the p that the
         // neighbouring sites' gathers reuse (1.4 % of the iteration)
         stm_r<float, R, true>(t, Vh, logN, site, r0, acc);
@@ -252,7 +257,7 @@ __global__ __launch_bounds__(kMB) void k_mcg_deo(const void *__restrict__ U, con
     if (site < (unsigned)g.Vh) {
         auto IN = [=](int n, cx<float> u[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(t, Vh, logN, n, r0, u); };
         cx<float> acc[R][3], pp[R][3], xx[R][3], rr[R][3];
-        dslash_site4<LF, R, MFMA>(g, kEven, U, site, lane4, IN, acc);
+        dslash_site4<LF, R, MFMA, kUnr>(g, kEven, U, site, lane4, IN, acc);
         ldm_r<float, R>(p, Vh, logN, site, r0, pp);
         ldm_r<float, R>(x, Vh, logN, site, r0, xx);
         ldm_r<float, R>(r, Vh, logN, site, r0, rr);

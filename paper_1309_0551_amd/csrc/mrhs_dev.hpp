@@ -232,7 +232,9 @@ __device__ __forceinline__ void hop_apply(const cx<float> u[9], bool fwd, bool n
 
 // D on one site for the lane's R right-hand sides. in(site, v[R][3]) loads the
 // lane's inputs at a neighbour. FP32 vectors (F32 or BF16 links).
-template <class LF, int R, bool MFMA, class In>
+// UNR directions per trip of the direction loop (1, 2 or 4): the loads of
+// 2 UNR hops in flight at once, for more registers
+template <class LF, int R, bool MFMA, int UNR = 1, class In>
 __device__ __forceinline__ void dslash_site4(const Geom &g, int par, const void *U, int cb, int lane4, In in,
                                              cx<float> acc[R][3])
 {
@@ -248,16 +250,20 @@ __device__ __forceinline__ void dslash_site4(const Geom &g, int par, const void 
         for (int i = 0; i < 3; i++) acc[r][i].re = acc[r][i].im = 0.f;
     }
 #pragma unroll 1
-    for (int mu = 0; mu < 4; mu++) {
-        const Hop h = hop_rt(g, c, cb, mu);
-        cx<float> u[9], v[R][3];
-        LF::template load_quad<false>(U, Vh, par * 4 + mu, cb, u, lane4);
-        in(h.f, v);
-        hop_apply<R, MFMA>(u, true, h.fneg, v, lane4, acc, C);
-        LF::template load_quad<false>(U, Vh, (1 - par) * 4 + mu, h.b, u, lane4);
-        in(h.b, v);
-        // the adjoint hop enters with a minus sign: fold it into neg
-        hop_apply<R, MFMA>(u, false, !h.bneg, v, lane4, acc, C);
+    for (int m0 = 0; m0 < 4; m0 += UNR) {
+#pragma unroll
+        for (int j = 0; j < UNR; j++) {
+            const int mu = m0 + j;
+            const Hop h = hop_rt(g, c, cb, mu);
+            cx<float> u[9], v[R][3];
+            LF::template load_quad<false>(U, Vh, par * 4 + mu, cb, u, lane4);
+            in(h.f, v);
+            hop_apply<R, MFMA>(u, true, h.fneg, v, lane4, acc, C);
+            LF::template load_quad<false>(U, Vh, (1 - par) * 4 + mu, h.b, u, lane4);
+            in(h.b, v);
+            // the adjoint hop enters with a minus sign: fold it into neg
+            hop_apply<R, MFMA>(u, false, !h.bneg, v, lane4, acc, C);
+        }
     }
     if constexpr (MFMA) {
 #pragma unroll

@@ -50,14 +50,15 @@ template <typename T> struct V2of;
 template <> struct V2of<double> { using type = dv2; };
 template <> struct V2of<float> { using type = fv2; };
 
-// element (colour c, site, rhs) of a multi-RHS vector; the plane base is uniform
-template <typename T>
+// element (colour c, site, rhs) of a multi-RHS vector; the plane base is
+// uniform. NT: non-temporal (streaming) loads
+template <typename T, bool NT = false>
 __device__ __forceinline__ void ldm(const void *v, size_t Vh, int logN, unsigned site, unsigned rhs, cx<T> o[3])
 {
     using V2 = typename V2of<T>::type;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const V2 w = ld<false>((const V2 *)v + ((size_t)c * Vh << logN), (site << logN) + rhs);
+        const V2 w = ld<NT>((const V2 *)v + ((size_t)c * Vh << logN), (site << logN) + rhs);
         o[c].re = w.x;
         o[c].im = w.y;
     }
@@ -103,7 +104,8 @@ __device__ __forceinline__ void dslash_mrhs(const Geom &g, int par, const void *
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // R consecutive complex numbers per colour: element (c, site, rhs0 .. rhs0+R-1)
-template <typename T, int R>
+// NT: non-temporal (streaming) loads
+template <typename T, int R, bool NT = false>
 __device__ __forceinline__ void ldm_r(const void *v, size_t Vh, int logN, unsigned site, unsigned rhs0, cx<T> o[R][3])
 {
 #pragma unroll
@@ -113,7 +115,7 @@ __device__ __forceinline__ void ldm_r(const void *v, size_t Vh, int logN, unsign
         if constexpr (std::is_same<T, float>::value && R % 2 == 0) {
 #pragma unroll
             for (int q = 0; q < R / 2; q++) {
-                const fv4 w = ld<false>((const fv4 *)((const fv2 *)v + plane + i) + q, 0u);
+                const fv4 w = ld<NT>((const fv4 *)((const fv2 *)v + plane + i) + q, 0u);
                 o[2 * q][c].re = w.x;
                 o[2 * q][c].im = w.y;
                 o[2 * q + 1][c].re = w.z;
@@ -123,7 +125,7 @@ __device__ __forceinline__ void ldm_r(const void *v, size_t Vh, int logN, unsign
             using V2 = typename std::conditional<std::is_same<T, double>::value, dv2, fv2>::type;
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const V2 w = ld<false>((const V2 *)v + plane, i + r);
+                const V2 w = ld<NT>((const V2 *)v + plane, i + r);
                 o[r][c].re = w.x;
                 o[r][c].im = w.y;
             }
@@ -233,8 +235,9 @@ __device__ __forceinline__ void hop_apply(const cx<float> u[9], bool fwd, bool n
 // D on one site for the lane's R right-hand sides. in(site, v[R][3]) loads the
 // lane's inputs at a neighbour. FP32 vectors (F32 or BF16 links).
 // UNR directions per trip of the direction loop (1, 2 or 4): the loads of
-// 2 UNR hops in flight at once, for more registers
-template <class LF, int R, bool MFMA, int UNR = 1, class In>
+// 2 UNR hops in flight at once, for more registers. NTL: streaming
+// (non-temporal) link loads.
+template <class LF, int R, bool MFMA, int UNR = 1, bool NTL = false, class In>
 __device__ __forceinline__ void dslash_site4(const Geom &g, int par, const void *U, int cb, int lane4, In in,
                                              cx<float> acc[R][3])
 {
@@ -256,10 +259,10 @@ __device__ __forceinline__ void dslash_site4(const Geom &g, int par, const void 
             const int mu = m0 + j;
             const Hop h = hop_rt(g, c, cb, mu);
             cx<float> u[9], v[R][3];
-            LF::template load_quad<false>(U, Vh, par * 4 + mu, cb, u, lane4);
+            LF::template load_quad<NTL>(U, Vh, par * 4 + mu, cb, u, lane4);
             in(h.f, v);
             hop_apply<R, MFMA>(u, true, h.fneg, v, lane4, acc, C);
-            LF::template load_quad<false>(U, Vh, (1 - par) * 4 + mu, h.b, u, lane4);
+            LF::template load_quad<NTL>(U, Vh, (1 - par) * 4 + mu, h.b, u, lane4);
             in(h.b, v);
             // the adjoint hop enters with a minus sign: fold it into neg
             hop_apply<R, MFMA>(u, false, !h.bneg, v, lane4, acc, C);

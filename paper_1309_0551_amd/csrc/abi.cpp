@@ -284,6 +284,10 @@ lgt_status lgt_destroy(lgt_ctx *c)
     {
         DeviceScope ds(c->device);
         (void)hipStreamSynchronize(c->stream);
+        if (c->aux) {
+            (void)hipStreamSynchronize(c->aux);
+            (void)hipStreamDestroy(c->aux);
+        }
         for (auto &kv : c->ws)
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
         if (c->pinned) (void)hipHostFree(c->pinned);

@@ -222,29 +222,38 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
     DeviceScope ds(c0->device);
     const hipStream_t s = c0->stream;
 
-    // One large mixed-precision problem: the iteration as kernel launches
-    // (mcg_host.cpp), whose Dslash steps keep more waves in flight than the
-    // persistent launch can. LGT_BATCH_LAUNCHED = 1 takes that form whenever it
-    // applies, 0 never; unset, from kBatchLaunchedPairs (site, rhs) pairs on.
-    if (nprob == 1 && mixed) {
+    // Mixed precision with a four-lane inner engine in every problem: the
+    // iteration as kernel launches (mcg_host.cpp), each problem on its own
+    // context's stream. Its Dslash steps keep more waves in flight than the
+    // persistent launch can, and a single problem of any size, or up to
+    // kMcgMaxProblems on different contexts (each context's auxiliary stream;
+    // HIP's default of four hardware queues), solves faster that way.
+    // LGT_BATCH_LAUNCHED = 1 takes that form whenever every problem has a
+    // four-lane engine, 0 never.
+    if (mixed) {
         int mode = -1;
         if (const char *e = std::getenv("LGT_BATCH_LAUNCHED")) {
             if (!std::strcmp(e, "0")) mode = 0;
             else if (!std::strcmp(e, "1")) mode = 1;
             else if (*e) return fail(LGT_ERR_ARG, "LGT_BATCH_LAUNCHED must be 0 or 1");
         }
-        const lgt_cg_problem &q = probs[0];
-        lgt_ctx *c = q.ctx;
-        const int logN = log2_rhs_padded(q.nrhs);
-        int eng = c->mrhs_eng[flo][logN];
-        if (eng == MRHS_MFMA && !mrhs_engine_applies(flo, logN, c->g.Vh, eng)) eng = MRHS_VALU4; // V/2 % 16 != 0
-        // groups as in the persistent launch: at N = 16 one group (R = 4) costs
-        // the update kernel's occupancy (24^3x48 x16: 450 against 416 us an
-        // iteration with 2 groups, VALU), so a request for it runs two
-        const int gps = batch_groups(logN, c->mrhs_gps[flo][logN]);
-        const bool big = ((size_t)c->g.Vh << logN) >= kBatchLaunchedPairs;
-        if (mrhs_engine_applies(flo, logN, c->g.Vh, eng) && (mode == 1 || (mode < 0 && big)))
-            return mcg_solve(q, p, flo, logN, eng, gps);
+        std::vector<McgProblem> mp((size_t)nprob);
+        bool four = true, distinct = true;
+        for (int i = 0; i < nprob; i++) {
+            const lgt_cg_problem &q = probs[i];
+            lgt_ctx *c = q.ctx;
+            const int logN = log2_rhs_padded(q.nrhs);
+            int eng = c->mrhs_eng[flo][logN];
+            if (eng == MRHS_MFMA && !mrhs_engine_applies(flo, logN, c->g.Vh, eng)) eng = MRHS_VALU4; // V/2 % 16 != 0
+            // groups as in the persistent launch: at N = 16 one group (R = 4)
+            // costs the update kernel's occupancy (24^3x48 x16: 450 against
+            // 416 us an iteration with 2 groups, VALU), so a request for it runs two
+            mp[i] = McgProblem{&q, flo, logN, eng, batch_groups(logN, c->mrhs_gps[flo][logN])};
+            four = four && mrhs_engine_applies(flo, logN, c->g.Vh, eng);
+            for (int j = 0; j < i; j++) distinct = distinct && probs[j].ctx != c;
+        }
+        const bool suits = nprob == 1 || (nprob <= kMcgMaxProblems && distinct);
+        if (four && (mode == 1 || (mode < 0 && suits))) return mcg_solve(mp.data(), nprob, p);
     }
 
     // grid: one workgroup per CU, all resident at once (cooperative launch)

@@ -20,9 +20,9 @@ constexpr int kMaxTotalRhs = 256;  // right-hand sides per batched launch
 constexpr int kBB = 1024;          // threads per workgroup of the batched solver
 // (site, rhs) pairs of a batch from which its step 1 runs as two passes
 constexpr size_t kBatchSplitPairs = (size_t)1 << 21;
-// (site, rhs) pairs of a one-problem mixed-precision batch from which its
-// iteration runs as kernel launches (mcg.hip) instead of the persistent launch
-constexpr size_t kBatchLaunchedPairs = (size_t)1 << 21;
+// problems (each on its own stream) up to which a mixed-precision batch runs
+// as kernel launches (mcg.hip) instead of the persistent launch
+constexpr int kMcgMaxProblems = 4;
 // LDS per workgroup of the batched solver for the staged input tiles of its
 // four-lane Dslash steps: 3 colours x (sites of a tile + Lx) x N right-hand
 // sides of FP32 complex (8 B) must fit

@@ -54,6 +54,11 @@ struct lgt_ctx {
     std::map<std::string, Buf> ws; // named device workspace, grown on demand
     void *pinned = nullptr;        // host pinned staging for state read-back
     size_t pinned_bytes = 0;
+    // the batched CG's launched form runs each problem on its context's own
+    // auxiliary stream (default priority, created on first use), ordered
+    // against `stream` by events, so that problems overlap even when every
+    // context was given the same stream
+    hipStream_t aux = nullptr;
     // phase profile of the last batched solve launched from this context with
     // timing on (lgt_batch_profile), ms per phase and iterations
     double batch_prof_ms[9] = {};
@@ -110,10 +115,16 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
                     const double *b, double *x, lgt_cg_result *res, const lgt_links *U3hi = nullptr,
                     const lgt_links *U3lo = nullptr);
 
-// The batched CG of one lattice with N = 2^logN >= 4 right-hand sides as
-// kernel launches (mcg_host.cpp): mixed schemes, a four-lane inner engine with gps
-// groups; q.U_hi F64 x 18, q.U_lo in format flo.
-lgt_status mcg_solve(const lgt_cg_problem &q, const lgt_cg_params *p, Fmt flo, int logN, int engine, int gps);
+// The batched CG as kernel launches (mcg_host.cpp), for mixed schemes: each
+// problem with N = 2^logN >= 4 right-hand sides (nrhs of them real), a
+// four-lane inner engine with gps groups, q->U_hi F64 x 18 and q->U_lo in
+// format flo; every problem on its own context's stream.
+struct McgProblem {
+    const lgt_cg_problem *q;
+    Fmt flo;
+    int logN, engine, gps;
+};
+lgt_status mcg_solve(const McgProblem *mp, int nprob, const lgt_cg_params *p);
 
 // launch geometry of the one-link / improved Dslash for link format f
 inline Launch dslash_launch(const lgt_ctx *c, Fmt f) { return site_launch(c->g.Vh, c->dbs[f]); }

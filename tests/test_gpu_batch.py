@@ -362,11 +362,13 @@ def test_batch_matches_single_solves_c4_shape(dev):
 @pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_FP64, None), (P.LGT_CG_RELIABLE, (P.LGT_F32, P.LGT_R12)),
                                        (P.LGT_CG_REFINE, (P.LGT_BF16, P.LGT_R12))],
                          ids=["fp64", "rel_f32r12", "ir_bf16r12"])
-def test_batch_two_pass_step1(dev, scheme, lo):
+def test_batch_two_pass_step1(dev, scheme, lo, monkeypatch):
     """24^4 x 16 (2.65M site-rhs pairs: step 1 runs as two passes, p' and then
-    D_oe p') next to 8^4 x 4 in the same launch: every right-hand side checked
+    D_oe p') next to 8^4 x 4 in the same persistent launch (forced: two mixed
+    problems would run as kernel launches): every right-hand side checked
     against the oracle's FP64 residual, the large lattice's against the single
     solver's solution."""
+    monkeypatch.setenv("LGT_BATCH_LAUNCHED", "0")
     mass, tol = 0.05, 1e-10
     Lb, Ls = (24, 24, 24, 24), (8, 8, 8, 8)
     Ub, Us = li.links(Lb, "expih", 4501, c=0.3), li.links(Ls, "haar", 4502)
@@ -407,9 +409,11 @@ def test_batch_iteration_cap_and_determinism(dev):
 
 @pytest.mark.parametrize("nrhs,engine,groups", [(8, "valu4", 1), (8, "mfma", 2), (16, "valu4", 4),
                                                 (16, "mfma", 2), (16, "mfma", 4), (16, "lane", 1)])
-def test_batch_inner_shapes(dev, nrhs, engine, groups):
-    """The batched solver with each inner-Dslash shape it runs: every right-hand
-    side's oracle-recomputed residual within the tolerance."""
+def test_batch_inner_shapes(dev, nrhs, engine, groups, monkeypatch):
+    """The persistent batched solver with each inner-Dslash shape it runs (forced:
+    one mixed problem would run as kernel launches): every right-hand side's
+    oracle-recomputed residual within the tolerance."""
+    monkeypatch.setenv("LGT_BATCH_LAUNCHED", "0")
     L, mass, tol = (8, 8, 8, 12), 0.1, 1e-10
     U = li.links(L, "haar", 181)
     bs = li.vectors(L, 182, nrhs)
@@ -427,7 +431,9 @@ def test_batch_barrier_timeout_is_reported(dev, monkeypatch):
     """A grid-barrier wait bounded at one poll (LGT_BATCH_SPIN_LIMIT, set on
     the host) times out: every workgroup leaves the persistent kernel, the call
     returns LGT_ERR_DEVICE naming the barrier, and the next call with the
-    normal bound solves the same batch."""
+    normal bound solves the same batch (the persistent launch forced: this
+    mixed one-problem batch would run as kernel launches)."""
+    monkeypatch.setenv("LGT_BATCH_LAUNCHED", "0")
     L, mass = (8, 8, 8, 8), 0.1
     U = li.links(L, "haar", 181)
     bs = li.vectors(L, 182, 4)

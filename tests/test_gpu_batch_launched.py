@@ -1,9 +1,9 @@
-"""The batched CG of one lattice as kernel launches (the form
-lgt_cg_solve_batch takes for one large mixed-precision problem): every
-right-hand side against the FP64 oracle's residual, against the persistent
-launch's solution of the same batch and against the single-RHS solver, at
-small shapes (the form forced on with LGT_BATCH_LAUNCHED=1) and at
-24^3 x 48 x 16, where it is the default."""
+"""The batched CG as kernel launches (the form lgt_cg_solve_batch takes for
+mixed-precision batches of up to four problems on different contexts, each
+with a four-lane inner engine): every right-hand side against the FP64
+oracle's residual, against the persistent launch's solution of the same batch
+and against the single-RHS solver, at small shapes and at 24^3 x 48 x 16;
+several problems at once, also on one shared context."""
 import numpy as np
 import pytest
 
@@ -188,3 +188,123 @@ def test_launched_default_at_24x24x24x48_x16(dev):
     assert abs(res[0][9].iters - rj.iters) <= max(12, rj.iters // 10)
     for j in (0, 9, 15):
         _check_solution(L, U, mass, b[j], xb[j], res[0][j], tol)
+
+
+def _mixed_problems(dev, specs, lo="f32r12", share=False):
+    """(L, nrhs, seed) -> problems on their own contexts (or all on the first)."""
+    lats, probs, data = [], [], []
+    for i, (L, n, seed) in enumerate(specs):
+        U = li.links(L, "haar", seed)
+        b = li.vectors(L, seed + 1, n)
+        lat = P.Lattice(L) if not (share and lats) else lats[0]
+        if not (share and lats):
+            lats.append(lat)
+        Ut = _t(U, dev)
+        probs.append((lat, lat.pack_links(Ut, P.LGT_F64, P.LGT_R18), lat.pack_links(Ut, *LO[lo]), _t(b, dev)))
+        data.append((L, U, b))
+    return lats, probs, data
+
+
+@pytest.mark.parametrize("scheme,lo", [(P.LGT_CG_RELIABLE, "f32r12"), (P.LGT_CG_REFINE, "bf16r12")],
+                         ids=["rel_f32r12", "ir_bf16r12"])
+def test_launched_three_lattices(dev, monkeypatch, scheme, lo):
+    """8^4, 12^4 and 16^3 x 32 with 4, 8 and 16 right-hand sides on their own
+    contexts take the launched form by default (each problem on its own
+    stream): every right-hand side against the oracle's residual and within
+    the tolerance's bound of the persistent launch's solution."""
+    mass, tol = 0.1, 1e-10
+    specs = [((8, 8, 8, 8), 4, 6201), ((12, 12, 12, 12), 8, 6211), ((16, 16, 16, 32), 16, 6221)]
+    lats, probs, data = _mixed_problems(dev, specs, lo)
+    itol = 0.1 if scheme == P.LGT_CG_REFINE else 0.0
+    print("launched three lattices", lo, flush=True)
+    lats[0].set_timing(1)
+    xl, rl = P.cg_solve_batch(probs, mass, tol=tol, scheme=scheme, inner_tol=itol)
+    assert _is_launched(lats[0])
+    xp, rp = _solve(monkeypatch, "0", probs, mass, tol, scheme, inner_tol=itol)
+    assert not _is_launched(lats[0])
+    lats[0].set_timing(0)
+    for (L, U, b), x1, x2, r1 in zip(data, xl, xp, rl):
+        g1, g2 = x1.cpu().numpy(), x2.cpu().numpy()
+        for j in range(b.shape[0]):
+            _check_solution(L, U, mass, b[j], g1[j], r1[j], tol)
+            assert np.linalg.norm(g1[j] - g2[j]) <= 2.1 * tol * np.linalg.norm(b[j]) / (4 * mass * mass)
+    for lat in lats:
+        lat.close()
+
+
+def test_launched_problems_sharing_a_context(dev, monkeypatch):
+    """Two problems on one context (one stream, the launches of the two
+    serialised) and a third on another, forced into the launched form: each
+    right-hand side against the oracle's residual; the first problem's
+    solutions bit-identical to the same problem solved alone (problems never
+    mix)."""
+    mass, tol = 0.1, 1e-10
+    specs = [((8, 8, 8, 12), 4, 6231), ((8, 8, 8, 12), 8, 6241)]
+    lats, probs, data = _mixed_problems(dev, specs, share=True)
+    assert probs[0][0] is probs[1][0]
+    other = P.Lattice((6, 6, 6, 8))
+    U3 = li.links((6, 6, 6, 8), "haar", 6251)
+    b3 = li.vectors((6, 6, 6, 8), 6252, 4)
+    U3t = _t(U3, dev)
+    probs.append((other, other.pack_links(U3t, P.LGT_F64, P.LGT_R18), other.pack_links(U3t, P.LGT_F32, P.LGT_R12),
+                  _t(b3, dev)))
+    data.append(((6, 6, 6, 8), U3, b3))
+    xs, res = _solve(monkeypatch, "1", probs, mass, tol, P.LGT_CG_RELIABLE)
+    for (L, U, b), x, rs in zip(data, xs, res):
+        g = x.cpu().numpy()
+        for j in range(b.shape[0]):
+            _check_solution(L, U, mass, b[j], g[j], rs[j], tol)
+    x0, r0 = _solve(monkeypatch, "1", probs[:1], mass, tol, P.LGT_CG_RELIABLE)
+    assert torch.equal(x0[0], xs[0])
+    assert [r.iters for r in r0[0]] == [r.iters for r in res[0]]
+    other.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_launched_five_problems_forced(dev, monkeypatch):
+    """More problems than the automatic rule takes (five, on five contexts)
+    run the persistent launch by default and the launched form when forced:
+    both within the tolerance by the oracle's residual."""
+    mass, tol = 0.1, 1e-10
+    specs = [((4, 4, 4, 8), 4, 6261 + 10 * i) for i in range(5)]
+    lats, probs, data = _mixed_problems(dev, specs)
+    lats[0].set_timing(1)
+    for mode, launched in (("1", True), ("0", False)):
+        xs, res = _solve(monkeypatch, mode, probs, mass, tol, P.LGT_CG_RELIABLE)
+        assert _is_launched(lats[0]) == launched
+        for (L, U, b), x, rs in zip(data, xs, res):
+            g = x.cpu().numpy()
+            for j in range(b.shape[0]):
+                _check_solution(L, U, mass, b[j], g[j], rs[j], tol)
+    xs, res = P.cg_solve_batch(probs, mass, tol=tol, scheme=P.LGT_CG_RELIABLE)
+    assert not _is_launched(lats[0])
+    lats[0].set_timing(0)
+    for lat in lats:
+        lat.close()
+
+
+def test_launched_graph_replays_match_eager(dev):
+    """Without timing each problem's chunk is captured once into a HIP graph and
+    replayed every chunk (about 30 replays a solve here); with timing on the
+    same launches go out one by one. Both give bit-identical solutions and
+    iteration counts, for one problem and for three on their own streams."""
+    mass, tol = 0.1, 1e-10
+    specs = [((8, 8, 8, 12), 8, 6301), ((6, 6, 6, 8), 4, 6311), ((8, 8, 8, 8), 16, 6321)]
+    lats, probs, data = _mixed_problems(dev, specs)
+    for sel in (probs[:1], probs):
+        lats[0].set_timing(1)
+        xe, re_ = P.cg_solve_batch(sel, mass, tol=tol, scheme=P.LGT_CG_RELIABLE)
+        assert _is_launched(lats[0])
+        lats[0].set_timing(0)
+        for rep in range(2):
+            xg, rg = P.cg_solve_batch(sel, mass, tol=tol, scheme=P.LGT_CG_RELIABLE)
+            for a, b, ra, rb in zip(xe, xg, re_, rg):
+                assert torch.equal(a, b)
+                assert [r.iters for r in ra] == [r.iters for r in rb]
+    for (L, U, b), x, rs in zip(data, xg, rg):
+        g = x.cpu().numpy()
+        for j in range(b.shape[0]):
+            _check_solution(L, U, mass, b[j], g[j], rs[j], tol)
+    for lat in lats:
+        lat.close()

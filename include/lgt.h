@@ -551,25 +551,35 @@ typedef struct {
 
 /* Independent even-odd CGs (own alpha, beta and stop test per right-hand
  * side; not block CG) for every right-hand side of every problem, lattices of
- * different sizes included, in ONE cooperative persistent launch (one
- * workgroup per CU) on the stream of probs[0].ctx -- except for one problem
- * with a mixed scheme, a four-lane inner engine (F32/BF16 links, nrhs > 2)
- * and at least 2^21 (site, rhs) pairs (V/2 times nrhs rounded up to a power
- * of two), which runs the same iteration as a sequence of kernel launches
- * (five per iteration, one chunk of ru_interval iterations -- refinement:
- * check_interval, 10 when 0 -- enqueued ahead of the host's read-back of the
- * states, the FP64 steps between chunks; a right-hand side that meets its
- * inner stop test inside a chunk waits for the chunk's end). The environment
- * variable LGT_BATCH_LAUNCHED = 1 takes that form whenever the problem
- * qualifies apart from its size, 0 never (other values: LGT_ERR_ARG). Not
- * from the paper, which
- * solves one system at a time: each right-hand side runs the CG iteration of
- * lgt_cg_solve, with <p, A p> taken as 4m^2 |p|^2 + |D_oe p|^2 (the same number,
- * since D_eo = -D_oe^dag) so that alpha is known before D_eo, and batching
- * shares each link load among the right-hand sides of a lattice. An iteration
- * has two grid barriers; every workgroup sums the per-workgroup partial sums itself,
- * in a fixed order, so results are bit-reproducible for a given device. FP64
- * reliable updates / refinement steps run inside the same launch. The inner
+ * different sizes included. Not from the paper, which solves one system at a
+ * time: each right-hand side runs the CG iteration of lgt_cg_solve, with
+ * <p, A p> taken as 4m^2 |p|^2 + |D_oe p|^2 (the same number, since D_eo =
+ * -D_oe^dag) so that alpha is known before D_eo, and batching shares each
+ * link load among the right-hand sides of a lattice. Two forms, the same
+ * iteration and results to rounding:
+ *  - kernel launches, when the scheme is mixed, every problem has a four-lane
+ *    inner engine (F32/BF16 links, nrhs > 2), and there is one problem or up
+ *    to four problems on different contexts: five launches per iteration per
+ *    problem, each problem on an auxiliary stream of its context (created on
+ *    first use, default priority, ordered against the context's stream and
+ *    probs[0].ctx's stream by events, so that the problems overlap); chunks
+ *    of ru_interval iterations (refinement: check_interval, 10 when 0) go out
+ *    ahead of the host's read-back of the states, as one replay of a HIP
+ *    graph captured at the start of the call (timing off) or as single
+ *    launches (timing on), the FP64 steps between chunks; a right-hand side
+ *    that meets its inner stop test inside a chunk waits for the chunk's end.
+ *  - otherwise ONE cooperative persistent launch (one workgroup per CU) on
+ *    the stream of probs[0].ctx: two grid barriers an iteration, every
+ *    workgroup summing the per-workgroup partial sums itself, FP64 reliable
+ *    updates / refinement steps inside the same launch. Every grid-barrier
+ *    wait is bounded (about 2^21 polls, seconds; the environment variable
+ *    LGT_BATCH_SPIN_LIMIT sets another bound in [1, 2^30]): a wait that runs
+ *    out ends the launch in every workgroup and the call returns
+ *    LGT_ERR_DEVICE.
+ * The environment variable LGT_BATCH_LAUNCHED = 1 takes the launched form
+ * whenever the scheme and engines allow it (any number of problems), 0 never
+ * (other values: LGT_ERR_ARG). Sums are taken in a fixed order in both forms,
+ * so results are bit-reproducible for a given device and form. The inner
  * Dslash of each problem uses the multi-RHS variant of that problem's own
  * context (lgt_set_mrhs_engine / lgt_set_mrhs_variant / lgt_tune_dslash_mrhs).
  * Schemes and parameters as lgt_cg_solve (shared by all problems); res[j].seconds
@@ -578,10 +588,7 @@ typedef struct {
  * nprob <= 64; the sum over problems of nrhs rounded up to a power of two
  * is <= 256 (a padding right-hand side costs the work of a real one but
  * converges at once and is never reported); a context may appear in several
- * problems. Every grid-barrier wait inside the launch is bounded (about 2^21
- * polls, seconds; the environment variable LGT_BATCH_SPIN_LIMIT sets another
- * bound in [1, 2^30]): a wait that runs out ends the launch in every
- * workgroup and the call returns LGT_ERR_DEVICE. Synchronous. */
+ * problems. Synchronous. */
 lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const lgt_cg_params *p);
 
 /* Phase profile of the last lgt_cg_solve_batch whose first problem's context
@@ -595,8 +602,9 @@ lgt_status lgt_cg_solve_batch(const lgt_cg_problem *probs, int32_t nprob, const 
  * (8) the FP64 reliable updates / refinement steps; iters the iterations run
  * (the most of any right-hand side, for the launched form). A wait is the
  * slowest workgroup's extra time plus the barrier itself. For the launched
- * form (lgt_cg_solve_batch) the entries are the summed kernel times of each
- * kind, measured with events around every launch, and the waits are zero.
+ * form (lgt_cg_solve_batch) the entries are the kernel times of each kind,
+ * measured with events around every launch and summed over the problems
+ * (which overlap in time), and the waits are zero.
  * Zeros before any such solve. Host only. */
 lgt_status lgt_batch_profile(lgt_ctx *ctx, double ms[9], int32_t *iters);
 

@@ -788,8 +788,9 @@ def routine(lat: "Lattice", name: str, a: torch.Tensor, b: torch.Tensor, s: floa
 def cg_solve_batch(problems, mass: float, tol: float = 1e-10, scheme: int = LGT_CG_RELIABLE,
                    ru_interval: int = 50, inner_tol: float = 0.0, max_iter: int = 100000,
                    raise_on_fail: bool = True):
-    """Independent CGs for every right-hand side of every problem in one persistent launch
-    (one large mixed-precision problem: the same iteration as kernel launches).
+    """Independent CGs for every right-hand side of every problem: one persistent launch, or
+    (mixed precision, four-lane inner engines, one problem or up to four on different
+    contexts) the same iteration as kernel launches, problems on their own streams.
 
     problems: list of (lattice, U_hi, U_lo, b) with b a float64 tensor [N][V/2][3][2]
     (1 <= N <= 16). Returns ([x per problem], [[CgResult per rhs] per problem]).

@@ -74,6 +74,9 @@ struct Run {
     int enq = 0;             // chunks enqueued
     ~Run()
     {
+        // an error return may leave launches of this problem queued: let them
+        // finish before its graph and events go
+        if (s) (void)hipStreamSynchronize(s);
         if (chunk) (void)hipGraphExecDestroy(chunk);
     }
 };

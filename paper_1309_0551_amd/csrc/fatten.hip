@@ -148,10 +148,12 @@ __global__ __launch_bounds__(kBS) void k_fat_inner(const double *__restrict__ U,
 }
 
 // F_mu(x) and N_mu(x) for every site x of direction mu, the innermost level from
-// W; 2 * nbh_pad blocks
+// W; with I set, also the six fields I_a(x + a) under the outer staples
+// (slot a; each (a, y) is reached from exactly one x), which the chain rule
+// needs again; 2 * nbh_pad blocks
 __global__ __launch_bounds__(kBS) void k_fat_outer(const double *__restrict__ U, const double *__restrict__ W,
                                                    double *__restrict__ F, double *__restrict__ N, Geom g, int mu,
-                                                   FatCoeffs w, int nbh_pad)
+                                                   FatCoeffs w, int nbh_pad, double *__restrict__ I)
 {
     const int64_t V = 2 * (int64_t)g.Vh;
     const int64_t ex = xcd_site(g, (int)(blockIdx.x & 7), (int)(blockIdx.x >> 3), nbh_pad, (int)threadIdx.x);
@@ -165,7 +167,9 @@ __global__ __launch_bounds__(kBS) void k_fat_outer(const double *__restrict__ U,
         const int a = other_axis(mu, ia >> 1), sa = (ia & 1) ? -1 : 1;
         int xa[4];
         step(g, x, a, sa, xa);
-        axpy(acc, 1.0, staple(U, V, g, x, mu, a, sa, mid_field(U, W, g, xa, mu, ia, w)));
+        const M3 m = mid_field(U, W, g, xa, mu, ia, w);
+        if (I) stm3(I, V, ia, eo_of(g, xa), m);
+        axpy(acc, 1.0, staple(U, V, g, x, mu, a, sa, m));
     }
     stm3(F, V, mu, ex, acc);
 
@@ -376,23 +380,28 @@ __global__ __launch_bounds__(kBS) void k_vjp_tr(const double *__restrict__ U, co
 } // namespace
 
 hipError_t launch_fatten(const double *U, double *F, double *N, double *W, const Geom &g, const FatCoeffs &w,
-                         hipStream_t s)
+                         hipStream_t s, double *I)
 {
+    const int64_t V = 2 * (int64_t)g.Vh;
     const int nbh = (int)(((int64_t)g.Vh + kBS - 1) / kBS), nbh_pad = (nbh + 7) / 8 * 8;
     for (int mu = 0; mu < 4; mu++) {
-        hipLaunchKernelGGL(k_fat_inner, dim3(6u * (unsigned)nbh_pad), dim3(kBS), 0, s, U, W, g, mu, w.c5, w.c7,
+        // with I: the fields of every direction kept (W per direction, I after them)
+        double *Wm = I ? W + (size_t)mu * 3 * V * 18 : W;
+        double *Im = I ? I + (size_t)mu * 6 * V * 18 : nullptr;
+        hipLaunchKernelGGL(k_fat_inner, dim3(6u * (unsigned)nbh_pad), dim3(kBS), 0, s, U, Wm, g, mu, w.c5, w.c7,
                            nbh_pad);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_fat_outer, dim3(2u * (unsigned)nbh_pad), dim3(kBS), 0, s, U, W, F, N, g, mu, w,
-                           nbh_pad);
+        hipLaunchKernelGGL(k_fat_outer, dim3(2u * (unsigned)nbh_pad), dim3(kBS), 0, s, U, Wm, F, N, g, mu, w,
+                           nbh_pad, Im);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 hipError_t launch_fatten_vjp(const double *U, const double *GF, const double *GN, double *GU, double *ws,
-                             const Geom &g, const FatCoeffs &w, double scale, bool accumulate, hipStream_t s)
+                             const Geom &g, const FatCoeffs &w, double scale, bool accumulate, hipStream_t s,
+                             const double *Wk, const double *Ik)
 {
     const int64_t V = 2 * (int64_t)g.Vh;
     const int nbh = (int)(((int64_t)g.Vh + kBS - 1) / kBS), nbh_pad = (nbh + 7) / 8 * 8;
@@ -401,8 +410,13 @@ hipError_t launch_fatten_vjp(const double *U, const double *GF, const double *GN
     if (!accumulate && (e = launch_zero(GU, (size_t)4 * V * 18 * sizeof(double), s)) != hipSuccess) return e;
     const dim3 b(kBS), g2(2u * (unsigned)nbh_pad), g6(6u * (unsigned)nbh_pad), g12(12u * (unsigned)nbh_pad);
     for (int mu = 0; mu < 4; mu++) {
-        hipLaunchKernelGGL(k_fat_inner, g6, b, 0, s, U, W, g, mu, w.c5, w.c7, nbh_pad);
-        hipLaunchKernelGGL(k_vjp_mid, g12, b, 0, s, U, W, I, g, mu, w, nbh_pad);
+        if (Wk) { // the forward's fields of this direction
+            W = (double *)Wk + (size_t)mu * 3 * V * 18;
+            I = (double *)Ik + (size_t)mu * 6 * V * 18;
+        } else {
+            hipLaunchKernelGGL(k_fat_inner, g6, b, 0, s, U, W, g, mu, w.c5, w.c7, nbh_pad);
+            hipLaunchKernelGGL(k_vjp_mid, g12, b, 0, s, U, W, I, g, mu, w, nbh_pad);
+        }
         hipLaunchKernelGGL(k_vjp_q, g12, b, 0, s, U, GF, Q, g, mu, scale, nbh_pad);
         hipLaunchKernelGGL(k_vjp_r, g6, b, 0, s, U, Q, R, g, mu, nbh_pad);
         hipLaunchKernelGGL(k_vjp_mu, g2, b, 0, s, U, GF, GN, Q, R, GU, g, mu, w, scale, nbh_pad);

@@ -79,12 +79,14 @@ bool overlap(const void *p, const void *q, size_t bytes)
     return a < b + bytes && b < a + bytes;
 }
 
+// Wk, Ik: the fields a launch_fatten at the same U kept, or null
 lgt_status fatten_vjp(lgt_ctx *c, const double *U, const FatCoeffs &fc, const double *GF, const double *GN,
-                      double scale, bool accumulate, double *GU)
+                      double scale, bool accumulate, double *GU, const double *Wk = nullptr,
+                      const double *Ik = nullptr)
 {
     double *ws = (double *)workspace(c, "fatten.vjp", (size_t)kFatVjpMatrices * volume(c) * 18 * sizeof(double));
     if (!ws) return fail(LGT_ERR_OOM, "cannot allocate the fattening workspace");
-    LGT_HIP(launch_fatten_vjp(U, GF, GN, GU, ws, c->g, fc, scale, accumulate, c->stream));
+    LGT_HIP(launch_fatten_vjp(U, GF, GN, GU, ws, c->g, fc, scale, accumulate, c->stream, Wk, Ik));
     return LGT_OK;
 }
 
@@ -131,8 +133,11 @@ lgt_status hmc_trajectory(lgt_ctx *c, double *U, double *P, const double *R_e, c
     void *nv_out = workspace(c, "hmc.nv_out", v64);
     if (!U0 || !P0 || !G || !Uhi || (mixed && !Ulo) || !phi || !X || !t || !nv_in || !nv_out)
         return fail(LGT_ERR_OOM, "cannot allocate the HMC workspace");
-    // improved: canonical F, N and their derivatives, packed Naik fields
-    double *Fc = nullptr, *Nc = nullptr, *GF = nullptr, *GN = nullptr;
+    // improved: canonical F, N and their derivatives, packed Naik fields, and
+    // the fattening's intermediate fields of every direction (12 V and 24 V
+    // matrices), kept by each fattening for the chain rule at the same U,
+    // which then skips a third of its products
+    double *Fc = nullptr, *Nc = nullptr, *GF = nullptr, *GN = nullptr, *Wk = nullptr, *Ik = nullptr;
     void *Nhi = nullptr, *Nlo = nullptr;
     if (imp) {
         Fc = (double *)workspace(c, "hmc.F", fb);
@@ -141,7 +146,9 @@ lgt_status hmc_trajectory(lgt_ctx *c, double *U, double *P, const double *R_e, c
         GN = (double *)workspace(c, "hmc.GN", fb);
         Nhi = workspace(c, "hmc.Nhi", lb_hi);
         Nlo = mixed ? workspace(c, "hmc.Nlo", lb_lo) : nullptr;
-        if (!Fc || !Nc || !GF || !GN || !Nhi || (mixed && !Nlo))
+        Wk = (double *)workspace(c, "hmc.fatW", (size_t)12 * V * 18 * sizeof(double));
+        Ik = (double *)workspace(c, "hmc.fatI", (size_t)24 * V * 18 * sizeof(double));
+        if (!Fc || !Nc || !GF || !GN || !Nhi || (mixed && !Nlo) || !Wk || !Ik)
             return fail(LGT_ERR_OOM, "cannot allocate the HMC workspace");
     }
     LGT_HIP(hipMemcpyAsync(U0, U, fb, hipMemcpyDeviceToDevice, st));
@@ -159,7 +166,7 @@ lgt_status hmc_trajectory(lgt_ctx *c, double *U, double *P, const double *R_e, c
             if (r == LGT_OK && mixed) r = lgt_pack_links(c, U, LGT_F32, LGT_R12, Ulo);
             return r;
         }
-        if ((r = lgt_fatten_links(c, U, &w, Fc, Nc)) != LGT_OK) return r;
+        LGT_HIP(launch_fatten(U, Fc, Nc, Wk, c->g, *fc, st, Ik));
         if ((r = lgt_pack_links(c, Fc, LGT_F64, LGT_R18, Uhi)) != LGT_OK) return r;
         if ((r = lgt_pack_links(c, Nc, LGT_F64, LGT_R18, Nhi)) != LGT_OK) return r;
         if (mixed && (r = lgt_pack_links(c, Fc, LGT_F32, LGT_R18, Ulo)) != LGT_OK) return r;
@@ -198,7 +205,8 @@ lgt_status hmc_trajectory(lgt_ctx *c, double *U, double *P, const double *R_e, c
             if ((q = lgt_force(c, &lhi, X, 1.0, G)) != LGT_OK) return q;
         } else {
             if ((q = lgt_force_improved(c, &lhi, &nhi, X, 1.0, GF, GN)) != LGT_OK) return q;
-            if ((q = fatten_vjp(c, U, *fc, GF, GN, 1.0, false, G)) != LGT_OK) return q;
+            // the last fattening ran at this U (pack() before the solve)
+            if ((q = fatten_vjp(c, U, *fc, GF, GN, 1.0, false, G, Wk, Ik)) != LGT_OK) return q;
         }
         LGT_HIP(launch_gauge_force(U, G, c->g, hp->beta, 1.0, 1, st));
         LGT_HIP(launch_momentum(U, G, P, V, h, st));

@@ -143,14 +143,19 @@ struct FatCoeffs {
     double c1, c3, c5, c7, cL, cN; // one link, 3-, 5-, 7-link staples, Lepage, Naik
 };
 // F, N (canonical [4][V][3][3][2] float64) from U in the same layout; W: workspace
-// of 3 V matrices (the innermost staple fields of one direction at a time)
+// of 3 V matrices (the innermost staple fields of one direction at a time).
+// With I set, W must hold 4 * 3 V and I 4 * 6 V matrices: every direction's
+// innermost fields and the fields under its outer staples are kept there for
+// launch_fatten_vjp at the same U.
 hipError_t launch_fatten(const double *U, double *F, double *N, double *W, const Geom &g, const FatCoeffs &w,
-                         hipStream_t s);
+                         hipStream_t s, double *I = nullptr);
 // GU (+)= scale * dS/dU from GF = dS/dF and GN = dS/dN (all canonical); ws:
-// workspace of kFatVjpMatrices * V matrices (18 doubles each)
+// workspace of kFatVjpMatrices * V matrices (18 doubles each). Wk, Ik: the
+// fields launch_fatten kept at this U (then not recomputed), or null.
 constexpr int kFatVjpMatrices = 18;
 hipError_t launch_fatten_vjp(const double *U, const double *GF, const double *GN, double *GU, double *ws,
-                             const Geom &g, const FatCoeffs &w, double scale, bool accumulate, hipStream_t s);
+                             const Geom &g, const FatCoeffs &w, double scale, bool accumulate, hipStream_t s,
+                             const double *Wk = nullptr, const double *Ik = nullptr);
 
 // ---- Table 1 routines (routines.hip) ---------------------------------------
 hipError_t launch_routine(int routine, bool f64, const void *a, const void *b, void *c, int64_t n, double s,

@@ -615,7 +615,7 @@ __global__ __launch_bounds__(kBB) void k_batch_cg(const BatchArgs *__restrict__ 
         s.max_iter = A->max_iter;
         s.scheme = A->scheme;
         s.ru_fixed = A->scheme == SCH_RELIABLE;
-        s.pend = s.pad1 = 0;
+        s.pend = s.pcur = 0;
         S.acc[q] = 0.0;
         S.coef[q] = 0.0;
         S.run[q] = 0;

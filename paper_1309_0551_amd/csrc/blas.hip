@@ -70,9 +70,10 @@ __global__ __launch_bounds__(kBS) void k_x_pending(VecArgs a)
     const int cb = blockIdx.x * kBS + threadIdx.x;
     if (cb >= a.Vh) return;
     const T alpha = (T)a.st->alpha;
+    const void *pc = a.p2 && a.st->pcur ? a.p2 : a.p; // the p alpha belongs to
     cx<T> x[3], p[3];
     VecFmt<T>::template load<false>(a.x, (size_t)a.Vh, cb, x);
-    VecFmt<T>::template load<false>(a.p, (size_t)a.Vh, cb, p);
+    VecFmt<T>::template load<false>(pc, (size_t)a.Vh, cb, p);
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         x[i].re = fma(alpha, p[i].re, x[i].re);
@@ -167,7 +168,7 @@ __global__ void k_state_init(CgState *st, int scheme, int ru_fixed, int max_iter
     st->max_iter = max_iter;
     st->scheme = scheme;
     st->ru_fixed = ru_fixed;
-    st->pend = st->pad1 = 0;
+    st->pend = st->pcur = 0;
 }
 
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol, double inner,

@@ -53,12 +53,39 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
     const size_t Vh = (size_t)a.g.Vh;
     [[maybe_unused]] const int s0 = blk * bs - a.g.hx, ns = staged_sites(a.g, bs);
     [[maybe_unused]] S2 *lds = (S2 *)lds_dyn; // [3][ns]
+    // EPI_PAPX: the gathered input is p' = r + beta p_old, formed here with the
+    // same arithmetic as k_xpay (so the results do not depend on which runs)
+    [[maybe_unused]] const void *pin = a.in;
+    [[maybe_unused]] T beta = T(0);
+    if constexpr (EPI == EPI_PAPX) {
+        pin = a.st->pcur ? a.pb : a.in;
+        beta = (T)a.st->beta;
+    }
+    auto load_in = [&](int n, cx<T> v[3]) __attribute__((always_inline)) {
+        VF::template load<false>(pin, Vh, n, v);
+        if constexpr (EPI == EPI_PAPX) {
+            cx<T> rr[3];
+            VF::template load<false>(a.rin, Vh, n, rr);
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                v[i].re = fma(beta, v[i].re, rr[i].re);
+                v[i].im = fma(beta, v[i].im, rr[i].im);
+            }
+        }
+    };
     if constexpr (HPI == 4) {
         for (int i = threadIdx.x; i < ns; i += bs) {
             const int n = s0 + i;
             if (n >= 0 && n < a.g.Vh) {
+                if constexpr (EPI == EPI_PAPX) {
+                    cx<T> v[3];
+                    load_in(n, v);
 #pragma unroll
-                for (int k = 0; k < 3; k++) lds[k * ns + i] = ((const S2 *)a.in)[k * Vh + n];
+                    for (int k = 0; k < 3; k++) lds[k * ns + i] = S2{v[k].re, v[k].im};
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 3; k++) lds[k * ns + i] = ((const S2 *)a.in)[k * Vh + n];
+                }
             }
         }
         __syncthreads();
@@ -80,9 +107,9 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 const void *W = naik ? a.U3 : a.U;
                 cx<T> u[9], v[3], w[9], z[3];
                 LF::template load<NTL>(W, Vh, a.par * 4 + mu, cb, u);
-                VF::template load<false>(a.in, Vh, h.f, v);
+                load_in(h.f, v);
                 LF::template load<NTL>(W, Vh, (1 - a.par) * 4 + mu, h.b, w);
-                VF::template load<false>(a.in, Vh, h.b, z);
+                load_in(h.b, z);
                 negate_if(h.fneg, v);
                 mv_add(u, v, acc);
                 negate_if(h.bneg, z);
@@ -94,13 +121,13 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 cx<T> u[9], v[3];
                 // forward hop: U_mu(x) in(x+mu)
                 LF::template load<NTL>(a.U, Vh, a.par * 4 + mu, cb, u);
-                VF::template load<false>(a.in, Vh, nbr_fwd(a.g, c, cb, mu), v);
+                load_in(nbr_fwd(a.g, c, cb, mu), v);
                 negate_if(fwd_neg(a.g, c, mu), v);
                 mv_add(u, v, acc);
                 // backward hop: U_mu(x-mu)^dag in(x-mu)
                 const int b = nbr_bwd(a.g, c, cb, mu);
                 LF::template load<NTL>(a.U, Vh, (1 - a.par) * 4 + mu, b, u);
-                VF::template load<false>(a.in, Vh, b, v);
+                load_in(b, v);
                 negate_if(bwd_neg(a.g, c, mu), v);
                 amv_sub(u, v, acc);
             }
@@ -115,26 +142,39 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 stride = staged ? (size_t)ns : Vh;
                 return staged ? lds + j : gin + n;
             };
+            // EPI_PAPX: a hop outside the staged range forms r + beta p itself
+            auto fetch = [&](int n, cx<T> v[3]) __attribute__((always_inline)) {
+                if constexpr (EPI == EPI_PAPX) {
+                    const unsigned j = (unsigned)(n - s0);
+                    if (j < (unsigned)ns) {
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            const S2 x = lds[k * ns + j];
+                            v[k].re = x.x;
+                            v[k].im = x.y;
+                        }
+                    } else {
+                        load_in(n, v);
+                    }
+                } else {
+                    size_t st;
+                    const S2 *q = vsrc(n, st);
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const S2 x = q[k * st];
+                        v[k].re = x.x;
+                        v[k].im = x.y;
+                    }
+                }
+            };
 #pragma unroll 1
             for (int mu = 0; mu < 4; mu++) {
                 const Hop h = hop_rt(a.g, c, cb, mu);
                 cx<T> u[9], v[3], w[9], z[3];
-                size_t sf, sb;
-                const S2 *pf = vsrc(h.f, sf), *pb = vsrc(h.b, sb);
                 LF::template load<NTL>(a.U, Vh, a.par * 4 + mu, cb, u);
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    const S2 x = pf[k * sf];
-                    v[k].re = x.x;
-                    v[k].im = x.y;
-                }
+                fetch(h.f, v);
                 LF::template load<NTL>(a.U, Vh, (1 - a.par) * 4 + mu, h.b, w);
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    const S2 x = pb[k * sb];
-                    z[k].re = x.x;
-                    z[k].im = x.y;
-                }
+                fetch(h.b, z);
                 negate_if(h.fneg, v);
                 mv_add(u, v, acc);
                 negate_if(h.bneg, z);
@@ -146,9 +186,9 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 const Hop h = hop_rt(a.g, c, cb, mu);
                 cx<T> u[9], v[3], w[9], z[3];
                 LF::template load<NTL>(a.U, Vh, a.par * 4 + mu, cb, u);
-                VF::template load<false>(a.in, Vh, h.f, v);
+                load_in(h.f, v);
                 LF::template load<NTL>(a.U, Vh, (1 - a.par) * 4 + mu, h.b, w);
-                VF::template load<false>(a.in, Vh, h.b, z);
+                load_in(h.b, z);
                 negate_if(h.fneg, v);
                 mv_add(u, v, acc);
                 negate_if(h.bneg, z);
@@ -162,14 +202,16 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
                 const Hop h = hop_rt(a.g, c, cb, mu);
                 cx<T> u[9], v[3];
                 LF::template load<NTL>(a.U, Vh, fwd ? a.par * 4 + mu : (1 - a.par) * 4 + mu, fwd ? cb : h.b, u);
-                VF::template load<false>(a.in, Vh, fwd ? h.f : h.b, v);
+                load_in(fwd ? h.f : h.b, v);
                 negate_if(fwd ? h.fneg : h.bneg, v);
                 if (fwd) mv_add(u, v, acc);
                 else amv_sub(u, v, acc);
             }
         }
         if constexpr (EPI == EPI_UPD) {
-            VF::template load<false>(a.aux0, Vh, cb, pu);
+            // double-buffered p: the new p is buffer 1 - pcur (pcur flips at the beta step)
+            const void *pn = a.pb ? (a.st->pcur ? a.aux0 : a.pb) : a.aux0;
+            VF::template load<false>(pn, Vh, cb, pu);
             VF::template load<false>(a.rw, Vh, cb, ru);
         }
     }
@@ -207,6 +249,32 @@ __global__ __launch_bounds__(kBS) void k_dslash(DslashArgs a)
             for (int i = 0; i < 3; i++)
                 part += a.m4 * ((double)p[i].re * (double)p[i].re + (double)p[i].im * (double)p[i].im) +
                         ((double)acc[i].re * (double)acc[i].re + (double)acc[i].im * (double)acc[i].im);
+            VF::template store<true>(a.out, Vh, cb, acc);
+        } else if constexpr (EPI == EPI_PAPX) {
+            // p' = r + beta p_old into the other buffer, x += alpha p_old if
+            // pending, out = D p' ; partial m4 |p'|^2 + |out|^2
+            cx<T> po[3], pn[3];
+            VF::template load<false>(pin, Vh, cb, po);
+            VF::template load<false>(a.rin, Vh, cb, pn);
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                pn[i].re = fma(beta, po[i].re, pn[i].re);
+                pn[i].im = fma(beta, po[i].im, pn[i].im);
+                part += a.m4 * ((double)pn[i].re * (double)pn[i].re + (double)pn[i].im * (double)pn[i].im) +
+                        ((double)acc[i].re * (double)acc[i].re + (double)acc[i].im * (double)acc[i].im);
+            }
+            VF::template store<false>(pin == a.in ? a.pb : (void *)a.in, Vh, cb, pn);
+            if (a.st->pend) {
+                const T alpha = (T)a.st->alpha;
+                cx<T> x[3];
+                VF::template load<false>(a.xw, Vh, cb, x);
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    x[i].re = fma(alpha, po[i].re, x[i].re);
+                    x[i].im = fma(alpha, po[i].im, x[i].im);
+                }
+                VF::template store<false>(a.xw, Vh, cb, x);
+            }
             VF::template store<true>(a.out, Vh, cb, acc);
         } else if constexpr (EPI == EPI_UPD) {
             // Ap = m4 p - D in ; r -= alpha Ap ; partial |r|^2
@@ -282,6 +350,7 @@ static hipError_t launch_fmt(int epi, const DslashArgs &a, hipStream_t s, hipEve
     case EPI_A: launch_k(k_dslash<LF, EPI_A, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_PAP: launch_k(k_dslash<LF, EPI_PAP, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_UPD: launch_k(k_dslash<LF, EPI_UPD, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
+    case EPI_PAPX: launch_k(k_dslash<LF, EPI_PAPX, HPI, NTL>, grid, block, shm, s, a, e0, e1); break;
     case EPI_RES:
     case EPI_RES_LO:
         if constexpr (std::is_same<typename LF::real, double>::value) {

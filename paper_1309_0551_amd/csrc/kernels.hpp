@@ -47,7 +47,8 @@ struct CgState {
     int pend; // 1 while x still lacks alpha p of the last update: the next
               // p = r + beta p adds it (it reads p anyway), else the reliable
               // update or the final residual does, before using x
-    int pad1;
+    int pcur; // double-buffered p (the CG with p = r + beta p inside D_oe):
+              // the buffer holding the current p; the beta step flips it
 };
 
 // Early-exit rule of a solver kernel, read from CgState at kernel start
@@ -74,7 +75,7 @@ inline Launch site_launch(int Vh, int bs = kBS)
 inline bool dslash_bs_ok(int bs) { return bs == 64 || bs == 128 || bs == 256; }
 
 // ---- Dslash family ------------------------------------------------------
-enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3, EPI_PAP = 4, EPI_UPD = 5 };
+enum Epi { EPI_PLAIN = 0, EPI_A = 1, EPI_RES = 2, EPI_RES_LO = 3, EPI_PAP = 4, EPI_UPD = 5, EPI_PAPX = 6 };
 
 struct DslashArgs {
     const void *U;   // packed links (the fat one-link field of the improved operator)
@@ -92,11 +93,21 @@ struct DslashArgs {
     // EPI_UPD: rw -= alpha (m4*aux0 - D in) (D_eo t, Ap never stored), partial
     //          |rw|^2; alpha = rho / (sum of the nparts_in partials parts_in of the
     //          preceding EPI_PAP), every workgroup summing them in the same order
-    //          (workgroup 0 records it in st), or st->alpha when nparts_in == 0
+    //          (workgroup 0 records it in st), or st->alpha when nparts_in == 0;
+    //          with pb set, p is double-buffered and aux0 / pb are buffers 0 / 1:
+    //          the update reads the new p, buffer 1 - st->pcur
+    // EPI_PAPX: EPI_PAP with p' = r + beta p formed here: in / pb are the p
+    //          buffers 0 / 1 (the old p is buffer st->pcur), rin is r; every
+    //          gathered input is r + beta p_old; at its own index each thread
+    //          writes p' to the other buffer and, with st->pend, x += alpha
+    //          p_old into xw; partials m4 |p'|^2 + |out|^2
     const void *aux0;
     const void *aux1;
     void *out_lo;
     void *rw;
+    void *pb;        // second p buffer (double-buffered p), else null
+    const void *rin; // EPI_PAPX: r
+    void *xw;        // EPI_PAPX: x
     const double *parts_in;
     int nparts_in;
     double m4;
@@ -118,6 +129,7 @@ hipError_t launch_index_maps(int32_t *lex_of_eo, int32_t *nbr, const Geom &g, hi
 // ---- vector kernels (solver.hip) -----------------------------------------
 struct VecArgs {
     void *x, *r, *p;
+    void *p2; // double-buffered p: the second buffer (the current p is p2 when st->pcur), else null
     int Vh;
     Launch l;
     CgState *st;

@@ -112,7 +112,7 @@ __global__ void k_mcg_init(CgState *st, int N, int scheme, int ru_fixed, int max
     s.max_iter = max_iter;
     s.scheme = scheme;
     s.ru_fixed = ru_fixed;
-    s.pend = s.pad1 = 0;
+    s.pend = s.pcur = 0;
 }
 
 // partials of |b|^2

@@ -62,6 +62,7 @@ __device__ inline void finalize(int fin, CgState *st, double sum)
     case FIN_UPDATE: { // rho' = |r|^2, beta = rho'/rho
         st->iter += 1;
         st->pend = 1; // x += alpha p still to do
+        st->pcur ^= 1; // double-buffered p: the p of this iteration is current
         if (!isfinite(sum)) {
             st->state = ST_FAIL;
             break;

@@ -12,9 +12,13 @@
 // alpha) and the partials of |r|^2; and the one-workgroup step for beta and the
 // stop tests. On lattices with more than kFuseAlphaMaxParts Dslash workgroups
 // a one-workgroup alpha step runs between the two Dslash launches instead,
-// since the redundant sums grow with the square of the lattice size. (Forming
-// r + beta p inside D_oe instead saves the xpay pass but gathers two vectors
-// at every neighbour, which costs more cache misses than the pass it saves.)
+// since the redundant sums grow with the square of the lattice size. Where an
+// inner-precision vector fits in about one XCD's L2 (kFusedXpayMaxBytes),
+// p = r + beta p (with the pending x += alpha p) is formed inside D_oe
+// instead, three launches an iteration: D_oe gathers r and the old p at every
+// neighbour and writes the new p into the other of two p buffers (the state's
+// pcur says which is current; the beta step flips it). On larger lattices the
+// second gathered vector costs more cache misses than the pass it saves.
 // The host enqueues iterations in chunks and reads the state back once per
 // chunk, one chunk behind, so the GPU never waits for the host.
 //
@@ -62,6 +66,24 @@ struct Events {
 // Largest partial count for which the update kernel sums the <p, Ap>
 // partials itself; LGT_FUSE_ALPHA_MAX overrides the built-in value (both
 // paths give the same bits, so this only moves work between launches).
+// p = r + beta p inside D_oe (EPI_PAPX, p double-buffered) instead of a pass
+// of its own: one launch less per iteration, two vectors gathered at every
+// neighbour instead of one. It pays while an inner-precision vector fits in
+// about one XCD's L2, kFusedXpayMaxBytes (measured, us an iteration, separate
+// -> fused: FP32 x 12 8^4 22.4 -> 18.7, 16^4 23.2 -> 21.4, 24^4 41.3 -> 37.9,
+// 32^4 100.8 -> 105.8; BF16 x 12 16^4 50.1 -> 39.3, 24^4 52.5 -> 49.0; FP64
+// 8^4 22.0 -> 20.6, 20^4 51.0 -> 47.5, 24^4 90.2 -> 98.9, 32^4 261 -> 292).
+// The results are bit-identical either way. LGT_CG_FUSED_XPAY = 1 / 0
+// forces it on / off; else `dflt`.
+constexpr size_t kFusedXpayMaxBytes = (size_t)4 << 20;
+bool fused_xpay(bool dflt)
+{
+    const char *e = std::getenv("LGT_CG_FUSED_XPAY");
+    if (e && !std::strcmp(e, "1")) return true;
+    if (e && !std::strcmp(e, "0")) return false;
+    return dflt;
+}
+
 int fuse_alpha_max()
 {
     const char *e = std::getenv("LGT_FUSE_ALPHA_MAX");
@@ -106,6 +128,8 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     double *q64 = (double *)workspace(c, "cg.q64", v64); // scratch FP64 residual
     void *r = workspace(c, "cg.r", vlo);
     void *pp = workspace(c, "cg.p", vlo);
+    const bool fx = fused_xpay(vlo <= kFusedXpayMaxBytes);
+    void *pp2 = fx ? workspace(c, "cg.p2", vlo) : nullptr;
     void *t = workspace(c, "cg.t", vlo);
     void *xlo = mixed ? workspace(c, "cg.xlo", vlo) : x64;
     // Dslash launches of the two link formats (their workgroup sizes are
@@ -119,7 +143,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     double *partials2 = partials ? partials + np1 : nullptr;
     CgState *dst = (CgState *)workspace(c, "cg.state", sizeof(CgState));
     CgState *host = (CgState *)pinned(c, 3 * sizeof(CgState));
-    if (!b64 || !x64 || !t64 || !q64 || !r || !pp || !t || !xlo || !partials || !dst || !host)
+    if (!b64 || !x64 || !t64 || !q64 || !r || !pp || (fx && !pp2) || !t || !xlo || !partials || !dst || !host)
         return fail(LGT_ERR_OOM, "cannot allocate the solver workspace");
 
     const bool timing = c->timing > 0;
@@ -136,7 +160,8 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     // one partial sum per workgroup for the kernel that follows.
     auto D = [&](Fmt f, int epi, int par, const void *U, const void *in, void *out, int gate, const void *aux0,
                  const void *aux1, void *out_lo, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
-                 void *rw = nullptr, double *parts = nullptr, const double *parts_in = nullptr, int nparts_in = 0) {
+                 void *rw = nullptr, double *parts = nullptr, const double *parts_in = nullptr, int nparts_in = 0,
+                 void *pb = nullptr, const void *rin = nullptr, void *xw = nullptr) {
         DslashArgs a;
         a.U = U;
         // the improved operator's Naik field that goes with this fat field
@@ -153,6 +178,9 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         a.m4 = m4;
         a.partials = parts ? parts : partials;
         a.rw = rw;
+        a.pb = pb;
+        a.rin = rin;
+        a.xw = xw;
         a.parts_in = parts_in;
         a.nparts_in = nparts_in;
         a.st = dst;
@@ -179,6 +207,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
     va.x = xlo;
     va.r = r;
     va.p = pp;
+    va.p2 = pp2;
     va.Vh = Vh;
     va.l = l;
     // partial slots from nblk on belong to idle workgroups (zeros): sum nblk
@@ -237,6 +266,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         for (int i = 0; i < nreal; i += every) {
             for (int k = 0; k < kVec; k++) {
                 if (k == 1 || (k == 3 && fuse_alpha)) continue; // the update runs inside D_eo
+                if (k == 0 && fx) continue;                      // p = r + beta p runs inside D_oe
                 float ms = 0.f;
                 hipError_t e = hipEventElapsedTime(&ms, vv(slot, i, k, true), vv(slot, i, k, false));
                 if (e != hipSuccess) return e;
@@ -280,10 +310,17 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
         for (int i = 0; i < chunk; i++) {
             const int ts = i % every == 0 ? slot : -1;
             const void *Ui = mixed ? Ulo->ptr : Uhi->ptr;
-            LGT_HIP(launch_xpay(lo_is_f64, va, s, vv(ts, i, 0, true), vv(ts, i, 0, false)));
-            // t = D_oe p with the partials of <p, A p> = m4 |p|^2 + |t|^2
-            LGT_HIP(D(flo, EPI_PAP, LGT_ODD, Ui, pp, t, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i, true),
-                      ev(ts, 2 * i, false)));
+            if (fx) {
+                // p' = r + beta p (and the pending x += alpha p) inside D_oe, p' into
+                // the other p buffer; t = D_oe p' with the partials of <p', A p'>
+                LGT_HIP(D(flo, EPI_PAPX, LGT_ODD, Ui, pp, t, GATE_ITER, nullptr, nullptr, nullptr,
+                          ev(ts, 2 * i, true), ev(ts, 2 * i, false), nullptr, nullptr, nullptr, 0, pp2, r, xlo));
+            } else {
+                LGT_HIP(launch_xpay(lo_is_f64, va, s, vv(ts, i, 0, true), vv(ts, i, 0, false)));
+                // t = D_oe p with the partials of <p, A p> = m4 |p|^2 + |t|^2
+                LGT_HIP(D(flo, EPI_PAP, LGT_ODD, Ui, pp, t, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i, true),
+                          ev(ts, 2 * i, false)));
+            }
             if (!fuse_alpha)
                 LGT_HIP(launch_finalize(partials, llo.nblk, dst, FIN_ALPHA, GATE_ITER, s, vv(ts, i, 3, true),
                                         vv(ts, i, 3, false)));
@@ -291,7 +328,7 @@ lgt_status cg_solve(lgt_ctx *c, const lgt_links *Uhi, const lgt_links *Ulo, cons
             // from D_oe's partials in every workgroup when fused)
             LGT_HIP(D(flo, EPI_UPD, LGT_EVEN, Ui, t, nullptr, GATE_ITER, pp, nullptr, nullptr, ev(ts, 2 * i + 1, true),
                       ev(ts, 2 * i + 1, false), r, partials2, fuse_alpha ? partials : nullptr,
-                      fuse_alpha ? llo.nblk : 0));
+                      fuse_alpha ? llo.nblk : 0, pp2));
             LGT_HIP(launch_finalize(partials2, llo.nblk, dst, FIN_UPDATE, GATE_ITER, s, vv(ts, i, 2, true),
                                     vv(ts, i, 2, false)));
         }

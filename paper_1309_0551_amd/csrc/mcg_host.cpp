@@ -13,12 +13,15 @@
 // right-hand side that meets its inner stop test inside a chunk idles (its
 // kernels skip it) until the FP64 step at the end of the chunk.
 //
-// Each problem runs on its context's auxiliary stream, after the work already
-// queued on the context's own stream and on the first problem's, so the
-// launches of different problems overlap on the GPU (problems that share a
-// context share its auxiliary stream and run one after the other); at the
-// end each context's stream waits for its problems, and the batch's time is
-// taken on the first problem's stream.
+// A single problem runs on its context's stream. Several problems run each on
+// its context's auxiliary stream, after the work already queued on the
+// context's own stream and on the first problem's, so the launches of
+// different problems overlap on the GPU (problems that share a context share
+// its auxiliary stream and run one after the other); at the end each
+// context's stream waits for its problems, and the batch's time is taken on
+// the first problem's stream. (Auxiliary streams only where they serve
+// overlap: HIP maps streams onto four hardware queues by default, and
+// streams beyond that share queues and serialise.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,7 +64,7 @@ constexpr int kK = 5; // launches of an iteration: xpay, D_oe, alpha, D_eo, beta
 struct Run {
     const lgt_cg_problem *q = nullptr;
     Fmt flo = F32R12;
-    hipStream_t s = nullptr;  // the context's auxiliary stream: the problem's work
+    hipStream_t s = nullptr;  // the problem's work: the context's stream, or its auxiliary one
     hipStream_t cs = nullptr; // the context's stream
     McgArgs a;
     int N = 0, nit = 0, nlane = 0, nxp = 0;
@@ -108,11 +111,11 @@ lgt_status mcg_solve(const McgProblem *mp, int nprob, const lgt_cg_params *p)
         const Geom g = c->g;
         R.q = m.q;
         R.flo = m.flo;
-        if (!c->aux && hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+        if (nprob > 1 && !c->aux && hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
             c->aux = nullptr;
             return fail(LGT_ERR_DEVICE, "cannot create the auxiliary stream of problem %d", i);
         }
-        R.s = c->aux;
+        R.s = nprob > 1 ? c->aux : c->stream;
         R.cs = c->stream;
         R.N = 1 << m.logN;
         R.n = (size_t)g.Vh << m.logN;
@@ -213,8 +216,8 @@ lgt_status mcg_solve(const McgProblem *mp, int nprob, const lgt_cg_params *p)
         const Geom &g = a.g;
         // after what the caller queued on the first problem's stream and on
         // this problem's context stream (b and x are read there)
-        LGT_HIP(hipStreamWaitEvent(R.s, top.ev[0], 0));
-        if (R.cs != s0) {
+        if (R.s != s0) LGT_HIP(hipStreamWaitEvent(R.s, top.ev[0], 0));
+        if (R.cs != s0 && R.cs != R.s) {
             LGT_HIP(hipEventRecord(R.evs.ev[5], R.cs));
             LGT_HIP(hipStreamWaitEvent(R.s, R.evs.ev[5], 0));
         }
@@ -238,12 +241,25 @@ lgt_status mcg_solve(const McgProblem *mp, int nprob, const lgt_cg_params *p)
     // chunk holds kernels only (no memset nodes); its arguments never change
     // within a solve, the kernels read their gates from the device states.
     if (!timing) {
+        // captured on a stream of its own (the context's stream may be the
+        // null stream, which cannot be captured), replayed on the problem's
+        struct CaptureStream {
+            hipStream_t s = nullptr;
+            ~CaptureStream()
+            {
+                if (s) (void)hipStreamDestroy(s);
+            }
+        } cap;
+        LGT_HIP(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
         for (auto &run : runs) {
             Run &R = *run;
             hipGraph_t gr = nullptr;
+            const hipStream_t exec = R.s;
+            R.s = cap.s; // enqueue_chunk launches on R.s
             LGT_HIP(hipStreamBeginCapture(R.s, hipStreamCaptureModeThreadLocal));
             const hipError_t e = enqueue_chunk(R, 0);
             const hipError_t e2 = hipStreamEndCapture(R.s, &gr);
+            R.s = exec;
             if (e != hipSuccess || e2 != hipSuccess) {
                 if (gr) (void)hipGraphDestroy(gr);
                 return fail(LGT_ERR_DEVICE, "capturing the batched CG chunk failed: %s",
@@ -311,8 +327,8 @@ lgt_status mcg_solve(const McgProblem *mp, int nprob, const lgt_cg_params *p)
         LGT_HIP(launch_unpack_mrhs(true, a.x64, R.q->x, a.g, a.logN, R.s, R.q->nrhs));
         LGT_HIP(hipMemcpyAsync(R.host + (size_t)2 * R.N, a.st, sizeof(CgState) * R.N, hipMemcpyDeviceToHost, R.s));
         LGT_HIP(hipEventRecord(R.evs.ev[4], R.s));
-        LGT_HIP(hipStreamWaitEvent(s0, R.evs.ev[4], 0));
-        if (R.cs != s0) LGT_HIP(hipStreamWaitEvent(R.cs, R.evs.ev[4], 0));
+        if (R.s != s0) LGT_HIP(hipStreamWaitEvent(s0, R.evs.ev[4], 0));
+        if (R.cs != s0 && R.cs != R.s) LGT_HIP(hipStreamWaitEvent(R.cs, R.evs.ev[4], 0));
     }
     LGT_HIP(hipEventRecord(top.ev[1], s0));
     LGT_HIP(hipEventSynchronize(top.ev[1]));

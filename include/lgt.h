@@ -560,9 +560,10 @@ typedef struct {
  *  - kernel launches, when the scheme is mixed, every problem has a four-lane
  *    inner engine (F32/BF16 links, nrhs > 2), and there is one problem or up
  *    to four problems on different contexts: five launches per iteration per
- *    problem, each problem on an auxiliary stream of its context (created on
- *    first use, default priority, ordered against the context's stream and
- *    probs[0].ctx's stream by events, so that the problems overlap); chunks
+ *    problem; one problem runs on its context's stream, several each on an
+ *    auxiliary stream of its context (created on first use, default
+ *    priority, ordered against the context's stream and probs[0].ctx's
+ *    stream by events, so that the problems overlap); chunks
  *    of ru_interval iterations (refinement: check_interval, 10 when 0) go out
  *    ahead of the host's read-back of the states, as one replay of a HIP
  *    graph captured at the start of the call (timing off) or as single

@@ -148,34 +148,42 @@ __host__ __device__ __forceinline__ int xcd_block(int bid, int nblk_pad)
 // z-blocked XCD order of site tiles, for kernels whose input vector is too
 // large for an XCD's L2 to hold the three t-slices a slab walk reuses (many
 // right-hand sides per site). Tiles are runs of `T` consecutive cb sites; when
-// a t-slice (V/2 / Lt sites) holds a whole number n_ts >= 8 of them, XCD x
-// takes, for every t, the tiles at positions [x n_ts / 8, (x+1) n_ts / 8) of
-// the slice -- a range of z planes -- and walks them t-major. The input a tile
-// reads from t +- 1 was then loaded a few tiles earlier by the same XCD; only
-// the two z planes bounding the range come from another XCD's share.
+// a t-slice (V/2 / Lt sites) holds a whole number n_ts >= 8 of them, the 8
+// XCDs form a kz x (8 / kz) grid over (z, t): XCD x takes the tiles at
+// positions [zx n_ts / kz, (zx+1) n_ts / kz) of each slice -- a range of z
+// planes -- for the t-slices of range tx of the 8 / kz equal t ranges
+// (zx = x mod kz, tx = x / kz), and walks them t-major. The input a tile reads
+// from t +- 1 was then loaded a few tiles earlier by the same XCD; only the
+// two z planes bounding the range (and the two slices bounding the t range)
+// come from another XCD's share. Fewer z ranges halve the z-boundary
+// fetches at the price of t-boundary ones and of a longer t-reuse distance.
 struct TileOrder {
     int n_ts; // tiles per t-slice; 0: plain slab order (xcd_block)
     int Lt;
-    int per;  // blocks launched per XCD: Lt * ceil(n_ts / 8)
+    int per;  // blocks launched per XCD: ceil(Lt / (8 / kz)) * ceil(n_ts / kz)
+    int kz;   // z ranges: 8, 4, 2 or 1
 };
 
-__host__ __device__ __forceinline__ TileOrder tile_order(const Geom &g, int T)
+__host__ __device__ __forceinline__ TileOrder tile_order(const Geom &g, int T, int kz = 8)
 {
-    TileOrder o{0, g.L[3], 0};
+    TileOrder o{0, g.L[3], 0, kz};
     const int slice = g.Vh / g.L[3];
     if (T <= 0 || slice % T != 0 || slice / T < 8) return o;
+    const int kt = 8 / kz;
     o.n_ts = slice / T;
-    o.per = g.L[3] * ((o.n_ts + 7) / 8);
+    o.per = (g.L[3] + kt - 1) / kt * ((o.n_ts + kz - 1) / kz);
     return o;
 }
 
 // tile of the k-th block of XCD x under order o, or -1 past its share
 __host__ __device__ __forceinline__ int zorder_tile(const TileOrder &o, int x, int k)
 {
-    const int lo = (x * o.n_ts) >> 3, hi = ((x + 1) * o.n_ts) >> 3, ns = hi - lo;
-    if (k >= o.Lt * ns) return -1;
+    const int kt = 8 / o.kz, zx = x % o.kz, tx = x / o.kz;
+    const int lo = zx * o.n_ts / o.kz, hi = (zx + 1) * o.n_ts / o.kz, ns = hi - lo;
+    const int t0 = tx * o.Lt / kt, nt = (tx + 1) * o.Lt / kt - t0;
+    if (k >= nt * ns) return -1;
     const int t = k / ns;
-    return t * o.n_ts + lo + (k - t * ns);
+    return (t0 + t) * o.n_ts + lo + (k - t * ns);
 }
 
 } // namespace lgt

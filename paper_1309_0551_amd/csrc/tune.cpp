@@ -131,6 +131,27 @@ void cache_store(const std::string &key, int hops, int stream, int bs, const dou
     out << "\n";
 }
 
+// Runs `step` (one or two launches on s) until kWarmMs of GPU time have
+// passed, at most 256 times, before any variant is timed: coming out of idle
+// (a fifth of a second is enough) the GPU runs a bandwidth-bound kernel up
+// to a fifth slower for the first tens of milliseconds (24^3 x 48, 16
+// right-hand sides: 89 against 74 us), which would rank the variants timed
+// first unfairly and report times no sustained run sees.
+constexpr float kWarmMs = 40.f;
+template <class Step> hipError_t warm_up(Step step, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    hipError_t e = hipEventRecord(e0, s);
+    for (int round = 0; round < 64 && e == hipSuccess; round++) {
+        for (int k = 0; k < 4 && e == hipSuccess; k++) e = step();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms >= kWarmMs) break;
+    }
+    return e;
+}
+
 } // namespace
 
 extern "C" {
@@ -258,6 +279,10 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[24])
     // timed only below 1024 workgroups of 256 sites (4 per CU).
     const bool small = site_launch(c->g.Vh).nblk < 1024;
     for (int i = 0; i < kN; i++) t[i] = -1.0;
+    a.hpi = kHops[0];
+    a.ntl = kStream[0];
+    a.l = site_launch(c->g.Vh, kBsList[0]);
+    e = warm_up(pair, c->stream, e0, e1);
     for (int i = 0; i < kN && e == hipSuccess; i++) {
         if (kBsList[i / kNumVariants] != 256 && !small) continue;
         a.hpi = kHops[i % kNumVariants];
@@ -369,9 +394,11 @@ lgt_status lgt_tune_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_
     double best_t = 1e300;
     const int reps = 5;
     const bool small = site_launch(c->g.Vh).nblk < 1024;
-    hipError_t e = hipSuccess;
+    for (int i = 0; i < kN; i++) t[i] = -1.0;
+    a.ntl = 1;
+    a.l = site_launch(c->g.Vh, kBsList[0]);
+    hipError_t e = warm_up(pair, c->stream, e0, e1);
     for (int i = 0; i < kN && e == hipSuccess; i++) {
-        t[i] = -1.0;
         if (kBsList[i / 2] != 256 && !small) continue;
         a.ntl = 1 - (i & 1);
         a.l = site_launch(c->g.Vh, kBsList[i / 2]);
@@ -477,8 +504,20 @@ lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, do
     double best_t = 1e300;
     const int reps = 10;
     hipError_t e = hipSuccess;
+    for (int v = 0; v < kNumMrhs; v++) t[v] = -1.0;
+    for (int v = 0; v < kNumMrhs; v++) {
+        if (!mrhs_variant_runs(f, c->g, logN, v)) continue;
+        int par = 0;
+        e = warm_up(
+            [&]() {
+                par ^= 1;
+                return launch_dslash_mrhs(f, U->ptr, in, out, c->g, par, logN, c->stream, kMrhsEngine[v],
+                                          kMrhsGroups[v], kMrhsStaged[v] != 0);
+            },
+            c->stream, e0, e1);
+        break;
+    }
     for (int v = 0; v < kNumMrhs && e == hipSuccess; v++) {
-        t[v] = -1.0;
         if (!mrhs_variant_runs(f, c->g, logN, v)) continue;
         auto run = [&](int par) {
             return launch_dslash_mrhs(f, U->ptr, in, out, c->g, par, logN, c->stream, kMrhsEngine[v], kMrhsGroups[v],

@@ -141,6 +141,8 @@ hipError_t launch_xpay(bool f64, const VecArgs &a, hipStream_t s, hipEvent_t e0 
 hipError_t launch_x_pending(bool f64, const VecArgs &a, hipStream_t s);
 hipError_t launch_ru_accum(double *x64, void *xlo, int Vh, CgState *st, int gate, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// n reals (double if f64, else float) of pseudo-random values in [-1, 1)
+hipError_t launch_fill_noise(void *p, size_t n, bool f64, hipStream_t s);
 hipError_t launch_state_init(CgState *st, int scheme, int ru_fixed, int max_iter, double tol,
                              double inner, hipStream_t s);
 hipError_t launch_norm_init(const double *b64, int Vh, double *partials, CgState *st, hipStream_t s);

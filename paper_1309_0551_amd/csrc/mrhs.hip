@@ -15,9 +15,10 @@ namespace lgt {
 
 // XCD grid of the standalone four-lane kernels' tile order: 4 z ranges x 2 t
 // ranges, which halves the gathers across the z boundary of an XCD's share
-// (at 24^3 x 48 with 16 right-hand sides, FP32 x 12, on one GPU: 74.2-75.7
-// us against 75.5-76.0 with 8 z ranges; 2 x 4 was no faster). The batched CG
-// keeps 8 z ranges, which its kernels run about 1 % faster on.
+// (at 24^3 x 48 with 16 right-hand sides, FP32 x 12, pseudo-random input, on
+// one GPU: VALU engine 81.8-82.1 us against 83.0-83.4 with 8 z ranges, MFMA
+// engine 91.9-93.3 against 95.7-96.7). The batched CG keeps 8 z ranges,
+// which its kernels run about 1 % faster on.
 constexpr int kMrhsKz = 4;
 
 template <class LF>

@@ -132,11 +132,11 @@ void cache_store(const std::string &key, int hops, int stream, int bs, const dou
 }
 
 // Runs `step` (one or two launches on s) until kWarmMs of GPU time have
-// passed, at most 256 times, before any variant is timed: coming out of idle
-// (a fifth of a second is enough) the GPU runs a bandwidth-bound kernel up
-// to a fifth slower for the first tens of milliseconds (24^3 x 48, 16
-// right-hand sides: 89 against 74 us), which would rank the variants timed
-// first unfairly and report times no sustained run sees.
+// passed, at most 256 times, before any variant is timed, so that the first
+// variants are not timed while the GPU comes out of idle: on all-zero input
+// the multi-RHS Dslash (24^3 x 48, 16 right-hand sides) ran its first tens of
+// milliseconds after a fifth of a second of idle a fifth slower (89 against
+// 74 us); on pseudo-random input no such difference was seen (84-88 us).
 constexpr float kWarmMs = 40.f;
 template <class Step> hipError_t warm_up(Step step, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
@@ -232,8 +232,10 @@ lgt_status lgt_tune_dslash(lgt_ctx *c, const lgt_links *U, double times_us[24])
     double *parts = (double *)workspace(c, "tune.partials", sizeof(double) * (size_t)l.nblk_pad);
     CgState *cgs = (CgState *)workspace(c, "tune.state", sizeof(CgState));
     if (!in || !out || !ap || !parts || !cgs) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
-    LGT_HIP(launch_zero(in, vb, c->stream));
-    LGT_HIP(launch_zero(ap, vb, c->stream));
+    // data like a solver's (on zeros, kernels run faster than in a solve);
+    // the zeroed state gives alpha = 0, so r stays as it is
+    LGT_HIP(launch_fill_noise(in, vb / (fmt_is_f64(f) ? 8 : 4), fmt_is_f64(f), c->stream));
+    LGT_HIP(launch_fill_noise(ap, vb / (fmt_is_f64(f) ? 8 : 4), fmt_is_f64(f), c->stream));
     LGT_HIP(launch_zero(cgs, sizeof(CgState), c->stream));
     hipEvent_t e0, e1;
     LGT_HIP(hipEventCreate(&e0));
@@ -355,8 +357,10 @@ lgt_status lgt_tune_dslash_improved(lgt_ctx *c, const lgt_links *fat, const lgt_
     double *parts = (double *)workspace(c, "tune.partials", sizeof(double) * (size_t)l64.nblk_pad);
     CgState *cgs = (CgState *)workspace(c, "tune.state", sizeof(CgState));
     if (!in || !out || !ap || !parts || !cgs) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
-    LGT_HIP(launch_zero(in, vb, c->stream));
-    LGT_HIP(launch_zero(ap, vb, c->stream));
+    // data like a solver's (timed on zeros, kernels run faster than they do
+    // in a solve); the zeroed state gives alpha = 0, so r stays as it is
+    LGT_HIP(launch_fill_noise(in, vb / (fmt_is_f64(f) ? 8 : 4), fmt_is_f64(f), c->stream));
+    LGT_HIP(launch_fill_noise(ap, vb / (fmt_is_f64(f) ? 8 : 4), fmt_is_f64(f), c->stream));
     LGT_HIP(launch_zero(cgs, sizeof(CgState), c->stream));
     hipEvent_t e0, e1;
     LGT_HIP(hipEventCreate(&e0));
@@ -492,7 +496,7 @@ lgt_status lgt_tune_dslash_mrhs(lgt_ctx *c, const lgt_links *U, int32_t nrhs, do
     void *in = workspace(c, "tune.mrhs_in", vb);
     void *out = workspace(c, "tune.mrhs_out", vb);
     if (!in || !out) return fail(LGT_ERR_OOM, "cannot allocate the tuning vectors");
-    LGT_HIP(launch_zero(in, vb, c->stream));
+    LGT_HIP(launch_fill_noise(in, vb / (fmt_is_f64(f) ? 8 : 4), fmt_is_f64(f), c->stream)); // data like a solver's
     hipEvent_t e0, e1;
     LGT_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {

@@ -159,7 +159,9 @@ lgt_status lgt_set_dslash_workgroup(lgt_ctx *ctx, int32_t prec, int32_t recon, i
 lgt_status lgt_get_dslash_workgroup(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t *threads);
 /* Time every variant on U as the CG runs it (1 warm-up and 5 timed pairs of a
  * plain D_oe and a D_eo with the 4m^2 p epilogue and its partial sums, on the
- * context's stream; synchronises) and keep, for U's format, the first variant
+ * context's stream, on pseudo-random vectors in [-1, 1), after about 40 ms of
+ * the first variant so the GPU is out of idle; synchronises) and keep, for
+ * U's format, the first variant
  * in the order below whose time is within 1 % of the fastest. times_us (host,
  * may be NULL; 24 entries) receives the mean launch time of the variants
  * (hops, streaming) = (8,1) (2,1) (1,1) (4,1) (8,0) (2,0) (1,0) (4,0), first
@@ -179,7 +181,8 @@ lgt_status lgt_tune_dslash(lgt_ctx *ctx, const lgt_links *U, double times_us[24]
  * Speed only, as for the one-link variants. */
 lgt_status lgt_set_dslash_improved_variant(lgt_ctx *ctx, int32_t prec, int32_t streaming, int32_t threads);
 lgt_status lgt_get_dslash_improved_variant(lgt_ctx *ctx, int32_t prec, int32_t *streaming, int32_t *threads);
-/* Time the improved operator's CG pair (as lgt_tune_dslash does) on fat and
+/* Time the improved operator's CG pair (as lgt_tune_dslash does, warm-up and
+ * pseudo-random vectors included) on fat and
  * naik (one 18-real format) for streaming and cached link loads with 256-,
  * 128- and 64-site workgroups (the smaller ones only below 1024 workgroups of
  * 256 sites) and keep the first within 1 % of the fastest. times_us (host, may
@@ -530,8 +533,10 @@ lgt_status lgt_get_mrhs_variant(lgt_ctx *ctx, int32_t prec, int32_t recon, int32
 lgt_status lgt_set_mrhs_staging(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t staged);
 lgt_status lgt_get_mrhs_staging(lgt_ctx *ctx, int32_t prec, int32_t recon, int32_t nrhs, int32_t *staged);
 /* Autotuner of the multi-RHS tile shape: times every variant that applies to
- * U's format and nrhs on this lattice (10 launches each, alternating output
- * parity, zero input), keeps the fastest for that (format, nrhs) in the
+ * U's format and nrhs on this lattice (10 launches each after 2 untimed,
+ * alternating output parity, pseudo-random input in [-1, 1), the first
+ * variant first run for about 40 ms so the GPU is out of idle), keeps the
+ * fastest for that (format, nrhs) in the
  * context (engine, groups and staging), and with LGT_TUNE_CACHE set caches it
  * like lgt_tune_dslash. times_us: NULL, or 13 doubles in this order: lane;
  * VALU with 1, 2, 4 groups; MFMA with 1, 2, 4 groups; then the same six

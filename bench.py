@@ -584,6 +584,42 @@ def main():
                           "GBps_best": round(lb.Vh * (8 * 48 + 2 * n * 24) / (best * 1e-6) / 1e9, 1)}
         log(f"mrhs tune {key}: {mrhs_tune[key]}")
     torch.cuda.synchronize()
+    # the tuner's times come from one buffer set launched back to back, whose
+    # 12-real FP32 links (and part of the input) stay in the 256 MB Infinity
+    # Cache between launches; the chosen variant on the large lattice again,
+    # this time over three link and vector sets in turn (1.1 GB), which no
+    # launch finds in that cache
+    if not args.no_tune:
+        lb, _, ul, bb = big[0]
+        n = int(bb.shape[0])
+        key = f"{'x'.join(map(str, lb.L))}_f32r12_N{n}"
+        sets = []
+        for k in range(3):
+            Uk = ul if k == 0 else lb.pack_links(
+                torch.from_numpy(li.links(lb.L, "haar", c4["link_seed"] + 7919 * k)).to(dev), P.LGT_F32, P.LGT_R12)
+            xk = torch.from_numpy(li.vectors(lb.L, c4["src_seed"] + 7919 * k, n)).to(dev)
+            xk = lb.pack_vec_mrhs(xk, P.LGT_F32)
+            sets.append((Uk, xk, torch.empty_like(xk)))
+        for k in range(30):  # warm
+            Uk, xk, yk = sets[k % 3]
+            lb.dslash_mrhs(Uk, xk, k & 1, yk)
+        per = []
+        for rep in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(lb.stream)
+            for k in range(30):
+                Uk, xk, yk = sets[k % 3]
+                lb.dslash_mrhs(Uk, xk, k & 1, yk)
+            e1.record(lb.stream)
+            torch.cuda.synchronize()
+            per.append(e0.elapsed_time(e1) * 1e3 / 30)
+        us = statistics.median(per)
+        ab = mrhs_tune[key]["alg_bytes"]
+        mrhs_tune[key]["three_sets_in_turn"] = {"us": round(us, 2), "GBps": round(ab / (us * 1e-6) / 1e9, 1),
+                                               "frac": round(ab / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"mrhs three sets in turn {key}: {mrhs_tune[key]['three_sets_in_turn']}")
+        del sets
+        torch.cuda.synchronize()
 
     def batched():
         out = {}

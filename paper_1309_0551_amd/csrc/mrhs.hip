@@ -60,7 +60,11 @@ __global__ __launch_bounds__(kBS) void k_dslash_mrhs4(const void *__restrict__ U
     const unsigned rhs0 = (idx % LPS) * R;
     auto IN = [=](int s, cx<float> v[R][3]) __attribute__((always_inline)) { ldm_r<float, R>(in, Vh, logN, s, rhs0, v); };
     cx<float> acc[R][3];
-    dslash_site4<LF, R, MFMA>(g, par, U, site, lane4, IN, acc);
+    // two directions per trip of the direction loop, four hops' loads in
+    // flight (same hop order, so the same sums): at 24^3 x 48 with 16
+    // right-hand sides, FP32 x 12, the VALU engine with two groups 81.1-81.8
+    // -> 76.9-77.6 us, one group 96.3-97.2 -> 82.8-84.0; MFMA a tie
+    dslash_site4<LF, R, MFMA, 2>(g, par, U, site, lane4, IN, acc);
     stm_r<float, R, true>(out, Vh, logN, site, rhs0, acc);
 }
 
